@@ -1,0 +1,416 @@
+"""Pins of the FP64 oracle against closed forms, invariants, library routines
+and brute force.  CPU only.
+
+Each test names the property it checks; a plausible slip in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, FP64 instead of
+FP32 thresholds, accumulate-before-stop) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sps
+
+from oracle import oracle as orc
+from paper_2605_08699_amd import synth
+from tests.handmade import Y00, eye_pose, intr, make_scene, random_tiny_scene
+
+A_MAX = float(np.float32(0.99))
+
+
+# ------------------------------------------------------------ spherical harmonics
+
+def _real_sh_scipy(l, m, theta, phi):
+    """Real SH with the Condon-Shortley phase from scipy's complex harmonics."""
+    if m > 0:
+        return math.sqrt(2.0) * np.real(sps.sph_harm_y(l, m, theta, phi))
+    if m < 0:
+        return math.sqrt(2.0) * np.imag(sps.sph_harm_y(l, -m, theta, phi))
+    return np.real(sps.sph_harm_y(l, 0, theta, phi))
+
+
+def test_sh_basis_matches_scipy():
+    rng = np.random.default_rng(0)
+    theta = rng.uniform(0, math.pi, 200)
+    phi = rng.uniform(0, 2 * math.pi, 200)
+    d = np.column_stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+    Y = orc.sh_basis(d)
+    i = 0
+    for l in range(4):
+        for m in range(-l, l + 1):
+            ref = _real_sh_scipy(l, m, theta, phi)
+            np.testing.assert_allclose(Y[:, i], ref, rtol=0, atol=1e-12, err_msg=f"l={l} m={m}")
+            i += 1
+
+
+def test_sh_addition_theorem():
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=(500, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = orc.sh_basis(d)
+    i = 0
+    for l in range(4):
+        s = np.sum(Y[:, i:i + 2 * l + 1] ** 2, axis=1)
+        np.testing.assert_allclose(s, (2 * l + 1) / (4 * math.pi), rtol=1e-12)
+        i += 2 * l + 1
+
+
+def test_sh_orthonormal_by_quadrature():
+    # Gauss-Legendre in cos(theta) x uniform in phi integrates degree <= 6 products exactly
+    x, w = np.polynomial.legendre.leggauss(12)
+    phi = np.arange(24) * (2 * math.pi / 24)
+    ct, ph = np.meshgrid(x, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    d = np.column_stack([(st * np.cos(ph)).ravel(), (st * np.sin(ph)).ravel(), ct.ravel()])
+    wt = (w[:, None] * np.full(24, 2 * math.pi / 24)[None, :]).ravel()
+    Y = orc.sh_basis(d)
+    G = (Y * wt[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_single_coefficients_and_clamp():
+    k = np.zeros((16, 3))
+    k[2, :] = [0.4, -0.4, 2.0]                      # Y_1,0 = sqrt(3/4pi) z
+    c = orc.sh_color(1, [0, 0, 1], k)
+    s = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose(c, [0.5 + 0.4 * s, 0.5 - 0.4 * s, 0.5 + 2.0 * s], atol=1e-15)
+    k = np.zeros((16, 3))
+    k[0, :] = [-10.0, 0.0, 10.0]                    # clamped below at 0, not above 1
+    c = orc.sh_color(0, [1, 0, 0], k)
+    np.testing.assert_allclose(c, [0.0, 0.5, 0.5 + 10 * Y00], atol=1e-15)
+    # degree limit: coefficients above the requested degree are ignored
+    k = np.zeros((16, 3))
+    k[9:, :] = 1.0
+    np.testing.assert_allclose(orc.sh_color(2, [0.6, 0.0, 0.8], k), [0.5, 0.5, 0.5], atol=1e-15)
+
+
+# ------------------------------------------------------------------ camera model
+
+def test_camera_axes_convention():
+    # a camera at t looking along its own z axis: points along R[:,0] (right)
+    # land right of cx, along R[:,1] (down) below cy, straight ahead on (cx, cy)
+    R = synth.look_at([3.0, -1.0, 2.0], [0.0, 0.5, 0.0])
+    t = np.array([3.0, -1.0, 2.0])
+    pose = synth.Pose(R.astype(np.float32), t.astype(np.float32))
+    Rf = pose.R.astype(np.float64)
+    fwd, right, down = Rf[:, 2], Rf[:, 0], Rf[:, 1]
+    pts = np.stack([t + 3 * fwd, t + 3 * fwd + 0.2 * right, t + 3 * fwd + 0.2 * down])
+    s = make_scene(pts)
+    p = orc.preprocess(s, pose, intr(100.0, 50.0, 40.0), 100, 80)
+    u, v, z = p.field("u"), p.field("v"), p.field("z")
+    np.testing.assert_allclose([u[0], v[0]], [50.0, 40.0], atol=1e-4)
+    assert u[1] > 50.0 + 5 and abs(v[1] - 40.0) < 1e-3
+    assert v[2] > 40.0 + 5 and abs(u[2] - 50.0) < 1e-3
+    np.testing.assert_allclose(z, 3.0, rtol=1e-6)
+
+
+def test_projection_homogeneous_matrix_form():
+    # lambda [u v 1]^T = K [R^T | -R^T t] [mu 1]^T with lambda = z_c, by matrix products
+    rng = np.random.default_rng(3)
+    R = synth.look_at([1.0, 2.0, -6.0])
+    t = np.array([1.0, 2.0, -6.0])
+    pose = synth.Pose(R.astype(np.float32), t.astype(np.float32))
+    mu = rng.uniform(-1, 1, (20, 3))
+    s = make_scene(mu)
+    K = np.array([[300.0, 0, 160.0], [0, 310.0, 120.0], [0, 0, 1]])
+    p = orc.preprocess(s, pose, synth.Intrinsics(300.0, 310.0, 160.0, 120.0), 320, 240)
+    Rf = pose.R.astype(np.float64)
+    Twc = np.eye(4)
+    Twc[:3, :3] = Rf.T
+    Twc[:3, 3] = -Rf.T @ pose.t.astype(np.float64)
+    pc = (Twc @ np.column_stack([s.means.astype(np.float64), np.ones(20)]).T)[:3]
+    uvw = K @ pc
+    np.testing.assert_allclose(p.field("u"), uvw[0] / uvw[2], rtol=1e-12)
+    np.testing.assert_allclose(p.field("v"), uvw[1] / uvw[2], rtol=1e-12)
+    np.testing.assert_allclose(p.field("z"), pc[2], rtol=1e-12)
+
+
+def test_rung_scaling():
+    k = synth.fov_intrinsics(1920, 1080)
+    for s, (w, h) in zip(synth.RUNG_SCALES, [(480, 270), (960, 540), (1440, 810), (1920, 1080)]):
+        ow, oh, (fx, fy, cx, cy) = orc.rung(k, 1920, 1080, s)
+        assert (ow, oh) == (w, h)
+        assert cx == w / 2 and cy == h / 2           # principal point stays centred
+        assert fx == float(np.float32(k.fx * w / 1920.0))
+    # a point's image position scales with the rung
+    s = make_scene([[0.3, -0.2, 4.0]])
+    full = orc.preprocess(s, eye_pose(), k, 1920, 1080)
+    half = orc.preprocess(s, eye_pose(), k, 1920, 1080, scale=0.5)
+    np.testing.assert_allclose(half.field("u"), full.field("u") * 0.5, rtol=1e-7)
+    np.testing.assert_allclose(half.field("v"), full.field("v") * 0.5, rtol=1e-7)
+
+
+# ------------------------------------------------------------------ EWA closed forms
+
+def test_isotropic_gaussian_peak_and_falloff():
+    f, z, sc, logit = 200.0, 4.0, 0.03, 1.2
+    col, bg = np.array([0.9, 0.3, 0.1]), np.array([0.2, 0.4, 0.6])
+    s = make_scene([[0.0, 0.0, z]], log_scales=[[math.log(sc)] * 3], logits=[logit], colors=[col])
+    p = orc.preprocess(s, eye_pose(), intr(f, 16.5, 16.5), 33, 33)
+    sc = math.exp(float(s.log_scales[0, 0]))                  # the FP32-stored inputs
+    logit = float(s.opacity_logits[0])
+    col = 0.5 + Y00 * s.sh[0, 0].astype(np.float64)
+    sig2 = (f * sc / z) ** 2 + 0.3
+    np.testing.assert_allclose([p.field("a")[0], p.field("b")[0], p.field("c")[0]], [sig2, 0.0, sig2],
+                               rtol=1e-12, atol=1e-12)
+    img = orc.render_nominal(p, bg=bg)
+    o = 1 / (1 + math.exp(-logit))
+    for dy in range(-16, 17):
+        for dx in range(-16, 17):
+            a = min(A_MAX, o * math.exp(-(dx * dx + dy * dy) / (2 * sig2)))
+            want = bg if a < float(np.float32(1 / 255)) else col * a + (1 - a) * bg
+            np.testing.assert_allclose(img[16 + dy, 16 + dx], want, atol=1e-12)
+
+
+@pytest.mark.parametrize("x0", [0.5, -1.2, 9.0])
+def test_offaxis_axis_aligned_covariance(x0):
+    f, z0 = 150.0, 3.0
+    sx, sy, sz = 0.05, 0.02, 0.08
+    s = make_scene([[x0, 0.0, z0]], log_scales=[[math.log(sx), math.log(sy), math.log(sz)]])
+    W, H = 120, 100
+    p = orc.preprocess(s, eye_pose(), intr(f, 60.0, 50.0), W, H)
+    sx, sy, sz = np.exp(s.log_scales[0].astype(np.float64))
+    x0 = float(s.means[0, 0])
+    lim = 1.3 * 60.0 / f
+    r = max(-lim, min(lim, x0 / z0))
+    a = (f / z0) ** 2 * (sx ** 2 + r ** 2 * sz ** 2) + 0.3
+    c = (f / z0) ** 2 * sy ** 2 + 0.3
+    np.testing.assert_allclose([p.field("a")[0], p.field("b")[0], p.field("c")[0]], [a, 0.0, c],
+                               rtol=1e-12, atol=1e-14)
+    det = a * c
+    np.testing.assert_allclose([p.field("con_a")[0], p.field("con_c")[0]], [c / det, a / det], rtol=1e-12)
+
+
+def test_ewa_matches_finite_difference_jacobian():
+    # the 2D covariance is the first-order push-forward of the 3D covariance
+    # through the pinhole map: J_num Sigma J_num^T + 0.3 I with J_num from
+    # central differences of the projection (inside the 1.3x FoV clamp)
+    rng = np.random.default_rng(11)
+    cam_t = np.array([0.4, -0.3, -5.0])
+    R = synth.look_at(cam_t, [0.2, 0.1, 0.0]).astype(np.float32)
+    pose = synth.Pose(R, cam_t.astype(np.float32))
+    s = make_scene(rng.uniform(-1, 1, (12, 3)), log_scales=rng.normal(-3, 0.4, (12, 3)),
+                   quats=rng.normal(size=(12, 4)))
+    fx, fy, cx, cy = 400.0, 380.0, 160.0, 130.0
+    p = orc.preprocess(s, pose, synth.Intrinsics(fx, fy, cx, cy), 320, 260)
+    Rf, tf = pose.R.astype(np.float64), pose.t.astype(np.float64)
+
+    def proj(m):
+        pc = Rf.T @ (m - tf)
+        return np.array([fx * pc[0] / pc[2] + cx, fy * pc[1] / pc[2] + cy])
+
+    for g in range(12):
+        mu = s.means[g].astype(np.float64)
+        h = 1e-5
+        Jn = np.column_stack([(proj(mu + h * e) - proj(mu - h * e)) / (2 * h) for e in np.eye(3)])
+        q = s.quats[g].astype(np.float64)
+        q /= np.linalg.norm(q)
+        Rq = synth._quat_to_mat(q[None])[0]
+        S = np.diag(np.exp(s.log_scales[g].astype(np.float64)))
+        Sig = Rq @ S @ S @ Rq.T
+        C2 = Jn @ Sig @ Jn.T + 0.3 * np.eye(2)
+        got = [p.field("a")[g], p.field("b")[g], p.field("c")[g]]
+        np.testing.assert_allclose(got, [C2[0, 0], C2[0, 1], C2[1, 1]], rtol=1e-6, atol=1e-9)
+
+
+def test_sh_colour_uses_camera_to_gaussian_direction():
+    # only the Y_1,0 (z) coefficient: seen from -z the direction is +z
+    k = 0.3
+    s = make_scene([[0, 0, 3], [0, 0, -3]])
+    s.sh[:, 2, :] = k
+    s.sh_degree = 1
+    c1 = math.sqrt(3 / (4 * math.pi))
+    k32 = float(np.float32(k))
+    front = orc.preprocess(s, eye_pose(), intr(40, 4, 4), 8, 8)
+    np.testing.assert_allclose(front.values[0, orc.F["r"]:orc.F["r"] + 3], 0.5 + c1 * k32, atol=1e-12)
+    # camera turned around at the origin looking at the second one (direction -z)
+    back = synth.Pose(np.diag([-1.0, 1.0, -1.0]).astype(np.float32), np.zeros(3, np.float32))
+    p2 = orc.preprocess(s, back, intr(40, 4, 4), 8, 8)
+    np.testing.assert_allclose(p2.values[1, orc.F["r"]:orc.F["r"] + 3], 0.5 - c1 * k32, atol=1e-12)
+
+
+def test_quaternion_rotation_conventions():
+    sx, sy, sz = 0.05, 0.02, 0.03
+    ls = [[math.log(sx), math.log(sy), math.log(sz)]] * 4
+    h = math.sqrt(0.5)
+    quats = [[1, 0, 0, 0], [h, 0, 0, h], [-h, 0, 0, -h], [2 * h, 0, 0, 2 * h]]  # id, 90deg z, -q, unnormalised
+    s = make_scene([[0, 0, 3]] * 4, log_scales=ls, quats=quats)
+    p = orc.preprocess(s, eye_pose(), intr(100, 20, 20), 40, 40)
+    sx, sy, sz = np.exp(s.log_scales[0].astype(np.float64))
+    a, c = p.field("a"), p.field("c")
+    k = (100 / 3) ** 2
+    np.testing.assert_allclose([a[0], c[0]], [k * sx ** 2 + 0.3, k * sy ** 2 + 0.3], rtol=1e-12)
+    np.testing.assert_allclose([a[1], c[1]], [c[0], a[0]], rtol=1e-12)   # 90 deg about z swaps
+    np.testing.assert_allclose([a[2], c[2]], [a[1], c[1]], rtol=1e-12)   # q and -q
+    np.testing.assert_allclose([a[3], c[3]], [a[1], c[1]], rtol=1e-12)   # normalised first
+
+
+def test_support_box_is_the_alpha_threshold_ellipse():
+    rng = np.random.default_rng(5)
+    s = random_tiny_scene(rng, n=40)
+    p = orc.preprocess(s, eye_pose(), intr(80, 32, 32), 64, 64)
+    for g in np.nonzero(p.valid)[0]:
+        v = p.values[g]
+        if v[orc.F["ext_x"]] == 0:
+            continue
+        con = np.array([[v[orc.F["con_a"]], v[orc.F["con_b"]]], [v[orc.F["con_b"]], v[orc.F["con_c"]]]])
+        k2 = 2 * math.log(255 * v[orc.F["opacity"]])
+        # the extreme x of the ellipse d^T con d = k2 is at d = Sigma e_x * sqrt(k2 / Sigma_xx)
+        Sig = np.linalg.inv(con)
+        d = Sig[:, 0] * math.sqrt(k2 / Sig[0, 0])
+        np.testing.assert_allclose(abs(d[0]), v[orc.F["ext_x"]], rtol=1e-9)
+        alpha = v[orc.F["opacity"]] * math.exp(-0.5 * d @ con @ d)
+        np.testing.assert_allclose(alpha, 1 / 255, rtol=1e-9)
+
+
+# ------------------------------------------------------------------ blending rules
+
+def test_two_saturated_layers_hide_everything_behind():
+    bg = np.array([0.1, 0.2, 0.3])
+    c1, c2 = np.array([0.9, 0.8, 0.7]), np.array([0.0, 1.0, 0.0])
+    # large layers: both front layers saturate (alpha clamps to 0.99) over the whole 8x8 image
+    base = dict(log_scales=[[math.log(5.0)] * 3] * 3, logits=[10.0, 10.0, 10.0])
+    f1 = orc.render_nominal(orc.preprocess(make_scene([[0, 0, 2], [0, 0, 3], [0, 0, 4]],
+                                                      colors=[c1, c2, [1, 0, 0]], **base),
+                                           eye_pose(), intr(50, 4, 4), 8, 8), bg=bg)
+    f2 = orc.render_nominal(orc.preprocess(make_scene([[0, 0, 2], [0, 0, 3], [0, 0, 4]],
+                                                      colors=[c1, c2, [0, 0, 1]], **base),
+                                           eye_pose(), intr(50, 4, 4), 8, 8), bg=bg)
+    np.testing.assert_array_equal(f1, f2)                    # the third layer is invisible
+    want = A_MAX * c1 + (1 - A_MAX) * bg                     # FP32 constants: the 2nd layer stops
+    np.testing.assert_allclose(f1[4, 4], want, atol=1e-14)
+    # with FP64 constants the second layer would contribute ~0.0099 * c2
+    assert abs(f1[4, 4, 1] - (want[1] + (1 - 0.99) * 0.99 * (c2[1] - bg[1]))) > 1e-3
+
+
+def test_skip_rule_opacity_below_threshold():
+    bg = np.array([0.25, 0.5, 0.75])
+    logit = math.log((1 / 256) / (1 - 1 / 256))           # o = 1/256 < 1/255
+    s = make_scene([[0, 0, 3], [0.01, 0, 3.5]], log_scales=[[math.log(0.2)] * 3] * 2,
+                   logits=[logit, logit], colors=[[1, 1, 1], [0, 0, 0]])
+    img = orc.render_nominal(orc.preprocess(s, eye_pose(), intr(40, 8, 8), 16, 16), bg=bg)
+    assert np.all(img == bg)
+
+
+def test_skip_rule_alpha_just_above_and_below():
+    # alpha at the pixel centre set to 1/255 * (1 +- 1e-3) through the opacity
+    thr = float(np.float32(1 / 255))
+    res = []
+    for fac in (1 + 1e-3, 1 - 1e-3):
+        o = thr * fac
+        s = make_scene([[0, 0, 3]], log_scales=[[math.log(0.2)] * 3], logits=[math.log(o / (1 - o))],
+                       colors=[[1, 1, 1]])
+        img = orc.render_nominal(orc.preprocess(s, eye_pose(), intr(40, 8.5, 8.5), 17, 17))
+        res.append(img[8, 8, 0])
+    np.testing.assert_allclose(res[0], thr * (1 + 1e-3), rtol=1e-6)
+    assert res[1] == 0.0
+
+
+def test_transmittance_telescopes_to_one():
+    rng = np.random.default_rng(7)
+    s = random_tiny_scene(rng, n=64)
+    s.sh[:] = 0
+    s.sh[:, 0, :] = (1.0 - 0.5) / Y00                     # every colour exactly 1
+    p = orc.preprocess(s, eye_pose(), intr(60, 24, 24), 48, 48)
+    out, nb = orc.render_frame(p, bg=(0, 0, 0), band_a=0, band_t=0, max_branches=1)
+    C, T = out[:, :, 0, 0], out[:, :, 0, 3]
+    np.testing.assert_allclose(C + T, 1.0, atol=1e-12)
+    assert np.all((T >= 0) & (T <= 1))
+    assert np.any(T < 0.5)
+
+
+def test_equal_colour_and_background():
+    rng = np.random.default_rng(8)
+    s = random_tiny_scene(rng, n=64)
+    c = np.array([0.3, 0.6, 0.9])
+    s.sh[:] = 0
+    s.sh[:, 0, :] = ((c - 0.5) / Y00).astype(np.float32)
+    img = orc.render_nominal(orc.preprocess(s, eye_pose(), intr(60, 24, 24), 48, 48), bg=c)
+    np.testing.assert_allclose(img, np.broadcast_to(c, img.shape), atol=1e-6)   # FP32-stored SH
+
+
+def test_storage_order_invariance():
+    rng = np.random.default_rng(9)
+    s = random_tiny_scene(rng, n=64)
+    s.means[4, 2] += 0.01                                   # make all depths distinct
+    s.means[6, 2] += 0.02
+    perm = rng.permutation(s.n)
+    k = intr(60, 24, 24)
+    a = orc.render_nominal(orc.preprocess(s, eye_pose(), k, 48, 48))
+    b = orc.render_nominal(orc.preprocess(s.permuted(perm), eye_pose(), k, 48, 48))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_world_scale_invariance():
+    rng = np.random.default_rng(10)
+    s = random_tiny_scene(rng, n=64, depth=(3.0, 5.0))
+    s.means[2, 2] = 1.0                                     # keep every Gaussian beyond the near plane
+    pose = synth.Pose(np.eye(3, dtype=np.float32), np.array([0.1, -0.2, -0.5], np.float32))
+    k = intr(70, 24, 24)
+    a = orc.render_nominal(orc.preprocess(s, pose, k, 48, 48))
+    s2 = synth.Scene(s.means * 2, s.log_scales + np.float32(math.log(2.0)), s.quats, s.opacity_logits, s.sh, 3)
+    pose2 = synth.Pose(pose.R, pose.t * 2)
+    b = orc.render_nominal(orc.preprocess(s2, pose2, k, 48, 48))
+    np.testing.assert_allclose(a, b, atol=1e-6)
+    assert np.abs(a - b).max() < 1e-6 and a.max() > 0.1
+
+
+def test_equal_depth_ties_by_index():
+    s = make_scene([[0, 0, 3], [0, 0, 3]], log_scales=[[math.log(0.3)] * 3] * 2, logits=[10, 10],
+                   colors=[[1, 0, 0], [0, 1, 0]])
+    p = orc.preprocess(s, eye_pose(), intr(40, 4, 4), 8, 8)
+    assert p.zkey[0] == p.zkey[1]
+    np.testing.assert_array_equal(p.order, [0, 1])
+    img = orc.render_nominal(p)
+    assert img[4, 4, 0] > 0.9 and img[4, 4, 1] < 0.02
+
+
+def test_near_plane_nan_and_degenerate_inputs_dropped():
+    s = make_scene([[0, 0, 0.19], [0, 0, -2], [0, 0, 3], [0, 0, 3], [0, 0, 3]],
+                   log_scales=[[math.log(0.3)] * 3] * 5, logits=[5] * 5)
+    s.quats[3] = 0.0                                        # zero quaternion
+    s.means[4, 0] = np.nan                                  # NaN centre
+    p = orc.preprocess(s, eye_pose(), intr(40, 4, 4), 8, 8)
+    np.testing.assert_array_equal(p.valid, [False, False, True, False, False])
+    empty = make_scene(np.zeros((0, 3)))
+    pe = orc.preprocess(empty, eye_pose(), intr(40, 4, 4), 8, 8)
+    img = orc.render_nominal(pe, bg=(0.1, 0.2, 0.3))
+    np.testing.assert_array_equal(img, np.broadcast_to([0.1, 0.2, 0.3], img.shape))
+
+
+def test_prefilter_equals_brute_force():
+    for seed in range(6):
+        rng = np.random.default_rng(100 + seed)
+        s = random_tiny_scene(rng, n=64, extent=1.5)
+        R = synth.look_at([0.3 * seed, -0.2, -1.0], [0, 0, 3]).astype(np.float32)
+        p = orc.preprocess(s, synth.Pose(R, np.array([0.3 * seed, -0.2, -1.0], np.float32)),
+                           intr(50 + 10 * seed, 31.0 + seed, 33.5), 64, 64)
+        a, na = orc.render_frame(p, bg=(0.1, 0.2, 0.3), prefilter=True)
+        b, nb = orc.render_frame(p, bg=(0.1, 0.2, 0.3), prefilter=False)
+        np.testing.assert_array_equal(na, nb)
+        np.testing.assert_array_equal(a, b)
+
+
+def test_set_valued_branches_at_the_stop_threshold():
+    # choose alpha so that T' lands exactly on the 1e-4 threshold after two layers
+    t_min = float(np.float32(1e-4))
+    a = 1 - math.sqrt(t_min)
+    o = a
+    s = make_scene([[0, 0, 2], [0, 0, 3]], log_scales=[[math.log(0.3)] * 3] * 2,
+                   logits=[math.log(o / (1 - o))] * 2, colors=[[1, 0, 0], [0, 1, 0]])
+    p = orc.preprocess(s, eye_pose(), intr(40, 4.5, 4.5), 9, 9)
+    out, nb = orc.render_pixels(p, [4], [4])
+    assert nb[0] == 2                                       # stopped and not-stopped both admitted
+    greens = sorted(out[0, :2, 1])
+    assert greens[0] == 0.0 and greens[1] > 0.009
+
+
+def test_rungs_reproduce_the_paper_ladder():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ladder_table1.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    k = synth.fov_intrinsics(1280, 720)
+    for sc, w, h in rows:
+        ow, oh, (fx, fy, cx, cy) = orc.rung(k, 1280, 720, float(sc))
+        assert (ow, oh) == (int(w), int(h))
+        assert (cx, cy) == (ow / 2, oh / 2)
