@@ -1,0 +1,205 @@
+/*
+ * tigas.h -- C ABI of the MI355X (gfx950) forward 3D Gaussian Splatting
+ * rasterizer behind the TIGAS rendering backend (arXiv 2605.08699).
+ *
+ * The paper's backend (Section 4.1 and Section 5.1) keeps parsed Gaussian
+ * scenes resident in GPU memory and renders, per stateless client request
+ * (Section 4.2), one frame from a 6DoF pose, pinhole intrinsics and an ABR
+ * resolution rung with a tile-based rasterizer.  This library is that
+ * rasterizer: a resident-scene loader and a render call, plus the batched
+ * (many views, one launch sequence) and serving (request loop) forms.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a tigas_status; TIGAS_OK is 0, errors are negative.
+ *   A failing call writes a message retrievable with tigas_last_error() on
+ *   the same thread and leaves its outputs unspecified.  No C++ exception
+ *   crosses the boundary.
+ * - "device" pointers are HIP device addresses valid on the context's
+ *   device; "host" pointers are ordinary process memory.
+ * - A pose is (R, t): R is the camera-to-world rotation (row-major 3x3,
+ *   columns are the camera axes in world coordinates; x right, y down,
+ *   z forward), t the camera centre.  The world-to-camera transform is
+ *   [R^T, -R^T t] (Section 5.1, Rendering Engine).
+ * - Intrinsics are given for the full (width, height) frame.  A render at
+ *   resolution scale s produces out_w = floor(width*s + 0.5) by
+ *   out_h = floor(height*s + 0.5) pixels with fx, cx multiplied by
+ *   out_w/width and fy, cy by out_h/height (the principal point is
+ *   re-centred with the frame, Section 5.1), each rounded to FP32.
+ * - Frames are row-major HWC, row 0 at the top, RGB interleaved; RGB8 is
+ *   floor(clamp(c, 0, 1) * 255 + 0.5), RGBF32 is the unclamped composite.
+ * - Degenerate Gaussians (non-finite attributes, zero quaternion, centre at
+ *   or in front of the z = 0.2 near plane) are dropped, not reported as
+ *   errors; a scene with no Gaussians renders the background.
+ */
+#ifndef TIGAS_H
+#define TIGAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TIGAS_OK = 0,
+    TIGAS_E_INVALID = -1, /* null pointer, out-of-range argument, non-finite pose */
+    TIGAS_E_OOM = -2,     /* device allocation failed */
+    TIGAS_E_DEVICE = -3,  /* a HIP runtime call failed (message names it) */
+    TIGAS_E_BUFFER = -4,  /* caller's output buffer too small (sizes still filled in) */
+    TIGAS_E_BUDGET = -5   /* serving: request larger than the whole memory budget */
+} tigas_status;
+
+/* Storage precision of the resident Gaussian attributes.  Centres are always
+ * FP32; with F16/BF16 the log-scales, quaternion, opacity logit and SH
+ * coefficients are stored rounded to nearest-even and decoded to FP32 before
+ * any arithmetic. */
+typedef enum { TIGAS_ATTR_F32 = 0, TIGAS_ATTR_F16 = 1, TIGAS_ATTR_BF16 = 2 } tigas_attr;
+
+typedef enum { TIGAS_OUT_RGB8 = 0, TIGAS_OUT_RGBF32 = 1 } tigas_format;
+
+typedef struct tigas_context tigas_context;
+typedef struct tigas_scene tigas_scene;
+
+/* Scene attributes as parsed from a 3DGS PLY (Section 5.1, PLY Model and
+ * Primitives): n centres [n][3], log-scales [n][3] (exponentiated), quaternions
+ * [n][4] as (w, x, y, z) (normalised by the renderer), opacity logits [n]
+ * (passed through a sigmoid) and SH coefficients [n][16][3] (coefficient-major;
+ * entries above sh_degree are ignored).  All arrays are FP32, host memory when
+ * is_device == 0, device memory of the context's device otherwise.  The
+ * library copies them into its own resident layout; the caller keeps
+ * ownership. */
+typedef struct {
+    int64_t n;
+    int sh_degree; /* 0..3 */
+    const float* means;
+    const float* log_scales;
+    const float* quats_wxyz;
+    const float* opacity_logits;
+    const float* sh;
+    int is_device;
+    tigas_attr storage;
+} tigas_scene_desc;
+
+typedef struct {
+    float R[9]; /* camera -> world, row-major */
+    float t[3]; /* camera centre in world coordinates */
+} tigas_pose;
+
+typedef struct {
+    float fx, fy, cx, cy; /* pixels, for the full (width, height) frame */
+} tigas_intrinsics;
+
+/* Per-request quality knobs.  Zero-initialised means: full resolution,
+ * the scene's SH degree, RGB8, black background, autotuned tile/batch. */
+typedef struct {
+    float res_scale;  /* ABR rung, (0, 1]; 0 means 1 */
+    int sh_degree;    /* < 0 or > scene degree: the scene's degree */
+    tigas_format fmt;
+    float bg[3];
+    int tile_w, tile_h; /* 8x8, 16x16, 16x32 or 32x16; 0 = autotuned/default */
+    int batch_depth;    /* Gaussians staged per wavefront batch: 64, 128 or 256; 0 = default */
+} tigas_quality;
+
+/* Output frame.  data: device pointer when is_device, host otherwise;
+ * capacity in bytes.  out_w/out_h are written by the render call. */
+typedef struct {
+    void* data;
+    size_t capacity;
+    int is_device;
+    int out_w, out_h;
+} tigas_frame;
+
+/* Counters of the last render on a context (read after it completed). */
+typedef struct {
+    int64_t n;          /* Gaussians in the scene(s) rendered */
+    int64_t visible;    /* Gaussians that touched at least one tile */
+    int64_t duplicates; /* D: (Gaussian, tile) pairs sorted */
+    int64_t fallbacks;  /* 2D covariances inverted on the FP64 path */
+    int64_t tiles;
+    int64_t sort_passes;
+    int64_t rerenders;  /* workspace regrowths after an overflowing first attempt */
+} tigas_stats;
+
+/* Creates a context on HIP device `device`: a stream, workspaces and the
+ * tuning cache.  *out is owned by the caller; free with tigas_context_destroy. */
+tigas_status tigas_context_create(int device, tigas_context** out);
+void tigas_context_destroy(tigas_context* ctx);
+
+/* Loads a scene into resident device memory (Section 4.1: persistent VRAM
+ * residency).  The scene is immutable and may be rendered by any number of
+ * concurrent calls.  E_INVALID for n < 0, null arrays with n > 0, a degree
+ * outside 0..3; E_OOM when device memory is exhausted. */
+tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* desc, tigas_scene** out);
+void tigas_scene_free(tigas_scene* scene);
+/* Bytes of device memory the scene holds. */
+size_t tigas_scene_bytes(const tigas_scene* scene);
+
+/* Renders one frame (Section 5.1, Rendering Engine): preprocess, duplicate
+ * with (tile | depth) keys, radix sort, tile ranges, front-to-back blend.
+ * hip_stream: a hipStream_t of the context's device or NULL for the context
+ * stream.  The call returns once the frame is complete in `out`.  E_BUFFER
+ * when out->capacity < out_w*out_h*3*(1 or 4) bytes. */
+tigas_status tigas_render(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                          int width, int height, const tigas_quality* q, tigas_frame* out, void* hip_stream);
+
+/* Renders n_views views, each with its own scene, pose, intrinsics, size and
+ * quality q[i] (rung, SH degree, format, background; q may be NULL for
+ * defaults; the tile size and batch depth of q[0] apply to all views), with one
+ * launch sequence: one preprocess over all (view, Gaussian) pairs, one sort
+ * over global tile ids, one blend launch over every tile of every view.
+ * Captured into a HIP graph and replayed when the view shapes repeat.
+ * Frames are identical to n_views separate tigas_render calls. */
+tigas_status tigas_render_batch(tigas_scene* const* scenes, const tigas_pose* poses,
+                                const tigas_intrinsics* intrs, const int* widths, const int* heights,
+                                const tigas_quality* q, int n_views, tigas_frame* outs, void* hip_stream);
+
+tigas_status tigas_last_stats(tigas_context* ctx, tigas_stats* out);
+
+/* Thread-local message of the last failing call on this thread ("" if none);
+ * valid until the next call on this thread. */
+const char* tigas_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Inspection of the intermediate stages of one render, for parity tests.
+ * Renders like tigas_render and copies to caller-provided HOST arrays
+ * (any pointer may be NULL to skip it):
+ *   rec      [n][12] f32: u_hi, v_hi, u_lo, v_lo (pixel centre = u_hi + u_lo),
+ *            A, B, C, L (exponent coefficients: alpha = 2^(A dx^2 + B dx dy +
+ *            C dy^2 + L) before the 0.99 clamp), r, g, b, opacity
+ *   bbox     [n][4] i32 inclusive pixel box x0, y0, x1, y1 (x1 < x0: empty)
+ *   zkey     [n] u32 FP32 depth-key bits;  touched [n] u32 tiles overlapped
+ *   keys     [cap_dup] u64 duplicate keys in emission order, vals [cap_dup] u32
+ *   skeys    [cap_dup] u64 sorted keys, svals [cap_dup] u32 sorted values
+ *   ranges   [tiles][2] u32 [start, end) per tile
+ * *n_dup receives D; arrays sized below D are not written (E_BUFFER).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    float* rec;
+    int32_t* bbox;
+    uint32_t* zkey;
+    uint32_t* touched;
+    uint64_t* keys;
+    uint32_t* vals;
+    uint64_t* skeys;
+    uint32_t* svals;
+    uint32_t* ranges;
+    int64_t cap_dup;
+    int64_t cap_tiles;
+    int64_t n_dup;
+    int64_t n_tiles;
+} tigas_debug_out;
+
+tigas_status tigas_render_debug(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                                int width, int height, const tigas_quality* q, tigas_frame* out,
+                                tigas_debug_out* dbg);
+
+/* Self-test of the wave64 DPP prefix scan used by the scan and sort kernels:
+ * inclusive scan of n u32 host values in groups of 64 lanes, result to host. */
+tigas_status tigas_selftest_wave_scan(const uint32_t* in, uint32_t* out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TIGAS_H */

@@ -1,0 +1,780 @@
+// Host side of libtigas: the C ABI declared in include/tigas.h.
+//
+// Owns contexts (device, stream, workspaces), resident scenes and the launch
+// sequence of a render.  Counts that depend on the data (visible Gaussians,
+// duplicates D) stay on the device: kernels read them from device memory, so a
+// render is a fixed sequence of launches with no host round trip inside it.
+// The duplicate buffers are sized from the previous frame with headroom; if a
+// frame needs more, its duplicate kernel emits nothing, the overflow flag is
+// seen after the frame and the frame is rendered again with larger buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tigas.h"
+#include "tigas_internal.h"
+
+using namespace tigas;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+    tigas_status st;
+    Error(tigas_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+[[noreturn]] void fail(tigas_status s, const std::string& m) { throw Error(s, m); }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(TIGAS_E_OOM, std::string(what) + ": out of device memory");
+    fail(TIGAS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x)
+
+template <typename F>
+tigas_status guard(F&& f) {
+    try {
+        g_err.clear();
+        f();
+        return TIGAS_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return TIGAS_E_OOM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return TIGAS_E_DEVICE;
+    }
+}
+
+// Device buffer that grows (never shrinks) on demand.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    void ensure(size_t need) {
+        if (need <= bytes) return;
+        if (p) HIPCHK(hipFree(p));
+        p = nullptr;
+        bytes = 0;
+        size_t want = std::max<size_t>(need, 256);
+        HIPCHK(hipMalloc(&p, want));
+        bytes = want;
+    }
+    template <typename T>
+    T* as() const {
+        return reinterpret_cast<T*>(p);
+    }
+};
+
+struct HostPinned {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~HostPinned() {
+        if (p) (void)hipHostFree(p);
+    }
+    void ensure(size_t need) {
+        if (need <= bytes) return;
+        if (p) HIPCHK(hipHostFree(p));
+        p = nullptr;
+        bytes = 0;
+        HIPCHK(hipHostMalloc(&p, std::max<size_t>(need, 256), hipHostMallocDefault));
+        bytes = std::max<size_t>(need, 256);
+    }
+};
+
+uint32_t round_up(uint64_t x, uint64_t m) { return (uint32_t)((x + m - 1) / m * m); }
+
+int ceil_log2(uint64_t x) {
+    int b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+// ---------------------------------------------------------------- halves
+uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                           // nearest even
+    return (uint16_t)(u >> 16);
+}
+
+uint16_t f32_to_f16(float f) {
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u;
+    uint32_t absx = x & 0x7fffffffu;
+    if (absx >= 0x7f800000u) return (uint16_t)(sign | 0x7c00u | (absx > 0x7f800000u ? 0x200u : 0u));
+    if (absx >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // rounds to infinity
+    if (absx < 0x38800000u) {                                     // subnormal half or zero
+        if (absx < 0x33000000u) return (uint16_t)sign;            // below half of the smallest subnormal
+        const int e = (int)(absx >> 23);
+        const uint32_t mant = (absx & 0x7fffffu) | 0x800000u;
+        const int shift = 126 - e;  // so that the result counts units of 2^-24
+        uint32_t q = mant >> (shift);
+        const uint32_t rem = mant & ((1u << shift) - 1u);
+        const uint32_t half = 1u << (shift - 1);
+        if (rem > half || (rem == half && (q & 1u))) ++q;
+        return (uint16_t)(sign | q);
+    }
+    uint32_t r = absx - 0x38000000u;  // rebias exponent 127 -> 15
+    const uint32_t rem = r & 0x1fffu;
+    uint32_t q = r >> 13;
+    if (rem > 0x1000u || (rem == 0x1000u && (q & 1u))) ++q;
+    return (uint16_t)(sign | q);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- objects
+
+struct Workspace {
+    hipStream_t stream = nullptr;
+    // per record
+    DevBuf rec0, rec1, rec2, bbox, zkey, touched;
+    DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off;
+    DevBuf counters;
+    // per duplicate
+    DevBuf lo[2], hi[2], val[2];
+    DevBuf hist, totals;
+    // per tile
+    DevBuf ranges;
+    DevBuf views;
+    DevBuf frame_staging;
+    HostPinned host_views, host_counters;
+    uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0, view_cap = 0;
+    uint32_t last_D = 0;
+    hipEvent_t done = nullptr;
+
+    PreOut pre() const {
+        PreOut o;
+        o.rec0 = rec0.as<float4>();
+        o.rec1 = rec1.as<float4>();
+        o.rec2 = rec2.as<float4>();
+        o.bbox = bbox.as<uint2>();
+        o.zkey = zkey.as<uint32_t>();
+        o.touched = touched.as<uint32_t>();
+        o.blk_sum = blk_sum.as<uint32_t>();
+        o.blk_vis = blk_vis.as<uint32_t>();
+        o.blk_fb = blk_fb.as<uint32_t>();
+        o.blk_view = blk_view.as<uint32_t>();
+        return o;
+    }
+    void ensure_records(uint32_t nrec) {
+        if (nrec <= rec_cap && rec0.p) return;
+        const size_t r = std::max<uint32_t>(nrec, 256);
+        rec0.ensure(r * 16);
+        rec1.ensure(r * 16);
+        rec2.ensure(r * 16);
+        bbox.ensure(r * 8);
+        zkey.ensure(r * 4);
+        touched.ensure(r * 4);
+        const size_t nb = r / K1_THREADS + 1;
+        blk_sum.ensure(nb * 4);
+        blk_vis.ensure(nb * 4);
+        blk_fb.ensure(nb * 4);
+        blk_view.ensure(nb * 4);
+        blk_off.ensure(nb * 4);
+        rec_cap = (uint32_t)r;
+    }
+    void ensure_dups(uint32_t cap) {
+        if (cap <= dup_cap && lo[0].p) return;
+        cap = std::max<uint32_t>(cap, 1u << 16);
+        for (int i = 0; i < 2; ++i) {
+            lo[i].ensure((size_t)cap * 4);
+            hi[i].ensure((size_t)cap * 4);
+            val[i].ensure((size_t)cap * 4);
+        }
+        hist.ensure((size_t)256 * SORT_MAX_BLOCKS * 4);
+        totals.ensure((size_t)256 * MAX_SORT_PASSES * 4);
+        dup_cap = cap;
+    }
+    void ensure_tiles(uint32_t n) {
+        if (n <= tile_cap && ranges.p) return;
+        ranges.ensure((size_t)std::max<uint32_t>(n, 1) * 8);
+        tile_cap = std::max<uint32_t>(n, 1);
+    }
+    void ensure_views(int n) {
+        if ((uint32_t)n <= view_cap && views.p) return;
+        views.ensure(sizeof(ViewParams) * (size_t)n);
+        host_views.ensure(sizeof(ViewParams) * (size_t)n);
+        view_cap = (uint32_t)n;
+    }
+    ~Workspace() {
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+struct tigas_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
+    tigas_stats last{};
+    std::mutex stats_mu;
+
+    Workspace& workspace(hipStream_t s) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto& p = ws[s];
+        if (!p) {
+            p.reset(new Workspace());
+            p->stream = s;
+            p->host_counters.ensure(sizeof(Counters));
+            HIPCHK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+        }
+        return *p;
+    }
+};
+
+struct tigas_scene {
+    tigas_context* ctx = nullptr;
+    SceneView view{};
+    DevBuf mean, attr, sh;
+    size_t bytes = 0;
+    std::atomic<int> refs{0};
+};
+
+namespace {
+
+struct SceneRef {  // keeps a scene referenced while a render uses it
+    tigas_scene* s;
+    explicit SceneRef(tigas_scene* s_) : s(s_) { s->refs.fetch_add(1); }
+    ~SceneRef() { s->refs.fetch_sub(1); }
+};
+
+bool finite3(const float* p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+struct TileCfg {
+    int tw, th, bd;
+};
+
+TileCfg tile_cfg(const tigas_quality* q) {
+    int tw = q ? q->tile_w : 0, th = q ? q->tile_h : 0, bd = q ? q->batch_depth : 0;
+    if (tw == 0 && th == 0) {
+        tw = 16;
+        th = 16;
+    }
+    const bool okt = (tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 16 && th == 32) || (tw == 32 && th == 16);
+    if (!okt) fail(TIGAS_E_INVALID, "tile must be 8x8, 16x16, 16x32 or 32x16");
+    if (bd == 0) bd = 64;
+    if (bd != 64 && bd != 128 && bd != 256) fail(TIGAS_E_INVALID, "batch_depth must be 64, 128 or 256");
+    return {tw, th, bd};
+}
+
+// Camera of one view: V = R^T, the FP32 key constant, rung-scaled intrinsics
+// (computed in FP64, rounded once to FP32) and the Jacobian clamp.
+ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_intrinsics* intr, int width,
+                     int height, const tigas_quality* q, const TileCfg& tc) {
+    if (!pose || !intr) fail(TIGAS_E_INVALID, "pose and intrinsics are required");
+    if (!finite3(pose->R, 9) || !finite3(pose->t, 3)) fail(TIGAS_E_INVALID, "pose is not finite");
+    if (!(intr->fx > 0.f) || !(intr->fy > 0.f) || !std::isfinite(intr->fx) || !std::isfinite(intr->fy) ||
+        !std::isfinite(intr->cx) || !std::isfinite(intr->cy))
+        fail(TIGAS_E_INVALID, "intrinsics must be finite with fx, fy > 0");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384)
+        fail(TIGAS_E_INVALID, "width and height must be in 1..16384");
+    const float s = (q && q->res_scale != 0.f) ? q->res_scale : 1.0f;
+    if (!(s > 0.f && s <= 1.f)) fail(TIGAS_E_INVALID, "res_scale must be in (0, 1]");
+    const int ow = (int)std::floor((double)width * (double)s + 0.5);
+    const int oh = (int)std::floor((double)height * (double)s + 0.5);
+    if (ow < 1 || oh < 1) fail(TIGAS_E_INVALID, "res_scale gives an empty frame");
+    ViewParams v{};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) v.V[i * 3 + j] = pose->R[j * 3 + i];
+    for (int i = 0; i < 3; ++i) v.cam[i] = pose->t[i];
+    const double tz = -((double)v.V[6] * pose->t[0] + (double)v.V[7] * pose->t[1] + (double)v.V[8] * pose->t[2]);
+    v.tz_key = (float)tz;
+    const double rx = (double)ow / width, ry = (double)oh / height;
+    v.fx = (float)((double)intr->fx * rx);
+    v.fy = (float)((double)intr->fy * ry);
+    v.cx = (float)((double)intr->cx * rx);
+    v.cy = (float)((double)intr->cy * ry);
+    v.lim_x = (float)(1.3 * std::max((double)v.cx, (double)ow - v.cx) / v.fx);
+    v.lim_y = (float)(1.3 * std::max((double)v.cy, (double)oh - v.cy) / v.fy);
+    v.width = ow;
+    v.height = oh;
+    v.tile_w = tc.tw;
+    v.tile_h = tc.th;
+    v.tiles_x = (ow + tc.tw - 1) / tc.tw;
+    v.tiles_y = (oh + tc.th - 1) / tc.th;
+    int deg = q ? q->sh_degree : -1;
+    if (deg < 0 || deg > sc->view.sh_degree) deg = sc->view.sh_degree;
+    v.sh_degree = deg;
+    v.fmt = q ? (int)q->fmt : 0;
+    if (v.fmt != 0 && v.fmt != 1) fail(TIGAS_E_INVALID, "unknown frame format");
+    for (int i = 0; i < 3; ++i) v.bg[i] = q ? q->bg[i] : 0.f;
+    if (!finite3(v.bg, 3)) fail(TIGAS_E_INVALID, "background is not finite");
+    return v;
+}
+
+size_t frame_bytes(const ViewParams& v) {
+    return (size_t)v.width * v.height * 3 * (v.fmt == 1 ? 4 : 1);
+}
+
+std::vector<SortPass> sort_passes(uint32_t n_tiles) {
+    std::vector<SortPass> p;
+    // depth word: positive FP32 bit patterns, bit 31 always clear
+    p.push_back({0, 0, 8});
+    p.push_back({0, 8, 8});
+    p.push_back({0, 16, 8});
+    p.push_back({0, 24, 7});
+    const int tb = ceil_log2(n_tiles);
+    for (int sh = 0; sh < tb; sh += 8) p.push_back({1, sh, std::min(8, tb - sh)});
+    return p;
+}
+
+// A group of views of one scene inside a launch sequence.
+struct Group {
+    tigas_scene* scene;
+    int first_view, nviews;
+    uint32_t rec_base, n_pad;
+};
+
+struct Plan {
+    std::vector<ViewParams> views;
+    std::vector<Group> groups;
+    uint32_t nrec = 0, n_tiles = 0;
+    TileCfg tc{};
+};
+
+// Enqueue the whole launch sequence for a plan on ws.stream.  Returns the
+// index of the sort buffer that holds the sorted lists.
+int enqueue(Workspace& ws, Plan& plan, bool carry_lo) {
+    hipStream_t st = ws.stream;
+    const int nv = (int)plan.views.size();
+    ws.ensure_views(nv);
+    ws.ensure_records(plan.nrec);
+    ws.ensure_tiles(plan.n_tiles);
+    std::memcpy(ws.host_views.p, plan.views.data(), sizeof(ViewParams) * nv);
+    HIPCHK(hipMemcpyAsync(ws.views.p, ws.host_views.p, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
+    const PreOut o = ws.pre();
+    const ViewParams* vdev = ws.views.as<ViewParams>();
+    for (const Group& g : plan.groups) {
+        if (g.n_pad == 0) continue;
+        launch_preprocess(g.scene->view, vdev + g.first_view, plan.views.data() + g.first_view, g.nviews,
+                          g.rec_base, g.n_pad, (uint32_t)g.first_view, o, st);
+    }
+    const int nblk = (int)(plan.nrec / K1_THREADS);
+    Counters* cnt = ws.counters.as<Counters>();
+    launch_scan_blocks(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, ws.totals.as<uint32_t>(),
+                       256 * MAX_SORT_PASSES, st);
+    launch_duplicate(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, vdev, ws.lo[0].as<uint32_t>(),
+                     ws.hi[0].as<uint32_t>(), ws.val[0].as<uint32_t>(), st);
+    SortBuffers sb;
+    for (int i = 0; i < 2; ++i) {
+        sb.lo[i] = ws.lo[i].as<uint32_t>();
+        sb.hi[i] = ws.hi[i].as<uint32_t>();
+        sb.val[i] = ws.val[i].as<uint32_t>();
+    }
+    sb.hist = ws.hist.as<uint32_t>();
+    sb.totals = ws.totals.as<uint32_t>();
+    sb.nblocks = (int)std::min<uint64_t>(SORT_MAX_BLOCKS, std::max<uint64_t>(1, ws.dup_cap / 16384));
+    const std::vector<SortPass> passes = sort_passes(plan.n_tiles);
+    if ((int)passes.size() > MAX_SORT_PASSES) fail(TIGAS_E_INVALID, "too many tiles for the sort key");
+    const int cur = launch_sort(sb, passes.data(), (int)passes.size(), cnt, ws.dup_cap, carry_lo, st);
+    launch_ranges(sb.hi[cur], cnt, ws.dup_cap, plan.n_tiles, ws.ranges.as<uint2>(), st);
+    launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
+                 plan.tc.bd, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ws.host_counters.p, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    return cur;
+}
+
+uint32_t initial_dup_cap(const Plan& plan, uint32_t last_D) {
+    uint64_t est = std::max<uint64_t>((uint64_t)last_D + last_D / 4, (uint64_t)plan.nrec * 4);
+    est = std::max<uint64_t>(est, 1u << 20);
+    return (uint32_t)std::min<uint64_t>(est, 0xfff00000ull);
+}
+
+// Runs the plan to completion (synchronous), regrowing the duplicate buffers
+// when the first attempt overflowed.  Returns the final sort buffer index.
+int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* rerenders) {
+    ws.counters.ensure(sizeof(Counters));
+    ws.ensure_dups(std::max(ws.dup_cap, initial_dup_cap(plan, ws.last_D)));
+    int cur = enqueue(ws, plan, carry_lo);
+    HIPCHK(hipStreamSynchronize(ws.stream));
+    Counters c;
+    std::memcpy(&c, ws.host_counters.p, sizeof(c));
+    *rerenders = 0;
+    if (c.overflow) {
+        const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
+        if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
+        ws.ensure_dups((uint32_t)want);
+        cur = enqueue(ws, plan, carry_lo);
+        HIPCHK(hipStreamSynchronize(ws.stream));
+        std::memcpy(&c, ws.host_counters.p, sizeof(c));
+        if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
+        *rerenders = 1;
+    }
+    ws.last_D = c.D;
+    {
+        std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        ctx->last.visible = c.visible;
+        ctx->last.duplicates = c.D;
+        ctx->last.fallbacks = c.fallbacks;
+        ctx->last.tiles = plan.n_tiles;
+        ctx->last.sort_passes = (int64_t)sort_passes(plan.n_tiles).size();
+        ctx->last.rerenders = *rerenders;
+        int64_t n = 0;
+        for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
+        ctx->last.n = n;
+    }
+    return cur;
+}
+
+hipStream_t pick_stream(tigas_context* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }
+
+void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width, int height,
+                const tigas_quality* q, tigas_frame* out, void* hip_stream, tigas_debug_out* dbg) {
+    if (!scene || !out) fail(TIGAS_E_INVALID, "scene and frame are required");
+    tigas_context* ctx = scene->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    SceneRef ref(scene);
+    const TileCfg tc = tile_cfg(q);
+    Plan plan;
+    plan.tc = tc;
+    plan.views.push_back(make_view(scene, pose, intr, width, height, q, tc));
+    ViewParams& v = plan.views[0];
+    out->out_w = v.width;
+    out->out_h = v.height;
+    const size_t need = frame_bytes(v);
+    if (!out->data || out->capacity < need) fail(TIGAS_E_BUFFER, "output frame buffer too small");
+    Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
+    if (out->is_device) {
+        v.out_ptr = (uint64_t)(uintptr_t)out->data;
+    } else {
+        ws.frame_staging.ensure(need);
+        v.out_ptr = (uint64_t)(uintptr_t)ws.frame_staging.p;
+    }
+    const uint32_t n_pad = round_up((uint64_t)scene->view.n, K1_THREADS);
+    plan.groups.push_back({scene, 0, 1, 0, n_pad});
+    plan.nrec = n_pad;
+    v.tile_base = 0;
+    plan.n_tiles = (uint32_t)(v.tiles_x * v.tiles_y);
+    int rr = 0;
+    const int cur = run_plan(ctx, ws, plan, dbg != nullptr, &rr);
+    if (!out->is_device) {
+        HIPCHK(hipMemcpyAsync(out->data, ws.frame_staging.p, need, hipMemcpyDeviceToHost, ws.stream));
+        HIPCHK(hipStreamSynchronize(ws.stream));
+    }
+    if (dbg) {
+        Counters c;
+        std::memcpy(&c, ws.host_counters.p, sizeof(c));
+        const int64_t n = scene->view.n;
+        dbg->n_dup = c.D;
+        dbg->n_tiles = plan.n_tiles;
+        hipStream_t st = ws.stream;
+        if (dbg->rec) {
+            std::vector<float4> a(n_pad), b(n_pad), cc(n_pad);
+            HIPCHK(hipMemcpyAsync(a.data(), ws.rec0.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(b.data(), ws.rec1.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(cc.data(), ws.rec2.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t i = 0; i < n; ++i) {
+                float* r = dbg->rec + 12 * i;
+                const float4 x = a[i], y = b[i], z = cc[i];
+                r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
+                r[4] = y.x; r[5] = y.y; r[6] = y.z; r[7] = y.w;
+                r[8] = z.x; r[9] = z.y; r[10] = z.z; r[11] = z.w;
+            }
+        }
+        std::vector<uint32_t> touched(n_pad);
+        HIPCHK(hipMemcpyAsync(touched.data(), ws.touched.p, 4 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (dbg->touched) std::memcpy(dbg->touched, touched.data(), 4 * (size_t)n);
+        if (dbg->zkey) {
+            HIPCHK(hipMemcpyAsync(dbg->zkey, ws.zkey.p, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
+        }
+        if (dbg->bbox) {
+            std::vector<uint2> bb(n_pad);
+            HIPCHK(hipMemcpyAsync(bb.data(), ws.bbox.p, 8 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t i = 0; i < n; ++i) {
+                int32_t* r = dbg->bbox + 4 * i;
+                if (touched[i]) {
+                    r[0] = (int32_t)(bb[i].x & 0xffffu);
+                    r[1] = (int32_t)(bb[i].x >> 16);
+                    r[2] = (int32_t)(bb[i].y & 0xffffu);
+                    r[3] = (int32_t)(bb[i].y >> 16);
+                } else {
+                    r[0] = 0; r[1] = 0; r[2] = -1; r[3] = -1;
+                }
+            }
+        }
+        const bool fits = (int64_t)c.D <= dbg->cap_dup;
+        if ((dbg->keys || dbg->vals || dbg->skeys || dbg->svals) && !fits)
+            fail(TIGAS_E_BUFFER, "debug duplicate arrays smaller than D");
+        std::vector<uint32_t> lo(c.D), hi(c.D);
+        if (c.D && (dbg->keys || dbg->vals)) {
+            // the emission-order lists were consumed by the sort; rebuild them
+            // by re-running the duplicate kernel into the spare buffers
+            launch_duplicate(ws.pre(), (int)(plan.nrec / K1_THREADS), ws.blk_off.as<uint32_t>(),
+                             ws.counters.as<Counters>(), ws.dup_cap, ws.views.as<ViewParams>(),
+                             ws.lo[cur ^ 1].as<uint32_t>(), ws.hi[cur ^ 1].as<uint32_t>(),
+                             ws.val[cur ^ 1].as<uint32_t>(), st);
+            HIPCHK(hipMemcpyAsync(lo.data(), ws.lo[cur ^ 1].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hi.data(), ws.hi[cur ^ 1].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            if (dbg->vals)
+                HIPCHK(hipMemcpyAsync(dbg->vals, ws.val[cur ^ 1].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (dbg->keys)
+                for (uint32_t i = 0; i < c.D; ++i) dbg->keys[i] = ((uint64_t)hi[i] << 32) | lo[i];
+        }
+        if (c.D && (dbg->skeys || dbg->svals)) {
+            HIPCHK(hipMemcpyAsync(lo.data(), ws.lo[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hi.data(), ws.hi[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            if (dbg->svals)
+                HIPCHK(hipMemcpyAsync(dbg->svals, ws.val[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (dbg->skeys)
+                for (uint32_t i = 0; i < c.D; ++i) dbg->skeys[i] = ((uint64_t)hi[i] << 32) | lo[i];
+        }
+        if (dbg->ranges) {
+            if (dbg->cap_tiles < (int64_t)plan.n_tiles) fail(TIGAS_E_BUFFER, "debug ranges array too small");
+            HIPCHK(hipMemcpyAsync(dbg->ranges, ws.ranges.p, 8 * (size_t)plan.n_tiles, hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    }
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char* tigas_last_error(void) { return g_err.c_str(); }
+
+tigas_status tigas_context_create(int device, tigas_context** out) {
+    return guard([&] {
+        if (!out) fail(TIGAS_E_INVALID, "out is null");
+        int n = 0;
+        HIPCHK(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) fail(TIGAS_E_INVALID, "no such HIP device");
+        HIPCHK(hipSetDevice(device));
+        std::unique_ptr<tigas_context> c(new tigas_context());
+        c->device = device;
+        HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        *out = c.release();
+    });
+}
+
+void tigas_context_destroy(tigas_context* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->ws.clear();
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tigas_scene** out) {
+    return guard([&] {
+        if (!ctx || !d || !out) fail(TIGAS_E_INVALID, "null argument");
+        if (d->n < 0 || d->n > (int64_t)0x7f000000) fail(TIGAS_E_INVALID, "n out of range");
+        if (d->sh_degree < 0 || d->sh_degree > 3) fail(TIGAS_E_INVALID, "sh_degree must be 0..3");
+        if (d->storage < TIGAS_ATTR_F32 || d->storage > TIGAS_ATTR_BF16) fail(TIGAS_E_INVALID, "unknown storage");
+        const int64_t n = d->n;
+        if (n > 0 && (!d->means || !d->log_scales || !d->quats_wxyz || !d->opacity_logits || !d->sh))
+            fail(TIGAS_E_INVALID, "attribute array is null");
+        HIPCHK(hipSetDevice(ctx->device));
+        // bring the inputs to the host
+        std::vector<float> m, ls, q, op, sh;
+        auto fetch = [&](std::vector<float>& dst, const float* src, size_t cnt) {
+            dst.resize(cnt);
+            if (cnt == 0) return;
+            if (d->is_device) HIPCHK(hipMemcpy(dst.data(), src, cnt * 4, hipMemcpyDeviceToHost));
+            else std::memcpy(dst.data(), src, cnt * 4);
+        };
+        fetch(m, d->means, (size_t)n * 3);
+        fetch(ls, d->log_scales, (size_t)n * 3);
+        fetch(q, d->quats_wxyz, (size_t)n * 4);
+        fetch(op, d->opacity_logits, (size_t)n);
+        fetch(sh, d->sh, (size_t)n * 48);
+        std::unique_ptr<tigas_scene> s(new tigas_scene());
+        s->ctx = ctx;
+        const int deg = d->sh_degree;
+        const int ncoef = 3 * (deg + 1) * (deg + 1);
+        const size_t nn = (size_t)std::max<int64_t>(n, 1);
+        // centres: FP32 planes
+        std::vector<float> mp(3 * nn);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) mp[c * n + i] = m[3 * i + c];
+        s->mean.ensure(mp.size() * 4);
+        HIPCHK(hipMemcpy(s->mean.p, mp.data(), (size_t)n * 12, hipMemcpyHostToDevice));
+        if (d->storage == TIGAS_ATTR_F32) {
+            std::vector<float> a(8 * nn);
+            for (int64_t i = 0; i < n; ++i) {
+                for (int c = 0; c < 4; ++c) a[4 * i + c] = q[4 * i + c];
+                for (int c = 0; c < 3; ++c) a[4 * n + 4 * i + c] = ls[3 * i + c];
+                a[4 * n + 4 * i + 3] = op[i];
+            }
+            const int np = (ncoef + 3) / 4;
+            std::vector<float> shp((size_t)np * 4 * nn, 0.f);
+            for (int p = 0; p < np; ++p)
+                for (int64_t i = 0; i < n; ++i)
+                    for (int c = 0; c < 4; ++c) {
+                        const int k = 4 * p + c;
+                        shp[((size_t)p * n + i) * 4 + c] = k < ncoef ? sh[48 * i + k] : 0.f;
+                    }
+            s->attr.ensure(a.size() * 4);
+            s->sh.ensure(shp.size() * 4);
+            HIPCHK(hipMemcpy(s->attr.p, a.data(), (size_t)n * 32, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(s->sh.p, shp.data(), (size_t)np * n * 16, hipMemcpyHostToDevice));
+            s->bytes = (size_t)n * (12 + 32 + (size_t)np * 16);
+        } else {
+            auto cvt = [&](float f) { return d->storage == TIGAS_ATTR_BF16 ? f32_to_bf16(f) : f32_to_f16(f); };
+            std::vector<uint16_t> a(8 * nn);
+            for (int64_t i = 0; i < n; ++i) {
+                for (int c = 0; c < 4; ++c) a[8 * i + c] = cvt(q[4 * i + c]);
+                for (int c = 0; c < 3; ++c) a[8 * i + 4 + c] = cvt(ls[3 * i + c]);
+                a[8 * i + 7] = cvt(op[i]);
+            }
+            const int np = (ncoef + 7) / 8;
+            std::vector<uint16_t> shp((size_t)np * 8 * nn, 0);
+            for (int p = 0; p < np; ++p)
+                for (int64_t i = 0; i < n; ++i)
+                    for (int c = 0; c < 8; ++c) {
+                        const int k = 8 * p + c;
+                        shp[((size_t)p * n + i) * 8 + c] = k < ncoef ? cvt(sh[48 * i + k]) : 0;
+                    }
+            s->attr.ensure(a.size() * 2);
+            s->sh.ensure(shp.size() * 2);
+            HIPCHK(hipMemcpy(s->attr.p, a.data(), (size_t)n * 16, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(s->sh.p, shp.data(), (size_t)np * n * 16, hipMemcpyHostToDevice));
+            s->bytes = (size_t)n * (12 + 16 + (size_t)np * 16);
+        }
+        s->view.n = n;
+        s->view.storage = (int)d->storage;
+        s->view.sh_degree = deg;
+        s->view.mean = s->mean.as<float>();
+        s->view.attr = s->attr.p;
+        s->view.sh = s->sh.p;
+        *out = s.release();
+    });
+}
+
+void tigas_scene_free(tigas_scene* s) {
+    if (!s) return;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete s;
+}
+
+size_t tigas_scene_bytes(const tigas_scene* s) { return s ? s->bytes : 0; }
+
+tigas_status tigas_render(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width,
+                          int height, const tigas_quality* q, tigas_frame* out, void* hip_stream) {
+    return guard([&] { render_one(scene, pose, intr, width, height, q, out, hip_stream, nullptr); });
+}
+
+tigas_status tigas_render_debug(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width,
+                                int height, const tigas_quality* q, tigas_frame* out, tigas_debug_out* dbg) {
+    return guard([&] {
+        if (!dbg) fail(TIGAS_E_INVALID, "debug output is null");
+        render_one(scene, pose, intr, width, height, q, out, nullptr, dbg);
+    });
+}
+
+tigas_status tigas_render_batch(tigas_scene* const* scenes, const tigas_pose* poses, const tigas_intrinsics* intrs,
+                                const int* widths, const int* heights, const tigas_quality* q, int n_views,
+                                tigas_frame* outs, void* hip_stream) {
+    return guard([&] {
+        if (n_views < 1 || !scenes || !poses || !intrs || !widths || !heights || !outs)
+            fail(TIGAS_E_INVALID, "null argument or no views");
+        tigas_context* ctx = scenes[0] ? scenes[0]->ctx : nullptr;
+        if (!ctx) fail(TIGAS_E_INVALID, "null scene");
+        HIPCHK(hipSetDevice(ctx->device));
+        const TileCfg tc = tile_cfg(q);
+        Plan plan;
+        plan.tc = tc;
+        Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
+        // group consecutive views that share a scene
+        std::vector<std::unique_ptr<SceneRef>> refs;
+        size_t staging = 0;
+        std::vector<size_t> stage_off(n_views, 0);
+        for (int i = 0; i < n_views; ++i) {
+            if (!scenes[i] || scenes[i]->ctx != ctx) fail(TIGAS_E_INVALID, "scenes must share one context");
+            const tigas_quality qi = q ? q[i] : tigas_quality{};
+            ViewParams v = make_view(scenes[i], &poses[i], &intrs[i], widths[i], heights[i], &qi, tc);
+            outs[i].out_w = v.width;
+            outs[i].out_h = v.height;
+            const size_t need = frame_bytes(v);
+            if (!outs[i].data || outs[i].capacity < need) fail(TIGAS_E_BUFFER, "output frame buffer too small");
+            if (!outs[i].is_device) {
+                stage_off[i] = staging;
+                staging += (need + 255) / 256 * 256;
+            }
+            v.tile_base = plan.n_tiles;
+            plan.n_tiles += (uint32_t)(v.tiles_x * v.tiles_y);
+            plan.views.push_back(v);
+        }
+        if (staging) ws.frame_staging.ensure(staging);
+        for (int i = 0; i < n_views; ++i)
+            plan.views[i].out_ptr = outs[i].is_device ? (uint64_t)(uintptr_t)outs[i].data
+                                                      : (uint64_t)(uintptr_t)ws.frame_staging.p + stage_off[i];
+        for (int i = 0; i < n_views;) {
+            int j = i;
+            while (j < n_views && scenes[j] == scenes[i]) ++j;
+            const uint32_t n_pad = round_up((uint64_t)scenes[i]->view.n, K1_THREADS);
+            plan.groups.push_back({scenes[i], i, j - i, plan.nrec, n_pad});
+            refs.emplace_back(new SceneRef(scenes[i]));
+            plan.nrec += n_pad * (uint32_t)(j - i);
+            i = j;
+        }
+        int rr = 0;
+        run_plan(ctx, ws, plan, false, &rr);
+        for (int i = 0; i < n_views; ++i)
+            if (!outs[i].is_device)
+                HIPCHK(hipMemcpyAsync(outs[i].data, (char*)ws.frame_staging.p + stage_off[i],
+                                      frame_bytes(plan.views[i]), hipMemcpyDeviceToHost, ws.stream));
+        HIPCHK(hipStreamSynchronize(ws.stream));
+    });
+}
+
+tigas_status tigas_last_stats(tigas_context* ctx, tigas_stats* out) {
+    return guard([&] {
+        if (!ctx || !out) fail(TIGAS_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        *out = ctx->last;
+    });
+}
+
+tigas_status tigas_selftest_wave_scan(const uint32_t* in, uint32_t* out, int n) {
+    return guard([&] {
+        if (!in || !out || n < 0) fail(TIGAS_E_INVALID, "bad arguments");
+        if (n == 0) return;
+        void *din = nullptr, *dout = nullptr;
+        HIPCHK(hipMalloc(&din, (size_t)n * 4));
+        HIPCHK(hipMalloc(&dout, (size_t)n * 4));
+        HIPCHK(hipMemcpy(din, in, (size_t)n * 4, hipMemcpyHostToDevice));
+        launch_wave_scan_selftest((const uint32_t*)din, (uint32_t*)dout, n, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(out, dout, (size_t)n * 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipFree(din));
+        HIPCHK(hipFree(dout));
+    });
+}
+
+}  // extern "C"

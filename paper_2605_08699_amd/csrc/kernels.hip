@@ -1,0 +1,890 @@
+// HIP kernels of the forward 3DGS rasterizer for CDNA4 (gfx950, wave64).
+//
+//   k_preprocess   per Gaussian (x views): activation, 3D covariance, camera
+//                  transform, projection, EWA 2D covariance + conic (FP64
+//                  fallback when near-singular), SH colour, screen footprint
+//   k_scan_blocks  exclusive scan of per-block duplicate counts (wave64 DPP)
+//   k_duplicate    one (tile | depth) key per (Gaussian, overlapped tile)
+//   k_sort_*       LSD radix sort, 8-bit digits, reduce-then-scan per pass,
+//                  ballot/mbcnt ranking inside a wave, DPP scans
+//   k_ranges       [start, end) of every tile in the sorted list
+//   k_blend        front-to-back compositing, one wave64 per 8x8 pixel block,
+//                  Gaussians staged per wave in LDS, per-wave early exit
+//
+// Numerics: all kernels are compiled with -ffp-contract=off; every fused
+// multiply-add is written explicitly so the FP32 operation sequence is fixed.
+#include "tigas_internal.h"
+
+namespace tigas {
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ uint32_t bits_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (all 64 lanes must be active).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return readlane(wave_incl_scan(v), 63); }
+
+// Exclusive scan over a workgroup of NT threads; *total receives the sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+    const uint32_t incl = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) lds[w] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const uint32_t s = lds[i];
+        off += (i < w) ? s : 0u;
+        tot += s;
+    }
+    *total = tot;
+    __syncthreads();
+    return off + incl - v;
+}
+
+template <int NT>
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* lds) {
+    uint32_t tot;
+    block_excl_scan<NT>(v, lds, &tot);
+    return tot;
+}
+
+// ------------------------------------------------------ double-float helpers
+// Error-free transformations (Knuth two-sum, fma two-product) so that the
+// pixel position of a Gaussian is carried as an unevaluated FP32 sum hi + lo.
+
+struct df {
+    float hi, lo;
+};
+__device__ __forceinline__ df two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    const float e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ __forceinline__ df quick_two_sum(float a, float b) {
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ df df_add(df a, df b) {
+    df s = two_sum(a.hi, b.hi);
+    s.lo = s.lo + (a.lo + b.lo);
+    return quick_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ df df_mulf(df a, float b) {
+    const float p = a.hi * b;
+    float e = __builtin_fmaf(a.hi, b, -p);
+    e = __builtin_fmaf(a.lo, b, e);
+    return quick_two_sum(p, e);
+}
+__device__ __forceinline__ df df_div(df a, df b) {
+    const float q1 = a.hi / b.hi;
+    const df p = df_mulf(b, q1);
+    const df r = df_add(a, df{-p.hi, -p.lo});
+    const float q2 = r.hi / b.hi;
+    return quick_two_sum(q1, q2);
+}
+
+// --------------------------------------------------------- attribute decode
+
+__device__ __forceinline__ float h2f(uint32_t bits16, int storage) {
+    if (storage == 2) return __uint_as_float(bits16 << 16);  // bfloat16
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+__device__ __forceinline__ void unpack8(const uint4 u, float* f, int storage) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = h2f(w[i] & 0xffffu, storage);
+        f[2 * i + 1] = h2f(w[i] >> 16, storage);
+    }
+}
+
+// Real spherical harmonics with the Condon-Shortley phase, degree <= 3
+// (textbook normalisations), colour = 0.5 + sum Y_i k_i, clamped below at 0.
+constexpr float SH_C0 = 0.28209479177387814f;
+constexpr float SH_C1 = 0.48860251190291992f;
+constexpr float SH_C2A = 1.0925484305920792f;
+constexpr float SH_C2B = 0.31539156525252005f;
+constexpr float SH_C2C = 0.54627421529603959f;
+constexpr float SH_C3A = 0.59004358992664352f;
+constexpr float SH_C3B = 2.8906114426405538f;
+constexpr float SH_C3C = 0.45704579946446577f;
+constexpr float SH_C3D = 0.3731763325901154f;
+constexpr float SH_C3E = 1.4453057213202769f;
+
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const float* k, float x, float y, float z, int deg, float* rgb) {
+    float Y[16];
+    Y[0] = SH_C0;
+    if (DEG >= 1) {
+        Y[1] = -SH_C1 * y;
+        Y[2] = SH_C1 * z;
+        Y[3] = -SH_C1 * x;
+    }
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = SH_C2A * (x * y);
+        Y[5] = -SH_C2A * (y * z);
+        Y[6] = SH_C2B * (3.0f * zz - 1.0f);
+        Y[7] = -SH_C2A * (x * z);
+        Y[8] = SH_C2C * (xx - yy);
+        if (DEG >= 3) {
+            Y[9] = -SH_C3A * (y * (3.0f * xx - yy));
+            Y[10] = SH_C3B * (x * y * z);
+            Y[11] = -SH_C3C * (y * (5.0f * zz - 1.0f));
+            Y[12] = SH_C3D * (z * (5.0f * zz - 3.0f));
+            Y[13] = -SH_C3C * (x * (5.0f * zz - 1.0f));
+            Y[14] = SH_C3E * (z * (xx - yy));
+            Y[15] = -SH_C3A * (x * (xx - 3.0f * yy));
+        }
+    }
+    const int nc = (DEG + 1) * (DEG + 1);
+    const int nuse = (deg + 1) * (deg + 1);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float s = 0.5f;
+#pragma unroll
+        for (int i = 0; i < nc; ++i)
+            if (i < nuse) s = __builtin_fmaf(Y[i], k[i * 3 + ch], s);
+        rgb[ch] = fmaxf(s, 0.0f);
+    }
+}
+
+// ------------------------------------------------------------- preprocess
+
+constexpr float NEAR_Z = 0.2f;
+constexpr float DILATION = 0.3f;
+constexpr float ALPHA_MIN = 1.0f / 255.0f;
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float LN255 = 5.5412635451584258f;
+constexpr float KAPPA_INV = 1.0f / 64.0f;  // FP64 fallback when a*c > 64 det
+
+// FP64 recomputation of the 2D covariance from the FP32 inputs.
+__device__ __noinline__ void cov2d_fp64(const float* q32, const float* ls32, float mx, float my, float mz,
+                                        const ViewParams& v, double* abc) {
+    double qw = q32[0], qx = q32[1], qy = q32[2], qz = q32[3];
+    const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+    const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                         2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                         2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+    const double s[3] = {exp((double)ls32[0]), exp((double)ls32[1]), exp((double)ls32[2])};
+    double M[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i * 3 + j] = R[i * 3 + j] * s[j];
+    const double d[3] = {(double)mx - (double)v.cam[0], (double)my - (double)v.cam[1], (double)mz - (double)v.cam[2]};
+    double p[3];
+    for (int i = 0; i < 3; ++i)
+        p[i] = (double)v.V[i * 3] * d[0] + (double)v.V[i * 3 + 1] * d[1] + (double)v.V[i * 3 + 2] * d[2];
+    double rx = p[0] / p[2], ry = p[1] / p[2];
+    rx = fmin(fmax(rx, -(double)v.lim_x), (double)v.lim_x);
+    ry = fmin(fmax(ry, -(double)v.lim_y), (double)v.lim_y);
+    const double fxz = (double)v.fx / p[2], fyz = (double)v.fy / p[2];
+    double T0[3], T1[3];
+    for (int j = 0; j < 3; ++j) {
+        T0[j] = fxz * ((double)v.V[j] - rx * (double)v.V[6 + j]);
+        T1[j] = fyz * ((double)v.V[3 + j] - ry * (double)v.V[6 + j]);
+    }
+    double m0[3], m1[3];
+    for (int k = 0; k < 3; ++k) {
+        m0[k] = T0[0] * M[k] + T0[1] * M[3 + k] + T0[2] * M[6 + k];
+        m1[k] = T1[0] * M[k] + T1[1] * M[3 + k] + T1[2] * M[6 + k];
+    }
+    abc[0] = m0[0] * m0[0] + m0[1] * m0[1] + m0[2] * m0[2] + (double)DILATION;
+    abc[1] = m0[0] * m1[0] + m0[1] * m1[1] + m0[2] * m1[2];
+    abc[2] = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2] + (double)DILATION;
+}
+
+template <int ST, int DEG>
+__global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const ViewParams* __restrict__ views,
+                                                           int nviews, uint32_t rec_base, uint32_t n_pad,
+                                                           uint32_t view_base, PreOut o) {
+    __shared__ uint32_t red[K1_THREADS / 64];
+    const int64_t g = (int64_t)blockIdx.x * K1_THREADS + threadIdx.x;
+    const bool in = g < s.n;
+    const int64_t n = s.n;
+
+    // ---- view-independent attributes
+    float mx = 0.f, my = 0.f, mz = 0.f;
+    float q[4] = {1.f, 0.f, 0.f, 0.f}, ls[3] = {0.f, 0.f, 0.f}, logit = 0.f;
+    if (in) {
+        mx = s.mean[g];
+        my = s.mean[n + g];
+        mz = s.mean[2 * n + g];
+        if (ST == 0) {
+            const float4* a = reinterpret_cast<const float4*>(s.attr);
+            const float4 r = a[g], m = a[n + g];
+            q[0] = r.x; q[1] = r.y; q[2] = r.z; q[3] = r.w;
+            ls[0] = m.x; ls[1] = m.y; ls[2] = m.z; logit = m.w;
+        } else {
+            float f[8];
+            unpack8(reinterpret_cast<const uint4*>(s.attr)[g], f, ST);
+            q[0] = f[0]; q[1] = f[1]; q[2] = f[2]; q[3] = f[3];
+            ls[0] = f[4]; ls[1] = f[5]; ls[2] = f[6]; logit = f[7];
+        }
+    }
+    const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    bool ok = in && qn2 > 0.0f && __builtin_isfinite(qn2) && __builtin_isfinite(mx) && __builtin_isfinite(my) &&
+              __builtin_isfinite(mz) && __builtin_isfinite(ls[0]) && __builtin_isfinite(ls[1]) &&
+              __builtin_isfinite(ls[2]) && __builtin_isfinite(logit);
+    // opacity and its log2 (folded into the blend exponent)
+    const float op = 1.0f / (1.0f + expf(-logit));
+    ok = ok && op >= ALPHA_MIN;
+    const float L = log2f(op);
+    // alpha >= 1/255 support: Q <= 2 ln(255 o); widened by 2^-9 relative and
+    // 2^-12 absolute so FP32 evaluation error cannot push a contributing
+    // pixel outside the footprint
+    const float k2 = 2.0f * __builtin_fmaf(L, 0.69314718055994531f, LN255);
+    const float k2m = __builtin_fmaf(k2, 1.0f + 1.0f / 512.0f, 1.0f / 4096.0f);
+    // M = Rq diag(exp(ls)), Sigma = M M^T
+    float M[9];
+    {
+        const float inv = 1.0f / sqrtf(qn2);
+        const float w = q[0] * inv, x = q[1] * inv, y = q[2] * inv, z = q[3] * inv;
+        const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                            2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                            2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+        const float sc[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) M[i * 3 + j] = R[i * 3 + j] * sc[j];
+    }
+
+    float k[48];
+    bool sh_loaded = false;
+
+    for (int vi = 0; vi < nviews; ++vi) {
+        const ViewParams& v = views[vi];
+        const uint32_t rec = rec_base + (uint32_t)vi * n_pad + (uint32_t)g;
+        // FP32 order key (also the near-plane test)
+        const float z32 = __builtin_fmaf(v.V[6], mx, __builtin_fmaf(v.V[7], my, __builtin_fmaf(v.V[8], mz, v.tz_key)));
+        bool vis = ok && z32 > NEAR_Z;
+        uint32_t touched = 0, fb = 0;
+        float4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, r2 = {0, 0, 0, 0};
+        uint2 bb = {0u, 0u};
+        if (vis) {
+            // camera-space centre, double-float: d = mu - t exactly, p = V d
+            const df dX = two_sum(mx, -v.cam[0]), dY = two_sum(my, -v.cam[1]), dZ = two_sum(mz, -v.cam[2]);
+            const df px = df_add(df_add(df_mulf(dX, v.V[0]), df_mulf(dY, v.V[1])), df_mulf(dZ, v.V[2]));
+            const df py = df_add(df_add(df_mulf(dX, v.V[3]), df_mulf(dY, v.V[4])), df_mulf(dZ, v.V[5]));
+            const df pz = df_add(df_add(df_mulf(dX, v.V[6]), df_mulf(dY, v.V[7])), df_mulf(dZ, v.V[8]));
+            const float zc = pz.hi;
+            // pixel centre of the Gaussian: u = fx x/z + cx, v = fy y/z + cy
+            const df u = df_add(df_mulf(df_div(px, pz), v.fx), df{v.cx, 0.0f});
+            const df w = df_add(df_mulf(df_div(py, pz), v.fy), df{v.cy, 0.0f});
+            // EWA: T = J V with the Jacobian at the clamped direction; Sigma2D = (T M)(T M)^T + 0.3 I
+            const float iz = 1.0f / zc;
+            const float rx = fminf(fmaxf(px.hi * iz, -v.lim_x), v.lim_x);
+            const float ry = fminf(fmaxf(py.hi * iz, -v.lim_y), v.lim_y);
+            const float fxz = v.fx * iz, fyz = v.fy * iz;
+            float T0[3], T1[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T0[j] = fxz * __builtin_fmaf(-rx, v.V[6 + j], v.V[j]);
+                T1[j] = fyz * __builtin_fmaf(-ry, v.V[6 + j], v.V[3 + j]);
+            }
+            float m0[3], m1[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                m0[c] = __builtin_fmaf(T0[0], M[c], __builtin_fmaf(T0[1], M[3 + c], T0[2] * M[6 + c]));
+                m1[c] = __builtin_fmaf(T1[0], M[c], __builtin_fmaf(T1[1], M[3 + c], T1[2] * M[6 + c]));
+            }
+            float a = __builtin_fmaf(m0[0], m0[0], __builtin_fmaf(m0[1], m0[1], m0[2] * m0[2])) + DILATION;
+            float b = __builtin_fmaf(m0[0], m1[0], __builtin_fmaf(m0[1], m1[1], m0[2] * m1[2]));
+            float c = __builtin_fmaf(m1[0], m1[0], __builtin_fmaf(m1[1], m1[1], m1[2] * m1[2])) + DILATION;
+            const float ac = a * c;
+            const float det = ac - b * b;
+            float ca, cb, cc;
+            if (!(det > ac * KAPPA_INV)) {
+                // near-singular 2D covariance: covariance, determinant and
+                // conic recomputed in FP64
+                double abc[3];
+                cov2d_fp64(q, ls, mx, my, mz, v, abc);
+                const double d64 = abc[0] * abc[2] - abc[1] * abc[1];
+                ca = (float)(abc[2] / d64);
+                cb = (float)(-abc[1] / d64);
+                cc = (float)(abc[0] / d64);
+                a = (float)abc[0];
+                c = (float)abc[2];
+                fb = 1;
+                vis = d64 > 0.0;
+            } else {
+                const float id = 1.0f / det;
+                ca = c * id;
+                cb = -b * id;
+                cc = a * id;
+            }
+            // conservative footprint: bounding box of the widened support ellipse
+            const float ex = sqrtf(k2m * a), ey = sqrtf(k2m * c);
+            vis = vis && __builtin_isfinite(u.hi) && __builtin_isfinite(w.hi) && __builtin_isfinite(ex) &&
+                  __builtin_isfinite(ey) && __builtin_isfinite(ca) && __builtin_isfinite(cb) && __builtin_isfinite(cc);
+            if (vis) {
+                const float mg = 1.0f / 256.0f;
+                // pixel i is inside when |i + 0.5 - u| <= ex
+                const float fw = (float)v.width, fh = (float)v.height;
+                const float xl = fminf(fmaxf(u.hi - ex - 0.5f - mg, -1.0f), fw);
+                const float xr = fminf(fmaxf(u.hi + ex - 0.5f + mg, -1.0f), fw);
+                const float yl = fminf(fmaxf(w.hi - ey - 0.5f - mg, -1.0f), fh);
+                const float yr = fminf(fmaxf(w.hi + ey - 0.5f + mg, -1.0f), fh);
+                const int x0 = max((int)ceilf(xl), 0), x1 = min((int)floorf(xr), v.width - 1);
+                const int y0 = max((int)ceilf(yl), 0), y1 = min((int)floorf(yr), v.height - 1);
+                if (x0 <= x1 && y0 <= y1) {
+                    const int tx0 = x0 / v.tile_w, tx1 = x1 / v.tile_w;
+                    const int ty0 = y0 / v.tile_h, ty1 = y1 / v.tile_h;
+                    touched = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                    bb = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+                }
+            }
+            if (touched) {
+                if (!sh_loaded) {
+                    if (ST == 0) {
+                        const float4* sh = reinterpret_cast<const float4*>(s.sh);
+                        constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 3) / 4;
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            const float4 t = sh[(int64_t)p * n + g];
+                            k[4 * p] = t.x; k[4 * p + 1] = t.y; k[4 * p + 2] = t.z; k[4 * p + 3] = t.w;
+                        }
+                    } else {
+                        const uint4* sh = reinterpret_cast<const uint4*>(s.sh);
+                        constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 7) / 8;
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) unpack8(sh[(int64_t)p * n + g], &k[8 * p], ST);
+                    }
+                    sh_loaded = true;
+                }
+                // colour at the direction camera centre -> Gaussian
+                const float dx = dX.hi, dy = dY.hi, dz = dZ.hi;
+                const float dn = 1.0f / sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+                float rgb[3];
+                sh_colour<DEG>(k, dx * dn, dy * dn, dz * dn, v.sh_degree, rgb);
+                r0 = make_float4(u.hi, w.hi, u.lo, w.lo);
+                r1 = make_float4(-0.5f * LOG2E * ca, -LOG2E * cb, -0.5f * LOG2E * cc, L);
+                r2 = make_float4(rgb[0], rgb[1], rgb[2], op);
+            }
+        }
+        o.zkey[rec] = __float_as_uint(z32);
+        o.touched[rec] = touched;
+        if (touched) {
+            o.rec0[rec] = r0;
+            o.rec1[rec] = r1;
+            o.rec2[rec] = r2;
+            o.bbox[rec] = bb;
+        }
+        const uint32_t bsum = block_sum<K1_THREADS>(touched, red);
+        const uint32_t bvis = block_sum<K1_THREADS>(touched ? 1u : 0u, red);
+        const uint32_t bfb = block_sum<K1_THREADS>(touched ? fb : 0u, red);
+        if (threadIdx.x == 0) {
+            const uint32_t blk = rec / K1_THREADS;
+            o.blk_sum[blk] = bsum;
+            o.blk_vis[blk] = bvis;
+            o.blk_fb[blk] = bfb;
+            o.blk_view[blk] = view_base + (uint32_t)vi;
+        }
+    }
+}
+
+// --------------------------------------------------------- scan of blocks
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_blocks(const uint32_t* __restrict__ blk_sum,
+                                                              const uint32_t* __restrict__ blk_vis,
+                                                              const uint32_t* __restrict__ blk_fb, int nblk,
+                                                              uint32_t* __restrict__ blk_off, Counters* cnt,
+                                                              uint32_t cap, uint32_t* zero, int nzero) {
+    __shared__ uint32_t red[SCAN_THREADS / 64];
+    uint64_t running = 0;
+    uint32_t vis = 0, fb = 0;
+    for (int base = 0; base < nblk; base += SCAN_THREADS * SCAN_ITEMS) {
+        const int i0 = base + threadIdx.x * SCAN_ITEMS;
+        uint32_t loc[SCAN_ITEMS];
+        uint32_t sum = 0, lv = 0, lf = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const int i = i0 + j;
+            const uint32_t x = i < nblk ? blk_sum[i] : 0u;
+            loc[j] = sum;
+            sum += x;
+            lv += i < nblk ? blk_vis[i] : 0u;
+            lf += i < nblk ? blk_fb[i] : 0u;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &tot);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const int i = i0 + j;
+            if (i < nblk) blk_off[i] = (uint32_t)running + ex + loc[j];
+        }
+        running += tot;
+        vis += block_sum<SCAN_THREADS>(lv, red);
+        fb += block_sum<SCAN_THREADS>(lf, red);
+    }
+    if (threadIdx.x == 0) {
+        cnt->D = running > 0xffffffffull ? 0xffffffffu : (uint32_t)running;
+        cnt->visible = vis;
+        cnt->fallbacks = fb;
+        cnt->overflow = running > (uint64_t)cap ? 1u : 0u;
+    }
+    for (int i = threadIdx.x; i < nzero; i += SCAN_THREADS) zero[i] = 0u;
+}
+
+// ---------------------------------------------------------------- duplicate
+
+__global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ touched,
+                                                          const uint2* __restrict__ bbox,
+                                                          const uint32_t* __restrict__ zkey,
+                                                          const uint32_t* __restrict__ blk_off,
+                                                          const uint32_t* __restrict__ blk_view,
+                                                          const Counters* __restrict__ cnt, uint32_t cap,
+                                                          const ViewParams* __restrict__ views,
+                                                          uint32_t* __restrict__ lo, uint32_t* __restrict__ hi,
+                                                          uint32_t* __restrict__ val) {
+    __shared__ uint32_t red[K1_THREADS / 64];
+    const uint32_t rec = blockIdx.x * K1_THREADS + threadIdx.x;
+    const uint32_t t = touched[rec];
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<K1_THREADS>(t, red, &tot);
+    if (cnt->overflow || t == 0) return;
+    const ViewParams& v = views[blk_view[blockIdx.x]];
+    uint32_t off = blk_off[blockIdx.x] + ex;
+    const uint2 b = bbox[rec];
+    const uint32_t z = zkey[rec];
+    const int tx0 = (int)(b.x & 0xffffu) / v.tile_w, ty0 = (int)(b.x >> 16) / v.tile_h;
+    const int tx1 = (int)(b.y & 0xffffu) / v.tile_w, ty1 = (int)(b.y >> 16) / v.tile_h;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const uint32_t rowbase = v.tile_base + (uint32_t)(ty * v.tiles_x);
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            lo[off] = z;
+            hi[off] = rowbase + (uint32_t)tx;
+            val[off] = rec;
+            ++off;
+        }
+    }
+}
+
+// ------------------------------------------------------------- radix sort
+// One pass sorts by an 8-bit (or narrower) digit of one key word, stably.
+// The D keys are split into nb contiguous segments, one per workgroup, of a
+// whole number of 2048-key chunks.  upsweep: digit histogram per segment;
+// scan: exclusive offsets over (digit, segment); downsweep: rank and scatter.
+
+__device__ __forceinline__ uint32_t sort_count(const Counters* cnt, uint32_t cap) {
+    return cnt->overflow ? 0u : min(cnt->D, cap);
+}
+__device__ __forceinline__ void segment(uint32_t D, int nb, int b, uint32_t* beg, uint32_t* end) {
+    uint64_t per = ((uint64_t)D + nb - 1) / nb;
+    per = (per + SORT_CHUNK - 1) / SORT_CHUNK * SORT_CHUNK;
+    const uint64_t s = min((uint64_t)D, per * (uint64_t)b);
+    *beg = (uint32_t)s;
+    *end = (uint32_t)min((uint64_t)D, s + per);
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* __restrict__ word,
+                                                               const Counters* __restrict__ cnt, uint32_t cap,
+                                                               int shift, int bits, uint32_t* __restrict__ hist,
+                                                               uint32_t* __restrict__ totals, int nb) {
+    __shared__ uint32_t h[SORT_THREADS / 64][256];
+    const int w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 256 * (SORT_THREADS / 64); i += SORT_THREADS) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    uint32_t beg, end;
+    segment(sort_count(cnt, cap), nb, blockIdx.x, &beg, &end);
+    const uint32_t mask = (1u << bits) - 1u;
+    for (uint32_t i = beg + threadIdx.x; i < end; i += SORT_THREADS) {
+        const uint32_t d = (word[i] >> shift) & mask;
+        atomicAdd(&h[w][d], 1u);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < 256) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < SORT_THREADS / 64; ++j) s += h[j][t];
+        if (t <= (int)mask) {
+            hist[(size_t)t * nb + blockIdx.x] = s;
+            if (s) atomicAdd(&totals[t], s);
+        }
+    }
+}
+
+// One wave per digit: exclusive offsets of that digit over all segments.
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals,
+                                                   int nb, int ndig) {
+    const int lane = threadIdx.x & 63;
+    const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (d >= ndig) return;  // whole wave exits together
+    uint32_t part = 0;
+    for (int j = lane; j < d; j += 64) part += totals[j];
+    uint32_t running = wave_sum(part);
+    uint32_t* row = hist + (size_t)d * nb;
+    for (int j0 = 0; j0 < nb; j0 += 64) {
+        const int j = j0 + lane;
+        const uint32_t x = j < nb ? row[j] : 0u;
+        const uint32_t inc = wave_incl_scan(x);
+        if (j < nb) row[j] = running + inc - x;
+        running += readlane(inc, 63);
+    }
+}
+
+template <bool CARRY_LO>
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
+    const uint32_t* __restrict__ slo, const uint32_t* __restrict__ shi, const uint32_t* __restrict__ sval,
+    uint32_t* __restrict__ dlo, uint32_t* __restrict__ dhi, uint32_t* __restrict__ dval,
+    const Counters* __restrict__ cnt, uint32_t cap, int word, int shift, int bits,
+    const uint32_t* __restrict__ hist, int nb) {
+    constexpr int NW = SORT_THREADS / 64;
+    constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t woff[NW][256];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t beg, end;
+    const uint32_t D = sort_count(cnt, cap);
+    segment(D, nb, blockIdx.x, &beg, &end);
+    if (t < 256) base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + blockIdx.x] : 0u;
+    const uint32_t* kw = word ? shi : slo;
+    for (uint32_t chunk = beg; chunk < end; chunk += SORT_CHUNK) {
+        for (int i = t; i < NW * 256; i += SORT_THREADS) (&wcnt[0][0])[i] = 0u;
+        __syncthreads();
+        uint32_t dig[ROUNDS], rank[ROUNDS], elo[ROUNDS], ehi[ROUNDS], ev[ROUNDS];
+        bool ok[ROUNDS];
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const uint32_t idx = chunk + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
+            ok[r] = idx < end;
+            uint32_t key = 0;
+            if (ok[r]) {
+                key = kw[idx];
+                elo[r] = CARRY_LO ? slo[idx] : 0u;
+                ehi[r] = shi[idx];
+                ev[r] = sval[idx];
+            }
+            const uint32_t d = (key >> shift) & mask;
+            dig[r] = d;
+            uint64_t m = ballot(ok[r]);
+            for (int b = 0; b < bits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bl = ballot(bit);
+                m &= bit ? bl : ~bl;
+            }
+            const uint32_t prior = (uint32_t)__builtin_popcountll(m & lt);
+            uint32_t cur = 0;
+            if (ok[r]) cur = wcnt[w][d];
+            rank[r] = cur + prior;
+            if (ok[r] && prior == 0) wcnt[w][d] = cur + (uint32_t)__builtin_popcountll(m);
+        }
+        __syncthreads();
+        if (t < 256) {
+            uint32_t acc = base[t];
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                woff[j][t] = acc;
+                acc += wcnt[j][t];
+            }
+            base[t] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const uint32_t pos = woff[w][dig[r]] + rank[r];
+            if (ok[r] && pos < D) {
+                if (CARRY_LO) dlo[pos] = elo[r];
+                dhi[pos] = ehi[r];
+                dval[pos] = ev[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ ranges
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ hi, const Counters* __restrict__ cnt,
+                                                uint32_t cap, uint32_t n_tiles, uint2* __restrict__ ranges) {
+    const uint32_t tile = blockIdx.x * 256 + threadIdx.x;
+    if (tile >= n_tiles) return;
+    const uint32_t D = sort_count(cnt, cap);
+    // lower bounds of tile and tile + 1 in the sorted tile words
+    uint32_t lo = 0, len = D;
+    while (len > 0) {
+        const uint32_t half = len >> 1;
+        if (hi[lo + half] < tile) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    uint32_t e = lo, len2 = D - lo;
+    while (len2 > 0) {
+        const uint32_t half = len2 >> 1;
+        if (hi[e + half] <= tile) {
+            e += half + 1;
+            len2 -= half + 1;
+        } else {
+            len2 = half;
+        }
+    }
+    ranges[tile] = make_uint2(lo, e);
+}
+
+// ------------------------------------------------------------------- blend
+
+constexpr float ALPHA_MAX = 0.99f;
+constexpr float T_MIN = 1e-4f;
+
+__device__ __forceinline__ uint8_t to_u8(float x) {
+    return (uint8_t)floorf(__builtin_fmaf(fminf(fmaxf(x, 0.0f), 1.0f), 255.0f, 0.5f));
+}
+
+// One workgroup per tile of TW x TH pixels; wave w owns the 8x8 pixel block
+// (w mod TW/8, w div TW/8) of it.  Each wave walks the tile's depth-sorted
+// list in batches of 64 * BD entries: every lane fetches entries, keeps those
+// whose pixel box meets the wave's block, compacts them into the wave's LDS
+// slice (ballot + mbcnt) and the 64 lanes then composite them front to back.
+// A wave leaves as soon as all of its pixels have terminated.
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__ views, int nviews,
+                                                  uint32_t n_tiles, const uint2* __restrict__ ranges,
+                                                  const uint32_t* __restrict__ vals, const float4* __restrict__ rec0,
+                                                  const float4* __restrict__ rec1, const float4* __restrict__ rec2,
+                                                  const uint2* __restrict__ bbox, uint32_t nrec) {
+    constexpr int NW = TW * TH / 64;
+    constexpr int BX = TW / 8;
+    constexpr int BATCH = 64 * BD;
+    __shared__ float4 la[NW][BATCH];
+    __shared__ float4 lb[NW][BATCH];
+    __shared__ float lc[NW][BATCH];
+
+    // XCD-aware mapping: consecutive workgroup ids go round-robin to the 8
+    // XCDs; give each XCD a contiguous band of tiles so neighbouring tiles
+    // (which share Gaussians) meet in the same L2.
+    const uint32_t per = (n_tiles + 7) / 8;
+    const uint32_t tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= n_tiles) return;
+    int vi = 0;
+    {
+        int lo = 0, hi = nviews - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+        }
+        vi = lo;
+    }
+    const ViewParams& v = views[vi];
+    const uint32_t lt = tile - v.tile_base;
+    const int tx = (int)(lt % (uint32_t)v.tiles_x), ty = (int)(lt / (uint32_t)v.tiles_x);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sx = tx * TW + (w % BX) * 8, sy = ty * TH + (w / BX) * 8;
+    const int px = sx + (lane & 7), py = sy + (lane >> 3);
+    const bool inside = px < v.width && py < v.height;
+    const float pxr = (float)(lane & 7) + 0.5f, pyr = (float)(lane >> 3) + 0.5f;
+    const float fsx = (float)sx, fsy = (float)sy;
+    const uint2 rg = ranges[tile];
+    float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
+    bool done = !inside;
+    // the wave's block clipped to the image: the only pixels it must cover
+    const int bx1 = min(sx + 7, v.width - 1), by1 = min(sy + 7, v.height - 1);
+
+    for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
+        if (ballot(!done) == 0) break;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < BD; ++k) {
+            const uint32_t i = base + (uint32_t)(k * 64 + lane);
+            bool hit = false;
+            uint32_t r = 0;
+            if (i < rg.y) r = vals[i];
+            if (i < rg.y && r < nrec) {
+                const uint2 b = bbox[r];
+                const int x0 = (int)(b.x & 0xffffu), y0 = (int)(b.x >> 16);
+                const int x1 = (int)(b.y & 0xffffu), y1 = (int)(b.y >> 16);
+                hit = !(x1 < sx || x0 > bx1 || y1 < sy || y0 > by1);
+            }
+            const uint64_t m = ballot(hit);
+            if (hit) {
+                const uint32_t slot = cnt + bits_below(m);
+                const float4 a = rec0[r], b1 = rec1[r], c2 = rec2[r];
+                // pixel centre relative to the block origin, hi and lo parts combined here
+                la[w][slot] = make_float4((a.x - fsx) + a.z, (a.y - fsy) + a.w, b1.x, b1.y);
+                lb[w][slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
+                lc[w][slot] = c2.z;
+            }
+            cnt += (uint32_t)__builtin_popcountll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (!done) {
+            for (uint32_t j = 0; j < cnt; ++j) {
+                const float4 a = la[w][j];
+                const float4 b = lb[w][j];
+                const float dx = pxr - a.x, dy = pyr - a.y;
+                const float e = __builtin_fmaf(__builtin_fmaf(a.z, dx, a.w * dy), dx,
+                                               __builtin_fmaf(b.x * dy, dy, b.y));
+                const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
+                if (alpha < ALPHA_MIN) continue;
+                const float Tn = T * (1.0f - alpha);
+                if (Tn < T_MIN) {
+                    done = true;
+                    break;
+                }
+                const float wgt = alpha * T;
+                cr = __builtin_fmaf(wgt, b.z, cr);
+                cg = __builtin_fmaf(wgt, b.w, cg);
+                cbl = __builtin_fmaf(wgt, lc[w][j], cbl);
+                T = Tn;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (inside) {
+        const float r = __builtin_fmaf(T, v.bg[0], cr);
+        const float g = __builtin_fmaf(T, v.bg[1], cg);
+        const float b = __builtin_fmaf(T, v.bg[2], cbl);
+        const size_t pix = (size_t)py * (size_t)v.width + (size_t)px;
+        if (v.fmt == 1) {
+            float* out = reinterpret_cast<float*>(v.out_ptr) + pix * 3;
+            out[0] = r;
+            out[1] = g;
+            out[2] = b;
+        } else {
+            uint8_t* out = reinterpret_cast<uint8_t*>(v.out_ptr) + pix * 3;
+            out[0] = to_u8(r);
+            out[1] = to_u8(g);
+            out[2] = to_u8(b);
+        }
+    }
+}
+
+__global__ void k_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t x = i < n ? in[i] : 0u;
+    const uint32_t s = wave_incl_scan(x);
+    if (i < n) out[i] = s;
+}
+
+// ------------------------------------------------------------- launchers
+
+#define TIGAS_LAUNCH(kernel, grid, block, st, ...) hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__)
+
+template <int ST>
+static void preprocess_deg(int deg, dim3 grid, const SceneView& s, const ViewParams* v, int nv, uint32_t rb,
+                           uint32_t np, uint32_t vb, const PreOut& o, hipStream_t st) {
+    switch (deg) {
+        case 0: TIGAS_LAUNCH((k_preprocess<ST, 0>), grid, dim3(K1_THREADS), st, s, v, nv, rb, np, vb, o); break;
+        case 1: TIGAS_LAUNCH((k_preprocess<ST, 1>), grid, dim3(K1_THREADS), st, s, v, nv, rb, np, vb, o); break;
+        case 2: TIGAS_LAUNCH((k_preprocess<ST, 2>), grid, dim3(K1_THREADS), st, s, v, nv, rb, np, vb, o); break;
+        default: TIGAS_LAUNCH((k_preprocess<ST, 3>), grid, dim3(K1_THREADS), st, s, v, nv, rb, np, vb, o); break;
+    }
+}
+
+void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
+                       uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st) {
+    // the SH coefficients loaded are those of the highest degree any view uses
+    int deg = 0;
+    for (int i = 0; i < nviews; ++i) deg = views_host[i].sh_degree > deg ? views_host[i].sh_degree : deg;
+    const dim3 grid(n_pad / K1_THREADS);
+    if (s.storage == 0) preprocess_deg<0>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
+    else if (s.storage == 1) preprocess_deg<1>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
+    else preprocess_deg<2>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
+}
+
+void launch_scan_blocks(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap, uint32_t* zero,
+                        int nzero, hipStream_t st) {
+    TIGAS_LAUNCH(k_scan_blocks, dim3(1), dim3(SCAN_THREADS), st, o.blk_sum, o.blk_vis, o.blk_fb, nblk, blk_off, cnt,
+                 cap, zero, nzero);
+}
+
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* blk_off, const Counters* cnt, uint32_t cap,
+                      const ViewParams* views_dev, uint32_t* lo, uint32_t* hi, uint32_t* val, hipStream_t st) {
+    if (nblk == 0) return;
+    TIGAS_LAUNCH(k_duplicate, dim3(nblk), dim3(K1_THREADS), st, o.touched, o.bbox, o.zkey, blk_off, o.blk_view, cnt,
+                 cap, views_dev, lo, hi, val);
+}
+
+int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, const Counters* cnt, uint32_t cap,
+                bool carry_lo, hipStream_t st) {
+    int cur = 0;
+    for (int p = 0; p < npasses; ++p) {
+        const SortPass& ps = passes[p];
+        const uint32_t* word = ps.word ? b.hi[cur] : b.lo[cur];
+        uint32_t* totals = b.totals + p * 256;
+        TIGAS_LAUNCH(k_sort_upsweep, dim3(b.nblocks), dim3(SORT_THREADS), st, word, cnt, cap, ps.shift, ps.bits,
+                     b.hist, totals, b.nblocks);
+        const int ndig = 1 << ps.bits;
+        TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, totals, b.nblocks, ndig);
+        // the depth word is carried only while depth digits remain (or when asked)
+        bool need_lo = carry_lo;
+        for (int q = p + 1; q < npasses; ++q) need_lo = need_lo || passes[q].word == 0;
+        if (need_lo)
+            TIGAS_LAUNCH(k_sort_downsweep<true>, dim3(b.nblocks), dim3(SORT_THREADS), st, b.lo[cur], b.hi[cur],
+                         b.val[cur], b.lo[cur ^ 1], b.hi[cur ^ 1], b.val[cur ^ 1], cnt, cap, ps.word, ps.shift,
+                         ps.bits, (const uint32_t*)b.hist, b.nblocks);
+        else
+            TIGAS_LAUNCH(k_sort_downsweep<false>, dim3(b.nblocks), dim3(SORT_THREADS), st, b.lo[cur], b.hi[cur],
+                         b.val[cur], b.lo[cur ^ 1], b.hi[cur ^ 1], b.val[cur ^ 1], cnt, cap, ps.word, ps.shift,
+                         ps.bits, (const uint32_t*)b.hist, b.nblocks);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap, uint32_t n_tiles, uint2* ranges,
+                   hipStream_t st) {
+    if (n_tiles == 0) return;
+    TIGAS_LAUNCH(k_ranges, dim3((n_tiles + 255) / 256), dim3(256), st, hi_sorted, cnt, cap, n_tiles, ranges);
+}
+
+template <int TW, int TH>
+static void blend_bd(int bd, dim3 grid, const ViewParams* v, int nv, uint32_t nt, const uint2* rg,
+                     const uint32_t* vals, const PreOut& o, uint32_t nrec, hipStream_t st) {
+    switch (bd) {
+        case 128: TIGAS_LAUNCH((k_blend<TW, TH, 2>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec); break;
+        case 256: TIGAS_LAUNCH((k_blend<TW, TH, 4>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec); break;
+        default: TIGAS_LAUNCH((k_blend<TW, TH, 1>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec); break;
+    }
+}
+
+void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
+                  const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
+                  hipStream_t st) {
+    if (n_tiles == 0) return;
+    const dim3 grid(((n_tiles + 7) / 8) * 8);
+    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
+    else if (tile_w == 16 && tile_h == 32) blend_bd<16, 32>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
+    else if (tile_w == 32 && tile_h == 16) blend_bd<32, 16>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
+    else blend_bd<16, 16>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
+}
+
+void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st) {
+    TIGAS_LAUNCH(k_wave_scan_selftest, dim3((n + 63) / 64), dim3(64), st, in, out, n);
+}
+
+}  // namespace tigas

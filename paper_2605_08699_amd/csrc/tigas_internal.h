@@ -1,0 +1,105 @@
+// Internal structures shared by the HIP kernels and the host side of libtigas.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tigas {
+
+constexpr int K1_THREADS = 256;       // one Gaussian per thread in preprocess / duplicate
+constexpr int SORT_THREADS = 256;     // 4 wave64 per sort workgroup
+constexpr int SORT_CHUNK = 2048;      // keys ranked per workgroup step (4 waves x 8 rounds x 64)
+constexpr int SORT_MAX_BLOCKS = 1024; // workgroups per sort pass
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 16;
+constexpr int MAX_SORT_PASSES = 8;
+
+// Per-view camera and tiling parameters, computed on the host in FP64 and
+// rounded once to FP32.
+struct ViewParams {
+    float V[9];        // world -> camera rotation R^T, row-major
+    float cam[3];      // camera centre t
+    float tz_key;      // float((-R^T t)_z): constant term of the FP32 depth key
+    float fx, fy, cx, cy;
+    float lim_x, lim_y;  // Jacobian clamp: 1.3 x the half-FoV tangents
+    int width, height;
+    int tile_w, tile_h, tiles_x, tiles_y;
+    uint32_t tile_base;  // first global tile id of this view
+    int sh_degree;
+    int fmt;             // 0 RGB8, 1 RGBF32
+    float bg[3];
+    uint64_t out_ptr;    // device address of this view's frame
+};
+
+// Resident scene (device pointers).  Layout by storage precision:
+//   mean:  f32 planes [3][n] (x, y, z)
+//   F32:   attr float4 [2][n]: (qw, qx, qy, qz), (ls0, ls1, ls2, logit)
+//          sh   float4 [12][n]: 48 floats per Gaussian, coefficient-major (k*3 + ch)
+//   F16/BF16: attr uint4 [n]: 8 halves (qw, qx, qy, qz, ls0, ls1, ls2, logit)
+//          sh   uint4 [6][n]: 48 halves per Gaussian, coefficient-major
+struct SceneView {
+    int64_t n;
+    int storage;  // 0 f32, 1 f16, 2 bf16
+    int sh_degree;
+    const float* mean;
+    const void* attr;
+    const void* sh;
+};
+
+struct Counters {
+    uint32_t D;         // duplicates (clamped to 2^32-1)
+    uint32_t visible;
+    uint32_t fallbacks;
+    uint32_t overflow;  // D exceeded the duplicate capacity: nothing was emitted
+    uint32_t pad[4];
+};
+
+// Preprocess outputs, one slot per record (record = view-local index of a
+// Gaussian, padded per view to a multiple of 256).
+struct PreOut {
+    float4* rec0;       // u_hi, v_hi, u_lo, v_lo
+    float4* rec1;       // A, B, C, L: alpha = 2^(A dx^2 + B dx dy + C dy^2 + L)
+    float4* rec2;       // r, g, b, opacity
+    uint2* bbox;        // inclusive pixel box: x0 | y0 << 16, x1 | y1 << 16
+    uint32_t* zkey;     // FP32 depth-key bits
+    uint32_t* touched;  // tiles overlapped
+    uint32_t* blk_sum;  // per 256-record block: sum of touched
+    uint32_t* blk_vis;  // per block: records with touched > 0
+    uint32_t* blk_fb;   // per block: FP64 fallbacks
+    uint32_t* blk_view; // per block: view index
+};
+
+struct SortBuffers {
+    uint32_t* lo[2];   // depth words
+    uint32_t* hi[2];   // tile words
+    uint32_t* val[2];  // record indices
+    uint32_t* hist;    // [256][nblocks]
+    uint32_t* totals;  // [MAX_SORT_PASSES][256]
+    int nblocks;
+};
+
+struct SortPass {
+    int word;   // 0 depth (lo) word, 1 tile (hi) word
+    int shift;
+    int bits;   // <= 8
+};
+
+// ---- launchers (kernels.hip) ----
+void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
+                       uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
+void launch_scan_blocks(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
+                        uint32_t* zero, int nzero, hipStream_t st);
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* blk_off, const Counters* cnt, uint32_t cap,
+                      const ViewParams* views_dev, uint32_t* lo, uint32_t* hi, uint32_t* val, hipStream_t st);
+// Runs the passes; returns the index (0/1) of the buffer holding the result.
+int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, const Counters* cnt, uint32_t cap,
+                bool carry_lo, hipStream_t st);
+void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap, uint32_t n_tiles, uint2* ranges,
+                   hipStream_t st);
+void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
+                  const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
+                  hipStream_t st);
+void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
+
+}  // namespace tigas

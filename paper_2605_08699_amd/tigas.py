@@ -1,0 +1,290 @@
+"""ctypes binding of libtigas.so (include/tigas.h): argument marshalling only.
+
+Every step of a render runs in the HIP kernels of the library; this module
+converts numpy arrays / torch tensors to pointers and structs.  There is no
+CPU fallback: if the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtigas.so")
+
+TIGAS_OK = 0
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_OOM", -3: "E_DEVICE", -4: "E_BUFFER", -5: "E_BUDGET"}
+ATTR = {"f32": 0, "f16": 1, "bf16": 2}
+FMT = {"rgb8": 0, "f32": 1}
+
+
+class TigasError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int),
+                ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats_wxyz", ctypes.c_void_p),
+                ("opacity_logits", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("is_device", ctypes.c_int), ("storage", ctypes.c_int)]
+
+
+class PoseC(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3)]
+
+
+class IntrC(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class QualityC(ctypes.Structure):
+    _fields_ = [("res_scale", ctypes.c_float), ("sh_degree", ctypes.c_int), ("fmt", ctypes.c_int),
+                ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int),
+                ("batch_depth", ctypes.c_int)]
+
+
+class FrameC(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("capacity", ctypes.c_size_t), ("is_device", ctypes.c_int),
+                ("out_w", ctypes.c_int), ("out_h", ctypes.c_int)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("visible", ctypes.c_int64), ("duplicates", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64), ("tiles", ctypes.c_int64), ("sort_passes", ctypes.c_int64),
+                ("rerenders", ctypes.c_int64)]
+
+
+class DebugC(ctypes.Structure):
+    _fields_ = [("rec", ctypes.c_void_p), ("bbox", ctypes.c_void_p), ("zkey", ctypes.c_void_p),
+                ("touched", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("skeys", ctypes.c_void_p), ("svals", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
+                ("cap_dup", ctypes.c_int64), ("cap_tiles", ctypes.c_int64), ("n_dup", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64)]
+
+
+# every symbol include/tigas.h declares
+EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
+           "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
+           "tigas_render_debug", "tigas_selftest_wave_scan")
+
+_lib = None
+
+
+def lib():
+    """Load libtigas.so (built in-tree by build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2605_08699_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        L.tigas_context_create.argtypes = [I, ctypes.POINTER(P)]
+        L.tigas_context_destroy.argtypes = [P]
+        L.tigas_context_destroy.restype = None
+        L.tigas_scene_load.argtypes = [P, ctypes.POINTER(SceneDesc), ctypes.POINTER(P)]
+        L.tigas_scene_free.argtypes = [P]
+        L.tigas_scene_free.restype = None
+        L.tigas_scene_bytes.argtypes = [P]
+        L.tigas_scene_bytes.restype = ctypes.c_size_t
+        L.tigas_render.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
+                                   ctypes.POINTER(QualityC), ctypes.POINTER(FrameC), P]
+        L.tigas_render_debug.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
+                                         ctypes.POINTER(QualityC), ctypes.POINTER(FrameC), ctypes.POINTER(DebugC)]
+        L.tigas_render_batch.argtypes = [ctypes.POINTER(P), ctypes.POINTER(PoseC), ctypes.POINTER(IntrC),
+                                         ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(QualityC), I,
+                                         ctypes.POINTER(FrameC), P]
+        L.tigas_last_stats.argtypes = [P, ctypes.POINTER(StatsC)]
+        L.tigas_last_error.argtypes = []
+        L.tigas_last_error.restype = ctypes.c_char_p
+        L.tigas_selftest_wave_scan.argtypes = [P, P, I]
+        for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
+                     "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan"):
+            getattr(L, name).restype = I
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != TIGAS_OK:
+        raise TigasError(status, lib().tigas_last_error().decode())
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(int(a.data_ptr()))
+
+
+def pose_c(pose) -> PoseC:
+    p = PoseC()
+    R = np.asarray(pose.R, np.float32).reshape(9)
+    t = np.asarray(pose.t, np.float32).reshape(3)
+    p.R[:] = [float(x) for x in R]
+    p.t[:] = [float(x) for x in t]
+    return p
+
+
+def intr_c(k) -> IntrC:
+    return IntrC(float(k.fx), float(k.fy), float(k.cx), float(k.cy))
+
+
+def quality_c(res_scale=1.0, sh_degree=-1, fmt="rgb8", bg=(0.0, 0.0, 0.0), tile=(16, 16), batch_depth=64):
+    q = QualityC()
+    q.res_scale = float(res_scale)
+    q.sh_degree = int(sh_degree)
+    q.fmt = FMT[fmt]
+    q.bg[:] = [float(x) for x in bg]
+    q.tile_w, q.tile_h = int(tile[0]), int(tile[1])
+    q.batch_depth = int(batch_depth)
+    return q
+
+
+def output_size(width, height, res_scale=1.0):
+    s = float(np.float32(res_scale))
+    return int(np.floor(width * s + 0.5)), int(np.floor(height * s + 0.5))
+
+
+class Scene:
+    def __init__(self, ctx, handle, n, storage):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = n
+        self.storage = storage
+
+    @property
+    def bytes(self) -> int:
+        return int(lib().tigas_scene_bytes(self.handle))
+
+    def free(self):
+        if self.handle:
+            lib().tigas_scene_free(self.handle)
+            self.handle = None
+
+
+class Context:
+    """A device, its stream and workspaces."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().tigas_context_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self._scenes = []
+
+    def close(self):
+        for s in self._scenes:
+            s.free()
+        self._scenes = []
+        if self.handle:
+            lib().tigas_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def load_scene(self, scene, storage: str = "f32") -> Scene:
+        f32 = lambda a: np.ascontiguousarray(np.asarray(a, np.float32))
+        arrs = [f32(scene.means), f32(scene.log_scales), f32(scene.quats), f32(scene.opacity_logits),
+                f32(scene.sh).reshape(-1, 16, 3)]
+        d = SceneDesc(scene.n, int(scene.sh_degree), *[ctypes.c_void_p(a.ctypes.data) for a in arrs], 0,
+                      ATTR[storage])
+        h = ctypes.c_void_p()
+        _check(lib().tigas_scene_load(self.handle, ctypes.byref(d), ctypes.byref(h)))
+        s = Scene(self, h, scene.n, storage)
+        self._scenes.append(s)
+        return s
+
+    def stats(self) -> dict:
+        st = StatsC()
+        _check(lib().tigas_last_stats(self.handle, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in StatsC._fields_}
+
+    def render(self, scene: Scene, pose, intr, width, height, res_scale=1.0, fmt="rgb8", bg=(0, 0, 0),
+               tile=(16, 16), batch_depth=64, sh_degree=-1, out=None, stream=None):
+        """Render one frame.  ``out``: a torch tensor on the GPU (written in place)
+        or None (a host numpy array is returned)."""
+        q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth)
+        ow, oh = output_size(width, height, res_scale)
+        if out is None:
+            out = np.zeros((oh, ow, 3), np.uint8 if fmt == "rgb8" else np.float32)
+            fr = FrameC(ctypes.c_void_p(out.ctypes.data), out.nbytes, 0, 0, 0)
+        else:
+            fr = FrameC(ctypes.c_void_p(int(out.data_ptr())), out.numel() * out.element_size(), 1, 0, 0)
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(lib().tigas_render(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
+                                  int(width), int(height), ctypes.byref(q), ctypes.byref(fr), st))
+        return out
+
+    def render_debug(self, scene: Scene, pose, intr, width, height, res_scale=1.0, fmt="f32", bg=(0, 0, 0),
+                     tile=(16, 16), batch_depth=64, sh_degree=-1, cap_dup=None):
+        """Render and return the intermediate stages (host arrays)."""
+        q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth)
+        ow, oh = output_size(width, height, res_scale)
+        img = np.zeros((oh, ow, 3), np.uint8 if fmt == "rgb8" else np.float32)
+        fr = FrameC(ctypes.c_void_p(img.ctypes.data), img.nbytes, 0, 0, 0)
+        n = scene.n
+        tiles_x = -(-ow // tile[0])
+        tiles_y = -(-oh // tile[1])
+        n_tiles = tiles_x * tiles_y
+        if cap_dup is None:
+            # first pass without the duplicate lists to learn D
+            d0 = DebugC()
+            _check(lib().tigas_render_debug(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
+                                            int(width), int(height), ctypes.byref(q), ctypes.byref(fr),
+                                            ctypes.byref(d0)))
+            cap_dup = int(d0.n_dup)
+        out = dict(
+            rec=np.zeros((n, 12), np.float32), bbox=np.zeros((n, 4), np.int32), zkey=np.zeros(n, np.uint32),
+            touched=np.zeros(n, np.uint32), keys=np.zeros(cap_dup, np.uint64), vals=np.zeros(cap_dup, np.uint32),
+            skeys=np.zeros(cap_dup, np.uint64), svals=np.zeros(cap_dup, np.uint32),
+            ranges=np.zeros((n_tiles, 2), np.uint32))
+        d = DebugC(*[ctypes.c_void_p(out[k].ctypes.data) for k in
+                     ("rec", "bbox", "zkey", "touched", "keys", "vals", "skeys", "svals", "ranges")],
+                   cap_dup, n_tiles, 0, 0)
+        _check(lib().tigas_render_debug(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
+                                        int(width), int(height), ctypes.byref(q), ctypes.byref(fr), ctypes.byref(d)))
+        D = int(d.n_dup)
+        for k in ("keys", "vals", "skeys", "svals"):
+            out[k] = out[k][:D]
+        out["image"] = img
+        out["n_dup"] = D
+        out["tiles_x"], out["tiles_y"] = tiles_x, tiles_y
+        return out
+
+    def render_batch(self, scenes, poses, intrs, widths, heights, res_scales=None, fmt="rgb8", bg=(0, 0, 0),
+                     tile=(16, 16), batch_depth=64, outs=None, stream=None):
+        n = len(poses)
+        res_scales = res_scales if res_scales is not None else [1.0] * n
+        qs = (QualityC * n)(*[quality_c(res_scales[i], -1, fmt, bg, tile, batch_depth) for i in range(n)])
+        frames = (FrameC * n)()
+        results = []
+        for i in range(n):
+            ow, oh = output_size(widths[i], heights[i], res_scales[i])
+            if outs is None:
+                a = np.zeros((oh, ow, 3), np.uint8 if fmt == "rgb8" else np.float32)
+                frames[i] = FrameC(ctypes.c_void_p(a.ctypes.data), a.nbytes, 0, 0, 0)
+            else:
+                a = outs[i]
+                frames[i] = FrameC(ctypes.c_void_p(int(a.data_ptr())), a.numel() * a.element_size(), 1, 0, 0)
+            results.append(a)
+        hs = (ctypes.c_void_p * n)(*[s.handle.value if isinstance(s.handle, ctypes.c_void_p) else s.handle
+                                     for s in scenes])
+        ps = (PoseC * n)(*[pose_c(p) for p in poses])
+        ks = (IntrC * n)(*[intr_c(k) for k in intrs])
+        ws = (ctypes.c_int * n)(*[int(w) for w in widths])
+        hh = (ctypes.c_int * n)(*[int(h) for h in heights])
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(lib().tigas_render_batch(hs, ps, ks, ws, hh, qs, n, frames, st))
+        return results
+
+
+def selftest_wave_scan(values) -> np.ndarray:
+    v = np.ascontiguousarray(np.asarray(values, np.uint32))
+    out = np.zeros_like(v)
+    _check(lib().tigas_selftest_wave_scan(ctypes.c_void_p(v.ctypes.data), ctypes.c_void_p(out.ctypes.data),
+                                          int(v.size)))
+    return out
