@@ -1,0 +1,194 @@
+"""Benchmark: frames/s and p50/p99 frame latency of the forward 3DGS rasterizer.
+
+Workload: 3M Gaussians (64 anisotropic clusters + 40% flattened surface
+splats, SH degree 3), 1920x1080, the 300-pose smooth 6DoF trajectory, with
+the attributes stored in FP32 (the headline value) and in FP16 / BF16.
+A step is one frame: preprocess, scan, duplicate, radix sort, tile ranges,
+blend + RGB8 pack, with the scene resident in HBM and the frame written to a
+device buffer.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 300] [--warmup 10] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed FMA), TFLOP/s
+# FP32 flops of one (pixel, Gaussian) evaluation in the blend: offsets (2),
+# exponent polynomial (3 mul/fma = 8 flops incl. 2 plain mul), exp2 (1), clamp
+# (1); a contribution adds transmittance (2), weight (1), 3 FMA colour (6)
+FLOPS_EVAL = 12
+FLOPS_CONTRIB = 9
+
+
+def _stats(ts):
+    a = np.asarray(ts) * 1e3
+    return float(np.median(a)), float(np.percentile(a, 99))
+
+
+def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch, count_work):
+    s = ctx.load_scene(scene, storage)
+    out = torch.empty((H, W, 3), dtype=torch.uint8, device="cuda")
+    for i in range(warmup):
+        ctx.render(s, traj[i % len(traj)], k, W, H, out=out)
+    torch.cuda.synchronize()
+    ctx.profile_stages(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        t = time.perf_counter()
+        ctx.render(s, traj[i % len(traj)], k, W, H, out=out)
+        lat.append(time.perf_counter() - t)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.profile_stages(False)
+    nfr = max(stages["frames"], 1)
+    # algorithmic work of the same frames (untimed second pass with the
+    # counting blend kernel): visible Gaussians, duplicates, evaluations
+    work = dict(frames=0, visible=0, duplicates=0, evaluations=0, contributions=0, fallbacks=0)
+    if count_work:
+        for i in range(steps):
+            e, c = ctx.count_blend_work(s, traj[i % len(traj)], k, W, H)
+            st = ctx.stats()
+            work["frames"] += 1
+            work["evaluations"] += e
+            work["contributions"] += c
+            for f in ("visible", "duplicates", "fallbacks"):
+                work[f] += st[f]
+    p50, p99 = _stats(lat)
+    res = dict(frames_per_s=steps / total, ms_per_frame=1e3 * total / steps, p50_ms=p50, p99_ms=p99,
+               gpu_ms_per_frame=sum(v for kk, v in stages.items() if kk != "frames") / nfr,
+               stage_ms={kk: v / nfr for kk, v in stages.items() if kk != "frames"},
+               work=work, scene_bytes=s.bytes)
+    s.free()
+    return res
+
+
+def roofline(v, n, storage):
+    """Roofline of the dominant stage of the FP32 run: algorithmic work per
+    frame (averaged over the timed frames) / mean stage time per frame."""
+    st = v["stage_ms"]
+    dom = max(st, key=st.get)
+    ms = st[dom]
+    w = v["work"]
+    nf = max(w["frames"], 1)
+    D = w["duplicates"] / nf
+    V = w["visible"] / nf
+    if dom == "blend":
+        flops = (FLOPS_EVAL * w["evaluations"] + FLOPS_CONTRIB * w["contributions"]) / nf
+        ach = flops / (ms * 1e-3) / 1e12
+        return dict(kernel="k_blend", bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=None, ms=ms)
+    if dom == "sort":
+        # 4 depth passes: read depth word (4) + read/write 12 B; tile passes read 4 + move 8 B
+        byts = D * (4 * (4 + 24) + 2 * (4 + 16))
+        kern = "k_sort_* (6 passes)"
+    elif dom == "preprocess":
+        attr = 44 if storage == "f32" else 28
+        shb = 192 if storage == "f32" else 96
+        byts = n * attr + V * shb + n * 8 + V * 56
+        kern = "k_preprocess"
+    else:
+        byts = D * 12
+        kern = "k_" + dom
+    ach = byts / (ms * 1e-3) / 1e9
+    return dict(kernel=kern, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=None, ms=ms)
+
+
+def cpu_baseline(scene, pose, k, W, H, n_pix=2048):
+    """The FP64 oracle, untuned, on a bounded sample of one frame."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    proj = orc.preprocess(scene, pose, k, W, H)
+    _ = proj.order
+    proj.boxes()
+    t1 = time.perf_counter()
+    idx = rng.choice(W * H, n_pix, replace=False)
+    orc.render_pixels(proj, idx % W, idx // W)
+    t2 = time.perf_counter()
+    frame_s = (t1 - t0) + (t2 - t1) * (W * H / n_pix)
+    return dict(value=1.0 / frame_s, unit="frames/s", cores=orc.num_threads(), kind="oracle",
+                sample=f"pose 0: FP64 projection + depth order of all {scene.n} Gaussians ({t1 - t0:.2f} s) and "
+                       f"{n_pix} random pixels of the {W}x{H} frame ({t2 - t1:.2f} s), extrapolated to the full frame")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="f32,f16,bf16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py renders on one GPU only: the rasterizer has no multi-GPU path in this build "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_08699_amd import synth, tigas
+
+    W, H = 1920, 1080
+    scene = synth.c3_scene(args.n)
+    traj = synth.c3_trajectory(300)
+    k = synth.fov_intrinsics(W, H)
+    ctx = tigas.Context(0)
+    variants = {}
+    for storage in args.variants.split(","):
+        variants[storage] = run_variant(ctx, tigas, scene, storage, traj, k, W, H, args.steps, args.warmup, torch,
+                                        count_work=(storage == "f32"))
+        print(f"# {storage}: {variants[storage]['frames_per_s']:.1f} frames/s, p50 "
+              f"{variants[storage]['p50_ms']:.3f} ms, p99 {variants[storage]['p99_ms']:.3f} ms", file=sys.stderr,
+              flush=True)
+    main_v = variants["f32"] if "f32" in variants else next(iter(variants.values()))
+    rl = roofline(main_v, scene.n, "f32")
+    line = {
+        "metric": "frames/s + p50/p99 render latency, 3M Gaussians @1080p, fp32 vs fp16-attr",
+        "value": main_v["frames_per_s"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_v["ms_per_frame"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3M Gaussians (64 clusters + 40% surface splats, SH deg 3), 1920x1080, "
+                               "300-pose 6DoF trajectory, FP32 attributes, RGB8 frame in HBM",
+                   "n_gaussians": scene.n, "width": W, "height": H, "poses": len(traj), "tile": "16x16",
+                   "batch_depth": 64},
+        "p50_ms": main_v["p50_ms"],
+        "p99_ms": main_v["p99_ms"],
+        "gpu_ms_per_frame": main_v["gpu_ms_per_frame"],
+        "stage_ms": main_v["stage_ms"],
+        "work_per_frame": {x: main_v["work"][x] / max(main_v["work"]["frames"], 1)
+                           for x in ("visible", "duplicates", "evaluations", "contributions", "fallbacks")},
+        "variants": {kk: {x: vv[x] for x in ("frames_per_s", "p50_ms", "p99_ms", "gpu_ms_per_frame", "stage_ms",
+                                              "scene_bytes")} for kk, vv in variants.items()},
+        "roofline": {x: rl[x] for x in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": rl["kernel"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, traj[0], k, W, H)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,26 @@ tigas_status tigas_render_batch(tigas_scene* const* scenes, const tigas_pose* po
 
 tigas_status tigas_last_stats(tigas_context* ctx, tigas_stats* out);
 
+/* Stage timing with HIP events recorded on the rendering stream around each
+ * stage of every render on this context (preprocess, block scan, duplicate,
+ * radix sort, tile ranges, blend).  tigas_profile_stages switches it on or
+ * off and resets the accumulated milliseconds; tigas_stage_times reads them
+ * (sums over `frames` renders). */
+typedef struct {
+    double preprocess, scan, duplicate, sort, ranges, blend; /* milliseconds */
+    int64_t frames;
+} tigas_stage_ms;
+
+tigas_status tigas_profile_stages(tigas_context* ctx, int enable);
+tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
+
+/* Renders like tigas_render with a blend kernel that also counts the work it
+ * does: *evaluations = (pixel, Gaussian) pairs whose alpha was evaluated
+ * before the pixel terminated, *contributions = pairs composited. */
+tigas_status tigas_count_blend_work(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                                    int width, int height, const tigas_quality* q, tigas_frame* out,
+                                    int64_t* evaluations, int64_t* contributions);
+
 /* Thread-local message of the last failing call on this thread ("" if none);
  * valid until the next call on this thread. */
 const char* tigas_last_error(void);

@@ -160,6 +160,8 @@ struct Workspace {
     DevBuf views;
     DevBuf frame_staging;
     HostPinned host_views, host_counters;
+    DevBuf work;              // blend work counters (evaluations, contributions)
+    hipEvent_t ev[7] = {};    // stage boundaries when stage timing is on
     uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0, view_cap = 0;
     uint32_t last_D = 0;
     hipEvent_t done = nullptr;
@@ -218,8 +220,14 @@ struct Workspace {
         host_views.ensure(sizeof(ViewParams) * (size_t)n);
         view_cap = (uint32_t)n;
     }
+    void ensure_events() {
+        if (ev[0]) return;
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    }
     ~Workspace() {
         if (done) (void)hipEventDestroy(done);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -230,6 +238,9 @@ struct tigas_context {
     std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
     tigas_stats last{};
     std::mutex stats_mu;
+    std::atomic<bool> profile{false};
+    double stage_ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t stage_frames = 0;
 
     Workspace& workspace(hipStream_t s) {
         std::lock_guard<std::mutex> lk(mu);
@@ -360,8 +371,12 @@ struct Plan {
 
 // Enqueue the whole launch sequence for a plan on ws.stream.  Returns the
 // index of the sort buffer that holds the sorted lists.
-int enqueue(Workspace& ws, Plan& plan, bool carry_lo) {
+int enqueue(Workspace& ws, Plan& plan, bool carry_lo, bool prof, unsigned long long* work) {
     hipStream_t st = ws.stream;
+    if (prof) ws.ensure_events();
+    auto mark = [&](int i) {
+        if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
+    };
     const int nv = (int)plan.views.size();
     ws.ensure_views(nv);
     ws.ensure_records(plan.nrec);
@@ -370,17 +385,21 @@ int enqueue(Workspace& ws, Plan& plan, bool carry_lo) {
     HIPCHK(hipMemcpyAsync(ws.views.p, ws.host_views.p, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
     const PreOut o = ws.pre();
     const ViewParams* vdev = ws.views.as<ViewParams>();
+    mark(0);
     for (const Group& g : plan.groups) {
         if (g.n_pad == 0) continue;
         launch_preprocess(g.scene->view, vdev + g.first_view, plan.views.data() + g.first_view, g.nviews,
                           g.rec_base, g.n_pad, (uint32_t)g.first_view, o, st);
     }
+    mark(1);
     const int nblk = (int)(plan.nrec / K1_THREADS);
     Counters* cnt = ws.counters.as<Counters>();
     launch_scan_blocks(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, ws.totals.as<uint32_t>(),
                        256 * MAX_SORT_PASSES, st);
+    mark(2);
     launch_duplicate(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, vdev, ws.lo[0].as<uint32_t>(),
                      ws.hi[0].as<uint32_t>(), ws.val[0].as<uint32_t>(), st);
+    mark(3);
     SortBuffers sb;
     for (int i = 0; i < 2; ++i) {
         sb.lo[i] = ws.lo[i].as<uint32_t>();
@@ -393,9 +412,12 @@ int enqueue(Workspace& ws, Plan& plan, bool carry_lo) {
     const std::vector<SortPass> passes = sort_passes(plan.n_tiles);
     if ((int)passes.size() > MAX_SORT_PASSES) fail(TIGAS_E_INVALID, "too many tiles for the sort key");
     const int cur = launch_sort(sb, passes.data(), (int)passes.size(), cnt, ws.dup_cap, carry_lo, st);
+    mark(4);
     launch_ranges(sb.hi[cur], cnt, ws.dup_cap, plan.n_tiles, ws.ranges.as<uint2>(), st);
+    mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
-                 plan.tc.bd, st);
+                 plan.tc.bd, work, st);
+    mark(6);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ws.host_counters.p, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     return cur;
@@ -409,10 +431,12 @@ uint32_t initial_dup_cap(const Plan& plan, uint32_t last_D) {
 
 // Runs the plan to completion (synchronous), regrowing the duplicate buffers
 // when the first attempt overflowed.  Returns the final sort buffer index.
-int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* rerenders) {
+int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* rerenders,
+             unsigned long long* work = nullptr) {
     ws.counters.ensure(sizeof(Counters));
     ws.ensure_dups(std::max(ws.dup_cap, initial_dup_cap(plan, ws.last_D)));
-    int cur = enqueue(ws, plan, carry_lo);
+    const bool prof = ctx->profile.load();
+    int cur = enqueue(ws, plan, carry_lo, prof, work);
     HIPCHK(hipStreamSynchronize(ws.stream));
     Counters c;
     std::memcpy(&c, ws.host_counters.p, sizeof(c));
@@ -421,7 +445,8 @@ int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* 
         const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
         if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
         ws.ensure_dups((uint32_t)want);
-        cur = enqueue(ws, plan, carry_lo);
+        if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
+        cur = enqueue(ws, plan, carry_lo, prof, work);
         HIPCHK(hipStreamSynchronize(ws.stream));
         std::memcpy(&c, ws.host_counters.p, sizeof(c));
         if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
@@ -430,6 +455,14 @@ int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* 
     ws.last_D = c.D;
     {
         std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        if (prof) {
+            for (int i = 0; i < 6; ++i) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ws.ev[i], ws.ev[i + 1]));
+                ctx->stage_ms[i] += ms;
+            }
+            ctx->stage_frames += 1;
+        }
         ctx->last.visible = c.visible;
         ctx->last.duplicates = c.D;
         ctx->last.fallbacks = c.fallbacks;
@@ -446,7 +479,8 @@ int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* 
 hipStream_t pick_stream(tigas_context* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }
 
 void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width, int height,
-                const tigas_quality* q, tigas_frame* out, void* hip_stream, tigas_debug_out* dbg) {
+                const tigas_quality* q, tigas_frame* out, void* hip_stream, tigas_debug_out* dbg,
+                int64_t* work_out = nullptr) {
     if (!scene || !out) fail(TIGAS_E_INVALID, "scene and frame are required");
     tigas_context* ctx = scene->ctx;
     HIPCHK(hipSetDevice(ctx->device));
@@ -473,7 +507,19 @@ void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsi
     v.tile_base = 0;
     plan.n_tiles = (uint32_t)(v.tiles_x * v.tiles_y);
     int rr = 0;
-    const int cur = run_plan(ctx, ws, plan, dbg != nullptr, &rr);
+    unsigned long long* work = nullptr;
+    if (work_out) {
+        ws.work.ensure(16);
+        work = ws.work.as<unsigned long long>();
+        HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
+    }
+    const int cur = run_plan(ctx, ws, plan, dbg != nullptr, &rr, work);
+    if (work_out) {
+        unsigned long long w[2];
+        HIPCHK(hipMemcpy(w, work, 16, hipMemcpyDeviceToHost));
+        work_out[0] = (int64_t)w[0];
+        work_out[1] = (int64_t)w[1];
+    }
     if (!out->is_device) {
         HIPCHK(hipMemcpyAsync(out->data, ws.frame_staging.p, need, hipMemcpyDeviceToHost, ws.stream));
         HIPCHK(hipStreamSynchronize(ws.stream));
@@ -758,6 +804,42 @@ tigas_status tigas_last_stats(tigas_context* ctx, tigas_stats* out) {
         if (!ctx || !out) fail(TIGAS_E_INVALID, "null argument");
         std::lock_guard<std::mutex> lk(ctx->stats_mu);
         *out = ctx->last;
+    });
+}
+
+tigas_status tigas_profile_stages(tigas_context* ctx, int enable) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        for (double& x : ctx->stage_ms) x = 0.0;
+        ctx->stage_frames = 0;
+        ctx->profile.store(enable != 0);
+    });
+}
+
+tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out) {
+    return guard([&] {
+        if (!ctx || !out) fail(TIGAS_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        out->preprocess = ctx->stage_ms[0];
+        out->scan = ctx->stage_ms[1];
+        out->duplicate = ctx->stage_ms[2];
+        out->sort = ctx->stage_ms[3];
+        out->ranges = ctx->stage_ms[4];
+        out->blend = ctx->stage_ms[5];
+        out->frames = ctx->stage_frames;
+    });
+}
+
+tigas_status tigas_count_blend_work(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                                    int width, int height, const tigas_quality* q, tigas_frame* out,
+                                    int64_t* evaluations, int64_t* contributions) {
+    return guard([&] {
+        if (!evaluations || !contributions) fail(TIGAS_E_INVALID, "null counter output");
+        int64_t w[2] = {0, 0};
+        render_one(scene, pose, intr, width, height, q, out, nullptr, nullptr, w);
+        *evaluations = w[0];
+        *contributions = w[1];
     });
 }
 

@@ -667,12 +667,13 @@ __device__ __forceinline__ uint8_t to_u8(float x) {
 // whose pixel box meets the wave's block, compacts them into the wave's LDS
 // slice (ballot + mbcnt) and the 64 lanes then composite them front to back.
 // A wave leaves as soon as all of its pixels have terminated.
-template <int TW, int TH, int BD>
+template <int TW, int TH, int BD, bool COUNT>
 __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__ views, int nviews,
                                                   uint32_t n_tiles, const uint2* __restrict__ ranges,
                                                   const uint32_t* __restrict__ vals, const float4* __restrict__ rec0,
                                                   const float4* __restrict__ rec1, const float4* __restrict__ rec2,
-                                                  const uint2* __restrict__ bbox, uint32_t nrec) {
+                                                  const uint2* __restrict__ bbox, uint32_t nrec,
+                                                  unsigned long long* __restrict__ work) {
     constexpr int NW = TW * TH / 64;
     constexpr int BX = TW / 8;
     constexpr int BATCH = 64 * BD;
@@ -707,6 +708,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
     const uint2 rg = ranges[tile];
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
     bool done = !inside;
+    uint32_t n_eval = 0, n_contrib = 0;  // (pixel, Gaussian) evaluations / contributions, COUNT only
     // the wave's block clipped to the image: the only pixels it must cover
     const int bx1 = min(sx + 7, v.width - 1), by1 = min(sy + 7, v.height - 1);
 
@@ -747,6 +749,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
                 const float e = __builtin_fmaf(__builtin_fmaf(a.z, dx, a.w * dy), dx,
                                                __builtin_fmaf(b.x * dy, dy, b.y));
                 const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
+                if (COUNT) ++n_eval;
                 if (alpha < ALPHA_MIN) continue;
                 const float Tn = T * (1.0f - alpha);
                 if (Tn < T_MIN) {
@@ -758,11 +761,19 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
                 cg = __builtin_fmaf(wgt, b.w, cg);
                 cbl = __builtin_fmaf(wgt, lc[w][j], cbl);
                 T = Tn;
+                if (COUNT) ++n_contrib;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (COUNT) {
+        const uint32_t se = wave_sum(n_eval), sc = wave_sum(n_contrib);
+        if (lane == 0) {
+            atomicAdd(&work[0], (unsigned long long)se);
+            atomicAdd(&work[1], (unsigned long long)sc);
+        }
     }
     if (inside) {
         const float r = __builtin_fmaf(T, v.bg[0], cr);
@@ -862,25 +873,33 @@ void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap,
     TIGAS_LAUNCH(k_ranges, dim3((n_tiles + 255) / 256), dim3(256), st, hi_sorted, cnt, cap, n_tiles, ranges);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool C>
 static void blend_bd(int bd, dim3 grid, const ViewParams* v, int nv, uint32_t nt, const uint2* rg,
-                     const uint32_t* vals, const PreOut& o, uint32_t nrec, hipStream_t st) {
+                     const uint32_t* vals, const PreOut& o, uint32_t nrec, unsigned long long* work, hipStream_t st) {
     switch (bd) {
-        case 128: TIGAS_LAUNCH((k_blend<TW, TH, 2>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec); break;
-        case 256: TIGAS_LAUNCH((k_blend<TW, TH, 4>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec); break;
-        default: TIGAS_LAUNCH((k_blend<TW, TH, 1>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec); break;
+        case 128: TIGAS_LAUNCH((k_blend<TW, TH, 2, C>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work); break;
+        case 256: TIGAS_LAUNCH((k_blend<TW, TH, 4, C>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work); break;
+        default: TIGAS_LAUNCH((k_blend<TW, TH, 1, C>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work); break;
     }
+}
+
+template <bool C>
+static void blend_tiles(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
+                        const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h,
+                        int batch_depth, unsigned long long* work, hipStream_t st) {
+    const dim3 grid(((n_tiles + 7) / 8) * 8);
+    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
+    else if (tile_w == 16 && tile_h == 32) blend_bd<16, 32, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
+    else if (tile_w == 32 && tile_h == 16) blend_bd<32, 16, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
+    else blend_bd<16, 16, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
 }
 
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  hipStream_t st) {
+                  unsigned long long* work, hipStream_t st) {
     if (n_tiles == 0) return;
-    const dim3 grid(((n_tiles + 7) / 8) * 8);
-    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
-    else if (tile_w == 16 && tile_h == 32) blend_bd<16, 32>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
-    else if (tile_w == 32 && tile_h == 16) blend_bd<32, 16>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
-    else blend_bd<16, 16>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, st);
+    if (work) blend_tiles<true>(views_dev, nviews, n_tiles, ranges, vals, o, nrec, tile_w, tile_h, batch_depth, work, st);
+    else blend_tiles<false>(views_dev, nviews, n_tiles, ranges, vals, o, nrec, tile_w, tile_h, batch_depth, nullptr, st);
 }
 
 void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st) {

@@ -99,7 +99,7 @@ void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap,
                    hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  hipStream_t st);
+                  unsigned long long* work, hipStream_t st);
 void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
 
 }  // namespace tigas

@@ -66,10 +66,17 @@ class DebugC(ctypes.Structure):
                 ("n_tiles", ctypes.c_int64)]
 
 
+class StageC(ctypes.Structure):
+    _fields_ = [("preprocess", ctypes.c_double), ("scan", ctypes.c_double), ("duplicate", ctypes.c_double),
+                ("sort", ctypes.c_double), ("ranges", ctypes.c_double), ("blend", ctypes.c_double),
+                ("frames", ctypes.c_int64)]
+
+
 # every symbol include/tigas.h declares
 EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
-           "tigas_render_debug", "tigas_selftest_wave_scan")
+           "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
+           "tigas_count_blend_work")
 
 _lib = None
 
@@ -101,8 +108,14 @@ def lib():
         L.tigas_last_error.argtypes = []
         L.tigas_last_error.restype = ctypes.c_char_p
         L.tigas_selftest_wave_scan.argtypes = [P, P, I]
+        L.tigas_profile_stages.argtypes = [P, I]
+        L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
+        L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
+                                             ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
+                                             ctypes.POINTER(I64), ctypes.POINTER(I64)]
         for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
-                     "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan"):
+                     "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
+                     "tigas_stage_times", "tigas_count_blend_work"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -202,6 +215,28 @@ class Context:
         st = StatsC()
         _check(lib().tigas_last_stats(self.handle, ctypes.byref(st)))
         return {f: int(getattr(st, f)) for f, _ in StatsC._fields_}
+
+    def profile_stages(self, enable: bool = True):
+        """Switch per-stage HIP-event timing on/off (resets the sums)."""
+        _check(lib().tigas_profile_stages(self.handle, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        st = StageC()
+        _check(lib().tigas_stage_times(self.handle, ctypes.byref(st)))
+        return {f: (int(getattr(st, f)) if f == "frames" else float(getattr(st, f))) for f, _ in StageC._fields_}
+
+    def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=(16, 16),
+                         batch_depth=64):
+        """(evaluations, contributions) of the blend kernel for one frame."""
+        q = quality_c(res_scale, -1, "rgb8", (0, 0, 0), tile, batch_depth)
+        ow, oh = output_size(width, height, res_scale)
+        img = np.zeros((oh, ow, 3), np.uint8)
+        fr = FrameC(ctypes.c_void_p(img.ctypes.data), img.nbytes, 0, 0, 0)
+        e, c = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tigas_count_blend_work(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
+                                            int(width), int(height), ctypes.byref(q), ctypes.byref(fr),
+                                            ctypes.byref(e), ctypes.byref(c)))
+        return int(e.value), int(c.value)
 
     def render(self, scene: Scene, pose, intr, width, height, res_scale=1.0, fmt="rgb8", bg=(0, 0, 0),
                tile=(16, 16), batch_depth=64, sh_degree=-1, out=None, stream=None):
