@@ -55,3 +55,11 @@ def sort_and_ranges(keys, vals, n_tiles: int):
     bounds = np.searchsorted(tiles, t, side="left")
     ranges = np.stack([bounds[:-1], bounds[1:]], 1).astype(np.uint32)
     return sk, sv, ranges
+
+
+def depth_first_emission(keys, vals):
+    """The duplicate list in the order a depth-first emitter produces it:
+    Gaussians taken in (depth, index) order, each with its tiles row-major.
+    That is the record-order list stably sorted by the depth word alone."""
+    order = np.argsort(keys & np.uint64(0xFFFFFFFF), kind="stable")
+    return keys[order], vals[order]

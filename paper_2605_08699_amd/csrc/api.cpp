@@ -150,11 +150,13 @@ struct Workspace {
     hipStream_t stream = nullptr;
     // per record
     DevBuf rec0, rec1, rec2, bbox, zkey, touched;
-    DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off;
+    DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf counters;
-    // per duplicate
-    DevBuf lo[2], hi[2], val[2];
+    // per duplicate (also holds the visible Gaussians for the depth passes)
+    DevBuf key[2], val[2], ext[2];
     DevBuf hist, totals;
+    // emission-order copies for the inspection entry point
+    DevBuf dbg_key, dbg_val, dbg_ext;
     // per tile
     DevBuf ranges;
     DevBuf views;
@@ -195,15 +197,17 @@ struct Workspace {
         blk_fb.ensure(nb * 4);
         blk_view.ensure(nb * 4);
         blk_off.ensure(nb * 4);
+        blk_sum2.ensure(nb * 4);
+        blk_off2.ensure(nb * 4);
         rec_cap = (uint32_t)r;
     }
-    void ensure_dups(uint32_t cap) {
-        if (cap <= dup_cap && lo[0].p) return;
-        cap = std::max<uint32_t>(cap, 1u << 16);
+    void ensure_dups(uint32_t cap, bool extra) {
+        if (cap <= dup_cap && key[0].p && (!extra || ext[0].p)) return;
+        cap = std::max<uint32_t>(std::max(cap, dup_cap), 1u << 16);
         for (int i = 0; i < 2; ++i) {
-            lo[i].ensure((size_t)cap * 4);
-            hi[i].ensure((size_t)cap * 4);
+            key[i].ensure((size_t)cap * 4);
             val[i].ensure((size_t)cap * 4);
+            if (extra) ext[i].ensure((size_t)cap * 4);
         }
         hist.ensure((size_t)256 * SORT_MAX_BLOCKS * 4);
         totals.ensure((size_t)256 * MAX_SORT_PASSES * 4);
@@ -343,17 +347,18 @@ size_t frame_bytes(const ViewParams& v) {
     return (size_t)v.width * v.height * 3 * (v.fmt == 1 ? 4 : 1);
 }
 
-std::vector<SortPass> sort_passes(uint32_t n_tiles) {
+// Depth digits of the (tile | depth) key: the positive FP32 bit patterns,
+// bit 31 always clear.
+const SortPass kDepthPasses[4] = {{0, 8}, {8, 8}, {16, 8}, {24, 7}};
+
+std::vector<SortPass> tile_passes(uint32_t n_tiles) {
     std::vector<SortPass> p;
-    // depth word: positive FP32 bit patterns, bit 31 always clear
-    p.push_back({0, 0, 8});
-    p.push_back({0, 8, 8});
-    p.push_back({0, 16, 8});
-    p.push_back({0, 24, 7});
     const int tb = ceil_log2(n_tiles);
-    for (int sh = 0; sh < tb; sh += 8) p.push_back({1, sh, std::min(8, tb - sh)});
+    for (int sh = 0; sh < tb; sh += 8) p.push_back({sh, std::min(8, tb - sh)});
     return p;
 }
+
+int sort_blocks(uint64_t n) { return (int)std::min<uint64_t>(SORT_MAX_BLOCKS, std::max<uint64_t>(1, n / 4096)); }
 
 // A group of views of one scene inside a launch sequence.
 struct Group {
@@ -371,7 +376,9 @@ struct Plan {
 
 // Enqueue the whole launch sequence for a plan on ws.stream.  Returns the
 // index of the sort buffer that holds the sorted lists.
-int enqueue(Workspace& ws, Plan& plan, bool carry_lo, bool prof, unsigned long long* work) {
+//   preprocess -> scan visible -> compact -> depth passes (visible Gaussians)
+//   -> duplicate in depth order -> tile passes (duplicates) -> ranges -> blend
+int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long* work) {
     hipStream_t st = ws.stream;
     if (prof) ws.ensure_events();
     auto mark = [&](int i) {
@@ -394,26 +401,42 @@ int enqueue(Workspace& ws, Plan& plan, bool carry_lo, bool prof, unsigned long l
     mark(1);
     const int nblk = (int)(plan.nrec / K1_THREADS);
     Counters* cnt = ws.counters.as<Counters>();
-    launch_scan_blocks(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, ws.totals.as<uint32_t>(),
-                       256 * MAX_SORT_PASSES, st);
+    launch_scan_visible(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, ws.totals.as<uint32_t>(),
+                        256 * MAX_SORT_PASSES, st);
     mark(2);
-    launch_duplicate(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, vdev, ws.lo[0].as<uint32_t>(),
-                     ws.hi[0].as<uint32_t>(), ws.val[0].as<uint32_t>(), st);
-    mark(3);
     SortBuffers sb;
     for (int i = 0; i < 2; ++i) {
-        sb.lo[i] = ws.lo[i].as<uint32_t>();
-        sb.hi[i] = ws.hi[i].as<uint32_t>();
+        sb.key[i] = ws.key[i].as<uint32_t>();
         sb.val[i] = ws.val[i].as<uint32_t>();
+        sb.ext[i] = ws.ext[i].as<uint32_t>();
     }
     sb.hist = ws.hist.as<uint32_t>();
     sb.totals = ws.totals.as<uint32_t>();
-    sb.nblocks = (int)std::min<uint64_t>(SORT_MAX_BLOCKS, std::max<uint64_t>(1, ws.dup_cap / 16384));
-    const std::vector<SortPass> passes = sort_passes(plan.n_tiles);
-    if ((int)passes.size() > MAX_SORT_PASSES) fail(TIGAS_E_INVALID, "too many tiles for the sort key");
-    const int cur = launch_sort(sb, passes.data(), (int)passes.size(), cnt, ws.dup_cap, carry_lo, st);
+    // depth digits, on the visible Gaussians (record order in, depth order out)
+    launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], st);
+    const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0, false, cnt, 0,
+                               st);
+    // duplicates in depth order
+    const int cd = cv ^ 1;
+    launch_duplicate(o, nblk, sb.val[cv], ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt, ws.dup_cap,
+                     vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
+    mark(3);
+    if (debug) {
+        const size_t bytes = (size_t)ws.dup_cap * 4;
+        ws.dbg_key.ensure(bytes);
+        ws.dbg_val.ensure(bytes);
+        ws.dbg_ext.ensure(bytes);
+        HIPCHK(hipMemcpyAsync(ws.dbg_key.p, sb.key[cd], bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(ws.dbg_val.p, sb.val[cd], bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(ws.dbg_ext.p, sb.ext[cd], bytes, hipMemcpyDeviceToDevice, st));
+    }
+    // tile digits, on the duplicates
+    const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
+    if ((int)tp.size() + 4 > MAX_SORT_PASSES) fail(TIGAS_E_INVALID, "too many tiles for the sort key");
+    const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap, sort_blocks(ws.dup_cap), cd,
+                                debug, cnt, 4, st);
     mark(4);
-    launch_ranges(sb.hi[cur], cnt, ws.dup_cap, plan.n_tiles, ws.ranges.as<uint2>(), st);
+    launch_ranges(sb.key[cur], cnt, ws.dup_cap, plan.n_tiles, ws.ranges.as<uint2>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
                  plan.tc.bd, work, st);
@@ -424,6 +447,8 @@ int enqueue(Workspace& ws, Plan& plan, bool carry_lo, bool prof, unsigned long l
 }
 
 uint32_t initial_dup_cap(const Plan& plan, uint32_t last_D) {
+    // never below the record count: the depth passes keep the visible
+    // Gaussians in the same buffers
     uint64_t est = std::max<uint64_t>((uint64_t)last_D + last_D / 4, (uint64_t)plan.nrec * 4);
     est = std::max<uint64_t>(est, 1u << 20);
     return (uint32_t)std::min<uint64_t>(est, 0xfff00000ull);
@@ -431,12 +456,12 @@ uint32_t initial_dup_cap(const Plan& plan, uint32_t last_D) {
 
 // Runs the plan to completion (synchronous), regrowing the duplicate buffers
 // when the first attempt overflowed.  Returns the final sort buffer index.
-int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* rerenders,
+int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool debug, int* rerenders,
              unsigned long long* work = nullptr) {
     ws.counters.ensure(sizeof(Counters));
-    ws.ensure_dups(std::max(ws.dup_cap, initial_dup_cap(plan, ws.last_D)));
+    ws.ensure_dups(std::max(ws.dup_cap, initial_dup_cap(plan, ws.last_D)), debug);
     const bool prof = ctx->profile.load();
-    int cur = enqueue(ws, plan, carry_lo, prof, work);
+    int cur = enqueue(ws, plan, debug, prof, work);
     HIPCHK(hipStreamSynchronize(ws.stream));
     Counters c;
     std::memcpy(&c, ws.host_counters.p, sizeof(c));
@@ -444,9 +469,9 @@ int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* 
     if (c.overflow) {
         const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
         if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
-        ws.ensure_dups((uint32_t)want);
+        ws.ensure_dups((uint32_t)want, debug);
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
-        cur = enqueue(ws, plan, carry_lo, prof, work);
+        cur = enqueue(ws, plan, debug, prof, work);
         HIPCHK(hipStreamSynchronize(ws.stream));
         std::memcpy(&c, ws.host_counters.p, sizeof(c));
         if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
@@ -467,7 +492,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool carry_lo, int* 
         ctx->last.duplicates = c.D;
         ctx->last.fallbacks = c.fallbacks;
         ctx->last.tiles = plan.n_tiles;
-        ctx->last.sort_passes = (int64_t)sort_passes(plan.n_tiles).size();
+        ctx->last.sort_passes = 4 + (int64_t)tile_passes(plan.n_tiles).size();
         ctx->last.rerenders = *rerenders;
         int64_t n = 0;
         for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
@@ -573,23 +598,18 @@ void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsi
             fail(TIGAS_E_BUFFER, "debug duplicate arrays smaller than D");
         std::vector<uint32_t> lo(c.D), hi(c.D);
         if (c.D && (dbg->keys || dbg->vals)) {
-            // the emission-order lists were consumed by the sort; rebuild them
-            // by re-running the duplicate kernel into the spare buffers
-            launch_duplicate(ws.pre(), (int)(plan.nrec / K1_THREADS), ws.blk_off.as<uint32_t>(),
-                             ws.counters.as<Counters>(), ws.dup_cap, ws.views.as<ViewParams>(),
-                             ws.lo[cur ^ 1].as<uint32_t>(), ws.hi[cur ^ 1].as<uint32_t>(),
-                             ws.val[cur ^ 1].as<uint32_t>(), st);
-            HIPCHK(hipMemcpyAsync(lo.data(), ws.lo[cur ^ 1].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(hi.data(), ws.hi[cur ^ 1].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            // entries as emitted (Gaussians in depth order), saved before the tile passes
+            HIPCHK(hipMemcpyAsync(hi.data(), ws.dbg_key.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(lo.data(), ws.dbg_ext.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
             if (dbg->vals)
-                HIPCHK(hipMemcpyAsync(dbg->vals, ws.val[cur ^ 1].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(dbg->vals, ws.dbg_val.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             if (dbg->keys)
                 for (uint32_t i = 0; i < c.D; ++i) dbg->keys[i] = ((uint64_t)hi[i] << 32) | lo[i];
         }
         if (c.D && (dbg->skeys || dbg->svals)) {
-            HIPCHK(hipMemcpyAsync(lo.data(), ws.lo[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(hi.data(), ws.hi[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hi.data(), ws.key[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(lo.data(), ws.ext[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
             if (dbg->svals)
                 HIPCHK(hipMemcpyAsync(dbg->svals, ws.val[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));

@@ -3,10 +3,14 @@
 //   k_preprocess   per Gaussian (x views): activation, 3D covariance, camera
 //                  transform, projection, EWA 2D covariance + conic (FP64
 //                  fallback when near-singular), SH colour, screen footprint
-//   k_scan_blocks  exclusive scan of per-block duplicate counts (wave64 DPP)
+//   k_scan_*       exclusive scans of per-block counts (wave64 DPP)
+//   k_compact      visible Gaussians as (depth key, record) pairs
+//   k_sort_*       LSD radix sort passes, 8-bit digits, reduce-then-scan,
+//                  ballot/mbcnt ranking inside a wave, DPP scans; the depth
+//                  digits of the (tile | depth) keys are sorted on the
+//                  visible Gaussians before duplication, the tile digits on
+//                  the duplicates after it
 //   k_duplicate    one (tile | depth) key per (Gaussian, overlapped tile)
-//   k_sort_*       LSD radix sort, 8-bit digits, reduce-then-scan per pass,
-//                  ballot/mbcnt ranking inside a wave, DPP scans
 //   k_ranges       [start, end) of every tile in the sorted list
 //   k_blend        front-to-back compositing, one wave64 per 8x8 pixel block,
 //                  Gaussians staged per wave in LDS, per-wave early exit
@@ -407,90 +411,180 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
     }
 }
 
-// --------------------------------------------------------- scan of blocks
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_blocks(const uint32_t* __restrict__ blk_sum,
-                                                              const uint32_t* __restrict__ blk_vis,
-                                                              const uint32_t* __restrict__ blk_fb, int nblk,
-                                                              uint32_t* __restrict__ blk_off, Counters* cnt,
-                                                              uint32_t cap, uint32_t* zero, int nzero) {
-    __shared__ uint32_t red[SCAN_THREADS / 64];
+// ------------------------------------------------------------- block scans
+// Exclusive scan of n per-block counts by one workgroup (wave64 DPP scans,
+// SCAN_ITEMS consecutive counts per thread); returns the 64-bit total.
+__device__ uint64_t scan_counts(const uint32_t* __restrict__ in, int n, uint32_t* __restrict__ out, uint32_t* red) {
     uint64_t running = 0;
-    uint32_t vis = 0, fb = 0;
-    for (int base = 0; base < nblk; base += SCAN_THREADS * SCAN_ITEMS) {
+    for (int base = 0; base < n; base += SCAN_THREADS * SCAN_ITEMS) {
         const int i0 = base + threadIdx.x * SCAN_ITEMS;
         uint32_t loc[SCAN_ITEMS];
-        uint32_t sum = 0, lv = 0, lf = 0;
+        uint32_t sum = 0;
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const int i = i0 + j;
-            const uint32_t x = i < nblk ? blk_sum[i] : 0u;
             loc[j] = sum;
-            sum += x;
-            lv += i < nblk ? blk_vis[i] : 0u;
-            lf += i < nblk ? blk_fb[i] : 0u;
+            sum += i < n ? in[i] : 0u;
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &tot);
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
             const int i = i0 + j;
-            if (i < nblk) blk_off[i] = (uint32_t)running + ex + loc[j];
+            if (i < n) out[i] = (uint32_t)running + ex + loc[j];
         }
         running += tot;
-        vis += block_sum<SCAN_THREADS>(lv, red);
-        fb += block_sum<SCAN_THREADS>(lf, red);
     }
+    return running;
+}
+
+__device__ uint64_t sum_counts(const uint32_t* __restrict__ in, int n, uint32_t* red) {
+    uint64_t s = 0;
+    for (int base = 0; base < n; base += SCAN_THREADS) {
+        const int i = base + threadIdx.x;
+        s += block_sum<SCAN_THREADS>(i < n ? in[i] : 0u, red);
+    }
+    return s;
+}
+
+// After preprocess: compaction offsets of the visible records, the totals
+// V, D and FP64-fallback count, the overflow flag; clears the digit totals of
+// the sort passes.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* __restrict__ blk_sum,
+                                                               const uint32_t* __restrict__ blk_vis,
+                                                               const uint32_t* __restrict__ blk_fb, int nblk,
+                                                               uint32_t* __restrict__ blk_off, Counters* cnt,
+                                                               uint32_t cap, uint32_t* zero, int nzero) {
+    __shared__ uint32_t red[SCAN_THREADS / 64];
+    const uint64_t V = scan_counts(blk_vis, nblk, blk_off, red);
+    const uint64_t D = sum_counts(blk_sum, nblk, red);
+    const uint64_t fb = sum_counts(blk_fb, nblk, red);
     if (threadIdx.x == 0) {
-        cnt->D = running > 0xffffffffull ? 0xffffffffu : (uint32_t)running;
-        cnt->visible = vis;
-        cnt->fallbacks = fb;
-        cnt->overflow = running > (uint64_t)cap ? 1u : 0u;
+        cnt->D = D > 0xffffffffull ? 0xffffffffu : (uint32_t)D;
+        cnt->visible = (uint32_t)V;
+        cnt->fallbacks = (uint32_t)fb;
+        cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
     }
     for (int i = threadIdx.x; i < nzero; i += SCAN_THREADS) zero[i] = 0u;
 }
 
-// ---------------------------------------------------------------- duplicate
+// Emission offsets: exclusive scan of the duplicate counts of the
+// depth-sorted visible Gaussians, per 256-element block.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_dups(const uint32_t* __restrict__ blk_sum, int nblk,
+                                                            uint32_t* __restrict__ blk_off) {
+    __shared__ uint32_t red[SCAN_THREADS / 64];
+    scan_counts(blk_sum, nblk, blk_off, red);
+}
 
-__global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ touched,
+// Visible records, in record order, as (depth key, record) pairs.
+__global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restrict__ touched,
+                                                        const uint32_t* __restrict__ zkey,
+                                                        const uint32_t* __restrict__ blk_off,
+                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    __shared__ uint32_t red[K1_THREADS / 64];
+    const uint32_t rec = blockIdx.x * K1_THREADS + threadIdx.x;
+    const bool vis = touched[rec] != 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<K1_THREADS>(vis ? 1u : 0u, red, &tot);
+    if (vis) {
+        const uint32_t pos = blk_off[blockIdx.x] + ex;
+        key[pos] = zkey[rec];
+        val[pos] = rec;
+    }
+}
+
+// Per 256 depth-sorted visible Gaussians: sum of their tile counts.
+__global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __restrict__ sorted_rec,
+                                                            const uint32_t* __restrict__ touched,
+                                                            const Counters* __restrict__ cnt,
+                                                            uint32_t* __restrict__ blk_sum) {
+    __shared__ uint32_t red[K1_THREADS / 64];
+    const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
+    const uint32_t V = cnt->visible;
+    const uint32_t t = i < V ? touched[sorted_rec[i]] : 0u;
+    const uint32_t s = block_sum<K1_THREADS>(t, red);
+    if (threadIdx.x == 0) blk_sum[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------- duplicate
+// One entry per (Gaussian, overlapped tile), Gaussians taken in depth order,
+// tiles row-major over the Gaussian's tile rectangle: tile word = global tile
+// id, value = record, and (when asked) the depth word, so that the entry's
+// 64-bit key is (tile id << 32) | depth bits.  Load-balanced: the threads of a
+// workgroup write consecutive entries of their 256 Gaussians' output range,
+// each finding its Gaussian by binary search over the LDS prefix sums.
+template <bool DEPTH>
+__global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ sorted_rec,
+                                                          const uint32_t* __restrict__ touched,
                                                           const uint2* __restrict__ bbox,
                                                           const uint32_t* __restrict__ zkey,
                                                           const uint32_t* __restrict__ blk_off,
                                                           const uint32_t* __restrict__ blk_view,
                                                           const Counters* __restrict__ cnt, uint32_t cap,
                                                           const ViewParams* __restrict__ views,
-                                                          uint32_t* __restrict__ lo, uint32_t* __restrict__ hi,
-                                                          uint32_t* __restrict__ val) {
+                                                          uint32_t* __restrict__ tile_out,
+                                                          uint32_t* __restrict__ val_out,
+                                                          uint32_t* __restrict__ depth_out) {
     __shared__ uint32_t red[K1_THREADS / 64];
-    const uint32_t rec = blockIdx.x * K1_THREADS + threadIdx.x;
-    const uint32_t t = touched[rec];
+    __shared__ uint32_t pre[K1_THREADS + 1];  // inclusive prefix of tile counts, pre[0] = 0
+    __shared__ uint32_t srec[K1_THREADS];
+    __shared__ uint32_t sx0[K1_THREADS], stx[K1_THREADS], snx[K1_THREADS], stb[K1_THREADS];
+    const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
+    const uint32_t V = cnt->visible;
+    uint32_t rec = 0, t = 0;
+    if (i < V) {
+        rec = sorted_rec[i];
+        t = touched[rec];
+    }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<K1_THREADS>(t, red, &tot);
-    if (cnt->overflow || t == 0) return;
-    const ViewParams& v = views[blk_view[blockIdx.x]];
-    uint32_t off = blk_off[blockIdx.x] + ex;
-    const uint2 b = bbox[rec];
-    const uint32_t z = zkey[rec];
-    const int tx0 = (int)(b.x & 0xffffu) / v.tile_w, ty0 = (int)(b.x >> 16) / v.tile_h;
-    const int tx1 = (int)(b.y & 0xffffu) / v.tile_w, ty1 = (int)(b.y >> 16) / v.tile_h;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        const uint32_t rowbase = v.tile_base + (uint32_t)(ty * v.tiles_x);
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            lo[off] = z;
-            hi[off] = rowbase + (uint32_t)tx;
-            val[off] = rec;
-            ++off;
+    if (cnt->overflow || tot == 0) return;  // uniform across the workgroup
+    pre[threadIdx.x + 1] = ex + t;
+    if (threadIdx.x == 0) pre[0] = 0;
+    srec[threadIdx.x] = rec;
+    if (t) {
+        const ViewParams& v = views[blk_view[rec / K1_THREADS]];
+        const uint2 b = bbox[rec];
+        const int tx0 = (int)(b.x & 0xffffu) / v.tile_w, ty0 = (int)(b.x >> 16) / v.tile_h;
+        const int tx1 = (int)(b.y & 0xffffu) / v.tile_w;
+        sx0[threadIdx.x] = (uint32_t)tx0;
+        snx[threadIdx.x] = (uint32_t)(tx1 - tx0 + 1);
+        stb[threadIdx.x] = v.tile_base;
+        // tiles_x of the view, packed with the first row
+        stx[threadIdx.x] = (uint32_t)ty0 | ((uint32_t)v.tiles_x << 16);
+    }
+    __syncthreads();
+    const uint32_t base = blk_off[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < tot; j += K1_THREADS) {
+        // owner: the last e with pre[e] <= j
+        uint32_t lo = 0, hi = K1_THREADS;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= j) lo = mid; else hi = mid;
         }
+        const uint32_t e = lo;
+        const uint32_t k = j - pre[e];
+        const uint32_t nx = snx[e];
+        const uint32_t ty = (stx[e] & 0xffffu) + k / nx, tx = sx0[e] + k % nx;
+        const uint32_t tiles_x = stx[e] >> 16;
+        const uint32_t r = srec[e];
+        tile_out[base + j] = stb[e] + ty * tiles_x + tx;
+        val_out[base + j] = r;
+        if (DEPTH) depth_out[base + j] = zkey[r];
     }
 }
 
 // ------------------------------------------------------------- radix sort
-// One pass sorts by an 8-bit (or narrower) digit of one key word, stably.
-// The D keys are split into nb contiguous segments, one per workgroup, of a
-// whole number of 2048-key chunks.  upsweep: digit histogram per segment;
-// scan: exclusive offsets over (digit, segment); downsweep: rank and scatter.
+// One pass sorts (key, value[, extra]) triples stably by an 8-bit (or
+// narrower) digit of the key.  The count comes from the device counters
+// (which = 0: duplicates D, 1: visible Gaussians V) and is split into nb
+// contiguous segments, one per workgroup, of a whole number of 2048-key
+// chunks.  upsweep: digit histogram per segment; scan: exclusive offsets over
+// (digit, segment); downsweep: rank (wave ballots + per-wave LDS counters)
+// and scatter.
 
-__device__ __forceinline__ uint32_t sort_count(const Counters* cnt, uint32_t cap) {
+__device__ __forceinline__ uint32_t sort_count(const Counters* cnt, int which, uint32_t cap) {
+    if (which == 1) return min(cnt->visible, cap);
     return cnt->overflow ? 0u : min(cnt->D, cap);
 }
 __device__ __forceinline__ void segment(uint32_t D, int nb, int b, uint32_t* beg, uint32_t* end) {
@@ -501,20 +595,32 @@ __device__ __forceinline__ void segment(uint32_t D, int nb, int b, uint32_t* beg
     *end = (uint32_t)min((uint64_t)D, s + per);
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* __restrict__ word,
-                                                               const Counters* __restrict__ cnt, uint32_t cap,
-                                                               int shift, int bits, uint32_t* __restrict__ hist,
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* __restrict__ keys,
+                                                               const Counters* __restrict__ cnt, int which,
+                                                               uint32_t cap, int shift, int bits,
+                                                               uint32_t* __restrict__ hist,
                                                                uint32_t* __restrict__ totals, int nb) {
     __shared__ uint32_t h[SORT_THREADS / 64][256];
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < 256 * (SORT_THREADS / 64); i += SORT_THREADS) (&h[0][0])[i] = 0u;
     __syncthreads();
     uint32_t beg, end;
-    segment(sort_count(cnt, cap), nb, blockIdx.x, &beg, &end);
+    segment(sort_count(cnt, which, cap), nb, blockIdx.x, &beg, &end);
     const uint32_t mask = (1u << bits) - 1u;
-    for (uint32_t i = beg + threadIdx.x; i < end; i += SORT_THREADS) {
-        const uint32_t d = (word[i] >> shift) & mask;
-        atomicAdd(&h[w][d], 1u);
+    const uint64_t lt = (threadIdx.x & 63) == 0 ? 0ull : (~0ull >> (64 - (threadIdx.x & 63)));
+    // each wave walks whole 64-key rows so that equal digits are counted once
+    // per row by their leading lane (ballot match) instead of one LDS atomic each
+    for (uint32_t row = beg + (uint32_t)w * 64; row < end; row += SORT_THREADS) {
+        const uint32_t i = row + (threadIdx.x & 63);
+        const bool ok = i < end;
+        const uint32_t d = ok ? (keys[i] >> shift) & mask : 0u;
+        uint64_t m = ballot(ok);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bl = ballot(bit);
+            m &= bit ? bl : ~bl;
+        }
+        if (ok && (m & lt) == 0) h[w][d] += (uint32_t)__builtin_popcountll(m);
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -548,41 +654,51 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
     }
 }
 
-template <bool CARRY_LO>
+// Chunks of 2048 keys are ranked (per-wave ballot match + per-wave digit
+// counters), staged in LDS in chunk-local digit order, and written out so that
+// consecutive threads store consecutive positions of each digit run.
+template <bool EXTRA>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
-    const uint32_t* __restrict__ slo, const uint32_t* __restrict__ shi, const uint32_t* __restrict__ sval,
-    uint32_t* __restrict__ dlo, uint32_t* __restrict__ dhi, uint32_t* __restrict__ dval,
-    const Counters* __restrict__ cnt, uint32_t cap, int word, int shift, int bits,
+    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
+    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext,
+    const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits,
     const uint32_t* __restrict__ hist, int nb) {
+    static_assert(SORT_THREADS == 256, "one thread per digit");
     constexpr int NW = SORT_THREADS / 64;
     constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t base[256];    // global position of the next key of each digit
+    __shared__ uint32_t lstart[256];  // chunk-local start of each digit
     __shared__ uint32_t wcnt[NW][256];
-    __shared__ uint32_t woff[NW][256];
+    __shared__ uint32_t red[NW];
+    __shared__ uint32_t lkey[SORT_CHUNK];
+    __shared__ uint32_t lval[SORT_CHUNK];
+    __shared__ uint32_t lext[EXTRA ? SORT_CHUNK : 1];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t beg, end;
-    const uint32_t D = sort_count(cnt, cap);
+    const uint32_t D = sort_count(cnt, which, cap);
     segment(D, nb, blockIdx.x, &beg, &end);
-    if (t < 256) base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + blockIdx.x] : 0u;
-    const uint32_t* kw = word ? shi : slo;
+    base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + blockIdx.x] : 0u;
     for (uint32_t chunk = beg; chunk < end; chunk += SORT_CHUNK) {
-        for (int i = t; i < NW * 256; i += SORT_THREADS) (&wcnt[0][0])[i] = 0u;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
         __syncthreads();
-        uint32_t dig[ROUNDS], rank[ROUNDS], elo[ROUNDS], ehi[ROUNDS], ev[ROUNDS];
+        uint32_t dig[ROUNDS], rank[ROUNDS], ek[ROUNDS], ev[ROUNDS], ee[ROUNDS];
         bool ok[ROUNDS];
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
             const uint32_t idx = chunk + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
             ok[r] = idx < end;
             uint32_t key = 0;
+            ev[r] = 0;
+            ee[r] = 0;
             if (ok[r]) {
-                key = kw[idx];
-                elo[r] = CARRY_LO ? slo[idx] : 0u;
-                ehi[r] = shi[idx];
+                key = skey[idx];
                 ev[r] = sval[idx];
+                if (EXTRA) ee[r] = sext[idx];
             }
+            ek[r] = key;
             const uint32_t d = (key >> shift) & mask;
             dig[r] = d;
             uint64_t m = ballot(ok[r]);
@@ -598,26 +714,43 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             if (ok[r] && prior == 0) wcnt[w][d] = cur + (uint32_t)__builtin_popcountll(m);
         }
         __syncthreads();
-        if (t < 256) {
-            uint32_t acc = base[t];
+        // digit t: chunk-local start, then per-wave local offsets
+        uint32_t c = 0;
 #pragma unroll
-            for (int j = 0; j < NW; ++j) {
-                woff[j][t] = acc;
-                acc += wcnt[j][t];
-            }
-            base[t] = acc;
+        for (int j = 0; j < NW; ++j) c += wcnt[j][t];
+        uint32_t tot;
+        const uint32_t ls = block_excl_scan<SORT_THREADS>(c, red, &tot);
+        lstart[t] = ls;
+        uint32_t acc = ls;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const uint32_t x = wcnt[j][t];
+            wcnt[j][t] = acc;
+            acc += x;
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
-            const uint32_t pos = woff[w][dig[r]] + rank[r];
-            if (ok[r] && pos < D) {
-                if (CARRY_LO) dlo[pos] = elo[r];
-                dhi[pos] = ehi[r];
-                dval[pos] = ev[r];
+            if (ok[r]) {
+                const uint32_t l = wcnt[w][dig[r]] + rank[r];
+                lkey[l] = ek[r];
+                lval[l] = ev[r];
+                if (EXTRA) lext[l] = ee[r];
             }
         }
         __syncthreads();
+        for (uint32_t l = (uint32_t)t; l < tot; l += SORT_THREADS) {
+            const uint32_t k = lkey[l];
+            const uint32_t d = (k >> shift) & mask;
+            const uint32_t pos = base[d] + (l - lstart[d]);
+            if (pos < D) {
+                dkey[pos] = k;
+                dval[pos] = lval[l];
+                if (EXTRA) dext[pos] = lext[l];
+            }
+        }
+        __syncthreads();
+        base[t] += c;
     }
 }
 
@@ -627,7 +760,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ hi,
                                                 uint32_t cap, uint32_t n_tiles, uint2* __restrict__ ranges) {
     const uint32_t tile = blockIdx.x * 256 + threadIdx.x;
     if (tile >= n_tiles) return;
-    const uint32_t D = sort_count(cnt, cap);
+    const uint32_t D = sort_count(cnt, 0, cap);
     // lower bounds of tile and tile + 1 in the sorted tile words
     uint32_t lo = 0, len = D;
     while (len > 0) {
@@ -827,41 +960,49 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
     else preprocess_deg<2>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
 }
 
-void launch_scan_blocks(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap, uint32_t* zero,
-                        int nzero, hipStream_t st) {
-    TIGAS_LAUNCH(k_scan_blocks, dim3(1), dim3(SCAN_THREADS), st, o.blk_sum, o.blk_vis, o.blk_fb, nblk, blk_off, cnt,
+void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap, uint32_t* zero,
+                         int nzero, hipStream_t st) {
+    TIGAS_LAUNCH(k_scan_visible, dim3(1), dim3(SCAN_THREADS), st, o.blk_sum, o.blk_vis, o.blk_fb, nblk, blk_off, cnt,
                  cap, zero, nzero);
 }
 
-void launch_duplicate(const PreOut& o, int nblk, const uint32_t* blk_off, const Counters* cnt, uint32_t cap,
-                      const ViewParams* views_dev, uint32_t* lo, uint32_t* hi, uint32_t* val, hipStream_t st) {
+void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_duplicate, dim3(nblk), dim3(K1_THREADS), st, o.touched, o.bbox, o.zkey, blk_off, o.blk_view, cnt,
-                 cap, views_dev, lo, hi, val);
+    TIGAS_LAUNCH(k_compact, dim3(nblk), dim3(K1_THREADS), st, o.touched, o.zkey, blk_off, key, val);
 }
 
-int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, const Counters* cnt, uint32_t cap,
-                bool carry_lo, hipStream_t st) {
-    int cur = 0;
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, uint32_t* blk_sum2, uint32_t* blk_off2,
+                      const Counters* cnt, uint32_t cap, const ViewParams* views_dev, uint32_t* tile_out,
+                      uint32_t* val_out, uint32_t* depth_out, hipStream_t st) {
+    if (nblk == 0) return;
+    TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, cnt, blk_sum2);
+    TIGAS_LAUNCH(k_scan_dups, dim3(1), dim3(SCAN_THREADS), st, blk_sum2, nblk, blk_off2);
+    if (depth_out)
+        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, o.bbox, o.zkey,
+                     blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+    else
+        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, o.bbox, o.zkey,
+                     blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+}
+
+int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
+                int start, bool extra, const Counters* cnt, int totals_base, hipStream_t st) {
+    int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
-        const uint32_t* word = ps.word ? b.hi[cur] : b.lo[cur];
-        uint32_t* totals = b.totals + p * 256;
-        TIGAS_LAUNCH(k_sort_upsweep, dim3(b.nblocks), dim3(SORT_THREADS), st, word, cnt, cap, ps.shift, ps.bits,
-                     b.hist, totals, b.nblocks);
+        uint32_t* totals = b.totals + (totals_base + p) * 256;
+        TIGAS_LAUNCH(k_sort_upsweep, dim3(nblocks), dim3(SORT_THREADS), st, (const uint32_t*)b.key[cur], cnt, which,
+                     cap, ps.shift, ps.bits, b.hist, totals, nblocks);
         const int ndig = 1 << ps.bits;
-        TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, totals, b.nblocks, ndig);
-        // the depth word is carried only while depth digits remain (or when asked)
-        bool need_lo = carry_lo;
-        for (int q = p + 1; q < npasses; ++q) need_lo = need_lo || passes[q].word == 0;
-        if (need_lo)
-            TIGAS_LAUNCH(k_sort_downsweep<true>, dim3(b.nblocks), dim3(SORT_THREADS), st, b.lo[cur], b.hi[cur],
-                         b.val[cur], b.lo[cur ^ 1], b.hi[cur ^ 1], b.val[cur ^ 1], cnt, cap, ps.word, ps.shift,
-                         ps.bits, (const uint32_t*)b.hist, b.nblocks);
+        TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, totals, nblocks, ndig);
+        if (extra)
+            TIGAS_LAUNCH(k_sort_downsweep<true>, dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],
+                         b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift,
+                         ps.bits, (const uint32_t*)b.hist, nblocks);
         else
-            TIGAS_LAUNCH(k_sort_downsweep<false>, dim3(b.nblocks), dim3(SORT_THREADS), st, b.lo[cur], b.hi[cur],
-                         b.val[cur], b.lo[cur ^ 1], b.hi[cur ^ 1], b.val[cur ^ 1], cnt, cap, ps.word, ps.shift,
-                         ps.bits, (const uint32_t*)b.hist, b.nblocks);
+            TIGAS_LAUNCH(k_sort_downsweep<false>, dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],
+                         b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift,
+                         ps.bits, (const uint32_t*)b.hist, nblocks);
         cur ^= 1;
     }
     return cur;

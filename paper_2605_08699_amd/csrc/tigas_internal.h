@@ -70,31 +70,33 @@ struct PreOut {
     uint32_t* blk_view; // per block: view index
 };
 
+// Double-buffered (key, value, extra) words of a radix sort.
 struct SortBuffers {
-    uint32_t* lo[2];   // depth words
-    uint32_t* hi[2];   // tile words
-    uint32_t* val[2];  // record indices
+    uint32_t* key[2];
+    uint32_t* val[2];
+    uint32_t* ext[2];
     uint32_t* hist;    // [256][nblocks]
     uint32_t* totals;  // [MAX_SORT_PASSES][256]
-    int nblocks;
 };
 
 struct SortPass {
-    int word;   // 0 depth (lo) word, 1 tile (hi) word
     int shift;
-    int bits;   // <= 8
+    int bits;  // <= 8
 };
 
 // ---- launchers (kernels.hip) ----
 void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
                        uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
-void launch_scan_blocks(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
-                        uint32_t* zero, int nzero, hipStream_t st);
-void launch_duplicate(const PreOut& o, int nblk, const uint32_t* blk_off, const Counters* cnt, uint32_t cap,
-                      const ViewParams* views_dev, uint32_t* lo, uint32_t* hi, uint32_t* val, hipStream_t st);
-// Runs the passes; returns the index (0/1) of the buffer holding the result.
-int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, const Counters* cnt, uint32_t cap,
-                bool carry_lo, hipStream_t st);
+void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap, uint32_t* zero,
+                         int nzero, hipStream_t st);
+void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st);
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, uint32_t* blk_sum2, uint32_t* blk_off2,
+                      const Counters* cnt, uint32_t cap, const ViewParams* views_dev, uint32_t* tile_out,
+                      uint32_t* val_out, uint32_t* depth_out, hipStream_t st);
+// Runs LSD passes over the count selected by `which` (0 duplicates, 1 visible)
+// starting in buffer `start`; returns the buffer index holding the result.
+int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
+                int start, bool extra, const Counters* cnt, int totals_base, hipStream_t st);
 void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap, uint32_t n_tiles, uint2* ranges,
                    hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,

@@ -53,3 +53,35 @@ def test_empty_input():
     keys, vals = tiles.duplicates(rects, counts, np.zeros(0, np.uint32), 4)
     sk, sv, rg = tiles.sort_and_ranges(keys, vals, 12)
     assert keys.size == 0 and np.all(rg == 0)
+
+
+def test_depth_digits_first_gives_the_same_sorted_list():
+    # LSD radix sorting the (tile | depth) keys: sorting the depth digits on one
+    # representative per Gaussian before duplicating gives the identical list
+    rng = np.random.default_rng(3)
+    for trial in range(30):
+        n = 60
+        x0 = rng.integers(0, 50, n)
+        y0 = rng.integers(0, 40, n)
+        bbox = np.stack([x0, y0, x0 + rng.integers(-1, 30, n), y0 + rng.integers(-1, 30, n)], 1)
+        zbits = rng.integers(0x3e000000, 0x3e000008, n).astype(np.uint32)
+        rects, counts = tiles.tile_rects(bbox, 8, 8)
+        keys, vals = tiles.duplicates(rects, counts, zbits, 10)
+        ref = tiles.sort_and_ranges(keys, vals, 100)
+        # depth-first: stable order of Gaussians by depth, then their tiles
+        g_order = np.argsort(zbits, kind="stable")
+        k2 = []
+        v2 = []
+        for g in g_order:
+            sel = vals == g
+            k2.append(keys[sel])
+            v2.append(vals[sel])
+        k2 = np.concatenate(k2) if k2 else keys
+        v2 = np.concatenate(v2) if v2 else vals
+        ek, ev = tiles.depth_first_emission(keys, vals)
+        np.testing.assert_array_equal(ek, k2)
+        np.testing.assert_array_equal(ev, v2)
+        # tile-only stable sort of the depth-first list == full key sort
+        o = np.argsort(ek >> np.uint64(32), kind="stable")
+        np.testing.assert_array_equal(ek[o], ref[0])
+        np.testing.assert_array_equal(ev[o], ref[1])
