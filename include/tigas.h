@@ -192,7 +192,7 @@ const char* tigas_last_error(void);
  *   zkey     [n] u32 FP32 depth-key bits;  touched [n] u32 tiles overlapped
  *   keys     [cap_dup] u64 duplicate keys in emission order, vals [cap_dup] u32
  *   skeys    [cap_dup] u64 sorted keys, svals [cap_dup] u32 sorted values
- *   ranges   [tiles][2] u32 [start, end) per tile
+ *   ranges   [tiles][2] u32 [start, end) per tile, (0, 0) for an empty tile
  * *n_dup receives D; arrays sized below D are not written (E_BUFFER).
  * ------------------------------------------------------------------------- */
 typedef struct {

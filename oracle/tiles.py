@@ -46,7 +46,8 @@ def duplicates(rects, counts, zbits, tiles_x: int):
 
 
 def sort_and_ranges(keys, vals, n_tiles: int):
-    """Stable sort by key; per-tile [start, end) ranges of the sorted list."""
+    """Stable sort by key; per-tile [start, end) ranges of the sorted list
+    ((0, 0) for a tile without entries)."""
     order = np.argsort(keys, kind="stable")
     sk = keys[order]
     sv = vals[order]
@@ -54,6 +55,7 @@ def sort_and_ranges(keys, vals, n_tiles: int):
     t = np.arange(n_tiles + 1, dtype=np.int64)
     bounds = np.searchsorted(tiles, t, side="left")
     ranges = np.stack([bounds[:-1], bounds[1:]], 1).astype(np.uint32)
+    ranges[ranges[:, 0] == ranges[:, 1]] = 0
     return sk, sv, ranges
 
 

@@ -202,12 +202,13 @@ struct Workspace {
         rec_cap = (uint32_t)r;
     }
     void ensure_dups(uint32_t cap, bool extra) {
-        if (cap <= dup_cap && key[0].p && (!extra || ext[0].p)) return;
+        (void)extra;
+        if (cap <= dup_cap && key[0].p) return;
         cap = std::max<uint32_t>(std::max(cap, dup_cap), 1u << 16);
         for (int i = 0; i < 2; ++i) {
             key[i].ensure((size_t)cap * 4);
             val[i].ensure((size_t)cap * 4);
-            if (extra) ext[i].ensure((size_t)cap * 4);
+            ext[i].ensure((size_t)cap * 4);
         }
         hist.ensure((size_t)256 * SORT_MAX_BLOCKS * 4);
         totals.ensure((size_t)256 * MAX_SORT_PASSES * 4);
@@ -401,8 +402,16 @@ int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long
     mark(1);
     const int nblk = (int)(plan.nrec / K1_THREADS);
     Counters* cnt = ws.counters.as<Counters>();
-    launch_scan_visible(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, ws.totals.as<uint32_t>(),
-                        256 * MAX_SORT_PASSES, st);
+    ZeroList zl{};
+    zl.p[0] = ws.totals.as<uint32_t>();
+    zl.n[0] = 256 * MAX_SORT_PASSES;
+    zl.p[1] = ws.blk_sum2.as<uint32_t>();
+    zl.n[1] = (uint32_t)nblk;
+    zl.p[2] = ws.ranges.as<uint32_t>();
+    zl.n[2] = 2 * plan.n_tiles;
+    zl.p[3] = nullptr;
+    zl.n[3] = 0;
+    launch_scan_visible(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, zl, st);
     mark(2);
     SortBuffers sb;
     for (int i = 0; i < 2; ++i) {
@@ -415,11 +424,11 @@ int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long
     // depth digits, on the visible Gaussians (record order in, depth order out)
     launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], st);
     const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0, false, cnt, 0,
-                               st);
+                               o.touched, nullptr, st);
     // duplicates in depth order
     const int cd = cv ^ 1;
-    launch_duplicate(o, nblk, sb.val[cv], ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt, ws.dup_cap,
-                     vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
+    launch_duplicate(o, nblk, sb.val[cv], sb.ext[cv], ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
+                     ws.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
     mark(3);
     if (debug) {
         const size_t bytes = (size_t)ws.dup_cap * 4;
@@ -434,9 +443,9 @@ int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long
     const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
     if ((int)tp.size() + 4 > MAX_SORT_PASSES) fail(TIGAS_E_INVALID, "too many tiles for the sort key");
     const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap, sort_blocks(ws.dup_cap), cd,
-                                debug, cnt, 4, st);
+                                debug, cnt, 4, nullptr, nullptr, st);
     mark(4);
-    launch_ranges(sb.key[cur], cnt, ws.dup_cap, plan.n_tiles, ws.ranges.as<uint2>(), st);
+    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
                  plan.tc.bd, work, st);

@@ -438,34 +438,63 @@ __device__ uint64_t scan_counts(const uint32_t* __restrict__ in, int n, uint32_t
     return running;
 }
 
-__device__ uint64_t sum_counts(const uint32_t* __restrict__ in, int n, uint32_t* red) {
-    uint64_t s = 0;
-    for (int base = 0; base < n; base += SCAN_THREADS) {
-        const int i = base + threadIdx.x;
-        s += block_sum<SCAN_THREADS>(i < n ? in[i] : 0u, red);
-    }
-    return s;
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, unsigned long long* lds) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += lds[i];
+    __syncthreads();
+    return t;
 }
 
 // After preprocess: compaction offsets of the visible records, the totals
-// V, D and FP64-fallback count, the overflow flag; clears the digit totals of
-// the sort passes.
+// V, D and FP64-fallback count, the overflow flag; clears the per-frame
+// accumulators of later kernels (digit totals, per-block duplicate sums,
+// tile ranges).
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* __restrict__ blk_sum,
                                                                const uint32_t* __restrict__ blk_vis,
                                                                const uint32_t* __restrict__ blk_fb, int nblk,
                                                                uint32_t* __restrict__ blk_off, Counters* cnt,
-                                                               uint32_t cap, uint32_t* zero, int nzero) {
+                                                               uint32_t cap, ZeroList zl) {
     __shared__ uint32_t red[SCAN_THREADS / 64];
-    const uint64_t V = scan_counts(blk_vis, nblk, blk_off, red);
-    const uint64_t D = sum_counts(blk_sum, nblk, red);
-    const uint64_t fb = sum_counts(blk_fb, nblk, red);
+    __shared__ unsigned long long red64[SCAN_THREADS / 64];
+    uint64_t running = 0, dsum = 0, fsum = 0;
+    for (int base = 0; base < nblk; base += SCAN_THREADS * SCAN_ITEMS) {
+        const int i0 = base + threadIdx.x * SCAN_ITEMS;
+        uint32_t loc[SCAN_ITEMS];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const int i = i0 + j;
+            loc[j] = sum;
+            if (i < nblk) {
+                sum += blk_vis[i];
+                dsum += blk_sum[i];
+                fsum += blk_fb[i];
+            }
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &tot);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            const int i = i0 + j;
+            if (i < nblk) blk_off[i] = (uint32_t)running + ex + loc[j];
+        }
+        running += tot;
+    }
+    const uint64_t D = block_sum_u64(dsum, red64);
+    const uint64_t fb = block_sum_u64(fsum, red64);
     if (threadIdx.x == 0) {
         cnt->D = D > 0xffffffffull ? 0xffffffffu : (uint32_t)D;
-        cnt->visible = (uint32_t)V;
+        cnt->visible = (uint32_t)running;
         cnt->fallbacks = (uint32_t)fb;
         cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
     }
-    for (int i = threadIdx.x; i < nzero; i += SCAN_THREADS) zero[i] = 0u;
+#pragma unroll
+    for (int k = 0; k < ZeroList::N; ++k)
+        for (uint32_t i = threadIdx.x; i < zl.n[k]; i += SCAN_THREADS) zl.p[k][i] = 0u;
 }
 
 // Emission offsets: exclusive scan of the duplicate counts of the
@@ -493,16 +522,18 @@ __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restri
     }
 }
 
-// Per 256 depth-sorted visible Gaussians: sum of their tile counts.
-__global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __restrict__ sorted_rec,
-                                                            const uint32_t* __restrict__ touched,
+// Per 256 depth-sorted visible Gaussians: the sum of their tile counts.
+__global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __restrict__ sorted_touched,
                                                             const Counters* __restrict__ cnt,
                                                             uint32_t* __restrict__ blk_sum) {
     __shared__ uint32_t red[K1_THREADS / 64];
     const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
     const uint32_t V = cnt->visible;
-    const uint32_t t = i < V ? touched[sorted_rec[i]] : 0u;
-    const uint32_t s = block_sum<K1_THREADS>(t, red);
+    if (blockIdx.x * K1_THREADS >= V) {  // uniform: empty block
+        if (threadIdx.x == 0) blk_sum[blockIdx.x] = 0u;
+        return;
+    }
+    const uint32_t s = block_sum<K1_THREADS>(i < V ? sorted_touched[i] : 0u, red);
     if (threadIdx.x == 0) blk_sum[blockIdx.x] = s;
 }
 
@@ -529,6 +560,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     __shared__ uint32_t pre[K1_THREADS + 1];  // inclusive prefix of tile counts, pre[0] = 0
     __shared__ uint32_t srec[K1_THREADS];
     __shared__ uint32_t sx0[K1_THREADS], stx[K1_THREADS], snx[K1_THREADS], stb[K1_THREADS];
+    __shared__ float sinx[K1_THREADS];
     const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
     const uint32_t V = cnt->visible;
     uint32_t rec = 0, t = 0;
@@ -549,6 +581,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
         const int tx1 = (int)(b.y & 0xffffu) / v.tile_w;
         sx0[threadIdx.x] = (uint32_t)tx0;
         snx[threadIdx.x] = (uint32_t)(tx1 - tx0 + 1);
+        sinx[threadIdx.x] = 1.0f / (float)(tx1 - tx0 + 1);
         stb[threadIdx.x] = v.tile_base;
         // tiles_x of the view, packed with the first row
         stx[threadIdx.x] = (uint32_t)ty0 | ((uint32_t)v.tiles_x << 16);
@@ -565,7 +598,11 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
         const uint32_t e = lo;
         const uint32_t k = j - pre[e];
         const uint32_t nx = snx[e];
-        const uint32_t ty = (stx[e] & 0xffffu) + k / nx, tx = sx0[e] + k % nx;
+        // k / nx through the FP32 reciprocal, corrected to the exact quotient
+        uint32_t q = (uint32_t)((float)k * sinx[e]);
+        if (q * nx > k) --q;
+        if ((q + 1) * nx <= k) ++q;
+        const uint32_t ty = (stx[e] & 0xffffu) + q, tx = sx0[e] + (k - q * nx);
         const uint32_t tiles_x = stx[e] >> 16;
         const uint32_t r = srec[e];
         tile_out[base + j] = stb[e] + ty * tiles_x + tx;
@@ -608,19 +645,29 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     segment(sort_count(cnt, which, cap), nb, blockIdx.x, &beg, &end);
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = (threadIdx.x & 63) == 0 ? 0ull : (~0ull >> (64 - (threadIdx.x & 63)));
-    // each wave walks whole 64-key rows so that equal digits are counted once
-    // per row by their leading lane (ballot match) instead of one LDS atomic each
-    for (uint32_t row = beg + (uint32_t)w * 64; row < end; row += SORT_THREADS) {
-        const uint32_t i = row + (threadIdx.x & 63);
-        const bool ok = i < end;
-        const uint32_t d = ok ? (keys[i] >> shift) & mask : 0u;
-        uint64_t m = ballot(ok);
-        for (int b = 0; b < bits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bl = ballot(bit);
-            m &= bit ? bl : ~bl;
+    // each wave walks blocks of 8 rows of 64 keys (8 loads in flight per
+    // lane); equal digits of a row are counted once by their leading lane
+    // (ballot match) instead of one LDS atomic per key
+    constexpr int U = 8;
+    for (uint32_t blk = beg + (uint32_t)w * 64 * U; blk < end; blk += SORT_THREADS * U) {
+        uint32_t kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = blk + u * 64 + (threadIdx.x & 63);
+            kk[u] = keys[i < end ? i : beg];
         }
-        if (ok && (m & lt) == 0) h[w][d] += (uint32_t)__builtin_popcountll(m);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = blk + u * 64 + (threadIdx.x & 63) < end;
+            const uint32_t d = (kk[u] >> shift) & mask;
+            uint64_t m = ballot(ok);
+            for (int b = 0; b < bits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bl = ballot(bit);
+                m &= bit ? bl : ~bl;
+            }
+            if (ok && (m & lt) == 0) h[w][d] += (uint32_t)__builtin_popcountll(m);
+        }
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -645,11 +692,19 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
     for (int j = lane; j < d; j += 64) part += totals[j];
     uint32_t running = wave_sum(part);
     uint32_t* row = hist + (size_t)d * nb;
-    for (int j0 = 0; j0 < nb; j0 += 64) {
-        const int j = j0 + lane;
-        const uint32_t x = j < nb ? row[j] : 0u;
-        const uint32_t inc = wave_incl_scan(x);
-        if (j < nb) row[j] = running + inc - x;
+    constexpr int NJ = SORT_MAX_BLOCKS / 64;
+    uint32_t x[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const int j = q * 64 + lane;
+        x[q] = j < nb ? row[j] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        if (q * 64 >= nb) break;
+        const int j = q * 64 + lane;
+        const uint32_t inc = wave_incl_scan(x[q]);
+        if (j < nb) row[j] = running + inc - x[q];
         running += readlane(inc, 63);
     }
 }
@@ -657,12 +712,16 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
 // Chunks of 2048 keys are ranked (per-wave ballot match + per-wave digit
 // counters), staged in LDS in chunk-local digit order, and written out so that
 // consecutive threads store consecutive positions of each digit run.
-template <bool EXTRA>
+// SUMS (last depth pass): the extra output word is the tile count of each
+// Gaussian (gathered once here), so the emission offsets of k_duplicate can be
+// summed from a contiguous array.
+template <bool EXTRA, bool SUMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext,
     const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits,
-    const uint32_t* __restrict__ hist, int nb) {
+    const uint32_t* __restrict__ hist, int nb, const uint32_t* __restrict__ touched,
+    uint32_t* __restrict__ blk_sum) {
     static_assert(SORT_THREADS == 256, "one thread per digit");
     constexpr int NW = SORT_THREADS / 64;
     constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
@@ -672,7 +731,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     __shared__ uint32_t red[NW];
     __shared__ uint32_t lkey[SORT_CHUNK];
     __shared__ uint32_t lval[SORT_CHUNK];
-    __shared__ uint32_t lext[EXTRA ? SORT_CHUNK : 1];
+    __shared__ uint32_t lext[(EXTRA || SUMS) ? SORT_CHUNK : 1];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -690,14 +749,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
         for (int r = 0; r < ROUNDS; ++r) {
             const uint32_t idx = chunk + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
             ok[r] = idx < end;
-            uint32_t key = 0;
-            ev[r] = 0;
-            ee[r] = 0;
-            if (ok[r]) {
-                key = skey[idx];
-                ev[r] = sval[idx];
-                if (EXTRA) ee[r] = sext[idx];
-            }
+            const uint32_t ic = ok[r] ? idx : chunk;  // clamped: loads never depend on a branch
+            const uint32_t key = skey[ic];
+            ev[r] = sval[ic];
+            ee[r] = EXTRA ? sext[ic] : (SUMS ? touched[ev[r]] : 0u);
             ek[r] = key;
             const uint32_t d = (key >> shift) & mask;
             dig[r] = d;
@@ -735,7 +790,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
                 const uint32_t l = wcnt[w][dig[r]] + rank[r];
                 lkey[l] = ek[r];
                 lval[l] = ev[r];
-                if (EXTRA) lext[l] = ee[r];
+                if (EXTRA || SUMS) lext[l] = ee[r];
             }
         }
         __syncthreads();
@@ -744,9 +799,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             const uint32_t d = (k >> shift) & mask;
             const uint32_t pos = base[d] + (l - lstart[d]);
             if (pos < D) {
+                const uint32_t vv = lval[l];
                 dkey[pos] = k;
-                dval[pos] = lval[l];
-                if (EXTRA) dext[pos] = lext[l];
+                dval[pos] = vv;
+                if (EXTRA || SUMS) dext[pos] = lext[l];
             }
         }
         __syncthreads();
@@ -756,33 +812,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
 
 // ------------------------------------------------------------------ ranges
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ hi, const Counters* __restrict__ cnt,
-                                                uint32_t cap, uint32_t n_tiles, uint2* __restrict__ ranges) {
-    const uint32_t tile = blockIdx.x * 256 + threadIdx.x;
-    if (tile >= n_tiles) return;
+// Tile boundaries in the sorted tile words; the ranges array was cleared by
+// k_scan_visible, so tiles without entries stay [0, 0).
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tile, const Counters* __restrict__ cnt,
+                                                uint32_t cap, uint2* __restrict__ ranges) {
     const uint32_t D = sort_count(cnt, 0, cap);
-    // lower bounds of tile and tile + 1 in the sorted tile words
-    uint32_t lo = 0, len = D;
-    while (len > 0) {
-        const uint32_t half = len >> 1;
-        if (hi[lo + half] < tile) {
-            lo += half + 1;
-            len -= half + 1;
-        } else {
-            len = half;
-        }
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < D; i += gridDim.x * 256) {
+        const uint32_t t = tile[i];
+        if (i == 0 || tile[i - 1] != t) ranges[t].x = i;
+        if (i + 1 == D || tile[i + 1] != t) ranges[t].y = i + 1;
     }
-    uint32_t e = lo, len2 = D - lo;
-    while (len2 > 0) {
-        const uint32_t half = len2 >> 1;
-        if (hi[e + half] <= tile) {
-            e += half + 1;
-            len2 -= half + 1;
-        } else {
-            len2 = half;
-        }
-    }
-    ranges[tile] = make_uint2(lo, e);
 }
 
 // ------------------------------------------------------------------- blend
@@ -960,10 +999,10 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
     else preprocess_deg<2>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
 }
 
-void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap, uint32_t* zero,
-                         int nzero, hipStream_t st) {
+void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
+                         const ZeroList& zl, hipStream_t st) {
     TIGAS_LAUNCH(k_scan_visible, dim3(1), dim3(SCAN_THREADS), st, o.blk_sum, o.blk_vis, o.blk_fb, nblk, blk_off, cnt,
-                 cap, zero, nzero);
+                 cap, zl);
 }
 
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st) {
@@ -971,22 +1010,24 @@ void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t
     TIGAS_LAUNCH(k_compact, dim3(nblk), dim3(K1_THREADS), st, o.touched, o.zkey, blk_off, key, val);
 }
 
-void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, uint32_t* blk_sum2, uint32_t* blk_off2,
-                      const Counters* cnt, uint32_t cap, const ViewParams* views_dev, uint32_t* tile_out,
-                      uint32_t* val_out, uint32_t* depth_out, hipStream_t st) {
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint32_t* sorted_touched,
+                      uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
+                      const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
+                      hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, cnt, blk_sum2);
+    TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_touched, cnt, blk_sum2);
     TIGAS_LAUNCH(k_scan_dups, dim3(1), dim3(SCAN_THREADS), st, blk_sum2, nblk, blk_off2);
     if (depth_out)
         TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, o.bbox, o.zkey,
-                     blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+                     (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
         TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, o.bbox, o.zkey,
-                     blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+                     (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
 }
 
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, int totals_base, hipStream_t st) {
+                int start, bool extra, const Counters* cnt, int totals_base, const uint32_t* touched,
+                uint32_t* blk_sum, hipStream_t st) {
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
@@ -995,23 +1036,23 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
                      cap, ps.shift, ps.bits, b.hist, totals, nblocks);
         const int ndig = 1 << ps.bits;
         TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, totals, nblocks, ndig);
-        if (extra)
-            TIGAS_LAUNCH(k_sort_downsweep<true>, dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],
-                         b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift,
-                         ps.bits, (const uint32_t*)b.hist, nblocks);
-        else
-            TIGAS_LAUNCH(k_sort_downsweep<false>, dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],
-                         b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift,
-                         ps.bits, (const uint32_t*)b.hist, nblocks);
+        const bool sums = touched && p + 1 == npasses;
+#define TIGAS_DOWN(E, S)                                                                                        \
+    TIGAS_LAUNCH((k_sort_downsweep<E, S>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],      \
+                 b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits, \
+                 (const uint32_t*)b.hist, nblocks, touched, blk_sum)
+        if (extra && sums) TIGAS_DOWN(true, true);
+        else if (extra) TIGAS_DOWN(true, false);
+        else if (sums) TIGAS_DOWN(false, true);
+        else TIGAS_DOWN(false, false);
+#undef TIGAS_DOWN
         cur ^= 1;
     }
     return cur;
 }
 
-void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap, uint32_t n_tiles, uint2* ranges,
-                   hipStream_t st) {
-    if (n_tiles == 0) return;
-    TIGAS_LAUNCH(k_ranges, dim3((n_tiles + 255) / 256), dim3(256), st, hi_sorted, cnt, cap, n_tiles, ranges);
+void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st) {
+    TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges);
 }
 
 template <int TW, int TH, bool C>

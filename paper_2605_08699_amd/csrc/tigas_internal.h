@@ -79,6 +79,13 @@ struct SortBuffers {
     uint32_t* totals;  // [MAX_SORT_PASSES][256]
 };
 
+// Arrays cleared (as u32 words) by the first kernel after preprocess.
+struct ZeroList {
+    static constexpr int N = 4;
+    uint32_t* p[N];
+    uint32_t n[N];
+};
+
 struct SortPass {
     int shift;
     int bits;  // <= 8
@@ -87,18 +94,20 @@ struct SortPass {
 // ---- launchers (kernels.hip) ----
 void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
                        uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
-void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap, uint32_t* zero,
-                         int nzero, hipStream_t st);
+void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
+                         const ZeroList& zl, hipStream_t st);
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st);
-void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, uint32_t* blk_sum2, uint32_t* blk_off2,
-                      const Counters* cnt, uint32_t cap, const ViewParams* views_dev, uint32_t* tile_out,
-                      uint32_t* val_out, uint32_t* depth_out, hipStream_t st);
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint32_t* sorted_touched,
+                      uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
+                      const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
+                      hipStream_t st);
 // Runs LSD passes over the count selected by `which` (0 duplicates, 1 visible)
 // starting in buffer `start`; returns the buffer index holding the result.
+// With `touched`, the last pass also writes touched[value] as the extra word.
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, int totals_base, hipStream_t st);
-void launch_ranges(const uint32_t* hi_sorted, const Counters* cnt, uint32_t cap, uint32_t n_tiles, uint2* ranges,
-                   hipStream_t st);
+                int start, bool extra, const Counters* cnt, int totals_base, const uint32_t* touched,
+                uint32_t* blk_sum, hipStream_t st);
+void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
                   unsigned long long* work, hipStream_t st);
