@@ -98,8 +98,8 @@ typedef struct {
     int sh_degree;    /* < 0 or > scene degree: the scene's degree */
     tigas_format fmt;
     float bg[3];
-    int tile_w, tile_h; /* 8x8, 16x16, 16x32 or 32x16; 0 = autotuned/default */
-    int batch_depth;    /* Gaussians staged per wavefront batch: 64, 128 or 256; 0 = default */
+    int tile_w, tile_h; /* 8x8, 16x16, 16x32 or 32x16; 0x0 = autotuned for the workload's shape */
+    int batch_depth;    /* Gaussians staged per wavefront batch: 64, 128 or 256; 0 = autotuned (64 with an explicit tile) */
 } tigas_quality;
 
 /* Output frame.  data: device pointer when is_device, host otherwise;
@@ -120,10 +120,12 @@ typedef struct {
     int64_t tiles;
     int64_t sort_passes;
     int64_t rerenders;  /* workspace regrowths after an overflowing first attempt */
+    int32_t tile_w, tile_h, batch_depth; /* configuration used (requested or autotuned) */
 } tigas_stats;
 
 /* Creates a context on HIP device `device`: a stream, workspaces and the
- * tuning cache.  *out is owned by the caller; free with tigas_context_destroy. */
+ * tuning cache (the autotuner's choices per workload shape; persisted in the
+ * file named by the environment variable TIGAS_TUNE_CACHE when set).  *out is owned by the caller; free with tigas_context_destroy. */
 tigas_status tigas_context_create(int device, tigas_context** out);
 void tigas_context_destroy(tigas_context* ctx);
 
@@ -159,7 +161,8 @@ tigas_status tigas_last_stats(tigas_context* ctx, tigas_stats* out);
 
 /* Stage timing with HIP events recorded on the rendering stream around each
  * stage of every render on this context (preprocess, block scan, duplicate,
- * radix sort, tile ranges, blend).  tigas_profile_stages switches it on or
+ * radix sort, tile ranges, blend); while it is on, launch sequences run
+ * uncaptured (events between the launches).  tigas_profile_stages switches it on or
  * off and resets the accumulated milliseconds; tigas_stage_times reads them
  * (sums over `frames` renders). */
 typedef struct {
@@ -168,6 +171,10 @@ typedef struct {
 } tigas_stage_ms;
 
 tigas_status tigas_profile_stages(tigas_context* ctx, int enable);
+/* Launch sequences are captured into HIP graphs per workload shape and
+ * replayed (default on; environment TIGAS_GRAPHS=0 turns it off at context
+ * creation).  This switches it for the context. */
+tigas_status tigas_set_graphs(tigas_context* ctx, int enable);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 
 /* Renders like tigas_render with a blend kernel that also counts the work it

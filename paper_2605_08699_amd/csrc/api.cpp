@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -69,14 +71,16 @@ struct DevBuf {
     ~DevBuf() {
         if (p) (void)hipFree(p);
     }
-    void ensure(size_t need) {
-        if (need <= bytes) return;
+    // returns true when the buffer was (re)allocated
+    bool ensure(size_t need) {
+        if (need <= bytes) return false;
         if (p) HIPCHK(hipFree(p));
         p = nullptr;
         bytes = 0;
         size_t want = std::max<size_t>(need, 256);
         HIPCHK(hipMalloc(&p, want));
         bytes = want;
+        return true;
     }
     template <typename T>
     T* as() const {
@@ -146,27 +150,62 @@ uint16_t f32_to_f16(float f) {
 
 // ------------------------------------------------------------- objects
 
+namespace {
+
+struct TileCfg {
+    int tw, th, bd;
+    bool operator==(const TileCfg& o) const { return tw == o.tw && th == o.th && bd == o.bd; }
+};
+
+const TileCfg kTileCandidates[] = {{8, 8, 64},    {8, 8, 128},    {8, 8, 256},    {16, 16, 64}, {16, 16, 128},
+                                   {16, 16, 256}, {16, 32, 64},   {16, 32, 128},  {16, 32, 256}};
+
+// A group of views of one scene inside a launch sequence.
+struct Group {
+    tigas_scene* scene;
+    int first_view, nviews;
+    uint32_t rec_base, n_pad;
+};
+
+struct Plan {
+    std::vector<ViewParams> views;
+    std::vector<Group> groups;
+    uint32_t nrec = 0, n_tiles = 0;
+    TileCfg tc{16, 16, 64};
+    bool persistent = false;  // blend as a persistent kernel over a tile work queue
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = 0;
+    int cur = 0;
+};
+
+}  // namespace
+
 struct Workspace {
     hipStream_t stream = nullptr;
+    std::mutex mu;  // one launch sequence at a time per workspace
     // per record
     DevBuf rec0, rec1, rec2, bbox, zkey, touched;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf counters;
-    // per duplicate (also holds the visible Gaussians for the depth passes)
+    // per duplicate (also holds the visible Gaussians during the depth passes)
     DevBuf key[2], val[2], ext[2];
-    DevBuf hist, totals;
+    DevBuf hist, totals, queue;
     // emission-order copies for the inspection entry point
     DevBuf dbg_key, dbg_val, dbg_ext;
-    // per tile
+    // per tile / per view
     DevBuf ranges;
     DevBuf views;
     DevBuf frame_staging;
     HostPinned host_views, host_counters;
-    DevBuf work;              // blend work counters (evaluations, contributions)
-    hipEvent_t ev[7] = {};    // stage boundaries when stage timing is on
+    DevBuf work;            // blend work counters (evaluations, contributions)
+    hipEvent_t ev[7] = {};  // stage boundaries when stage timing is on
     uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0, view_cap = 0;
     uint32_t last_D = 0;
-    hipEvent_t done = nullptr;
+    uint64_t gen = 1;  // bumped whenever a buffer is reallocated (captured graphs hold its pointers)
+    std::map<std::string, GraphEntry> graphs;
 
     PreOut pre() const {
         PreOut o;
@@ -182,55 +221,59 @@ struct Workspace {
         o.blk_view = blk_view.as<uint32_t>();
         return o;
     }
+    void grow(DevBuf& b, size_t bytes) {
+        if (b.ensure(bytes)) ++gen;
+    }
     void ensure_records(uint32_t nrec) {
         if (nrec <= rec_cap && rec0.p) return;
         const size_t r = std::max<uint32_t>(nrec, 256);
-        rec0.ensure(r * 16);
-        rec1.ensure(r * 16);
-        rec2.ensure(r * 16);
-        bbox.ensure(r * 8);
-        zkey.ensure(r * 4);
-        touched.ensure(r * 4);
+        for (DevBuf* b : {&rec0, &rec1, &rec2}) grow(*b, r * 16);
+        grow(bbox, r * 8);
+        grow(zkey, r * 4);
+        grow(touched, r * 4);
         const size_t nb = r / K1_THREADS + 1;
-        blk_sum.ensure(nb * 4);
-        blk_vis.ensure(nb * 4);
-        blk_fb.ensure(nb * 4);
-        blk_view.ensure(nb * 4);
-        blk_off.ensure(nb * 4);
-        blk_sum2.ensure(nb * 4);
-        blk_off2.ensure(nb * 4);
+        for (DevBuf* b : {&blk_sum, &blk_vis, &blk_fb, &blk_view, &blk_off, &blk_sum2, &blk_off2}) grow(*b, nb * 4);
         rec_cap = (uint32_t)r;
     }
-    void ensure_dups(uint32_t cap, bool extra) {
-        (void)extra;
+    void ensure_dups(uint32_t cap) {
         if (cap <= dup_cap && key[0].p) return;
         cap = std::max<uint32_t>(std::max(cap, dup_cap), 1u << 16);
         for (int i = 0; i < 2; ++i) {
-            key[i].ensure((size_t)cap * 4);
-            val[i].ensure((size_t)cap * 4);
-            ext[i].ensure((size_t)cap * 4);
+            grow(key[i], (size_t)cap * 4);
+            grow(val[i], (size_t)cap * 4);
+            grow(ext[i], (size_t)cap * 4);
         }
-        hist.ensure((size_t)256 * SORT_MAX_BLOCKS * 4);
-        totals.ensure((size_t)256 * MAX_SORT_PASSES * 4);
+        grow(hist, (size_t)256 * SORT_MAX_BLOCKS * 4);
+        grow(totals, (size_t)256 * MAX_SORT_PASSES * 4);
+        grow(queue, 8 * 4);
         dup_cap = cap;
     }
     void ensure_tiles(uint32_t n) {
         if (n <= tile_cap && ranges.p) return;
-        ranges.ensure((size_t)std::max<uint32_t>(n, 1) * 8);
+        grow(ranges, (size_t)std::max<uint32_t>(n, 1) * 8);
         tile_cap = std::max<uint32_t>(n, 1);
     }
     void ensure_views(int n) {
         if ((uint32_t)n <= view_cap && views.p) return;
-        views.ensure(sizeof(ViewParams) * (size_t)n);
-        host_views.ensure(sizeof(ViewParams) * (size_t)n);
+        grow(views, sizeof(ViewParams) * (size_t)n);
+        if (host_views.bytes < sizeof(ViewParams) * (size_t)n) {
+            host_views.ensure(sizeof(ViewParams) * (size_t)n);
+            ++gen;
+        }
         view_cap = (uint32_t)n;
     }
     void ensure_events() {
         if (ev[0]) return;
         for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        ++gen;
+    }
+    void drop_graphs() {
+        for (auto& kv : graphs)
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        graphs.clear();
     }
     ~Workspace() {
-        if (done) (void)hipEventDestroy(done);
+        drop_graphs();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -238,14 +281,19 @@ struct Workspace {
 
 struct tigas_context {
     int device = 0;
+    int cus = 256;
     hipStream_t stream = nullptr;
     std::mutex mu;
     std::map<hipStream_t, std::unique_ptr<Workspace>> ws;
     tigas_stats last{};
     std::mutex stats_mu;
     std::atomic<bool> profile{false};
+    std::atomic<bool> use_graphs{true};
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
+    std::mutex tune_mu;
+    std::map<std::string, TileCfg> tuned;  // shape -> best tile / batch depth
+    std::string tune_file;
 
     Workspace& workspace(hipStream_t s) {
         std::lock_guard<std::mutex> lk(mu);
@@ -254,7 +302,6 @@ struct tigas_context {
             p.reset(new Workspace());
             p->stream = s;
             p->host_counters.ensure(sizeof(Counters));
-            HIPCHK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
         }
         return *p;
     }
@@ -282,9 +329,8 @@ bool finite3(const float* p, int n) {
     return true;
 }
 
-struct TileCfg {
-    int tw, th, bd;
-};
+// Tile configuration requested by q: {0, 0} asks for the autotuner.
+bool tile_requested(const tigas_quality* q) { return q && (q->tile_w != 0 || q->tile_h != 0); }
 
 TileCfg tile_cfg(const tigas_quality* q) {
     int tw = q ? q->tile_w : 0, th = q ? q->tile_h : 0, bd = q ? q->batch_depth : 0;
@@ -302,7 +348,7 @@ TileCfg tile_cfg(const tigas_quality* q) {
 // Camera of one view: V = R^T, the FP32 key constant, rung-scaled intrinsics
 // (computed in FP64, rounded once to FP32) and the Jacobian clamp.
 ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_intrinsics* intr, int width,
-                     int height, const tigas_quality* q, const TileCfg& tc) {
+                     int height, const tigas_quality* q) {
     if (!pose || !intr) fail(TIGAS_E_INVALID, "pose and intrinsics are required");
     if (!finite3(pose->R, 9) || !finite3(pose->t, 3)) fail(TIGAS_E_INVALID, "pose is not finite");
     if (!(intr->fx > 0.f) || !(intr->fy > 0.f) || !std::isfinite(intr->fx) || !std::isfinite(intr->fy) ||
@@ -330,10 +376,6 @@ ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_
     v.lim_y = (float)(1.3 * std::max((double)v.cy, (double)oh - v.cy) / v.fy);
     v.width = ow;
     v.height = oh;
-    v.tile_w = tc.tw;
-    v.tile_h = tc.th;
-    v.tiles_x = (ow + tc.tw - 1) / tc.tw;
-    v.tiles_y = (oh + tc.th - 1) / tc.th;
     int deg = q ? q->sh_degree : -1;
     if (deg < 0 || deg > sc->view.sh_degree) deg = sc->view.sh_degree;
     v.sh_degree = deg;
@@ -344,12 +386,9 @@ ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_
     return v;
 }
 
-size_t frame_bytes(const ViewParams& v) {
-    return (size_t)v.width * v.height * 3 * (v.fmt == 1 ? 4 : 1);
-}
+size_t frame_bytes(const ViewParams& v) { return (size_t)v.width * v.height * 3 * (v.fmt == 1 ? 4 : 1); }
 
-// Depth digits of the (tile | depth) key: the positive FP32 bit patterns,
-// bit 31 always clear.
+// Depth digits of the (tile | depth) key: positive FP32 bit patterns, bit 31 clear.
 const SortPass kDepthPasses[4] = {{0, 8}, {8, 8}, {16, 8}, {24, 7}};
 
 std::vector<SortPass> tile_passes(uint32_t n_tiles) {
@@ -361,35 +400,71 @@ std::vector<SortPass> tile_passes(uint32_t n_tiles) {
 
 int sort_blocks(uint64_t n) { return (int)std::min<uint64_t>(SORT_MAX_BLOCKS, std::max<uint64_t>(1, n / 4096)); }
 
-// A group of views of one scene inside a launch sequence.
-struct Group {
-    tigas_scene* scene;
-    int first_view, nviews;
-    uint32_t rec_base, n_pad;
-};
+// Tile layout of a plan for a tile configuration (tile ids are global:
+// view tile offset + row-major local id).
+void set_tiles(Plan& plan, const TileCfg& tc) {
+    plan.tc = tc;
+    plan.n_tiles = 0;
+    for (ViewParams& v : plan.views) {
+        v.tile_w = tc.tw;
+        v.tile_h = tc.th;
+        v.tiles_x = (v.width + tc.tw - 1) / tc.tw;
+        v.tiles_y = (v.height + tc.th - 1) / tc.th;
+        v.tile_base = plan.n_tiles;
+        plan.n_tiles += (uint32_t)(v.tiles_x * v.tiles_y);
+    }
+}
 
-struct Plan {
-    std::vector<ViewParams> views;
-    std::vector<Group> groups;
-    uint32_t nrec = 0, n_tiles = 0;
-    TileCfg tc{};
-};
+// Everything about a plan that a captured graph depends on, except the view
+// parameters themselves (copied from pinned memory by the graph each replay).
+std::string shape_key(const Plan& plan, bool with_tiles) {
+    std::string k;
+    char buf[160];
+    for (const Group& g : plan.groups) {
+        std::snprintf(buf, sizeof buf, "g%p:%lld:%d:%d:%d:%u:%u;", (void*)g.scene, (long long)g.scene->view.n,
+                      g.scene->view.storage, g.first_view, g.nviews, g.rec_base, g.n_pad);
+        k += buf;
+    }
+    for (const ViewParams& v : plan.views) {
+        std::snprintf(buf, sizeof buf, "v%dx%d:%d;", v.width, v.height, v.sh_degree);
+        k += buf;
+    }
+    if (with_tiles) {
+        std::snprintf(buf, sizeof buf, "t%dx%d:%d:%d", plan.tc.tw, plan.tc.th, plan.tc.bd, (int)plan.persistent);
+        k += buf;
+    }
+    return k;
+}
 
-// Enqueue the whole launch sequence for a plan on ws.stream.  Returns the
-// index of the sort buffer that holds the sorted lists.
+void prepare(Workspace& ws, const Plan& plan, bool debug) {
+    ws.counters.ensure(sizeof(Counters));
+    ws.ensure_views((int)plan.views.size());
+    ws.ensure_records(plan.nrec);
+    ws.ensure_tiles(plan.n_tiles);
+    // never below 4x the record count: the depth passes keep the visible
+    // Gaussians in the same buffers
+    uint64_t est = std::max<uint64_t>((uint64_t)ws.last_D + ws.last_D / 4, (uint64_t)plan.nrec * 4);
+    est = std::max<uint64_t>(est, 1u << 20);
+    ws.ensure_dups((uint32_t)std::min<uint64_t>(est, 0xfff00000ull));
+    if (debug) {
+        const size_t bytes = (size_t)ws.dup_cap * 4;
+        ws.dbg_key.ensure(bytes);
+        ws.dbg_val.ensure(bytes);
+        ws.dbg_ext.ensure(bytes);
+    }
+}
+
+// Enqueue the whole launch sequence of a plan on ws.stream (no allocation, no
+// host synchronisation: capturable).  Returns the index of the sort buffer
+// that holds the sorted lists.
 //   preprocess -> scan visible -> compact -> depth passes (visible Gaussians)
 //   -> duplicate in depth order -> tile passes (duplicates) -> ranges -> blend
-int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long* work) {
+int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks) {
     hipStream_t st = ws.stream;
-    if (prof) ws.ensure_events();
     auto mark = [&](int i) {
         if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
     };
     const int nv = (int)plan.views.size();
-    ws.ensure_views(nv);
-    ws.ensure_records(plan.nrec);
-    ws.ensure_tiles(plan.n_tiles);
-    std::memcpy(ws.host_views.p, plan.views.data(), sizeof(ViewParams) * nv);
     HIPCHK(hipMemcpyAsync(ws.views.p, ws.host_views.p, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
     const PreOut o = ws.pre();
     const ViewParams* vdev = ws.views.as<ViewParams>();
@@ -405,8 +480,8 @@ int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long
     ZeroList zl{};
     zl.p[0] = ws.totals.as<uint32_t>();
     zl.n[0] = 256 * MAX_SORT_PASSES;
-    zl.p[1] = ws.blk_sum2.as<uint32_t>();
-    zl.n[1] = (uint32_t)nblk;
+    zl.p[1] = ws.queue.as<uint32_t>();
+    zl.n[1] = 8;
     zl.p[2] = ws.ranges.as<uint32_t>();
     zl.n[2] = 2 * plan.n_tiles;
     zl.p[3] = nullptr;
@@ -432,85 +507,244 @@ int enqueue(Workspace& ws, Plan& plan, bool debug, bool prof, unsigned long long
     mark(3);
     if (debug) {
         const size_t bytes = (size_t)ws.dup_cap * 4;
-        ws.dbg_key.ensure(bytes);
-        ws.dbg_val.ensure(bytes);
-        ws.dbg_ext.ensure(bytes);
         HIPCHK(hipMemcpyAsync(ws.dbg_key.p, sb.key[cd], bytes, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(ws.dbg_val.p, sb.val[cd], bytes, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(ws.dbg_ext.p, sb.ext[cd], bytes, hipMemcpyDeviceToDevice, st));
     }
     // tile digits, on the duplicates
     const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
-    if ((int)tp.size() + 4 > MAX_SORT_PASSES) fail(TIGAS_E_INVALID, "too many tiles for the sort key");
     const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap, sort_blocks(ws.dup_cap), cd,
                                 debug, cnt, 4, nullptr, nullptr, st);
     mark(4);
     launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
-                 plan.tc.bd, work, st);
+                 plan.tc.bd, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, st);
     mark(6);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ws.host_counters.p, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     return cur;
 }
 
-uint32_t initial_dup_cap(const Plan& plan, uint32_t last_D) {
-    // never below the record count: the depth passes keep the visible
-    // Gaussians in the same buffers
-    uint64_t est = std::max<uint64_t>((uint64_t)last_D + last_D / 4, (uint64_t)plan.nrec * 4);
-    est = std::max<uint64_t>(est, 1u << 20);
-    return (uint32_t)std::min<uint64_t>(est, 0xfff00000ull);
+// Launch the plan once: from a captured graph when allowed (captured on the
+// first use of its shape, re-captured after any workspace reallocation), else
+// eagerly.  Returns the sort buffer index.
+int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, bool prof,
+                unsigned long long* work) {
+    std::memcpy(ws.host_views.p, plan.views.data(), sizeof(ViewParams) * plan.views.size());
+    if (prof) ws.ensure_events();
+    const int pblocks = plan.persistent ? ctx->cus * blend_persistent_occupancy(plan.tc.tw, plan.tc.th, plan.tc.bd) : 0;
+    // stage timing needs events between the launches: that runs uncaptured
+    const bool graph = ctx->use_graphs.load() && !debug && !work && !prof;
+    if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks);
+    const std::string key = shape_key(plan, true);
+    GraphEntry& g = ws.graphs[key];
+    if (!g.exec || g.gen != ws.gen) {
+        if (g.exec) HIPCHK(hipGraphExecDestroy(g.exec));
+        g.exec = nullptr;
+        if (ws.graphs.size() > 64) {  // bound the cache
+            ws.drop_graphs();
+            return launch_plan(ctx, ws, plan, debug, prof, work);
+        }
+        hipGraph_t graph_t = nullptr;
+        HIPCHK(hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal));
+        int cur = 0;
+        try {
+            cur = enqueue(ws, plan, debug, prof, work, pblocks);
+        } catch (...) {
+            (void)hipStreamEndCapture(ws.stream, &graph_t);
+            if (graph_t) (void)hipGraphDestroy(graph_t);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(ws.stream, &graph_t));
+        const hipError_t e = hipGraphInstantiate(&g.exec, graph_t, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph_t);
+        HIPCHK(e);
+        g.gen = ws.gen;
+        g.cur = cur;
+    }
+    HIPCHK(hipGraphLaunch(g.exec, ws.stream));
+    return g.cur;
 }
 
-// Runs the plan to completion (synchronous), regrowing the duplicate buffers
-// when the first attempt overflowed.  Returns the final sort buffer index.
-int run_plan(tigas_context* ctx, Workspace& ws, Plan& plan, bool debug, int* rerenders,
-             unsigned long long* work = nullptr) {
-    ws.counters.ensure(sizeof(Counters));
-    ws.ensure_dups(std::max(ws.dup_cap, initial_dup_cap(plan, ws.last_D)), debug);
+// Runs the plan to completion (synchronous).  A first attempt whose
+// duplicates overflowed the buffers emitted nothing; it is detected here and
+// the frame is rendered again with buffers sized from the true count.
+int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, unsigned long long* work = nullptr) {
+    prepare(ws, plan, debug);
     const bool prof = ctx->profile.load();
-    int cur = enqueue(ws, plan, debug, prof, work);
+    int cur = launch_plan(ctx, ws, plan, debug, prof, work);
     HIPCHK(hipStreamSynchronize(ws.stream));
     Counters c;
     std::memcpy(&c, ws.host_counters.p, sizeof(c));
-    *rerenders = 0;
+    int rerenders = 0;
     if (c.overflow) {
         const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
         if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
-        ws.ensure_dups((uint32_t)want, debug);
+        ws.ensure_dups((uint32_t)want);
+        if (debug) prepare(ws, plan, debug);
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
-        cur = enqueue(ws, plan, debug, prof, work);
+        cur = launch_plan(ctx, ws, plan, debug, prof, work);
         HIPCHK(hipStreamSynchronize(ws.stream));
         std::memcpy(&c, ws.host_counters.p, sizeof(c));
         if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
-        *rerenders = 1;
+        rerenders = 1;
     }
     ws.last_D = c.D;
-    {
-        std::lock_guard<std::mutex> lk(ctx->stats_mu);
-        if (prof) {
-            for (int i = 0; i < 6; ++i) {
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, ws.ev[i], ws.ev[i + 1]));
-                ctx->stage_ms[i] += ms;
-            }
-            ctx->stage_frames += 1;
+    std::lock_guard<std::mutex> lk(ctx->stats_mu);
+    if (prof) {
+        for (int i = 0; i < 6; ++i) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ws.ev[i], ws.ev[i + 1]));
+            ctx->stage_ms[i] += ms;
         }
-        ctx->last.visible = c.visible;
-        ctx->last.duplicates = c.D;
-        ctx->last.fallbacks = c.fallbacks;
-        ctx->last.tiles = plan.n_tiles;
-        ctx->last.sort_passes = 4 + (int64_t)tile_passes(plan.n_tiles).size();
-        ctx->last.rerenders = *rerenders;
-        int64_t n = 0;
-        for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
-        ctx->last.n = n;
+        ctx->stage_frames += 1;
     }
+    ctx->last.visible = c.visible;
+    ctx->last.duplicates = c.D;
+    ctx->last.fallbacks = c.fallbacks;
+    ctx->last.tiles = plan.n_tiles;
+    ctx->last.sort_passes = 4 + (int64_t)tile_passes(plan.n_tiles).size();
+    ctx->last.rerenders = rerenders;
+    ctx->last.tile_w = plan.tc.tw;
+    ctx->last.tile_h = plan.tc.th;
+    ctx->last.batch_depth = plan.tc.bd;
+    int64_t n = 0;
+    for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
+    ctx->last.n = n;
     return cur;
 }
 
+// ------------------------------------------------------------- autotuner
+
+void load_tune_file(tigas_context* ctx) {
+    if (ctx->tune_file.empty()) return;
+    FILE* f = std::fopen(ctx->tune_file.c_str(), "r");
+    if (!f) return;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        int tw, th, bd;
+        char key[4000];
+        if (std::sscanf(line, "%d %d %d %3999s", &tw, &th, &bd, key) == 4) ctx->tuned[key] = {tw, th, bd};
+    }
+    std::fclose(f);
+}
+
+void save_tune_file(tigas_context* ctx) {
+    if (ctx->tune_file.empty()) return;
+    const std::string tmp = ctx->tune_file + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto& kv : ctx->tuned) std::fprintf(f, "%d %d %d %s\n", kv.second.tw, kv.second.th, kv.second.bd,
+                                                   kv.first.c_str());
+    std::fclose(f);
+    std::rename(tmp.c_str(), ctx->tune_file.c_str());
+}
+
+// Picks the tile shape and batch depth for the plan's shape: each candidate
+// is rendered (graph captured, one warm-up) and timed over a few replays; the
+// fastest is cached per shape (and in the file named by TIGAS_TUNE_CACHE).
+// Frames are identical for every candidate, so tuning changes only speed.
+TileCfg autotune(tigas_context* ctx, Workspace& ws, Plan& plan) {
+    const std::string key = shape_key(plan, false) + (plan.persistent ? "|P" : "|G");
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto it = ctx->tuned.find(key);
+        if (it != ctx->tuned.end()) return it->second;
+    }
+    const bool prof = ctx->profile.exchange(false);
+    TileCfg best = kTileCandidates[3];
+    double best_ms = 1e30;
+    for (const TileCfg& tc : kTileCandidates) {
+        set_tiles(plan, tc);
+        run_plan(ctx, ws, plan, false);  // capture + warm
+        double t_min = 1e30;
+        for (int r = 0; r < 3; ++r) {
+            const auto t0 = std::chrono::steady_clock::now();
+            run_plan(ctx, ws, plan, false);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            t_min = std::min(t_min, ms);
+        }
+        if (t_min < best_ms) {
+            best_ms = t_min;
+            best = tc;
+        }
+    }
+    ctx->profile.store(prof);
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->tuned[key] = best;
+    save_tune_file(ctx);
+    return best;
+}
+
 hipStream_t pick_stream(tigas_context* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }
+
+// Host frames are rendered into a device staging buffer and copied out.
+void bind_outputs(Workspace& ws, Plan& plan, tigas_frame* outs, std::vector<size_t>& stage_off) {
+    size_t staging = 0;
+    stage_off.assign(plan.views.size(), 0);
+    for (size_t i = 0; i < plan.views.size(); ++i) {
+        const ViewParams& v = plan.views[i];
+        outs[i].out_w = v.width;
+        outs[i].out_h = v.height;
+        const size_t need = frame_bytes(v);
+        if (!outs[i].data || outs[i].capacity < need) fail(TIGAS_E_BUFFER, "output frame buffer too small");
+        if (!outs[i].is_device) {
+            stage_off[i] = staging;
+            staging += (need + 255) / 256 * 256;
+        }
+    }
+    if (staging) ws.frame_staging.ensure(staging);  // not referenced by kernels: no graph invalidation needed
+    for (size_t i = 0; i < plan.views.size(); ++i)
+        plan.views[i].out_ptr = outs[i].is_device ? (uint64_t)(uintptr_t)outs[i].data
+                                                  : (uint64_t)(uintptr_t)ws.frame_staging.p + stage_off[i];
+}
+
+void copy_host_outputs(Workspace& ws, const Plan& plan, tigas_frame* outs, const std::vector<size_t>& stage_off) {
+    bool any = false;
+    for (size_t i = 0; i < plan.views.size(); ++i)
+        if (!outs[i].is_device) {
+            HIPCHK(hipMemcpyAsync(outs[i].data, (char*)ws.frame_staging.p + stage_off[i], frame_bytes(plan.views[i]),
+                                  hipMemcpyDeviceToHost, ws.stream));
+            any = true;
+        }
+    if (any) HIPCHK(hipStreamSynchronize(ws.stream));
+}
+
+void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_pad, tigas_debug_out* dbg);
+
+// Renders the views of `plan` (already holding view parameters and groups)
+// into `outs`: tile configuration from q or the autotuner.
+void render_views(tigas_context* ctx, Workspace& ws, Plan& plan, const tigas_quality* q, tigas_frame* outs,
+                  tigas_debug_out* dbg, int64_t* work_out) {
+    std::lock_guard<std::mutex> lk(ws.mu);
+    std::vector<size_t> stage_off;
+    bind_outputs(ws, plan, outs, stage_off);
+    // explicit tile shape: as requested; otherwise the autotuned shape for
+    // this workload (16x16 for the inspection and counting entry points)
+    TileCfg tc = tile_cfg(q);
+    if (!tile_requested(q) && !dbg && !work_out) {
+        const int bd_req = tc.bd;
+        tc = autotune(ctx, ws, plan);
+        if (q && q->batch_depth != 0) tc.bd = bd_req;
+    }
+    set_tiles(plan, tc);
+    unsigned long long* work = nullptr;
+    if (work_out) {
+        ws.work.ensure(16);
+        work = ws.work.as<unsigned long long>();
+        HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
+    }
+    const int cur = run_plan(ctx, ws, plan, dbg != nullptr, work);
+    if (work_out) {
+        unsigned long long w[2];
+        HIPCHK(hipMemcpy(w, work, 16, hipMemcpyDeviceToHost));
+        work_out[0] = (int64_t)w[0];
+        work_out[1] = (int64_t)w[1];
+    }
+    copy_host_outputs(ws, plan, outs, stage_off);
+    if (dbg) debug_copy(ws, plan, cur, plan.groups[0].scene->view.n, plan.groups[0].n_pad, dbg);
+}
 
 void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width, int height,
                 const tigas_quality* q, tigas_frame* out, void* hip_stream, tigas_debug_out* dbg,
@@ -519,118 +753,82 @@ void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsi
     tigas_context* ctx = scene->ctx;
     HIPCHK(hipSetDevice(ctx->device));
     SceneRef ref(scene);
-    const TileCfg tc = tile_cfg(q);
     Plan plan;
-    plan.tc = tc;
-    plan.views.push_back(make_view(scene, pose, intr, width, height, q, tc));
-    ViewParams& v = plan.views[0];
-    out->out_w = v.width;
-    out->out_h = v.height;
-    const size_t need = frame_bytes(v);
-    if (!out->data || out->capacity < need) fail(TIGAS_E_BUFFER, "output frame buffer too small");
-    Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
-    if (out->is_device) {
-        v.out_ptr = (uint64_t)(uintptr_t)out->data;
-    } else {
-        ws.frame_staging.ensure(need);
-        v.out_ptr = (uint64_t)(uintptr_t)ws.frame_staging.p;
-    }
+    plan.views.push_back(make_view(scene, pose, intr, width, height, q));
     const uint32_t n_pad = round_up((uint64_t)scene->view.n, K1_THREADS);
     plan.groups.push_back({scene, 0, 1, 0, n_pad});
     plan.nrec = n_pad;
-    v.tile_base = 0;
-    plan.n_tiles = (uint32_t)(v.tiles_x * v.tiles_y);
-    int rr = 0;
-    unsigned long long* work = nullptr;
-    if (work_out) {
-        ws.work.ensure(16);
-        work = ws.work.as<unsigned long long>();
-        HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
+    Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
+    render_views(ctx, ws, plan, q, out, dbg, work_out);
+}
+
+void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_pad, tigas_debug_out* dbg) {
+    Counters c;
+    std::memcpy(&c, ws.host_counters.p, sizeof(c));
+    dbg->n_dup = c.D;
+    dbg->n_tiles = plan.n_tiles;
+    hipStream_t st = ws.stream;
+    if (dbg->rec) {
+        std::vector<float4> a(n_pad), b(n_pad), cc(n_pad);
+        HIPCHK(hipMemcpyAsync(a.data(), ws.rec0.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(b.data(), ws.rec1.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(cc.data(), ws.rec2.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i) {
+            float* r = dbg->rec + 12 * i;
+            const float4 x = a[i], y = b[i], z = cc[i];
+            r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
+            r[4] = y.x; r[5] = y.y; r[6] = y.z; r[7] = y.w;
+            r[8] = z.x; r[9] = z.y; r[10] = z.z; r[11] = z.w;
+        }
     }
-    const int cur = run_plan(ctx, ws, plan, dbg != nullptr, &rr, work);
-    if (work_out) {
-        unsigned long long w[2];
-        HIPCHK(hipMemcpy(w, work, 16, hipMemcpyDeviceToHost));
-        work_out[0] = (int64_t)w[0];
-        work_out[1] = (int64_t)w[1];
-    }
-    if (!out->is_device) {
-        HIPCHK(hipMemcpyAsync(out->data, ws.frame_staging.p, need, hipMemcpyDeviceToHost, ws.stream));
-        HIPCHK(hipStreamSynchronize(ws.stream));
-    }
-    if (dbg) {
-        Counters c;
-        std::memcpy(&c, ws.host_counters.p, sizeof(c));
-        const int64_t n = scene->view.n;
-        dbg->n_dup = c.D;
-        dbg->n_tiles = plan.n_tiles;
-        hipStream_t st = ws.stream;
-        if (dbg->rec) {
-            std::vector<float4> a(n_pad), b(n_pad), cc(n_pad);
-            HIPCHK(hipMemcpyAsync(a.data(), ws.rec0.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(b.data(), ws.rec1.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(cc.data(), ws.rec2.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int64_t i = 0; i < n; ++i) {
-                float* r = dbg->rec + 12 * i;
-                const float4 x = a[i], y = b[i], z = cc[i];
-                r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
-                r[4] = y.x; r[5] = y.y; r[6] = y.z; r[7] = y.w;
-                r[8] = z.x; r[9] = z.y; r[10] = z.z; r[11] = z.w;
+    std::vector<uint32_t> touched(n_pad);
+    if (n_pad) HIPCHK(hipMemcpyAsync(touched.data(), ws.touched.p, 4 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (dbg->touched && n) std::memcpy(dbg->touched, touched.data(), 4 * (size_t)n);
+    if (dbg->zkey && n) HIPCHK(hipMemcpyAsync(dbg->zkey, ws.zkey.p, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
+    if (dbg->bbox) {
+        std::vector<uint2> bb(n_pad);
+        if (n_pad) HIPCHK(hipMemcpyAsync(bb.data(), ws.bbox.p, 8 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t* r = dbg->bbox + 4 * i;
+            if (touched[i]) {
+                r[0] = (int32_t)(bb[i].x & 0xffffu);
+                r[1] = (int32_t)(bb[i].x >> 16);
+                r[2] = (int32_t)(bb[i].y & 0xffffu);
+                r[3] = (int32_t)(bb[i].y >> 16);
+            } else {
+                r[0] = 0; r[1] = 0; r[2] = -1; r[3] = -1;
             }
         }
-        std::vector<uint32_t> touched(n_pad);
-        HIPCHK(hipMemcpyAsync(touched.data(), ws.touched.p, 4 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (dbg->touched) std::memcpy(dbg->touched, touched.data(), 4 * (size_t)n);
-        if (dbg->zkey) {
-            HIPCHK(hipMemcpyAsync(dbg->zkey, ws.zkey.p, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
-        }
-        if (dbg->bbox) {
-            std::vector<uint2> bb(n_pad);
-            HIPCHK(hipMemcpyAsync(bb.data(), ws.bbox.p, 8 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int64_t i = 0; i < n; ++i) {
-                int32_t* r = dbg->bbox + 4 * i;
-                if (touched[i]) {
-                    r[0] = (int32_t)(bb[i].x & 0xffffu);
-                    r[1] = (int32_t)(bb[i].x >> 16);
-                    r[2] = (int32_t)(bb[i].y & 0xffffu);
-                    r[3] = (int32_t)(bb[i].y >> 16);
-                } else {
-                    r[0] = 0; r[1] = 0; r[2] = -1; r[3] = -1;
-                }
-            }
-        }
-        const bool fits = (int64_t)c.D <= dbg->cap_dup;
-        if ((dbg->keys || dbg->vals || dbg->skeys || dbg->svals) && !fits)
-            fail(TIGAS_E_BUFFER, "debug duplicate arrays smaller than D");
-        std::vector<uint32_t> lo(c.D), hi(c.D);
-        if (c.D && (dbg->keys || dbg->vals)) {
-            // entries as emitted (Gaussians in depth order), saved before the tile passes
-            HIPCHK(hipMemcpyAsync(hi.data(), ws.dbg_key.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(lo.data(), ws.dbg_ext.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            if (dbg->vals)
-                HIPCHK(hipMemcpyAsync(dbg->vals, ws.dbg_val.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            if (dbg->keys)
-                for (uint32_t i = 0; i < c.D; ++i) dbg->keys[i] = ((uint64_t)hi[i] << 32) | lo[i];
-        }
-        if (c.D && (dbg->skeys || dbg->svals)) {
-            HIPCHK(hipMemcpyAsync(hi.data(), ws.key[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(lo.data(), ws.ext[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            if (dbg->svals)
-                HIPCHK(hipMemcpyAsync(dbg->svals, ws.val[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            if (dbg->skeys)
-                for (uint32_t i = 0; i < c.D; ++i) dbg->skeys[i] = ((uint64_t)hi[i] << 32) | lo[i];
-        }
-        if (dbg->ranges) {
-            if (dbg->cap_tiles < (int64_t)plan.n_tiles) fail(TIGAS_E_BUFFER, "debug ranges array too small");
-            HIPCHK(hipMemcpyAsync(dbg->ranges, ws.ranges.p, 8 * (size_t)plan.n_tiles, hipMemcpyDeviceToHost, st));
-        }
-        HIPCHK(hipStreamSynchronize(st));
     }
+    const bool fits = (int64_t)c.D <= dbg->cap_dup;
+    if ((dbg->keys || dbg->vals || dbg->skeys || dbg->svals) && !fits)
+        fail(TIGAS_E_BUFFER, "debug duplicate arrays smaller than D");
+    std::vector<uint32_t> lo(c.D), hi(c.D);
+    if (c.D && (dbg->keys || dbg->vals)) {
+        // entries as emitted (Gaussians in depth order), saved before the tile passes
+        HIPCHK(hipMemcpyAsync(hi.data(), ws.dbg_key.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(lo.data(), ws.dbg_ext.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+        if (dbg->vals) HIPCHK(hipMemcpyAsync(dbg->vals, ws.dbg_val.p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (dbg->keys)
+            for (uint32_t i = 0; i < c.D; ++i) dbg->keys[i] = ((uint64_t)hi[i] << 32) | lo[i];
+    }
+    if (c.D && (dbg->skeys || dbg->svals)) {
+        HIPCHK(hipMemcpyAsync(hi.data(), ws.key[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(lo.data(), ws.ext[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+        if (dbg->svals) HIPCHK(hipMemcpyAsync(dbg->svals, ws.val[cur].p, 4 * (size_t)c.D, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (dbg->skeys)
+            for (uint32_t i = 0; i < c.D; ++i) dbg->skeys[i] = ((uint64_t)hi[i] << 32) | lo[i];
+    }
+    if (dbg->ranges) {
+        if (dbg->cap_tiles < (int64_t)plan.n_tiles) fail(TIGAS_E_BUFFER, "debug ranges array too small");
+        HIPCHK(hipMemcpyAsync(dbg->ranges, ws.ranges.p, 8 * (size_t)plan.n_tiles, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 }  // namespace
@@ -650,7 +848,13 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         HIPCHK(hipSetDevice(device));
         std::unique_ptr<tigas_context> c(new tigas_context());
         c->device = device;
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, device));
+        c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        if (const char* f = std::getenv("TIGAS_TUNE_CACHE")) c->tune_file = f;
+        if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
+        load_tune_file(c.get());
         *out = c.release();
     });
 }
@@ -781,34 +985,14 @@ tigas_status tigas_render_batch(tigas_scene* const* scenes, const tigas_pose* po
         tigas_context* ctx = scenes[0] ? scenes[0]->ctx : nullptr;
         if (!ctx) fail(TIGAS_E_INVALID, "null scene");
         HIPCHK(hipSetDevice(ctx->device));
-        const TileCfg tc = tile_cfg(q);
         Plan plan;
-        plan.tc = tc;
-        Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
-        // group consecutive views that share a scene
+        plan.persistent = true;
         std::vector<std::unique_ptr<SceneRef>> refs;
-        size_t staging = 0;
-        std::vector<size_t> stage_off(n_views, 0);
         for (int i = 0; i < n_views; ++i) {
             if (!scenes[i] || scenes[i]->ctx != ctx) fail(TIGAS_E_INVALID, "scenes must share one context");
-            const tigas_quality qi = q ? q[i] : tigas_quality{};
-            ViewParams v = make_view(scenes[i], &poses[i], &intrs[i], widths[i], heights[i], &qi, tc);
-            outs[i].out_w = v.width;
-            outs[i].out_h = v.height;
-            const size_t need = frame_bytes(v);
-            if (!outs[i].data || outs[i].capacity < need) fail(TIGAS_E_BUFFER, "output frame buffer too small");
-            if (!outs[i].is_device) {
-                stage_off[i] = staging;
-                staging += (need + 255) / 256 * 256;
-            }
-            v.tile_base = plan.n_tiles;
-            plan.n_tiles += (uint32_t)(v.tiles_x * v.tiles_y);
-            plan.views.push_back(v);
+            plan.views.push_back(make_view(scenes[i], &poses[i], &intrs[i], widths[i], heights[i], q ? &q[i] : nullptr));
         }
-        if (staging) ws.frame_staging.ensure(staging);
-        for (int i = 0; i < n_views; ++i)
-            plan.views[i].out_ptr = outs[i].is_device ? (uint64_t)(uintptr_t)outs[i].data
-                                                      : (uint64_t)(uintptr_t)ws.frame_staging.p + stage_off[i];
+        // consecutive views of one scene share one preprocess launch
         for (int i = 0; i < n_views;) {
             int j = i;
             while (j < n_views && scenes[j] == scenes[i]) ++j;
@@ -818,13 +1002,8 @@ tigas_status tigas_render_batch(tigas_scene* const* scenes, const tigas_pose* po
             plan.nrec += n_pad * (uint32_t)(j - i);
             i = j;
         }
-        int rr = 0;
-        run_plan(ctx, ws, plan, false, &rr);
-        for (int i = 0; i < n_views; ++i)
-            if (!outs[i].is_device)
-                HIPCHK(hipMemcpyAsync(outs[i].data, (char*)ws.frame_staging.p + stage_off[i],
-                                      frame_bytes(plan.views[i]), hipMemcpyDeviceToHost, ws.stream));
-        HIPCHK(hipStreamSynchronize(ws.stream));
+        Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
+        render_views(ctx, ws, plan, q, outs, nullptr, nullptr);
     });
 }
 
@@ -857,6 +1036,13 @@ tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out) {
         out->ranges = ctx->stage_ms[4];
         out->blend = ctx->stage_ms[5];
         out->frames = ctx->stage_frames;
+    });
+}
+
+tigas_status tigas_set_graphs(tigas_context* ctx, int enable) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        ctx->use_graphs.store(enable != 0);
     });
 }
 

@@ -833,42 +833,42 @@ __device__ __forceinline__ uint8_t to_u8(float x) {
     return (uint8_t)floorf(__builtin_fmaf(fminf(fmaxf(x, 0.0f), 1.0f), 255.0f, 0.5f));
 }
 
-// One workgroup per tile of TW x TH pixels; wave w owns the 8x8 pixel block
+struct BlendArgs {
+    const ViewParams* views;
+    int nviews;
+    uint32_t n_tiles;
+    const uint2* ranges;
+    const uint32_t* vals;
+    const float4* rec0;
+    const float4* rec1;
+    const float4* rec2;
+    const uint2* bbox;
+    uint32_t nrec;
+    unsigned long long* work;
+};
+
+// One tile of TW x TH pixels; wave w owns the 8x8 pixel block
 // (w mod TW/8, w div TW/8) of it.  Each wave walks the tile's depth-sorted
 // list in batches of 64 * BD entries: every lane fetches entries, keeps those
 // whose pixel box meets the wave's block, compacts them into the wave's LDS
 // slice (ballot + mbcnt) and the 64 lanes then composite them front to back.
-// A wave leaves as soon as all of its pixels have terminated.
+// A wave leaves as soon as all of its pixels have terminated; there is no
+// barrier between the waves of a tile.
 template <int TW, int TH, int BD, bool COUNT>
-__global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__ views, int nviews,
-                                                  uint32_t n_tiles, const uint2* __restrict__ ranges,
-                                                  const uint32_t* __restrict__ vals, const float4* __restrict__ rec0,
-                                                  const float4* __restrict__ rec1, const float4* __restrict__ rec2,
-                                                  const uint2* __restrict__ bbox, uint32_t nrec,
-                                                  unsigned long long* __restrict__ work) {
-    constexpr int NW = TW * TH / 64;
+__device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, float4 (*la)[64 * BD],
+                                           float4 (*lb)[64 * BD], float (*lc)[64 * BD]) {
     constexpr int BX = TW / 8;
     constexpr int BATCH = 64 * BD;
-    __shared__ float4 la[NW][BATCH];
-    __shared__ float4 lb[NW][BATCH];
-    __shared__ float lc[NW][BATCH];
-
-    // XCD-aware mapping: consecutive workgroup ids go round-robin to the 8
-    // XCDs; give each XCD a contiguous band of tiles so neighbouring tiles
-    // (which share Gaussians) meet in the same L2.
-    const uint32_t per = (n_tiles + 7) / 8;
-    const uint32_t tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= n_tiles) return;
     int vi = 0;
     {
-        int lo = 0, hi = nviews - 1;
+        int lo = 0, hi = A.nviews - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+            if (A.views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
         }
         vi = lo;
     }
-    const ViewParams& v = views[vi];
+    const ViewParams& v = A.views[vi];
     const uint32_t lt = tile - v.tile_base;
     const int tx = (int)(lt % (uint32_t)v.tiles_x), ty = (int)(lt / (uint32_t)v.tiles_x);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -877,7 +877,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
     const bool inside = px < v.width && py < v.height;
     const float pxr = (float)(lane & 7) + 0.5f, pyr = (float)(lane >> 3) + 0.5f;
     const float fsx = (float)sx, fsy = (float)sy;
-    const uint2 rg = ranges[tile];
+    const uint2 rg = A.ranges[tile];
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
     bool done = !inside;
     uint32_t n_eval = 0, n_contrib = 0;  // (pixel, Gaussian) evaluations / contributions, COUNT only
@@ -892,9 +892,9 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
             const uint32_t i = base + (uint32_t)(k * 64 + lane);
             bool hit = false;
             uint32_t r = 0;
-            if (i < rg.y) r = vals[i];
-            if (i < rg.y && r < nrec) {
-                const uint2 b = bbox[r];
+            if (i < rg.y) r = A.vals[i];
+            if (i < rg.y && r < A.nrec) {
+                const uint2 b = A.bbox[r];
                 const int x0 = (int)(b.x & 0xffffu), y0 = (int)(b.x >> 16);
                 const int x1 = (int)(b.y & 0xffffu), y1 = (int)(b.y >> 16);
                 hit = !(x1 < sx || x0 > bx1 || y1 < sy || y0 > by1);
@@ -902,7 +902,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
             const uint64_t m = ballot(hit);
             if (hit) {
                 const uint32_t slot = cnt + bits_below(m);
-                const float4 a = rec0[r], b1 = rec1[r], c2 = rec2[r];
+                const float4 a = A.rec0[r], b1 = A.rec1[r], c2 = A.rec2[r];
                 // pixel centre relative to the block origin, hi and lo parts combined here
                 la[w][slot] = make_float4((a.x - fsx) + a.z, (a.y - fsy) + a.w, b1.x, b1.y);
                 lb[w][slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
@@ -943,8 +943,8 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
     if (COUNT) {
         const uint32_t se = wave_sum(n_eval), sc = wave_sum(n_contrib);
         if (lane == 0) {
-            atomicAdd(&work[0], (unsigned long long)se);
-            atomicAdd(&work[1], (unsigned long long)sc);
+            atomicAdd(&A.work[0], (unsigned long long)se);
+            atomicAdd(&A.work[1], (unsigned long long)sc);
         }
     }
     if (inside) {
@@ -962,6 +962,52 @@ __global__ __launch_bounds__(TW* TH) void k_blend(const ViewParams* __restrict__
             out[0] = to_u8(r);
             out[1] = to_u8(g);
             out[2] = to_u8(b);
+        }
+    }
+}
+
+// One workgroup per tile.  XCD-aware mapping: consecutive workgroup ids go
+// round-robin to the 8 XCDs; each XCD gets a contiguous band of tiles so
+// neighbouring tiles (which share Gaussians) meet in the same L2.
+template <int TW, int TH, int BD, bool COUNT>
+__global__ __launch_bounds__(TW* TH) void k_blend(BlendArgs A) {
+    constexpr int NW = TW * TH / 64;
+    __shared__ float4 la[NW][64 * BD];
+    __shared__ float4 lb[NW][64 * BD];
+    __shared__ float lc[NW][64 * BD];
+    const uint32_t per = (A.n_tiles + 7) / 8;
+    const uint32_t tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= A.n_tiles) return;
+    blend_tile<TW, TH, BD, COUNT>(A, tile, la, lb, lc);
+}
+
+// Persistent form for many views of uneven size: a fixed grid of resident
+// workgroups pulls tiles from 8 device work queues, one per band of
+// consecutive tiles; a workgroup starts on the band of its XCD (id mod 8) and
+// moves on to the other bands when its own is drained.  The queue counters are
+// cleared by k_scan_visible each frame; every workgroup exits once all bands
+// are drained.
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW* TH) void k_blend_persistent(BlendArgs A, uint32_t* __restrict__ queue) {
+    constexpr int NW = TW * TH / 64;
+    __shared__ float4 la[NW][64 * BD];
+    __shared__ float4 lb[NW][64 * BD];
+    __shared__ float lc[NW][64 * BD];
+    __shared__ uint32_t next;
+    const uint32_t per = (A.n_tiles + 7) / 8;
+    const int home = blockIdx.x & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int band = (home + k) & 7;
+        const uint32_t first = (uint32_t)band * per;
+        const uint32_t band_end = min(A.n_tiles, first + per);
+        if (first >= band_end) continue;
+        for (;;) {
+            if (threadIdx.x == 0) next = first + atomicAdd(&queue[band], 1u);
+            __syncthreads();
+            const uint32_t tile = next;
+            __syncthreads();
+            if (tile >= band_end) break;
+            blend_tile<TW, TH, BD, false>(A, tile, la, lb, lc);
         }
     }
 }
@@ -1055,33 +1101,55 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
     TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges);
 }
 
-template <int TW, int TH, bool C>
-static void blend_bd(int bd, dim3 grid, const ViewParams* v, int nv, uint32_t nt, const uint2* rg,
-                     const uint32_t* vals, const PreOut& o, uint32_t nrec, unsigned long long* work, hipStream_t st) {
-    switch (bd) {
-        case 128: TIGAS_LAUNCH((k_blend<TW, TH, 2, C>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work); break;
-        case 256: TIGAS_LAUNCH((k_blend<TW, TH, 4, C>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work); break;
-        default: TIGAS_LAUNCH((k_blend<TW, TH, 1, C>), grid, dim3(TW * TH), st, v, nv, nt, rg, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work); break;
+template <int TW, int TH, int BD>
+static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int persistent_blocks, hipStream_t st) {
+    if (queue) {
+        TIGAS_LAUNCH((k_blend_persistent<TW, TH, BD>), dim3(persistent_blocks), dim3(TW * TH), st, A, queue);
+    } else {
+        const dim3 grid(((A.n_tiles + 7) / 8) * 8);
+        if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, true>), grid, dim3(TW * TH), st, A);
+        else TIGAS_LAUNCH((k_blend<TW, TH, BD, false>), grid, dim3(TW * TH), st, A);
     }
 }
 
-template <bool C>
-static void blend_tiles(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
-                        const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h,
-                        int batch_depth, unsigned long long* work, hipStream_t st) {
-    const dim3 grid(((n_tiles + 7) / 8) * 8);
-    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
-    else if (tile_w == 16 && tile_h == 32) blend_bd<16, 32, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
-    else if (tile_w == 32 && tile_h == 16) blend_bd<32, 16, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
-    else blend_bd<16, 16, C>(batch_depth, grid, views_dev, nviews, n_tiles, ranges, vals, o, nrec, work, st);
+template <int TW, int TH>
+static void blend_bd(int bd, const BlendArgs& A, bool count, uint32_t* queue, int pb, hipStream_t st) {
+    switch (bd) {
+        case 128: blend_launch<TW, TH, 2>(A, count, queue, pb, st); break;
+        case 256: blend_launch<TW, TH, 4>(A, count, queue, pb, st); break;
+        default: blend_launch<TW, TH, 1>(A, count, queue, pb, st); break;
+    }
 }
 
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  unsigned long long* work, hipStream_t st) {
+                  unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st) {
     if (n_tiles == 0) return;
-    if (work) blend_tiles<true>(views_dev, nviews, n_tiles, ranges, vals, o, nrec, tile_w, tile_h, batch_depth, work, st);
-    else blend_tiles<false>(views_dev, nviews, n_tiles, ranges, vals, o, nrec, tile_w, tile_h, batch_depth, nullptr, st);
+    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work};
+    const bool count = work != nullptr;
+    if (count) queue = nullptr;
+    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8>(batch_depth, A, count, queue, persistent_blocks, st);
+    else if (tile_w == 16 && tile_h == 32) blend_bd<16, 32>(batch_depth, A, count, queue, persistent_blocks, st);
+    else if (tile_w == 32 && tile_h == 16) blend_bd<32, 16>(batch_depth, A, count, queue, persistent_blocks, st);
+    else blend_bd<16, 16>(batch_depth, A, count, queue, persistent_blocks, st);
+}
+
+// Resident workgroups per CU of the persistent blend kernel for a tile shape.
+int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth) {
+    int n = 0;
+    auto occ = [&](auto kern, int threads) {
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0);
+    };
+    const int bd = batch_depth == 128 ? 2 : (batch_depth == 256 ? 4 : 1);
+#define TIGAS_OCC(TW, TH)                                                              \
+    if (tile_w == TW && tile_h == TH) {                                                \
+        if (bd == 1) occ(k_blend_persistent<TW, TH, 1>, TW * TH);                      \
+        else if (bd == 2) occ(k_blend_persistent<TW, TH, 2>, TW * TH);                 \
+        else occ(k_blend_persistent<TW, TH, 4>, TW * TH);                              \
+    }
+    TIGAS_OCC(8, 8) else TIGAS_OCC(16, 32) else TIGAS_OCC(32, 16) else TIGAS_OCC(16, 16)
+#undef TIGAS_OCC
+    return n > 0 ? n : 1;
 }
 
 void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st) {

@@ -110,7 +110,10 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  unsigned long long* work, hipStream_t st);
+                  unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st);
+// With `queue` (8 counters cleared per frame) the blend runs as a persistent
+// kernel of persistent_blocks workgroups pulling tiles from work queues.
+int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth);
 void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
 
 }  // namespace tigas

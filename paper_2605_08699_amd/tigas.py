@@ -55,7 +55,8 @@ class FrameC(ctypes.Structure):
 class StatsC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("visible", ctypes.c_int64), ("duplicates", ctypes.c_int64),
                 ("fallbacks", ctypes.c_int64), ("tiles", ctypes.c_int64), ("sort_passes", ctypes.c_int64),
-                ("rerenders", ctypes.c_int64)]
+                ("rerenders", ctypes.c_int64), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("batch_depth", ctypes.c_int32)]
 
 
 class DebugC(ctypes.Structure):
@@ -76,7 +77,7 @@ class StageC(ctypes.Structure):
 EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
-           "tigas_count_blend_work")
+           "tigas_count_blend_work", "tigas_set_graphs")
 
 _lib = None
 
@@ -109,13 +110,14 @@ def lib():
         L.tigas_last_error.restype = ctypes.c_char_p
         L.tigas_selftest_wave_scan.argtypes = [P, P, I]
         L.tigas_profile_stages.argtypes = [P, I]
+        L.tigas_set_graphs.argtypes = [P, I]
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
                                              ctypes.POINTER(I64), ctypes.POINTER(I64)]
         for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
-                     "tigas_stage_times", "tigas_count_blend_work"):
+                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -143,7 +145,10 @@ def intr_c(k) -> IntrC:
     return IntrC(float(k.fx), float(k.fy), float(k.cx), float(k.cy))
 
 
-def quality_c(res_scale=1.0, sh_degree=-1, fmt="rgb8", bg=(0.0, 0.0, 0.0), tile=(16, 16), batch_depth=64):
+def quality_c(res_scale=1.0, sh_degree=-1, fmt="rgb8", bg=(0.0, 0.0, 0.0), tile=None, batch_depth=None):
+    """tile=None / batch_depth=None: chosen by the library's autotuner."""
+    tile = (0, 0) if tile is None else tile
+    batch_depth = 0 if batch_depth is None else batch_depth
     q = QualityC()
     q.res_scale = float(res_scale)
     q.sh_degree = int(sh_degree)
@@ -225,8 +230,12 @@ class Context:
         _check(lib().tigas_stage_times(self.handle, ctypes.byref(st)))
         return {f: (int(getattr(st, f)) if f == "frames" else float(getattr(st, f))) for f, _ in StageC._fields_}
 
-    def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=(16, 16),
-                         batch_depth=64):
+    def set_graphs(self, enable: bool):
+        """Capture/replay launch sequences as HIP graphs (default on)."""
+        _check(lib().tigas_set_graphs(self.handle, 1 if enable else 0))
+
+    def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=None,
+                         batch_depth=None):
         """(evaluations, contributions) of the blend kernel for one frame."""
         q = quality_c(res_scale, -1, "rgb8", (0, 0, 0), tile, batch_depth)
         ow, oh = output_size(width, height, res_scale)
@@ -239,7 +248,7 @@ class Context:
         return int(e.value), int(c.value)
 
     def render(self, scene: Scene, pose, intr, width, height, res_scale=1.0, fmt="rgb8", bg=(0, 0, 0),
-               tile=(16, 16), batch_depth=64, sh_degree=-1, out=None, stream=None):
+               tile=None, batch_depth=None, sh_degree=-1, out=None, stream=None):
         """Render one frame.  ``out``: a torch tensor on the GPU (written in place)
         or None (a host numpy array is returned)."""
         q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth)
@@ -291,7 +300,7 @@ class Context:
         return out
 
     def render_batch(self, scenes, poses, intrs, widths, heights, res_scales=None, fmt="rgb8", bg=(0, 0, 0),
-                     tile=(16, 16), batch_depth=64, outs=None, stream=None):
+                     tile=None, batch_depth=None, outs=None, stream=None):
         n = len(poses)
         res_scales = res_scales if res_scales is not None else [1.0] * n
         qs = (QualityC * n)(*[quality_c(res_scales[i], -1, fmt, bg, tile, batch_depth) for i in range(n)])
