@@ -72,7 +72,7 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
     if count_work:
         for i in range(steps):
             e, c = ctx.count_blend_work(s, traj[i % len(traj)], k, W, H, tile=(cfg["tile_w"], cfg["tile_h"]),
-                                        batch_depth=cfg["batch_depth"])
+                                        batch_depth=cfg["batch_depth"], ppl=cfg["pixels_per_lane"])
             st = ctx.stats()
             work["frames"] += 1
             work["evaluations"] += e
@@ -80,6 +80,7 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
             for f in ("visible", "duplicates", "fallbacks"):
                 work[f] += st[f]
     res = dict(head, tile=f"{cfg['tile_w']}x{cfg['tile_h']}", batch_depth=cfg["batch_depth"],
+               pixels_per_lane=cfg["pixels_per_lane"],
                stage_pass=prof, gpu_ms_per_frame=sum(v for kk, v in stages.items() if kk != "frames") / nfr,
                stage_ms={kk: v / nfr for kk, v in stages.items() if kk != "frames"},
                work=work, scene_bytes=s.bytes)
@@ -129,7 +130,66 @@ def run_batched(ctx, scene, torch, steps=30, warmup=3):
     return dict(views=n, megapixels_per_step=px / 1e6, step_ms_p50=p50, step_ms_p99=p99,
                 views_per_s=n * steps / total, megapixels_per_s=px * steps / total / 1e6,
                 sequential_views_per_s=n / seq, tile=f"{st['tile_w']}x{st['tile_h']}",
-                batch_depth=st["batch_depth"], duplicates=st["duplicates"], tiles=st["tiles"])
+                batch_depth=st["batch_depth"], pixels_per_lane=st["pixels_per_lane"], duplicates=st["duplicates"],
+                tiles=st["tiles"])
+
+
+def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0), budget_gb=48,
+                batch_mpx=6.0):
+    """The serving form: 64 clients (Poisson arrivals, random rungs of
+    1920x1080, their own 6DoF walks) on 4 resident FP16 scenes of 0.5/1/3/6M
+    Gaussians, replayed open-loop into the library's continuous-batching
+    server (2 slots, memory budget).  Full offered load (60 req/s per client)
+    with latest-pose-wins, then a rate sweep without supersession to find the
+    largest per-client rate whose p99 latency for 1080p frames of the 3M scene
+    stays within 10 ms."""
+    from paper_2605_08699_amd import synth
+    scenes = [ctx.load_scene(sc, "f16") for sc in synth.serving_scenes()]
+    k = synth.fov_intrinsics(1920, 1080)
+    outs = [torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda") for _ in range(64)]
+
+    def trace(rate):
+        clients = synth.serving_clients(64, rate_hz=rate, duration_s=seconds)
+        reqs, meta = [], []
+        for c, cl in enumerate(clients):
+            for j in range(len(cl.arrivals_s)):
+                reqs.append((cl.arrivals_s[j], c, cl.scene_id, cl.poses[j], float(cl.rungs[j])))
+        reqs.sort(key=lambda r: r[0])
+        cs = [tigas.request_c(scenes[sid], pose, k, 1920, 1080, outs[c], client=c, arrival_s=t, res_scale=rung)
+              for t, c, sid, pose, rung in reqs]
+        return cs, reqs
+
+    def run(rate, supersede):
+        cs, reqs = trace(rate)
+        with tigas.Server(ctx, slots=2, max_batch=64, hbm_budget=int(budget_gb * 2 ** 30), supersede=supersede,
+                          max_batch_pixels=int(batch_mpx * 1e6)) as sv:
+            done = sv.replay(cs)
+            st = sv.stats()
+        lat, lat_hd = [], []
+        for d, r in zip(done, reqs):
+            if d["status"] != 0 or r[0] < warm:
+                continue
+            ms = 1e3 * (d["done_s"] - d["arrival_s"])
+            lat.append(ms)
+            if r[2] == 2 and r[4] == 1.0:
+                lat_hd.append(ms)
+        rendered = sum(1 for d, r in zip(done, reqs) if d["status"] == 0 and r[0] >= warm)
+        pct = lambda a, q: float(np.percentile(a, q)) if a else None
+        return dict(rate_per_client=rate, offered_req_per_s=len(reqs) / seconds, rendered_frames_per_s=rendered /
+                    (seconds - warm), p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p50_ms_1080p_3M=pct(lat_hd, 50),
+                    p99_ms_1080p_3M=pct(lat_hd, 99), superseded=st["superseded"], deferred=st["deferred"],
+                    admitted=st["admitted"], batches=st["batches"],
+                    mean_batch=st["admitted"] / max(st["batches"], 1), failed=st["failed"])
+
+    full = run(60.0, True)
+    sweep = [run(r, False) for r in rates]
+    ok = [x["rate_per_client"] for x in sweep if x["p99_ms_1080p_3M"] is not None and x["p99_ms_1080p_3M"] <= 10.0]
+    for s_ in scenes:
+        s_.free()
+    return dict(seconds=seconds, warmup_s=warm, clients=64, hbm_budget_gb=budget_gb, slots=2,
+                max_batch_megapixels=batch_mpx,
+                full_load_latest_pose_wins=full, sweep_no_supersede=sweep,
+                max_rate_per_client_p99_1080p_3M_within_10ms=max(ok) if ok else None)
 
 
 def roofline(v, n, storage):
@@ -191,6 +251,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py renders on one GPU only: the rasterizer has no multi-GPU path in this build "
@@ -230,7 +292,8 @@ def main():
         "config": {"workload": "3M Gaussians (64 clusters + 40% surface splats, SH deg 3), 1920x1080, "
                                "300-pose 6DoF trajectory, FP32 attributes, RGB8 frame in HBM",
                    "n_gaussians": scene.n, "width": W, "height": H, "poses": len(traj),
-                   "tile": main_v["tile"], "batch_depth": main_v["batch_depth"]},
+                   "tile": main_v["tile"], "batch_depth": main_v["batch_depth"],
+                   "pixels_per_lane": main_v["pixels_per_lane"]},
         "p50_ms": main_v["p50_ms"],
         "p99_ms": main_v["p99_ms"],
         "gpu_ms_per_frame": main_v["gpu_ms_per_frame"],
@@ -239,7 +302,8 @@ def main():
                            for x in ("visible", "duplicates", "evaluations", "contributions", "fallbacks")},
         "stage_pass": main_v["stage_pass"],
         "variants": {kk: {x: vv[x] for x in ("frames_per_s", "p50_ms", "p99_ms", "gpu_ms_per_frame", "stage_ms",
-                                              "scene_bytes", "tile", "batch_depth")} for kk, vv in variants.items()},
+                                              "scene_bytes", "tile", "batch_depth", "pixels_per_lane")}
+                     for kk, vv in variants.items()},
         "roofline": {x: rl[x] for x in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": rl["kernel"],
     }
@@ -247,6 +311,12 @@ def main():
         line["batched"] = run_batched(ctx, scene, torch)
         print(f"# batched: {line['batched']['views_per_s']:.0f} views/s "
               f"(one by one: {line['batched']['sequential_views_per_s']:.0f})", file=sys.stderr, flush=True)
+    if not args.no_serving:
+        line["serving"] = run_serving(ctx, torch, tigas, seconds=args.serve_seconds)
+        f = line["serving"]["full_load_latest_pose_wins"]
+        print(f"# serving at {f['offered_req_per_s']:.0f} req/s offered: {f['rendered_frames_per_s']:.0f} frames/s, "
+              f"p50 {f['p50_ms']:.2f} ms p99 {f['p99_ms']:.2f} ms (1080p 3M: p99 {f['p99_ms_1080p_3M']})",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, traj[0], k, W, H)
     print(json.dumps(line), flush=True)

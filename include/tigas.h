@@ -100,6 +100,8 @@ typedef struct {
     float bg[3];
     int tile_w, tile_h; /* 8x8, 16x16, 16x32 or 32x16; 0x0 = autotuned for the workload's shape */
     int batch_depth;    /* Gaussians staged per wavefront batch: 64, 128 or 256; 0 = autotuned (64 with an explicit tile) */
+    int pixels_per_lane; /* blend pixels per lane, 1 or 2 (tiles 16 or more tall); 0 = autotuned (1 with an
+                            explicit tile).  Frames are identical for every choice of these three fields. */
 } tigas_quality;
 
 /* Output frame.  data: device pointer when is_device, host otherwise;
@@ -120,7 +122,7 @@ typedef struct {
     int64_t tiles;
     int64_t sort_passes;
     int64_t rerenders;  /* workspace regrowths after an overflowing first attempt */
-    int32_t tile_w, tile_h, batch_depth; /* configuration used (requested or autotuned) */
+    int32_t tile_w, tile_h, batch_depth, pixels_per_lane; /* configuration used (requested or autotuned) */
 } tigas_stats;
 
 /* Creates a context on HIP device `device`: a stream, workspaces and the
@@ -175,6 +177,20 @@ tigas_status tigas_profile_stages(tigas_context* ctx, int enable);
  * replayed (default on; environment TIGAS_GRAPHS=0 turns it off at context
  * creation).  This switches it for the context. */
 tigas_status tigas_set_graphs(tigas_context* ctx, int enable);
+/* Radix sort of the key lists (the sort stage of Sec. 3's pipeline, the
+ * same stable LSD passes either way, so the lists are identical):
+ * single_pass = 0 runs each digit pass as count, scan and scatter kernels
+ * (the default); 1 runs one histogram kernel per sort and then one kernel
+ * per pass whose workgroups chain their digit offsets through a global
+ * look-back table (environment TIGAS_SORT=1 selects it at context creation).
+ * Its waits on other workgroups are bounded: should one give up, the frame
+ * is rendered again with the default passes, which then stay selected for
+ * the context, and tigas_sort_fallbacks counts the event.
+ * Returns TIGAS_E_INVALID for a null context. */
+tigas_status tigas_set_sort(tigas_context* ctx, int single_pass);
+/* Frames re-rendered because a single-pass sort wait gave up (-1 for a null
+ * context). */
+int64_t tigas_sort_fallbacks(const tigas_context* ctx);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 
 /* Renders like tigas_render with a blend kernel that also counts the work it
@@ -183,6 +199,76 @@ tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 tigas_status tigas_count_blend_work(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
                                     int width, int height, const tigas_quality* q, tigas_frame* out,
                                     int64_t* evaluations, int64_t* contributions);
+
+/* ---------------------------------------------------------------------------
+ * Serving form.  Many clients send per-frame requests (pose, intrinsics, ABR
+ * rung) for resident scenes (Sections 4.2 and 5.1: stateless per-frame
+ * requests, one shared resident model per scene, every request an isolated
+ * render task).  The server admits requests by a device-memory budget and
+ * renders them with continuous batching: whenever one of its slots (a stream
+ * with its own workspace) is idle, all pending requests that fit the slot's
+ * share of the budget (oldest first, up to max_batch) are rendered there as
+ * one launch sequence, while requests arriving meanwhile wait for the next
+ * idle slot; batches on different slots overlap on the device.  Frames are
+ * identical to rendering each request alone.
+ * ------------------------------------------------------------------------- */
+typedef struct tigas_server tigas_server;
+
+typedef struct {
+    int slots;         /* concurrent batches (streams, default priority); 0 = 2, at most 8 */
+    int max_batch;     /* requests per batch; 0 = 64 */
+    size_t hbm_budget; /* workspace bytes across all slots (resident scenes excluded), reserved at
+                          creation; 0 = unlimited (workspaces grow on demand) */
+    int supersede;     /* 1: a client's newer request replaces its request still waiting (latest pose wins) */
+    int tile_w, tile_h, batch_depth; /* 0 = 16x32 tiles, depth 64 */
+    int pixels_per_lane;             /* 0 = 2 for tiles 16 or more tall */
+    int64_t max_batch_pixels; /* output pixels per batch (bounds a batch's duration); 0 = no cap */
+} tigas_server_config;
+
+/* One request.  The output frame must stay valid until its completion is
+ * reported; `arrival_s` is used only by tigas_server_replay. */
+typedef struct {
+    tigas_scene* scene;
+    tigas_pose pose;
+    tigas_intrinsics intr;
+    int width, height;
+    tigas_quality q; /* rung, SH degree, format, background (tile fields ignored) */
+    tigas_frame out;
+    int client;
+    double arrival_s;
+} tigas_request;
+
+/* status: 0 rendered, 1 superseded (not rendered), < 0 a tigas_status error.
+ * Times in seconds on the server clock (replay: relative to its start). */
+typedef struct {
+    int64_t id;
+    int client;
+    int status;
+    double arrival_s, dispatch_s, done_s;
+    int batch_size;
+} tigas_completion;
+
+typedef struct {
+    int64_t admitted, deferred, superseded, rendered, failed, batches, max_batch_seen, pending;
+} tigas_server_stats;
+
+/* Starts the dispatcher and slot threads.  E_INVALID for bad configuration. */
+tigas_status tigas_server_create(tigas_context* ctx, const tigas_server_config* cfg, tigas_server** out);
+/* Waits for every submitted request, then stops the threads and frees the
+ * slot workspaces. */
+void tigas_server_destroy(tigas_server* server);
+/* Queues a request arriving now.  E_BUDGET when the request alone needs more
+ * workspace than a slot's share of the budget; E_INVALID for bad requests. */
+tigas_status tigas_server_submit(tigas_server* server, const tigas_request* req, int64_t* id);
+/* Moves up to max completions (in completion order) into out; *n = count. */
+tigas_status tigas_server_poll(tigas_server* server, tigas_completion* out, int max, int* n);
+/* Blocks until every submitted request has completed. */
+tigas_status tigas_server_drain(tigas_server* server);
+/* Open-loop replay: submits reqs[i] at time reqs[i].arrival_s after the call
+ * starts (from the calling thread), waits for all of them and writes the
+ * completion of reqs[i] to out[i]. */
+tigas_status tigas_server_replay(tigas_server* server, const tigas_request* reqs, int n, tigas_completion* out);
+tigas_status tigas_server_get_stats(tigas_server* server, tigas_server_stats* out);
 
 /* Thread-local message of the last failing call on this thread ("" if none);
  * valid until the next call on this thread. */

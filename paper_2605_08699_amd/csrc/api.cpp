@@ -13,6 +13,9 @@
 #include <atomic>
 #include <chrono>
 #include <cstdlib>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -153,12 +156,12 @@ uint16_t f32_to_f16(float f) {
 namespace {
 
 struct TileCfg {
-    int tw, th, bd;
-    bool operator==(const TileCfg& o) const { return tw == o.tw && th == o.th && bd == o.bd; }
+    int tw, th, bd, ppl;  // tile width/height, staged entries per wave batch, pixels per lane
 };
 
-const TileCfg kTileCandidates[] = {{8, 8, 64},    {8, 8, 128},    {8, 8, 256},    {16, 16, 64}, {16, 16, 128},
-                                   {16, 16, 256}, {16, 32, 64},   {16, 32, 128},  {16, 32, 256}};
+const TileCfg kTileCandidates[] = {{8, 8, 64, 1},   {8, 8, 128, 1},   {16, 16, 64, 1}, {16, 16, 64, 2},
+                                   {16, 16, 128, 2}, {16, 32, 64, 1}, {16, 32, 64, 2}, {16, 32, 128, 2},
+                                   {32, 16, 64, 2}};
 
 // A group of views of one scene inside a launch sequence.
 struct Group {
@@ -171,8 +174,9 @@ struct Plan {
     std::vector<ViewParams> views;
     std::vector<Group> groups;
     uint32_t nrec = 0, n_tiles = 0;
-    TileCfg tc{16, 16, 64};
+    TileCfg tc{16, 16, 64, 1};
     bool persistent = false;  // blend as a persistent kernel over a tile work queue
+    bool allow_graph = true;  // capture/replay (off for one-off shapes such as serving batches)
 };
 
 struct GraphEntry {
@@ -189,10 +193,12 @@ struct Workspace {
     // per record
     DevBuf rec0, rec1, rec2, bbox, zkey, touched;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
+    DevBuf fb_list;  // near-singular Gaussians for the FP64 conic kernel
     DevBuf counters;
     // per duplicate (also holds the visible Gaussians during the depth passes)
     DevBuf key[2], val[2], ext[2];
     DevBuf hist, totals, queue;
+    DevBuf lookback;  // single-pass sort: 256 look-back entries per 2048-key chunk
     // emission-order copies for the inspection entry point
     DevBuf dbg_key, dbg_val, dbg_ext;
     // per tile / per view
@@ -219,6 +225,9 @@ struct Workspace {
         o.blk_vis = blk_vis.as<uint32_t>();
         o.blk_fb = blk_fb.as<uint32_t>();
         o.blk_view = blk_view.as<uint32_t>();
+        o.fb_list = fb_list.as<uint2>();
+        o.fb_cap = rec_cap;
+        o.cnt = counters.as<Counters>();
         return o;
     }
     void grow(DevBuf& b, size_t bytes) {
@@ -233,6 +242,7 @@ struct Workspace {
         grow(touched, r * 4);
         const size_t nb = r / K1_THREADS + 1;
         for (DevBuf* b : {&blk_sum, &blk_vis, &blk_fb, &blk_view, &blk_off, &blk_sum2, &blk_off2}) grow(*b, nb * 4);
+        grow(fb_list, r * 8);
         rec_cap = (uint32_t)r;
     }
     void ensure_dups(uint32_t cap) {
@@ -245,7 +255,12 @@ struct Workspace {
         }
         grow(hist, (size_t)256 * SORT_MAX_BLOCKS * 4);
         grow(totals, (size_t)256 * MAX_SORT_PASSES * 4);
-        grow(queue, 8 * 4);
+        grow(queue, (8 + MAX_SORT_PASSES) * 4);  // blend band queues, then sort tickets
+        if (lookback.ensure(((size_t)cap / SORT_CHUNK + 2) * 256 * 8)) {
+            // entries carry a frame epoch; zero them once so no garbage can match
+            HIPCHK(hipMemset(lookback.p, 0, lookback.bytes));
+            ++gen;
+        }
         dup_cap = cap;
     }
     void ensure_tiles(uint32_t n) {
@@ -289,6 +304,8 @@ struct tigas_context {
     std::mutex stats_mu;
     std::atomic<bool> profile{false};
     std::atomic<bool> use_graphs{true};
+    std::atomic<bool> sort_onepass{false};  // single-pass (look-back) radix sort
+    std::atomic<int64_t> sort_fallbacks{0};  // frames redone after a look-back wait gave up
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
     std::mutex tune_mu;
@@ -302,6 +319,7 @@ struct tigas_context {
             p.reset(new Workspace());
             p->stream = s;
             p->host_counters.ensure(sizeof(Counters));
+            if (p->counters.ensure(sizeof(Counters))) HIPCHK(hipMemset(p->counters.p, 0, sizeof(Counters)));
         }
         return *p;
     }
@@ -342,7 +360,11 @@ TileCfg tile_cfg(const tigas_quality* q) {
     if (!okt) fail(TIGAS_E_INVALID, "tile must be 8x8, 16x16, 16x32 or 32x16");
     if (bd == 0) bd = 64;
     if (bd != 64 && bd != 128 && bd != 256) fail(TIGAS_E_INVALID, "batch_depth must be 64, 128 or 256");
-    return {tw, th, bd};
+    int ppl = q ? q->pixels_per_lane : 0;
+    if (ppl == 0) ppl = 1;
+    if (ppl != 1 && ppl != 2) fail(TIGAS_E_INVALID, "pixels_per_lane must be 1 or 2");
+    if (th < 16) ppl = 1;
+    return {tw, th, bd, ppl};
 }
 
 // Camera of one view: V = R^T, the FP32 key constant, rung-scaled intrinsics
@@ -383,6 +405,7 @@ ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_
     if (v.fmt != 0 && v.fmt != 1) fail(TIGAS_E_INVALID, "unknown frame format");
     for (int i = 0; i < 3; ++i) v.bg[i] = q ? q->bg[i] : 0.f;
     if (!finite3(v.bg, 3)) fail(TIGAS_E_INVALID, "background is not finite");
+    v.scene = sc->view;
     return v;
 }
 
@@ -430,14 +453,19 @@ std::string shape_key(const Plan& plan, bool with_tiles) {
         k += buf;
     }
     if (with_tiles) {
-        std::snprintf(buf, sizeof buf, "t%dx%d:%d:%d", plan.tc.tw, plan.tc.th, plan.tc.bd, (int)plan.persistent);
+        std::snprintf(buf, sizeof buf, "t%dx%d:%d:%d:%d", plan.tc.tw, plan.tc.th, plan.tc.bd, plan.tc.ppl,
+                      (int)plan.persistent);
         k += buf;
     }
     return k;
 }
 
 void prepare(Workspace& ws, const Plan& plan, bool debug) {
-    ws.counters.ensure(sizeof(Counters));
+    if (ws.counters.ensure(sizeof(Counters))) {
+        // the FP64-list count is cleared by each frame after use; start at zero
+        HIPCHK(hipMemset(ws.counters.p, 0, sizeof(Counters)));
+        ++ws.gen;
+    }
     ws.ensure_views((int)plan.views.size());
     ws.ensure_records(plan.nrec);
     ws.ensure_tiles(plan.n_tiles);
@@ -459,7 +487,8 @@ void prepare(Workspace& ws, const Plan& plan, bool debug) {
 // that holds the sorted lists.
 //   preprocess -> scan visible -> compact -> depth passes (visible Gaussians)
 //   -> duplicate in depth order -> tile passes (duplicates) -> ranges -> blend
-int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks) {
+int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks,
+            bool onepass) {
     hipStream_t st = ws.stream;
     auto mark = [&](int i) {
         if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
@@ -474,6 +503,7 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
         launch_preprocess(g.scene->view, vdev + g.first_view, plan.views.data() + g.first_view, g.nviews,
                           g.rec_base, g.n_pad, (uint32_t)g.first_view, o, st);
     }
+    if (plan.nrec) launch_conic_fp64(o, vdev, st);
     mark(1);
     const int nblk = (int)(plan.nrec / K1_THREADS);
     Counters* cnt = ws.counters.as<Counters>();
@@ -481,7 +511,7 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     zl.p[0] = ws.totals.as<uint32_t>();
     zl.n[0] = 256 * MAX_SORT_PASSES;
     zl.p[1] = ws.queue.as<uint32_t>();
-    zl.n[1] = 8;
+    zl.n[1] = 8 + MAX_SORT_PASSES;
     zl.p[2] = ws.ranges.as<uint32_t>();
     zl.n[2] = 2 * plan.n_tiles;
     zl.p[3] = nullptr;
@@ -498,8 +528,13 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     sb.totals = ws.totals.as<uint32_t>();
     // depth digits, on the visible Gaussians (record order in, depth order out)
     launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], st);
-    const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0, false, cnt, 0,
-                               o.touched, nullptr, st);
+    unsigned long long* lb = ws.lookback.as<unsigned long long>();
+    uint32_t* tickets = ws.queue.as<uint32_t>() + 8;
+    const int cv = onepass ? launch_sort_onesweep(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap,
+                                                  std::min(plan.nrec, ws.dup_cap), 0, false, cnt, 0, o.touched, lb,
+                                                  tickets, st)
+                           : launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0,
+                                         false, cnt, 0, o.touched, nullptr, st);
     // duplicates in depth order
     const int cd = cv ^ 1;
     launch_duplicate(o, nblk, sb.val[cv], sb.ext[cv], ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
@@ -513,13 +548,15 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     }
     // tile digits, on the duplicates
     const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
-    const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap, sort_blocks(ws.dup_cap), cd,
-                                debug, cnt, 4, nullptr, nullptr, st);
+    const int cur = onepass ? launch_sort_onesweep(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
+                                                   ws.dup_cap, cd, debug, cnt, 4, nullptr, lb, tickets, st)
+                            : launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
+                                          sort_blocks(ws.dup_cap), cd, debug, cnt, 4, nullptr, nullptr, st);
     mark(4);
     launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
-                 plan.tc.bd, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, st);
+                 plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, st);
     mark(6);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ws.host_counters.p, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -533,11 +570,13 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
                 unsigned long long* work) {
     std::memcpy(ws.host_views.p, plan.views.data(), sizeof(ViewParams) * plan.views.size());
     if (prof) ws.ensure_events();
-    const int pblocks = plan.persistent ? ctx->cus * blend_persistent_occupancy(plan.tc.tw, plan.tc.th, plan.tc.bd) : 0;
+    const int pblocks =
+        plan.persistent ? ctx->cus * blend_persistent_occupancy(plan.tc.tw, plan.tc.th, plan.tc.bd, plan.tc.ppl) : 0;
     // stage timing needs events between the launches: that runs uncaptured
-    const bool graph = ctx->use_graphs.load() && !debug && !work && !prof;
-    if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks);
-    const std::string key = shape_key(plan, true);
+    const bool onepass = ctx->sort_onepass.load();
+    const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof;
+    if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks, onepass);
+    const std::string key = shape_key(plan, true) + (onepass ? "s1" : "s3");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
         if (g.exec) HIPCHK(hipGraphExecDestroy(g.exec));
@@ -550,7 +589,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         HIPCHK(hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal));
         int cur = 0;
         try {
-            cur = enqueue(ws, plan, debug, prof, work, pblocks);
+            cur = enqueue(ws, plan, debug, prof, work, pblocks, onepass);
         } catch (...) {
             (void)hipStreamEndCapture(ws.stream, &graph_t);
             if (graph_t) (void)hipGraphDestroy(graph_t);
@@ -578,6 +617,18 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
     Counters c;
     std::memcpy(&c, ws.host_counters.p, sizeof(c));
     int rerenders = 0;
+    if (c.error) {
+        // a bounded wait of the single-pass sort gave up: the lists may be
+        // wrong.  Redo the frame with the three-kernel passes, which have no
+        // inter-workgroup waits, and keep them for this context.
+        ctx->sort_onepass.store(false);
+        if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
+        cur = launch_plan(ctx, ws, plan, debug, prof, work);
+        HIPCHK(hipStreamSynchronize(ws.stream));
+        std::memcpy(&c, ws.host_counters.p, sizeof(c));
+        rerenders = 1;
+        ctx->sort_fallbacks.fetch_add(1);
+    }
     if (c.overflow) {
         const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
         if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
@@ -588,7 +639,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
         HIPCHK(hipStreamSynchronize(ws.stream));
         std::memcpy(&c, ws.host_counters.p, sizeof(c));
         if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
-        rerenders = 1;
+        rerenders += 1;
     }
     ws.last_D = c.D;
     std::lock_guard<std::mutex> lk(ctx->stats_mu);
@@ -609,6 +660,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
     ctx->last.tile_w = plan.tc.tw;
     ctx->last.tile_h = plan.tc.th;
     ctx->last.batch_depth = plan.tc.bd;
+    ctx->last.pixels_per_lane = plan.tc.ppl;
     int64_t n = 0;
     for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
     ctx->last.n = n;
@@ -623,9 +675,9 @@ void load_tune_file(tigas_context* ctx) {
     if (!f) return;
     char line[4096];
     while (std::fgets(line, sizeof line, f)) {
-        int tw, th, bd;
+        int tw, th, bd, ppl;
         char key[4000];
-        if (std::sscanf(line, "%d %d %d %3999s", &tw, &th, &bd, key) == 4) ctx->tuned[key] = {tw, th, bd};
+        if (std::sscanf(line, "%d %d %d %d %3999s", &tw, &th, &bd, &ppl, key) == 5) ctx->tuned[key] = {tw, th, bd, ppl};
     }
     std::fclose(f);
 }
@@ -635,8 +687,8 @@ void save_tune_file(tigas_context* ctx) {
     const std::string tmp = ctx->tune_file + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
-    for (const auto& kv : ctx->tuned) std::fprintf(f, "%d %d %d %s\n", kv.second.tw, kv.second.th, kv.second.bd,
-                                                   kv.first.c_str());
+    for (const auto& kv : ctx->tuned)
+        std::fprintf(f, "%d %d %d %d %s\n", kv.second.tw, kv.second.th, kv.second.bd, kv.second.ppl, kv.first.c_str());
     std::fclose(f);
     std::rename(tmp.c_str(), ctx->tune_file.c_str());
 }
@@ -653,7 +705,7 @@ TileCfg autotune(tigas_context* ctx, Workspace& ws, Plan& plan) {
         if (it != ctx->tuned.end()) return it->second;
     }
     const bool prof = ctx->profile.exchange(false);
-    TileCfg best = kTileCandidates[3];
+    TileCfg best = kTileCandidates[2];
     double best_ms = 1e30;
     for (const TileCfg& tc : kTileCandidates) {
         set_tiles(plan, tc);
@@ -724,9 +776,10 @@ void render_views(tigas_context* ctx, Workspace& ws, Plan& plan, const tigas_qua
     // this workload (16x16 for the inspection and counting entry points)
     TileCfg tc = tile_cfg(q);
     if (!tile_requested(q) && !dbg && !work_out) {
-        const int bd_req = tc.bd;
+        const TileCfg req = tc;
         tc = autotune(ctx, ws, plan);
-        if (q && q->batch_depth != 0) tc.bd = bd_req;
+        if (q && q->batch_depth != 0) tc.bd = req.bd;
+        if (q && q->pixels_per_lane != 0 && tc.th >= 16) tc.ppl = req.ppl;
     }
     set_tiles(plan, tc);
     unsigned long long* work = nullptr;
@@ -833,6 +886,246 @@ void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_
 
 }  // namespace
 
+
+// ================================================================ serving
+
+struct tigas_server {
+    tigas_context* ctx = nullptr;
+    tigas_server_config cfg{};
+    std::chrono::steady_clock::time_point t0;
+
+    struct Req {
+        int64_t id;
+        tigas_request r;
+        double arrival, dispatch = 0, done = 0;
+        size_t need = 0;
+    };
+    struct Slot {
+        hipStream_t stream = nullptr;
+        std::thread th;
+        std::vector<Req> batch;
+        bool busy = false;
+    };
+
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_slot, cv_done;
+    std::deque<Req> pending;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::vector<tigas_completion> completed;
+    std::thread dispatcher;
+    bool stop = false;
+    int64_t next_id = 0, submitted = 0, finished = 0;
+    tigas_server_stats st{};
+    // largest duplicates-per-record seen, to size admission estimates
+    double dup_per_rec = 4.0;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+uint32_t request_records(const tigas_request& r) { return round_up((uint64_t)r.scene->view.n, K1_THREADS); }
+
+// Device bytes a request adds to a batch's workspace: per record the
+// preprocess outputs (64 B) and block arrays, per expected duplicate the
+// double-buffered key / value / extra words (24 B), plus a staging frame
+// for host outputs.
+double request_pixels(const tigas_request& r) {
+    const double s = r.q.res_scale != 0.f ? r.q.res_scale : 1.0;
+    return std::floor(r.width * s + 0.5) * std::floor(r.height * s + 0.5);
+}
+
+size_t request_need(const tigas_server* sv, const tigas_request& r) {
+    const double rec = (double)request_records(r);
+    const double dup = std::max(4.0, sv->dup_per_rec) * 1.25 * rec;
+    size_t frame = 0;
+    if (!r.out.is_device) {
+        const float s = r.q.res_scale != 0.f ? r.q.res_scale : 1.f;
+        frame = (size_t)((double)r.width * s + 1) * (size_t)((double)r.height * s + 1) * 3 *
+                (r.q.fmt == TIGAS_OUT_RGBF32 ? 4 : 1);
+    }
+    return (size_t)(rec * 72.0 + dup * 24.0) + frame;
+}
+
+void server_render(tigas_server* sv, tigas_server::Slot& slot) {
+    std::vector<tigas_server::Req>& b = slot.batch;
+    // views of one scene next to each other: one preprocess launch per scene
+    std::stable_sort(b.begin(), b.end(), [](const tigas_server::Req& x, const tigas_server::Req& y) {
+        return (uintptr_t)x.r.scene < (uintptr_t)y.r.scene;
+    });
+    tigas_context* ctx = sv->ctx;
+    Plan plan;
+    plan.persistent = true;
+    plan.allow_graph = false;
+    std::vector<tigas_frame> outs;
+    std::vector<std::unique_ptr<SceneRef>> refs;
+    for (const auto& q : b) {
+        plan.views.push_back(make_view(q.r.scene, &q.r.pose, &q.r.intr, q.r.width, q.r.height, &q.r.q));
+        outs.push_back(q.r.out);
+    }
+    for (size_t i = 0; i < b.size();) {
+        size_t j = i;
+        while (j < b.size() && b[j].r.scene == b[i].r.scene) ++j;
+        const uint32_t n_pad = request_records(b[i].r);
+        plan.groups.push_back({b[i].r.scene, (int)i, (int)(j - i), plan.nrec, n_pad});
+        refs.emplace_back(new SceneRef(b[i].r.scene));
+        plan.nrec += n_pad * (uint32_t)(j - i);
+        i = j;
+    }
+    tigas_quality q{};
+    q.tile_w = sv->cfg.tile_w;
+    q.tile_h = sv->cfg.tile_h;
+    q.batch_depth = sv->cfg.batch_depth;
+    q.pixels_per_lane = sv->cfg.pixels_per_lane;
+    Workspace& ws = ctx->workspace(slot.stream);
+    render_views(ctx, ws, plan, &q, outs.data(), nullptr, nullptr);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const double dpr = (double)ws.last_D / std::max<double>(1.0, (double)plan.nrec);
+    sv->dup_per_rec = std::max(sv->dup_per_rec, dpr);
+}
+
+void slot_main(tigas_server* sv, tigas_server::Slot* slot) {
+    (void)hipSetDevice(sv->ctx->device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_slot.wait(lk, [&] { return sv->stop || slot->busy; });
+        if (!slot->busy && sv->stop) return;
+        const double t_disp = sv->now();
+        for (auto& r : slot->batch) r.dispatch = t_disp;
+        lk.unlock();
+        int status = 0;
+        std::string err;
+        try {
+            server_render(sv, *slot);
+        } catch (const Error& e) {
+            status = e.st;
+            err = e.what();
+        } catch (const std::exception& e) {
+            status = TIGAS_E_DEVICE;
+            err = e.what();
+        }
+        const double t_done = sv->now();
+        lk.lock();
+        for (auto& r : slot->batch) {
+            tigas_completion c{};
+            c.id = r.id;
+            c.client = r.r.client;
+            c.status = status;
+            c.arrival_s = r.arrival;
+            c.dispatch_s = r.dispatch;
+            c.done_s = t_done;
+            c.batch_size = (int)slot->batch.size();
+            sv->completed.push_back(c);
+        }
+        sv->finished += (int64_t)slot->batch.size();
+        sv->st.batches += 1;
+        sv->st.rendered += (int64_t)slot->batch.size();
+        if (status != 0) sv->st.failed += (int64_t)slot->batch.size();
+        slot->batch.clear();
+        slot->busy = false;
+        sv->cv_sched.notify_all();
+        sv->cv_done.notify_all();
+    }
+}
+
+// Continuous batching: whenever a slot is idle and requests are pending, the
+// pending requests (oldest first) that fit the slot's share of the memory
+// budget (and the batch limit) are dispatched to it as one launch sequence.
+// Requests arriving meanwhile wait for the next idle slot; slots run on their
+// own streams, so batches overlap on the device.
+void dispatcher_main(tigas_server* sv) {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        tigas_server::Slot* idle = nullptr;
+        sv->cv_sched.wait(lk, [&] {
+            if (sv->stop) return true;
+            if (sv->pending.empty()) return false;
+            for (auto& s : sv->slots)
+                if (!s->busy) {
+                    idle = s.get();
+                    return true;
+                }
+            return false;
+        });
+        if (sv->stop) return;
+        const size_t budget = sv->cfg.hbm_budget ? sv->cfg.hbm_budget / sv->slots.size() : SIZE_MAX;
+        const double px_cap = sv->cfg.max_batch_pixels > 0 ? (double)sv->cfg.max_batch_pixels : 1e300;
+        size_t used = 0;
+        double px = 0.0;
+        std::deque<tigas_server::Req> keep;
+        while (!sv->pending.empty()) {
+            tigas_server::Req r = std::move(sv->pending.front());
+            sv->pending.pop_front();
+            r.need = request_need(sv, r.r);
+            const double rpx = request_pixels(r.r);
+            // the first request of a batch is always taken (its need fits the
+            // share: checked at submit), later ones while budget and caps allow
+            const bool first = idle->batch.empty();
+            if ((int)idle->batch.size() < sv->cfg.max_batch && used + r.need <= budget && (first || px + rpx <= px_cap)) {
+                used += r.need;
+                px += rpx;
+                idle->batch.push_back(std::move(r));
+            } else {
+                if (used + r.need > budget) sv->st.deferred += 1;
+                keep.push_back(std::move(r));
+            }
+        }
+        sv->pending.swap(keep);
+        if (idle->batch.empty()) {
+            // the oldest request alone exceeds what is left: it was admitted at
+            // submit (fits the whole share), so take it by itself
+            idle->batch.push_back(std::move(sv->pending.front()));
+            sv->pending.pop_front();
+        }
+        sv->st.admitted += (int64_t)idle->batch.size();
+        sv->st.max_batch_seen = std::max<int64_t>(sv->st.max_batch_seen, (int64_t)idle->batch.size());
+        idle->busy = true;
+        sv->cv_slot.notify_all();
+    }
+}
+
+void validate_request(tigas_server* sv, const tigas_request* r) {
+    if (!r || !r->scene) fail(TIGAS_E_INVALID, "request without a scene");
+    if (r->scene->ctx != sv->ctx) fail(TIGAS_E_INVALID, "scene belongs to another context");
+    (void)make_view(r->scene, &r->pose, &r->intr, r->width, r->height, &r->q);
+    if (!r->out.data) fail(TIGAS_E_INVALID, "request without an output frame");
+    if (sv->cfg.hbm_budget && request_need(sv, *r) > sv->cfg.hbm_budget / sv->slots.size())
+        fail(TIGAS_E_BUDGET, "request needs more workspace than a slot's share of the memory budget");
+}
+
+int64_t submit_locked(tigas_server* sv, const tigas_request* r, double arrival) {
+    tigas_server::Req q;
+    q.id = sv->next_id++;
+    q.r = *r;
+    q.arrival = arrival;
+    if (sv->cfg.supersede) {
+        // latest pose wins: a newer request replaces the client's waiting one
+        for (auto it = sv->pending.begin(); it != sv->pending.end(); ++it)
+            if (it->r.client == r->client) {
+                tigas_completion c{};
+                c.id = it->id;
+                c.client = it->r.client;
+                c.status = 1;
+                c.arrival_s = it->arrival;
+                c.dispatch_s = arrival;
+                c.done_s = arrival;
+                sv->completed.push_back(c);
+                sv->finished += 1;
+                sv->st.superseded += 1;
+                sv->pending.erase(it);
+                break;
+            }
+    }
+    sv->pending.push_back(std::move(q));
+    sv->submitted += 1;
+    sv->cv_sched.notify_all();
+    return sv->next_id - 1;
+}
+
+}  // namespace
+
 // ================================================================== C ABI
 
 extern "C" {
@@ -854,6 +1147,7 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         if (const char* f = std::getenv("TIGAS_TUNE_CACHE")) c->tune_file = f;
         if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
+        if (const char* g = std::getenv("TIGAS_SORT")) c->sort_onepass.store(std::atoi(g) != 0);
         load_tune_file(c.get());
         *out = c.release();
     });
@@ -1039,6 +1333,15 @@ tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out) {
     });
 }
 
+tigas_status tigas_set_sort(tigas_context* ctx, int single_pass) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        ctx->sort_onepass.store(single_pass != 0);
+    });
+}
+
+int64_t tigas_sort_fallbacks(const tigas_context* ctx) { return ctx ? ctx->sort_fallbacks.load() : -1; }
+
 tigas_status tigas_set_graphs(tigas_context* ctx, int enable) {
     return guard([&] {
         if (!ctx) fail(TIGAS_E_INVALID, "null context");
@@ -1071,6 +1374,153 @@ tigas_status tigas_selftest_wave_scan(const uint32_t* in, uint32_t* out, int n) 
         HIPCHK(hipMemcpy(out, dout, (size_t)n * 4, hipMemcpyDeviceToHost));
         HIPCHK(hipFree(din));
         HIPCHK(hipFree(dout));
+    });
+}
+
+
+tigas_status tigas_server_create(tigas_context* ctx, const tigas_server_config* cfg, tigas_server** out) {
+    return guard([&] {
+        if (!ctx || !out) fail(TIGAS_E_INVALID, "null argument");
+        HIPCHK(hipSetDevice(ctx->device));
+        std::unique_ptr<tigas_server> sv(new tigas_server());
+        sv->ctx = ctx;
+        if (cfg) sv->cfg = *cfg;
+        if (sv->cfg.slots <= 0) sv->cfg.slots = 2;
+        if (sv->cfg.slots > 8) fail(TIGAS_E_INVALID, "at most 8 slots");
+        if (sv->cfg.max_batch <= 0) sv->cfg.max_batch = 64;
+        if (sv->cfg.tile_w == 0 && sv->cfg.tile_h == 0) {
+            sv->cfg.tile_w = 16;
+            sv->cfg.tile_h = 32;
+        }
+        tigas_quality q{};
+        q.tile_w = sv->cfg.tile_w;
+        q.tile_h = sv->cfg.tile_h;
+        q.batch_depth = sv->cfg.batch_depth;
+        const TileCfg tc = tile_cfg(&q);
+        sv->cfg.batch_depth = tc.bd;
+        if (sv->cfg.pixels_per_lane == 0) sv->cfg.pixels_per_lane = tc.th >= 16 ? 2 : 1;
+        sv->t0 = std::chrono::steady_clock::now();
+        for (int i = 0; i < sv->cfg.slots; ++i) {
+            std::unique_ptr<tigas_server::Slot> sl(new tigas_server::Slot());
+            HIPCHK(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
+            sv->slots.push_back(std::move(sl));
+        }
+        if (sv->cfg.hbm_budget) {
+            // reserve each slot's workspace for its whole share up front, so
+            // serving never reallocates (a reallocation waits for the device)
+            const size_t share = sv->cfg.hbm_budget / sv->slots.size();
+            const uint64_t recs = share / (72 + 5 * 24 + 1);
+            for (auto& sl : sv->slots) {
+                Workspace& ws = ctx->workspace(sl->stream);
+                std::lock_guard<std::mutex> lk(ws.mu);
+                ws.counters.ensure(sizeof(Counters));
+                ws.ensure_records((uint32_t)std::min<uint64_t>(recs, 0x7f000000ull));
+                ws.ensure_dups((uint32_t)std::min<uint64_t>(recs * 5, 0xfff00000ull));
+                ws.ensure_views(sv->cfg.max_batch);
+                ws.ensure_tiles((uint32_t)std::min<uint64_t>((uint64_t)sv->cfg.max_batch * 16384, 1u << 26));
+            }
+        }
+        for (auto& sl : sv->slots) sl->th = std::thread(slot_main, sv.get(), sl.get());
+        sv->dispatcher = std::thread(dispatcher_main, sv.get());
+        *out = sv.release();
+    });
+}
+
+void tigas_server_destroy(tigas_server* sv) {
+    if (!sv) return;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->finished >= sv->submitted; });
+        sv->stop = true;
+        sv->cv_sched.notify_all();
+        sv->cv_slot.notify_all();
+    }
+    if (sv->dispatcher.joinable()) sv->dispatcher.join();
+    for (auto& sl : sv->slots)
+        if (sl->th.joinable()) sl->th.join();
+    (void)hipSetDevice(sv->ctx->device);
+    for (auto& sl : sv->slots) {
+        {
+            std::lock_guard<std::mutex> lk(sv->ctx->mu);
+            sv->ctx->ws.erase(sl->stream);
+        }
+        (void)hipStreamDestroy(sl->stream);
+    }
+    delete sv;
+}
+
+tigas_status tigas_server_submit(tigas_server* sv, const tigas_request* r, int64_t* id) {
+    return guard([&] {
+        if (!sv) fail(TIGAS_E_INVALID, "null server");
+        validate_request(sv, r);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        const int64_t i = submit_locked(sv, r, sv->now());
+        if (id) *id = i;
+    });
+}
+
+tigas_status tigas_server_poll(tigas_server* sv, tigas_completion* out, int max, int* n) {
+    return guard([&] {
+        if (!sv || !n || (max > 0 && !out)) fail(TIGAS_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        const int k = std::min<int>(max, (int)sv->completed.size());
+        for (int i = 0; i < k; ++i) out[i] = sv->completed[i];
+        sv->completed.erase(sv->completed.begin(), sv->completed.begin() + k);
+        *n = k;
+    });
+}
+
+tigas_status tigas_server_drain(tigas_server* sv) {
+    return guard([&] {
+        if (!sv) fail(TIGAS_E_INVALID, "null server");
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->finished >= sv->submitted; });
+    });
+}
+
+tigas_status tigas_server_replay(tigas_server* sv, const tigas_request* reqs, int n, tigas_completion* out) {
+    return guard([&] {
+        if (!sv || (n > 0 && (!reqs || !out))) fail(TIGAS_E_INVALID, "null argument");
+        for (int i = 0; i < n; ++i) validate_request(sv, &reqs[i]);
+        std::vector<int64_t> ids(n);
+        const double base = sv->now();
+        for (int i = 0; i < n; ++i) {
+            const double t = base + reqs[i].arrival_s;
+            // open loop: wait for the arrival time (sleep, then spin the last 200 us)
+            for (;;) {
+                const double left = t - sv->now();
+                if (left <= 0) break;
+                if (left > 3e-4) std::this_thread::sleep_for(std::chrono::duration<double>(left - 2e-4));
+            }
+            std::lock_guard<std::mutex> lk(sv->mu);
+            ids[i] = submit_locked(sv, &reqs[i], t);
+        }
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->finished >= sv->submitted; });
+        std::map<int64_t, tigas_completion> byid;
+        for (const auto& c : sv->completed) byid[c.id] = c;
+        std::vector<tigas_completion> rest;
+        for (int i = 0; i < n; ++i) {
+            auto it = byid.find(ids[i]);
+            out[i] = it != byid.end() ? it->second : tigas_completion{};
+            if (it != byid.end()) {
+                out[i].arrival_s -= base;
+                out[i].dispatch_s -= base;
+                out[i].done_s -= base;
+                byid.erase(it);
+            }
+        }
+        for (const auto& kv : byid) rest.push_back(kv.second);
+        sv->completed.swap(rest);
+    });
+}
+
+tigas_status tigas_server_get_stats(tigas_server* sv, tigas_server_stats* out) {
+    return guard([&] {
+        if (!sv || !out) fail(TIGAS_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        *out = sv->st;
+        out->pending = (int64_t)sv->pending.size();
     });
 }
 

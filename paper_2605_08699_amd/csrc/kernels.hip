@@ -186,7 +186,7 @@ constexpr float LN255 = 5.5412635451584258f;
 constexpr float KAPPA_INV = 1.0f / 64.0f;  // FP64 fallback when a*c > 64 det
 
 // FP64 recomputation of the 2D covariance from the FP32 inputs.
-__device__ __noinline__ void cov2d_fp64(const float* q32, const float* ls32, float mx, float my, float mz,
+__device__ __forceinline__ void cov2d_fp64(const float* q32, const float* ls32, float mx, float my, float mz,
                                         const ViewParams& v, double* abc) {
     double qw = q32[0], qx = q32[1], qy = q32[2], qz = q32[3];
     const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -221,11 +221,33 @@ __device__ __noinline__ void cov2d_fp64(const float* q32, const float* ls32, flo
     abc[2] = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2] + (double)DILATION;
 }
 
+// SH coefficients of Gaussian g (the planes of degree <= DEG) decoded to FP32.
+template <int ST, int DEG>
+__device__ __forceinline__ void load_sh(const SceneView& s, int64_t n, int64_t g, float* k) {
+    if (ST == 0) {
+        const float4* sh = reinterpret_cast<const float4*>(s.sh);
+        constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 3) / 4;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const float4 t = sh[(int64_t)p * n + g];
+            k[4 * p] = t.x;
+            k[4 * p + 1] = t.y;
+            k[4 * p + 2] = t.z;
+            k[4 * p + 3] = t.w;
+        }
+    } else {
+        const uint4* sh = reinterpret_cast<const uint4*>(s.sh);
+        constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 7) / 8;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) unpack8(sh[(int64_t)p * n + g], &k[8 * p], ST);
+    }
+}
+
 template <int ST, int DEG>
 __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const ViewParams* __restrict__ views,
                                                            int nviews, uint32_t rec_base, uint32_t n_pad,
                                                            uint32_t view_base, PreOut o) {
-    __shared__ uint32_t red[K1_THREADS / 64];
+    __shared__ uint32_t red[2][K1_THREADS / 64][3];
     const int64_t g = (int64_t)blockIdx.x * K1_THREADS + threadIdx.x;
     const bool in = g < s.n;
     const int64_t n = s.n;
@@ -264,6 +286,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
     const float k2m = __builtin_fmaf(k2, 1.0f + 1.0f / 512.0f, 1.0f / 4096.0f);
     // M = Rq diag(exp(ls)), Sigma = M M^T
     float M[9];
+    float smax = 0.0f;  // largest scale: bounds the screen footprint before the EWA step
     {
         const float inv = 1.0f / sqrtf(qn2);
         const float w = q[0] * inv, x = q[1] * inv, y = q[2] * inv, z = q[3] * inv;
@@ -271,6 +294,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
                             2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
                             2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
         const float sc[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+        smax = fmaxf(sc[0], fmaxf(sc[1], sc[2]));
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -299,6 +323,17 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             // pixel centre of the Gaussian: u = fx x/z + cx, v = fy y/z + cy
             const df u = df_add(df_mulf(df_div(px, pz), v.fx), df{v.cx, 0.0f});
             const df w = df_add(df_mulf(df_div(py, pz), v.fy), df{v.cy, 0.0f});
+            // start the SH loads now when the footprint can reach the image, so
+            // they arrive during the EWA step: the footprint half-width is at
+            // most 3.34 (f/z (1 + lim) max scale + 0.55) pixels
+            {
+                const float rb = 3.4f * (fmaxf(v.fx, v.fy) / zc * (1.0f + fmaxf(v.lim_x, v.lim_y)) * smax + 0.6f) + 1.0f;
+                const bool maybe = u.hi > -rb && u.hi < (float)v.width + rb && w.hi > -rb && w.hi < (float)v.height + rb;
+                if (maybe && !sh_loaded) {
+                    load_sh<ST, DEG>(s, n, g, k);
+                    sh_loaded = true;
+                }
+            }
             // EWA: T = J V with the Jacobian at the clamped direction; Sigma2D = (T M)(T M)^T + 0.3 I
             const float iz = 1.0f / zc;
             const float rx = fminf(fmaxf(px.hi * iz, -v.lim_x), v.lim_x);
@@ -323,18 +358,11 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             const float det = ac - b * b;
             float ca, cb, cc;
             if (!(det > ac * KAPPA_INV)) {
-                // near-singular 2D covariance: covariance, determinant and
-                // conic recomputed in FP64
-                double abc[3];
-                cov2d_fp64(q, ls, mx, my, mz, v, abc);
-                const double d64 = abc[0] * abc[2] - abc[1] * abc[1];
-                ca = (float)(abc[2] / d64);
-                cb = (float)(-abc[1] / d64);
-                cc = (float)(abc[0] / d64);
-                a = (float)abc[0];
-                c = (float)abc[2];
+                // near-singular 2D covariance: its conic is recomputed in FP64
+                // by k_conic_fp64 (listed below); a and c are sums of squares
+                // and exact enough for the footprint
+                ca = cb = cc = 0.0f;
                 fb = 1;
-                vis = d64 > 0.0;
             } else {
                 const float id = 1.0f / det;
                 ca = c * id;
@@ -364,20 +392,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             }
             if (touched) {
                 if (!sh_loaded) {
-                    if (ST == 0) {
-                        const float4* sh = reinterpret_cast<const float4*>(s.sh);
-                        constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 3) / 4;
-#pragma unroll
-                        for (int p = 0; p < NP; ++p) {
-                            const float4 t = sh[(int64_t)p * n + g];
-                            k[4 * p] = t.x; k[4 * p + 1] = t.y; k[4 * p + 2] = t.z; k[4 * p + 3] = t.w;
-                        }
-                    } else {
-                        const uint4* sh = reinterpret_cast<const uint4*>(s.sh);
-                        constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 7) / 8;
-#pragma unroll
-                        for (int p = 0; p < NP; ++p) unpack8(sh[(int64_t)p * n + g], &k[8 * p], ST);
-                    }
+                    load_sh<ST, DEG>(s, n, g, k);
                     sh_loaded = true;
                 }
                 // colour at the direction camera centre -> Gaussian
@@ -390,6 +405,19 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
                 r2 = make_float4(rgb[0], rgb[1], rgb[2], op);
             }
         }
+        {
+            // append near-singular visible Gaussians to the FP64 list (one atomic per wave)
+            const bool lst = touched && fb;
+            const uint64_t m = ballot(lst);
+            if (m) {
+                uint32_t base = 0;
+                if ((threadIdx.x & 63) == (uint32_t)__builtin_ctzll(m))
+                    base = atomicAdd(&o.cnt->fb_list, (uint32_t)__builtin_popcountll(m));
+                base = readlane(base, __builtin_ctzll(m));
+                const uint32_t pos = base + bits_below(m);
+                if (lst && pos < o.fb_cap) o.fb_list[pos] = make_uint2(rec, (uint32_t)g);
+            }
+        }
         o.zkey[rec] = __float_as_uint(z32);
         o.touched[rec] = touched;
         if (touched) {
@@ -398,16 +426,68 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             o.rec2[rec] = r2;
             o.bbox[rec] = bb;
         }
-        const uint32_t bsum = block_sum<K1_THREADS>(touched, red);
-        const uint32_t bvis = block_sum<K1_THREADS>(touched ? 1u : 0u, red);
-        const uint32_t bfb = block_sum<K1_THREADS>(touched ? fb : 0u, red);
+        // per-block counts: wave sums, then one barrier (LDS slots alternate
+        // between views so the next view cannot overwrite unread sums)
+        const uint32_t s0 = wave_sum(touched), s1 = wave_sum(touched ? 1u : 0u), s2 = wave_sum(touched ? fb : 0u);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[vi & 1][wv][0] = s0;
+            red[vi & 1][wv][1] = s1;
+            red[vi & 1][wv][2] = s2;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
+            uint32_t t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+            for (int j = 0; j < K1_THREADS / 64; ++j) {
+                t0 += red[vi & 1][j][0];
+                t1 += red[vi & 1][j][1];
+                t2 += red[vi & 1][j][2];
+            }
             const uint32_t blk = rec / K1_THREADS;
-            o.blk_sum[blk] = bsum;
-            o.blk_vis[blk] = bvis;
-            o.blk_fb[blk] = bfb;
+            o.blk_sum[blk] = t0;
+            o.blk_vis[blk] = t1;
+            o.blk_fb[blk] = t2;
             o.blk_view[blk] = view_base + (uint32_t)vi;
         }
+    }
+}
+
+// Conic of the listed near-singular Gaussians, recomputed in FP64 from the
+// FP32 inputs: Sigma2D, its determinant and its inverse; the exponent
+// coefficients of the record are overwritten (log2 opacity kept).
+__global__ __launch_bounds__(256) void k_conic_fp64(const uint2* __restrict__ list, Counters* cnt, uint32_t cap,
+                                                    const ViewParams* __restrict__ views,
+                                                    const uint32_t* __restrict__ blk_view, float4* __restrict__ rec1) {
+    const uint32_t n = min(cnt->fb_list, cap);
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint2 e = list[i];
+        const uint32_t rec = e.x;
+        const int64_t g = e.y;
+        const ViewParams& v = views[blk_view[rec / K1_THREADS]];
+        const SceneView& s = v.scene;
+        const int64_t N = s.n;
+        const float mx = s.mean[g], my = s.mean[N + g], mz = s.mean[2 * N + g];
+        float q[4], ls[3];
+        if (s.storage == 0) {
+            const float4* a = reinterpret_cast<const float4*>(s.attr);
+            const float4 r = a[g], m = a[N + g];
+            q[0] = r.x; q[1] = r.y; q[2] = r.z; q[3] = r.w;
+            ls[0] = m.x; ls[1] = m.y; ls[2] = m.z;
+        } else {
+            float f[8];
+            unpack8(reinterpret_cast<const uint4*>(s.attr)[g], f, s.storage);
+            q[0] = f[0]; q[1] = f[1]; q[2] = f[2]; q[3] = f[3];
+            ls[0] = f[4]; ls[1] = f[5]; ls[2] = f[6];
+        }
+        double abc[3];
+        cov2d_fp64(q, ls, mx, my, mz, v, abc);
+        const double d64 = abc[0] * abc[2] - abc[1] * abc[1];
+        float4 r = rec1[rec];
+        r.x = -0.5f * LOG2E * (float)(abc[2] / d64);
+        r.y = -LOG2E * (float)(-abc[1] / d64);
+        r.z = -0.5f * LOG2E * (float)(abc[0] / d64);
+        rec1[rec] = r;
     }
 }
 
@@ -491,6 +571,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
         cnt->visible = (uint32_t)running;
         cnt->fallbacks = (uint32_t)fb;
         cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
+        cnt->fb_list = 0u;  // consumed by k_conic_fp64, which ran before this kernel
+        cnt->epoch += MAX_SORT_PASSES;  // look-back entries of earlier frames never match
+        cnt->error = 0u;
     }
 #pragma unroll
     for (int k = 0; k < ZeroList::N; ++k)
@@ -810,6 +893,171 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     }
 }
 
+// ------------------------------------------------- single-pass radix sort
+// One kernel per pass ("chained scan with decoupled look-back"): workgroups
+// take chunks of 2048 keys in the order of an atomic ticket, rank them like
+// the downsweep, publish each digit's chunk count, and add the counts of the
+// chunks before theirs, read back from a global look-back table; a chunk
+// whose predecessor has published its inclusive prefix stops looking back.
+// The digit totals of all passes come from one histogram kernel per sort.
+// Look-back entries are 64-bit: epoch (30 bits) | flag (2 bits) | count (32
+// bits); the epoch changes every pass, so stale entries never match.  Every
+// wait is bounded: on time-out the kernel raises cnt->error and the frame is
+// redone by the host with the three-kernel passes.
+
+constexpr uint64_t LB_AGG = 1ull << 32, LB_INC = 2ull << 32;
+
+__device__ __forceinline__ void lb_store(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long lb_load(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Digit histograms of up to MAX_SORT_PASSES passes in one read of the keys.
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist_all(const uint32_t* __restrict__ keys,
+                                                                const Counters* __restrict__ cnt, int which,
+                                                                uint32_t cap, PassList pl,
+                                                                uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[MAX_SORT_PASSES][256];
+    for (int i = threadIdx.x; i < MAX_SORT_PASSES * 256; i += SORT_THREADS) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t D = sort_count(cnt, which, cap);
+    for (uint32_t i = blockIdx.x * SORT_THREADS + threadIdx.x; i < D; i += gridDim.x * SORT_THREADS) {
+        const uint32_t k = keys[i];
+        for (int p = 0; p < pl.n; ++p) atomicAdd(&h[p][(k >> pl.shift[p]) & ((1u << pl.bits[p]) - 1u)], 1u);
+    }
+    __syncthreads();
+    for (int p = 0; p < pl.n; ++p)
+        for (int t = threadIdx.x; t < (1 << pl.bits[p]); t += SORT_THREADS)
+            if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
+}
+
+template <bool EXTRA, bool SUMS>
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
+    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
+    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext, Counters* cnt, int which,
+    uint32_t cap, int shift, int bits, const uint32_t* __restrict__ ghist, unsigned long long* lookback,
+    uint32_t* ticket, uint32_t epoch_add, const uint32_t* __restrict__ touched) {
+    static_assert(SORT_THREADS == 256, "one thread per digit");
+    constexpr int NW = SORT_THREADS / 64;
+    constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t red[NW];
+    __shared__ uint32_t lkey[SORT_CHUNK];
+    __shared__ uint32_t lval[SORT_CHUNK];
+    __shared__ uint32_t lext[(EXTRA || SUMS) ? SORT_CHUNK : 1];
+    __shared__ uint32_t chunk_id;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t D = sort_count(cnt, which, cap);
+    const uint32_t nchunks = (D + SORT_CHUNK - 1) / SORT_CHUNK;
+    if (t == 0) chunk_id = atomicAdd(ticket, 1u);
+#pragma unroll
+    for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
+    __syncthreads();
+    const uint32_t c = chunk_id;
+    if (c >= nchunks) return;  // uniform
+    const uint64_t epoch = (uint64_t)((cnt->epoch + epoch_add) & 0x3fffffffu) << 34;
+    const uint32_t chunk = c * SORT_CHUNK;
+    const uint32_t end = min(D, chunk + SORT_CHUNK);
+    // global start of digit t: exclusive scan of the digit totals
+    uint32_t tot_all;
+    const uint32_t gstart = block_excl_scan<SORT_THREADS>(t <= (int)mask ? ghist[t] : 0u, red, &tot_all);
+    uint32_t dig[ROUNDS], rank[ROUNDS], ek[ROUNDS], ev[ROUNDS], ee[ROUNDS];
+    bool ok[ROUNDS];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t idx = chunk + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
+        ok[r] = idx < end;
+        const uint32_t ic = ok[r] ? idx : chunk;
+        const uint32_t key = skey[ic];
+        ev[r] = sval[ic];
+        ee[r] = EXTRA ? sext[ic] : (SUMS ? touched[ev[r]] : 0u);
+        ek[r] = key;
+        const uint32_t d = (key >> shift) & mask;
+        dig[r] = d;
+        uint64_t m = ballot(ok[r]);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bl = ballot(bit);
+            m &= bit ? bl : ~bl;
+        }
+        const uint32_t prior = (uint32_t)__builtin_popcountll(m & lt);
+        uint32_t cur = 0;
+        if (ok[r]) cur = wcnt[w][d];
+        rank[r] = cur + prior;
+        if (ok[r] && prior == 0) wcnt[w][d] = cur + (uint32_t)__builtin_popcountll(m);
+    }
+    __syncthreads();
+    uint32_t cc = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) cc += wcnt[j][t];
+    // publish this chunk's count of digit t, then add those of earlier chunks
+    unsigned long long* mine = lookback + (size_t)c * 256 + t;
+    uint64_t prefix = 0;
+    if (t <= (int)mask) {
+        if (c == 0) {
+            lb_store(mine, epoch | LB_INC | cc);
+        } else {
+            lb_store(mine, epoch | LB_AGG | cc);
+            int64_t j = (int64_t)c - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const uint64_t v = lb_load(lookback + (size_t)j * 256 + t);
+                if ((v & ~0x3ffffffffull) == epoch && (v & (3ull << 32))) {
+                    prefix += (uint32_t)v;
+                    if (v & LB_INC) break;
+                    --j;
+                    spins = 0;
+                } else if (++spins > (1u << 18)) {
+                    atomicOr(&cnt->error, 1u);
+                    break;
+                } else {
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            lb_store(mine, epoch | LB_INC | (uint32_t)(prefix + cc));
+        }
+    }
+    // chunk-local digit starts and per-wave offsets, as in the downsweep
+    uint32_t tot;
+    const uint32_t ls = block_excl_scan<SORT_THREADS>(cc, red, &tot);
+    lstart[t] = ls;
+    base[t] = gstart + (uint32_t)prefix;
+    uint32_t acc = ls;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        const uint32_t x = wcnt[j][t];
+        wcnt[j][t] = acc;
+        acc += x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        if (ok[r]) {
+            const uint32_t l = wcnt[w][dig[r]] + rank[r];
+            lkey[l] = ek[r];
+            lval[l] = ev[r];
+            if (EXTRA || SUMS) lext[l] = ee[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t l = (uint32_t)t; l < tot; l += SORT_THREADS) {
+        const uint32_t k = lkey[l];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = base[d] + (l - lstart[d]);
+        if (pos < D) {
+            dkey[pos] = k;
+            dval[pos] = lval[l];
+            if (EXTRA || SUMS) dext[pos] = lext[l];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ ranges
 
 // Tile boundaries in the sorted tile words; the ranges array was cleared by
@@ -847,16 +1095,28 @@ struct BlendArgs {
     unsigned long long* work;
 };
 
-// One tile of TW x TH pixels; wave w owns the 8x8 pixel block
-// (w mod TW/8, w div TW/8) of it.  Each wave walks the tile's depth-sorted
-// list in batches of 64 * BD entries: every lane fetches entries, keeps those
-// whose pixel box meets the wave's block, compacts them into the wave's LDS
-// slice (ballot + mbcnt) and the 64 lanes then composite them front to back.
-// A wave leaves as soon as all of its pixels have terminated; there is no
-// barrier between the waves of a tile.
-template <int TW, int TH, int BD, bool COUNT>
-__device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, float4 (*la)[64 * BD],
-                                           float4 (*lb)[64 * BD], float (*lc)[64 * BD]) {
+// Per-wave LDS slice of staged Gaussians: block-relative centre (u, v of the
+// first 8x8 block; v of the second one when a lane owns two pixels), the
+// exponent coefficients and the colour.
+template <int BD>
+struct Stage {
+    float4 a[64 * BD];  // u_rel, v_rel0, A, B
+    float4 b[64 * BD];  // C, L, r, g
+    float2 c[64 * BD];  // b, v_rel1
+};
+
+// One tile of TW x TH pixels.  Each wave owns a block of 8 x (8 PPL) pixels
+// (PPL pixels per lane, one per stacked 8x8 sub-block); wave w takes block
+// (w mod TW/8, w div TW/8).  The wave walks the tile's depth-sorted list in
+// batches of 64 * BD entries: every lane fetches entries, keeps those whose
+// pixel box meets the wave's block, compacts them into the wave's LDS slice
+// (ballot + mbcnt) and the 64 lanes then composite them front to back.  Each
+// pixel's operations (and their rounding) are the same for every tile shape
+// and PPL: offsets are taken from the 8x8 sub-block's own origin.  A wave
+// leaves as soon as all of its pixels have terminated; there is no barrier
+// between the waves of a tile.
+template <int TW, int TH, int BD, int PPL, bool COUNT>
+__device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, Stage<BD>* stage) {
     constexpr int BX = TW / 8;
     constexpr int BATCH = 64 * BD;
     int vi = 0;
@@ -872,20 +1132,33 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, fl
     const uint32_t lt = tile - v.tile_base;
     const int tx = (int)(lt % (uint32_t)v.tiles_x), ty = (int)(lt / (uint32_t)v.tiles_x);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sx = tx * TW + (w % BX) * 8, sy = ty * TH + (w / BX) * 8;
-    const int px = sx + (lane & 7), py = sy + (lane >> 3);
-    const bool inside = px < v.width && py < v.height;
+    Stage<BD>& S = stage[w];
+    const int sx = tx * TW + (w % BX) * 8, sy = ty * TH + (w / BX) * 8 * PPL;
+    const int px = sx + (lane & 7);
     const float pxr = (float)(lane & 7) + 0.5f, pyr = (float)(lane >> 3) + 0.5f;
-    const float fsx = (float)sx, fsy = (float)sy;
+    const float fsx = (float)sx;
+    float fsy[PPL];
+    int py[PPL];
+    bool done[PPL];
+    float T[PPL], cr[PPL], cg[PPL], cb[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        fsy[p] = (float)(sy + 8 * p);
+        py[p] = sy + 8 * p + (lane >> 3);
+        done[p] = !(px < v.width && py[p] < v.height);
+        T[p] = 1.0f;
+        cr[p] = cg[p] = cb[p] = 0.0f;
+    }
     const uint2 rg = A.ranges[tile];
-    float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
-    bool done = !inside;
     uint32_t n_eval = 0, n_contrib = 0;  // (pixel, Gaussian) evaluations / contributions, COUNT only
     // the wave's block clipped to the image: the only pixels it must cover
-    const int bx1 = min(sx + 7, v.width - 1), by1 = min(sy + 7, v.height - 1);
+    const int bx1 = min(sx + 7, v.width - 1), by1 = min(sy + 8 * PPL - 1, v.height - 1);
 
     for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-        if (ballot(!done) == 0) break;
+        bool alive = false;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) alive = alive || !done[p];
+        if (ballot(alive) == 0) break;
         uint32_t cnt = 0;
 #pragma unroll
         for (int k = 0; k < BD; ++k) {
@@ -903,37 +1176,49 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, fl
             if (hit) {
                 const uint32_t slot = cnt + bits_below(m);
                 const float4 a = A.rec0[r], b1 = A.rec1[r], c2 = A.rec2[r];
-                // pixel centre relative to the block origin, hi and lo parts combined here
-                la[w][slot] = make_float4((a.x - fsx) + a.z, (a.y - fsy) + a.w, b1.x, b1.y);
-                lb[w][slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
-                lc[w][slot] = c2.z;
+                // pixel centre relative to each 8x8 sub-block origin, hi and lo parts combined here
+                S.a[slot] = make_float4((a.x - fsx) + a.z, (a.y - fsy[0]) + a.w, b1.x, b1.y);
+                S.b[slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
+                S.c[slot] = make_float2(c2.z, PPL > 1 ? (a.y - fsy[PPL - 1]) + a.w : 0.0f);
             }
             cnt += (uint32_t)__builtin_popcountll(m);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (!done) {
+        if (alive) {
             for (uint32_t j = 0; j < cnt; ++j) {
-                const float4 a = la[w][j];
-                const float4 b = lb[w][j];
-                const float dx = pxr - a.x, dy = pyr - a.y;
-                const float e = __builtin_fmaf(__builtin_fmaf(a.z, dx, a.w * dy), dx,
-                                               __builtin_fmaf(b.x * dy, dy, b.y));
-                const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
-                if (COUNT) ++n_eval;
-                if (alpha < ALPHA_MIN) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < T_MIN) {
-                    done = true;
-                    break;
+                const float4 a = S.a[j];
+                const float4 b = S.b[j];
+                const float2 c = S.c[j];
+                const float dx = pxr - a.x;
+                bool all_done = true;
+#pragma unroll
+                for (int p = 0; p < PPL; ++p) {
+                    const float vrel = p == 0 ? a.y : c.y;
+                    const float dy = pyr - vrel;
+                    const float e = __builtin_fmaf(__builtin_fmaf(a.z, dx, a.w * dy), dx,
+                                                   __builtin_fmaf(b.x * dy, dy, b.y));
+                    const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
+                    if (!done[p]) {
+                        if (COUNT) ++n_eval;
+                        if (alpha >= ALPHA_MIN) {
+                            const float Tn = T[p] * (1.0f - alpha);
+                            if (Tn < T_MIN) {
+                                done[p] = true;
+                            } else {
+                                const float wgt = alpha * T[p];
+                                cr[p] = __builtin_fmaf(wgt, b.z, cr[p]);
+                                cg[p] = __builtin_fmaf(wgt, b.w, cg[p]);
+                                cb[p] = __builtin_fmaf(wgt, c.x, cb[p]);
+                                T[p] = Tn;
+                                if (COUNT) ++n_contrib;
+                            }
+                        }
+                    }
+                    all_done = all_done && done[p];
                 }
-                const float wgt = alpha * T;
-                cr = __builtin_fmaf(wgt, b.z, cr);
-                cg = __builtin_fmaf(wgt, b.w, cg);
-                cbl = __builtin_fmaf(wgt, lc[w][j], cbl);
-                T = Tn;
-                if (COUNT) ++n_contrib;
+                if (all_done) break;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -947,21 +1232,24 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, fl
             atomicAdd(&A.work[1], (unsigned long long)sc);
         }
     }
-    if (inside) {
-        const float r = __builtin_fmaf(T, v.bg[0], cr);
-        const float g = __builtin_fmaf(T, v.bg[1], cg);
-        const float b = __builtin_fmaf(T, v.bg[2], cbl);
-        const size_t pix = (size_t)py * (size_t)v.width + (size_t)px;
-        if (v.fmt == 1) {
-            float* out = reinterpret_cast<float*>(v.out_ptr) + pix * 3;
-            out[0] = r;
-            out[1] = g;
-            out[2] = b;
-        } else {
-            uint8_t* out = reinterpret_cast<uint8_t*>(v.out_ptr) + pix * 3;
-            out[0] = to_u8(r);
-            out[1] = to_u8(g);
-            out[2] = to_u8(b);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        if (px < v.width && py[p] < v.height) {
+            const float r = __builtin_fmaf(T[p], v.bg[0], cr[p]);
+            const float g = __builtin_fmaf(T[p], v.bg[1], cg[p]);
+            const float b = __builtin_fmaf(T[p], v.bg[2], cb[p]);
+            const size_t pix = (size_t)py[p] * (size_t)v.width + (size_t)px;
+            if (v.fmt == 1) {
+                float* out = reinterpret_cast<float*>(v.out_ptr) + pix * 3;
+                out[0] = r;
+                out[1] = g;
+                out[2] = b;
+            } else {
+                uint8_t* out = reinterpret_cast<uint8_t*>(v.out_ptr) + pix * 3;
+                out[0] = to_u8(r);
+                out[1] = to_u8(g);
+                out[2] = to_u8(b);
+            }
         }
     }
 }
@@ -969,16 +1257,14 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, fl
 // One workgroup per tile.  XCD-aware mapping: consecutive workgroup ids go
 // round-robin to the 8 XCDs; each XCD gets a contiguous band of tiles so
 // neighbouring tiles (which share Gaussians) meet in the same L2.
-template <int TW, int TH, int BD, bool COUNT>
-__global__ __launch_bounds__(TW* TH) void k_blend(BlendArgs A) {
-    constexpr int NW = TW * TH / 64;
-    __shared__ float4 la[NW][64 * BD];
-    __shared__ float4 lb[NW][64 * BD];
-    __shared__ float lc[NW][64 * BD];
+template <int TW, int TH, int BD, int PPL, bool COUNT>
+__global__ __launch_bounds__(TW* TH / PPL) void k_blend(BlendArgs A) {
+    constexpr int NW = TW * TH / (64 * PPL);
+    __shared__ Stage<BD> stage[NW];
     const uint32_t per = (A.n_tiles + 7) / 8;
     const uint32_t tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (tile >= A.n_tiles) return;
-    blend_tile<TW, TH, BD, COUNT>(A, tile, la, lb, lc);
+    blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, stage);
 }
 
 // Persistent form for many views of uneven size: a fixed grid of resident
@@ -987,12 +1273,10 @@ __global__ __launch_bounds__(TW* TH) void k_blend(BlendArgs A) {
 // moves on to the other bands when its own is drained.  The queue counters are
 // cleared by k_scan_visible each frame; every workgroup exits once all bands
 // are drained.
-template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW* TH) void k_blend_persistent(BlendArgs A, uint32_t* __restrict__ queue) {
-    constexpr int NW = TW * TH / 64;
-    __shared__ float4 la[NW][64 * BD];
-    __shared__ float4 lb[NW][64 * BD];
-    __shared__ float lc[NW][64 * BD];
+template <int TW, int TH, int BD, int PPL>
+__global__ __launch_bounds__(TW* TH / PPL) void k_blend_persistent(BlendArgs A, uint32_t* __restrict__ queue) {
+    constexpr int NW = TW * TH / (64 * PPL);
+    __shared__ Stage<BD> stage[NW];
     __shared__ uint32_t next;
     const uint32_t per = (A.n_tiles + 7) / 8;
     const int home = blockIdx.x & 7;
@@ -1007,7 +1291,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_persistent(BlendArgs A, uint32
             const uint32_t tile = next;
             __syncthreads();
             if (tile >= band_end) break;
-            blend_tile<TW, TH, BD, false>(A, tile, la, lb, lc);
+            blend_tile<TW, TH, BD, PPL, false>(A, tile, stage);
         }
     }
 }
@@ -1043,6 +1327,11 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
     if (s.storage == 0) preprocess_deg<0>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
     else if (s.storage == 1) preprocess_deg<1>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
     else preprocess_deg<2>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
+}
+
+void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t st) {
+    TIGAS_LAUNCH(k_conic_fp64, dim3(64), dim3(256), st, (const uint2*)o.fb_list, o.cnt, o.fb_cap, views_dev,
+                 (const uint32_t*)o.blk_view, o.rec1);
 }
 
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
@@ -1097,58 +1386,103 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
     return cur;
 }
 
+int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
+                         uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
+                         const uint32_t* touched, unsigned long long* lookback, uint32_t* tickets, hipStream_t st) {
+    PassList pl{};
+    pl.n = npasses;
+    for (int p = 0; p < npasses; ++p) {
+        pl.shift[p] = passes[p].shift;
+        pl.bits[p] = passes[p].bits;
+    }
+    uint32_t* ghist = b.totals + totals_base * 256;
+    TIGAS_LAUNCH(k_sort_hist_all, dim3(512), dim3(SORT_THREADS), st, (const uint32_t*)b.key[start], cnt, which, cap,
+                 pl, ghist);
+    const uint32_t grid = std::max<uint32_t>(1u, (max_items + SORT_CHUNK - 1) / SORT_CHUNK);
+    int cur = start;
+    for (int p = 0; p < npasses; ++p) {
+        const SortPass& ps = passes[p];
+        const bool sums = touched && p + 1 == npasses;
+#define TIGAS_ONE(E, S)                                                                                            \
+    TIGAS_LAUNCH((k_sort_onesweep<E, S>), dim3(grid), dim3(SORT_THREADS), st, b.key[cur], b.val[cur], b.ext[cur], \
+                 b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits,               \
+                 (const uint32_t*)(ghist + p * 256), lookback, tickets + totals_base + p,                        \
+                 (uint32_t)(totals_base + p), touched)
+        if (extra && sums) TIGAS_ONE(true, true);
+        else if (extra) TIGAS_ONE(true, false);
+        else if (sums) TIGAS_ONE(false, true);
+        else TIGAS_ONE(false, false);
+#undef TIGAS_ONE
+        cur ^= 1;
+    }
+    return cur;
+}
+
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st) {
     TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges);
 }
 
-template <int TW, int TH, int BD>
+template <int TW, int TH, int BD, int PPL>
 static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int persistent_blocks, hipStream_t st) {
     if (queue) {
-        TIGAS_LAUNCH((k_blend_persistent<TW, TH, BD>), dim3(persistent_blocks), dim3(TW * TH), st, A, queue);
+        TIGAS_LAUNCH((k_blend_persistent<TW, TH, BD, PPL>), dim3(persistent_blocks), dim3(TW * TH / PPL), st, A,
+                     queue);
     } else {
         const dim3 grid(((A.n_tiles + 7) / 8) * 8);
-        if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, true>), grid, dim3(TW * TH), st, A);
-        else TIGAS_LAUNCH((k_blend<TW, TH, BD, false>), grid, dim3(TW * TH), st, A);
+        if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, true>), grid, dim3(TW * TH / PPL), st, A);
+        else TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, false>), grid, dim3(TW * TH / PPL), st, A);
     }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPL>
 static void blend_bd(int bd, const BlendArgs& A, bool count, uint32_t* queue, int pb, hipStream_t st) {
     switch (bd) {
-        case 128: blend_launch<TW, TH, 2>(A, count, queue, pb, st); break;
-        case 256: blend_launch<TW, TH, 4>(A, count, queue, pb, st); break;
-        default: blend_launch<TW, TH, 1>(A, count, queue, pb, st); break;
+        case 128: blend_launch<TW, TH, 2, PPL>(A, count, queue, pb, st); break;
+        case 256: blend_launch<TW, TH, 4, PPL>(A, count, queue, pb, st); break;
+        default: blend_launch<TW, TH, 1, PPL>(A, count, queue, pb, st); break;
     }
 }
 
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st) {
+                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st) {
     if (n_tiles == 0) return;
     const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work};
     const bool count = work != nullptr;
     if (count) queue = nullptr;
-    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8>(batch_depth, A, count, queue, persistent_blocks, st);
-    else if (tile_w == 16 && tile_h == 32) blend_bd<16, 32>(batch_depth, A, count, queue, persistent_blocks, st);
-    else if (tile_w == 32 && tile_h == 16) blend_bd<32, 16>(batch_depth, A, count, queue, persistent_blocks, st);
-    else blend_bd<16, 16>(batch_depth, A, count, queue, persistent_blocks, st);
+    const bool two = ppl == 2 && tile_h >= 16;
+    if (tile_w == 8 && tile_h == 8) blend_bd<8, 8, 1>(batch_depth, A, count, queue, persistent_blocks, st);
+    else if (tile_w == 16 && tile_h == 32) {
+        if (two) blend_bd<16, 32, 2>(batch_depth, A, count, queue, persistent_blocks, st);
+        else blend_bd<16, 32, 1>(batch_depth, A, count, queue, persistent_blocks, st);
+    } else if (tile_w == 32 && tile_h == 16) {
+        if (two) blend_bd<32, 16, 2>(batch_depth, A, count, queue, persistent_blocks, st);
+        else blend_bd<32, 16, 1>(batch_depth, A, count, queue, persistent_blocks, st);
+    } else {
+        if (two) blend_bd<16, 16, 2>(batch_depth, A, count, queue, persistent_blocks, st);
+        else blend_bd<16, 16, 1>(batch_depth, A, count, queue, persistent_blocks, st);
+    }
 }
 
-// Resident workgroups per CU of the persistent blend kernel for a tile shape.
-int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth) {
+// Resident workgroups per CU of the persistent blend kernel for a configuration.
+int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth, int ppl) {
     int n = 0;
-    auto occ = [&](auto kern, int threads) {
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0);
-    };
     const int bd = batch_depth == 128 ? 2 : (batch_depth == 256 ? 4 : 1);
-#define TIGAS_OCC(TW, TH)                                                              \
-    if (tile_w == TW && tile_h == TH) {                                                \
-        if (bd == 1) occ(k_blend_persistent<TW, TH, 1>, TW * TH);                      \
-        else if (bd == 2) occ(k_blend_persistent<TW, TH, 2>, TW * TH);                 \
-        else occ(k_blend_persistent<TW, TH, 4>, TW * TH);                              \
-    }
-    TIGAS_OCC(8, 8) else TIGAS_OCC(16, 32) else TIGAS_OCC(32, 16) else TIGAS_OCC(16, 16)
-#undef TIGAS_OCC
+    const bool two = ppl == 2 && tile_h >= 16;
+#define TIGAS_OCC3(TW, TH, P)                                                                                       \
+    do {                                                                                                           \
+        if (bd == 1) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<TW, TH, 1, P>,       \
+                                                                         TW * TH / P, 0);                          \
+        else if (bd == 2) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<TW, TH, 2, P>,  \
+                                                                              TW * TH / P, 0);                     \
+        else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<TW, TH, 4, P>, TW * TH / P,  \
+                                                                 0);                                               \
+    } while (0)
+    if (tile_w == 8 && tile_h == 8) TIGAS_OCC3(8, 8, 1);
+    else if (tile_w == 16 && tile_h == 32) { if (two) TIGAS_OCC3(16, 32, 2); else TIGAS_OCC3(16, 32, 1); }
+    else if (tile_w == 32 && tile_h == 16) { if (two) TIGAS_OCC3(32, 16, 2); else TIGAS_OCC3(32, 16, 1); }
+    else { if (two) TIGAS_OCC3(16, 16, 2); else TIGAS_OCC3(16, 16, 1); }
+#undef TIGAS_OCC3
     return n > 0 ? n : 1;
 }
 

@@ -15,23 +15,6 @@ constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 16;
 constexpr int MAX_SORT_PASSES = 8;
 
-// Per-view camera and tiling parameters, computed on the host in FP64 and
-// rounded once to FP32.
-struct ViewParams {
-    float V[9];        // world -> camera rotation R^T, row-major
-    float cam[3];      // camera centre t
-    float tz_key;      // float((-R^T t)_z): constant term of the FP32 depth key
-    float fx, fy, cx, cy;
-    float lim_x, lim_y;  // Jacobian clamp: 1.3 x the half-FoV tangents
-    int width, height;
-    int tile_w, tile_h, tiles_x, tiles_y;
-    uint32_t tile_base;  // first global tile id of this view
-    int sh_degree;
-    int fmt;             // 0 RGB8, 1 RGBF32
-    float bg[3];
-    uint64_t out_ptr;    // device address of this view's frame
-};
-
 // Resident scene (device pointers).  Layout by storage precision:
 //   mean:  f32 planes [3][n] (x, y, z)
 //   F32:   attr float4 [2][n]: (qw, qx, qy, qz), (ls0, ls1, ls2, logit)
@@ -47,12 +30,33 @@ struct SceneView {
     const void* sh;
 };
 
+// Per-view camera and tiling parameters, computed on the host in FP64 and
+// rounded once to FP32.
+struct ViewParams {
+    float V[9];        // world -> camera rotation R^T, row-major
+    float cam[3];      // camera centre t
+    float tz_key;      // float((-R^T t)_z): constant term of the FP32 depth key
+    float fx, fy, cx, cy;
+    float lim_x, lim_y;  // Jacobian clamp: 1.3 x the half-FoV tangents
+    int width, height;
+    int tile_w, tile_h, tiles_x, tiles_y;
+    uint32_t tile_base;  // first global tile id of this view
+    int sh_degree;
+    int fmt;             // 0 RGB8, 1 RGBF32
+    float bg[3];
+    uint64_t out_ptr;    // device address of this view's frame
+    SceneView scene;     // the scene this view renders
+};
+
 struct Counters {
     uint32_t D;         // duplicates (clamped to 2^32-1)
     uint32_t visible;
     uint32_t fallbacks;
     uint32_t overflow;  // D exceeded the duplicate capacity: nothing was emitted
-    uint32_t pad[4];
+    uint32_t fb_list;   // entries in the FP64-fallback list (cleared after use)
+    uint32_t epoch;     // advanced every frame: tags the single-pass sort's look-back entries
+    uint32_t error;     // a bounded wait of the single-pass sort timed out (frame must be redone)
+    uint32_t pad;
 };
 
 // Preprocess outputs, one slot per record (record = view-local index of a
@@ -68,6 +72,9 @@ struct PreOut {
     uint32_t* blk_vis;  // per block: records with touched > 0
     uint32_t* blk_fb;   // per block: FP64 fallbacks
     uint32_t* blk_view; // per block: view index
+    uint2* fb_list;     // (record, Gaussian) pairs whose conic is recomputed in FP64
+    uint32_t fb_cap;
+    Counters* cnt;
 };
 
 // Double-buffered (key, value, extra) words of a radix sort.
@@ -86,6 +93,12 @@ struct ZeroList {
     uint32_t n[N];
 };
 
+struct PassList {
+    int n;
+    int shift[MAX_SORT_PASSES];
+    int bits[MAX_SORT_PASSES];
+};
+
 struct SortPass {
     int shift;
     int bits;  // <= 8
@@ -94,6 +107,9 @@ struct SortPass {
 // ---- launchers (kernels.hip) ----
 void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
                        uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
+// Recomputes, in FP64, the conic of every Gaussian preprocess listed as
+// near-singular (one launch after all preprocess launches of a frame).
+void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t st);
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st);
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st);
@@ -107,13 +123,21 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
                 int start, bool extra, const Counters* cnt, int totals_base, const uint32_t* touched,
                 uint32_t* blk_sum, hipStream_t st);
+// The same passes with one kernel each (look-back chained scan) after one
+// histogram kernel; tickets[totals_base + p] must be zero, lookback holds
+// 256 entries per 2048-key chunk of max_items (the most keys the count can
+// reach).
+int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
+                         uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
+                         const uint32_t* touched, unsigned long long* lookback, uint32_t* tickets, hipStream_t st);
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st);
+                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st);
 // With `queue` (8 counters cleared per frame) the blend runs as a persistent
 // kernel of persistent_blocks workgroups pulling tiles from work queues.
-int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth);
+// ppl: pixels per lane (1, or 2 for tiles at least 16 tall).
+int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth, int ppl);
 void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
 
 }  // namespace tigas

@@ -44,7 +44,7 @@ class IntrC(ctypes.Structure):
 class QualityC(ctypes.Structure):
     _fields_ = [("res_scale", ctypes.c_float), ("sh_degree", ctypes.c_int), ("fmt", ctypes.c_int),
                 ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int),
-                ("batch_depth", ctypes.c_int)]
+                ("batch_depth", ctypes.c_int), ("pixels_per_lane", ctypes.c_int)]
 
 
 class FrameC(ctypes.Structure):
@@ -56,7 +56,7 @@ class StatsC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("visible", ctypes.c_int64), ("duplicates", ctypes.c_int64),
                 ("fallbacks", ctypes.c_int64), ("tiles", ctypes.c_int64), ("sort_passes", ctypes.c_int64),
                 ("rerenders", ctypes.c_int64), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("batch_depth", ctypes.c_int32)]
+                ("batch_depth", ctypes.c_int32), ("pixels_per_lane", ctypes.c_int32)]
 
 
 class DebugC(ctypes.Structure):
@@ -77,7 +77,7 @@ class StageC(ctypes.Structure):
 EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
-           "tigas_count_blend_work", "tigas_set_graphs")
+           "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks")
 
 _lib = None
 
@@ -111,13 +111,16 @@ def lib():
         L.tigas_selftest_wave_scan.argtypes = [P, P, I]
         L.tigas_profile_stages.argtypes = [P, I]
         L.tigas_set_graphs.argtypes = [P, I]
+        L.tigas_set_sort.argtypes = [P, I]
+        L.tigas_sort_fallbacks.argtypes = [P]
+        L.tigas_sort_fallbacks.restype = I64
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
                                              ctypes.POINTER(I64), ctypes.POINTER(I64)]
         for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
-                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs"):
+                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -145,11 +148,12 @@ def intr_c(k) -> IntrC:
     return IntrC(float(k.fx), float(k.fy), float(k.cx), float(k.cy))
 
 
-def quality_c(res_scale=1.0, sh_degree=-1, fmt="rgb8", bg=(0.0, 0.0, 0.0), tile=None, batch_depth=None):
-    """tile=None / batch_depth=None: chosen by the library's autotuner."""
+def quality_c(res_scale=1.0, sh_degree=-1, fmt="rgb8", bg=(0.0, 0.0, 0.0), tile=None, batch_depth=None, ppl=None):
+    """tile / batch_depth / ppl = None: chosen by the library's autotuner."""
     tile = (0, 0) if tile is None else tile
     batch_depth = 0 if batch_depth is None else batch_depth
     q = QualityC()
+    q.pixels_per_lane = 0 if ppl is None else int(ppl)
     q.res_scale = float(res_scale)
     q.sh_degree = int(sh_degree)
     q.fmt = FMT[fmt]
@@ -234,10 +238,17 @@ class Context:
         """Capture/replay launch sequences as HIP graphs (default on)."""
         _check(lib().tigas_set_graphs(self.handle, 1 if enable else 0))
 
+    def set_sort(self, single_pass: bool):
+        """Single-pass look-back radix sort (True) or count/scan/scatter passes."""
+        _check(lib().tigas_set_sort(self.handle, 1 if single_pass else 0))
+
+    def sort_fallbacks(self) -> int:
+        return int(lib().tigas_sort_fallbacks(self.handle))
+
     def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=None,
-                         batch_depth=None):
+                         batch_depth=None, ppl=None):
         """(evaluations, contributions) of the blend kernel for one frame."""
-        q = quality_c(res_scale, -1, "rgb8", (0, 0, 0), tile, batch_depth)
+        q = quality_c(res_scale, -1, "rgb8", (0, 0, 0), tile, batch_depth, ppl)
         ow, oh = output_size(width, height, res_scale)
         img = np.zeros((oh, ow, 3), np.uint8)
         fr = FrameC(ctypes.c_void_p(img.ctypes.data), img.nbytes, 0, 0, 0)
@@ -248,10 +259,10 @@ class Context:
         return int(e.value), int(c.value)
 
     def render(self, scene: Scene, pose, intr, width, height, res_scale=1.0, fmt="rgb8", bg=(0, 0, 0),
-               tile=None, batch_depth=None, sh_degree=-1, out=None, stream=None):
+               tile=None, batch_depth=None, sh_degree=-1, out=None, stream=None, ppl=None):
         """Render one frame.  ``out``: a torch tensor on the GPU (written in place)
         or None (a host numpy array is returned)."""
-        q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth)
+        q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth, ppl)
         ow, oh = output_size(width, height, res_scale)
         if out is None:
             out = np.zeros((oh, ow, 3), np.uint8 if fmt == "rgb8" else np.float32)
@@ -300,10 +311,10 @@ class Context:
         return out
 
     def render_batch(self, scenes, poses, intrs, widths, heights, res_scales=None, fmt="rgb8", bg=(0, 0, 0),
-                     tile=None, batch_depth=None, outs=None, stream=None):
+                     tile=None, batch_depth=None, outs=None, stream=None, ppl=None):
         n = len(poses)
         res_scales = res_scales if res_scales is not None else [1.0] * n
-        qs = (QualityC * n)(*[quality_c(res_scales[i], -1, fmt, bg, tile, batch_depth) for i in range(n)])
+        qs = (QualityC * n)(*[quality_c(res_scales[i], -1, fmt, bg, tile, batch_depth, ppl) for i in range(n)])
         frames = (FrameC * n)()
         results = []
         for i in range(n):
@@ -332,3 +343,126 @@ def selftest_wave_scan(values) -> np.ndarray:
     _check(lib().tigas_selftest_wave_scan(ctypes.c_void_p(v.ctypes.data), ctypes.c_void_p(out.ctypes.data),
                                           int(v.size)))
     return out
+
+
+# ------------------------------------------------------------------ serving
+
+class ServerConfigC(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("max_batch", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
+                ("supersede", ctypes.c_int), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int),
+                ("batch_depth", ctypes.c_int), ("pixels_per_lane", ctypes.c_int), ("max_batch_pixels", ctypes.c_int64)]
+
+
+class RequestC(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("pose", PoseC), ("intr", IntrC), ("width", ctypes.c_int),
+                ("height", ctypes.c_int), ("q", QualityC), ("out", FrameC), ("client", ctypes.c_int),
+                ("arrival_s", ctypes.c_double)]
+
+
+class CompletionC(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("client", ctypes.c_int), ("status", ctypes.c_int),
+                ("arrival_s", ctypes.c_double), ("dispatch_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("batch_size", ctypes.c_int)]
+
+
+class ServerStatsC(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("admitted", "deferred", "superseded", "rendered", "failed", "batches",
+                                              "max_batch_seen", "pending")]
+
+
+SERVER_EXPORTS = ("tigas_server_create", "tigas_server_destroy", "tigas_server_submit", "tigas_server_poll",
+                  "tigas_server_drain", "tigas_server_replay", "tigas_server_get_stats")
+EXPORTS = EXPORTS + SERVER_EXPORTS
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_bound", False):
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.tigas_server_create.argtypes = [P, ctypes.POINTER(ServerConfigC), ctypes.POINTER(P)]
+        L.tigas_server_destroy.argtypes = [P]
+        L.tigas_server_destroy.restype = None
+        L.tigas_server_submit.argtypes = [P, ctypes.POINTER(RequestC), ctypes.POINTER(ctypes.c_int64)]
+        L.tigas_server_poll.argtypes = [P, ctypes.POINTER(CompletionC), I, ctypes.POINTER(I)]
+        L.tigas_server_drain.argtypes = [P]
+        L.tigas_server_replay.argtypes = [P, ctypes.POINTER(RequestC), I, ctypes.POINTER(CompletionC)]
+        L.tigas_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStatsC)]
+        for name in ("tigas_server_create", "tigas_server_submit", "tigas_server_poll", "tigas_server_drain",
+                     "tigas_server_replay", "tigas_server_get_stats"):
+            getattr(L, name).restype = I
+        L._server_bound = True
+    return L
+
+
+def request_c(scene: Scene, pose, intr, width, height, out, client=0, arrival_s=0.0, res_scale=1.0, fmt="rgb8",
+              bg=(0, 0, 0)):
+    """One request; ``out`` is a torch GPU tensor or a host numpy array of the
+    output frame (kept alive by the caller until it completes)."""
+    r = RequestC()
+    r.scene = scene.handle.value if isinstance(scene.handle, ctypes.c_void_p) else scene.handle
+    r.pose = pose_c(pose)
+    r.intr = intr_c(intr)
+    r.width, r.height = int(width), int(height)
+    r.q = quality_c(res_scale, -1, fmt, bg, (16, 32), 64)
+    if isinstance(out, np.ndarray):
+        r.out = FrameC(ctypes.c_void_p(out.ctypes.data), out.nbytes, 0, 0, 0)
+    else:
+        r.out = FrameC(ctypes.c_void_p(int(out.data_ptr())), out.numel() * out.element_size(), 1, 0, 0)
+    r.client = int(client)
+    r.arrival_s = float(arrival_s)
+    return r
+
+
+class Server:
+    """Continuous-batching request loop of the library (tigas_server_*)."""
+
+    def __init__(self, ctx: Context, slots=2, max_batch=64, hbm_budget=0, supersede=False, tile=(16, 32),
+                 batch_depth=64, max_batch_pixels=0):
+        L = _server_lib()
+        cfg = ServerConfigC(int(slots), int(max_batch), int(hbm_budget), 1 if supersede else 0, int(tile[0]),
+                            int(tile[1]), int(batch_depth), 0, int(max_batch_pixels))
+        h = ctypes.c_void_p()
+        _check(L.tigas_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _server_lib().tigas_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, req: RequestC) -> int:
+        i = ctypes.c_int64()
+        _check(_server_lib().tigas_server_submit(self.handle, ctypes.byref(req), ctypes.byref(i)))
+        return int(i.value)
+
+    def drain(self):
+        _check(_server_lib().tigas_server_drain(self.handle))
+
+    def poll(self, max_n=4096):
+        buf = (CompletionC * max_n)()
+        n = ctypes.c_int()
+        _check(_server_lib().tigas_server_poll(self.handle, buf, max_n, ctypes.byref(n)))
+        return [_completion_dict(buf[i]) for i in range(n.value)]
+
+    def replay(self, reqs):
+        n = len(reqs)
+        arr = (RequestC * n)(*reqs)
+        out = (CompletionC * n)()
+        _check(_server_lib().tigas_server_replay(self.handle, arr, n, out))
+        return [_completion_dict(out[i]) for i in range(n)]
+
+    def stats(self) -> dict:
+        st = ServerStatsC()
+        _check(_server_lib().tigas_server_get_stats(self.handle, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in ServerStatsC._fields_}
+
+
+def _completion_dict(c):
+    return dict(id=int(c.id), client=int(c.client), status=int(c.status), arrival_s=c.arrival_s,
+                dispatch_s=c.dispatch_s, done_s=c.done_s, batch_size=int(c.batch_size))

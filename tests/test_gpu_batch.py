@@ -31,17 +31,17 @@ def c2small():
     return scene, traj, synth.fov_intrinsics(1280, 720)
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 32)])
-def test_batch_equals_single_renders(ctx, c2small, tile):
+@pytest.mark.parametrize("tile,ppl", [((16, 16), 1), ((8, 8), 1), ((16, 32), 1), ((16, 16), 2), ((32, 16), 2)])
+def test_batch_equals_single_renders(ctx, c2small, tile, ppl):
     scene, traj, k = c2small
     s = ctx.load_scene(scene)
     poses = [traj[i] for i in range(0, 64, 8)]
     scales = [RUNGS[i % 4] for i in range(len(poses))]
     ks = [k] * len(poses)
     got = ctx.render_batch([s] * len(poses), poses, ks, [1280] * len(poses), [720] * len(poses), scales,
-                           fmt="f32", tile=tile, batch_depth=64)
+                           fmt="f32", tile=tile, batch_depth=64, ppl=ppl)
     for i, p in enumerate(poses):
-        want = ctx.render(s, p, k, 1280, 720, res_scale=scales[i], fmt="f32", tile=tile, batch_depth=64)
+        want = ctx.render(s, p, k, 1280, 720, res_scale=scales[i], fmt="f32", tile=(8, 8), batch_depth=64)
         np.testing.assert_array_equal(got[i], want, err_msg=f"view {i} rung {scales[i]}")
     st = ctx.stats()
     _say("batch", tile, st)
@@ -108,7 +108,7 @@ def test_autotuner_choice_does_not_change_frames(ctx, c2small):
     n = len(poses)
     auto = ctx.render_batch([s] * n, poses, [k] * n, [1280] * n, [720] * n, scales, fmt="f32")
     st = ctx.stats()
-    _say("autotuned", st["tile_w"], st["tile_h"], st["batch_depth"])
+    _say("autotuned", st["tile_w"], st["tile_h"], st["batch_depth"], st["pixels_per_lane"])
     assert (st["tile_w"], st["tile_h"]) in [(8, 8), (16, 16), (16, 32)]
     assert st["batch_depth"] in (64, 128, 256)
     fixed = ctx.render_batch([s] * n, poses, [k] * n, [1280] * n, [720] * n, scales, fmt="f32", tile=(16, 16),

@@ -88,10 +88,11 @@ def test_frames_bit_identical_across_tiles_and_batch_depths(ctx, c1):
     scene, poses, k, W, H = c1
     s = ctx.load_scene(scene)
     ref = ctx.render(s, poses[0], k, W, H, fmt="f32")
-    for tile in [(8, 8), (16, 32), (32, 16)]:
+    for tile in [(8, 8), (16, 16), (16, 32), (32, 16)]:
         for bd in (64, 128, 256):
-            got = ctx.render(s, poses[0], k, W, H, fmt="f32", tile=tile, batch_depth=bd)
-            np.testing.assert_array_equal(got, ref, err_msg=f"tile={tile} bd={bd}")
+            for ppl in ((1,) if tile[1] < 16 else (1, 2)):
+                got = ctx.render(s, poses[0], k, W, H, fmt="f32", tile=tile, batch_depth=bd, ppl=ppl)
+                np.testing.assert_array_equal(got, ref, err_msg=f"tile={tile} bd={bd} ppl={ppl}")
 
 
 def test_render_is_deterministic(ctx, c1):
@@ -184,3 +185,27 @@ def test_invalid_arguments_are_reported(ctx, c1):
     bad = synth.Pose(np.full((3, 3), np.nan, np.float32), np.zeros(3, np.float32))
     with pytest.raises(tigas.TigasError, match="E_INVALID"):
         ctx.render(s, bad, k, W, H)
+
+
+def test_single_pass_sort_gives_the_same_lists_and_frames(ctx, c1):
+    scene, poses, k, W, H = c1
+    s = ctx.load_scene(scene)
+    big = ctx.load_scene(synth.c2_scene(1_000_000))
+    traj = synth.c2_trajectory(8)
+    k2 = synth.fov_intrinsics(1280, 720)
+    ref = [ctx.render(big, traj[i], k2, 1280, 720, fmt="f32", tile=(16, 16)) for i in range(3)]
+    ctx.set_sort(True)
+    try:
+        _say("single-pass sort")
+        for tile in [(16, 16), (8, 8)]:
+            dbg = ctx.render_debug(s, poses[0], k, W, H, tile=tile)
+            gc.check_tiles(dbg, *tile)
+        for rep in range(2):  # captured graphs replay with fresh look-back epochs
+            for i in range(3):
+                got = ctx.render(big, traj[i], k2, 1280, 720, fmt="f32", tile=(16, 16))
+                np.testing.assert_array_equal(got, ref[i], err_msg=f"rep {rep} pose {i}")
+        _say("single-pass stats", ctx.stats())
+        assert ctx.sort_fallbacks() == 0
+    finally:
+        ctx.set_sort(False)
+        big.free()
