@@ -66,6 +66,14 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
     stages = ctx.stage_times()
     ctx.profile_stages(False)
     nfr = max(stages["frames"], 1)
+    # and once more with HIP events around every kernel launch: per-kernel
+    # average launch durations for the roofline
+    ctx.profile_kernels(True)
+    timed("kernels")
+    kt = ctx.kernel_times()
+    ctx.profile_kernels(False)
+    kernels = {name: dict(launches_per_frame=l / steps, avg_us=1e3 * ms / max(l, 1), ms_per_frame=ms / steps)
+               for name, (l, ms) in kt.items()}
     # algorithmic work of the same frames (untimed pass with the counting blend
     # kernel): visible Gaussians, duplicates, evaluations, contributions
     work = dict(frames=0, visible=0, duplicates=0, evaluations=0, contributions=0, fallbacks=0)
@@ -80,10 +88,11 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
             for f in ("visible", "duplicates", "fallbacks"):
                 work[f] += st[f]
     res = dict(head, tile=f"{cfg['tile_w']}x{cfg['tile_h']}", batch_depth=cfg["batch_depth"],
+               sort_passes=cfg["sort_passes"],
                pixels_per_lane=cfg["pixels_per_lane"],
                stage_pass=prof, gpu_ms_per_frame=sum(v for kk, v in stages.items() if kk != "frames") / nfr,
                stage_ms={kk: v / nfr for kk, v in stages.items() if kk != "frames"},
-               work=work, scene_bytes=s.bytes)
+               work=work, scene_bytes=s.bytes, kernels=kernels)
     s.free()
     return res
 
@@ -192,36 +201,76 @@ def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.
                 max_rate_per_client_p99_1080p_3M_within_10ms=max(ok) if ok else None)
 
 
-def roofline(v, n, storage):
-    """Roofline of the dominant stage of the FP32 run: algorithmic work per
-    frame (averaged over the timed frames) / mean stage time per frame."""
-    st = v["stage_ms"]
-    dom = max(st, key=st.get)
-    ms = st[dom]
-    w = v["work"]
+def kernel_work(name, w, n, storage, tile_passes):
+    """Algorithmic work of ONE launch of a kernel, averaged over the frames of
+    the work pass: (bound, amount, unit) with bytes for HBM-bound kernels and
+    FP32 flops for the blend, or None for a kernel without a model."""
     nf = max(w["frames"], 1)
     D = w["duplicates"] / nf
     V = w["visible"] / nf
-    if dom == "blend":
-        flops = (FLOPS_EVAL * w["evaluations"] + FLOPS_CONTRIB * w["contributions"]) / nf
-        ach = flops / (ms * 1e-3) / 1e12
-        return dict(kernel="k_blend", bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=None, ms=ms)
-    if dom == "sort":
-        # 4 depth passes: read depth word (4) + read/write 12 B; tile passes read 4 + move 8 B
-        byts = D * (4 * (4 + 24) + 2 * (4 + 16))
-        kern = "k_sort_* (6 passes)"
-    elif dom == "preprocess":
+    if "k_blend" in name:
+        return "alu", (FLOPS_EVAL * w["evaluations"] + FLOPS_CONTRIB * w["contributions"]) / nf
+    if "k_preprocess" in name:
+        # attributes of every Gaussian, SH of the visible ones, depth key +
+        # touched count of every record, three float4 records + box per visible
         attr = 44 if storage == "f32" else 28
         shb = 192 if storage == "f32" else 96
-        byts = n * attr + V * shb + n * 8 + V * 56
-        kern = "k_preprocess"
-    else:
-        byts = D * 12
-        kern = "k_" + dom
-    ach = byts / (ms * 1e-3) / 1e9
-    return dict(kernel=kern, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=None, ms=ms)
+        return "hbm", n * attr + V * shb + n * 8 + V * 56
+    if "k_duplicate" in name:
+        # sorted record id, sorted touched count and box per visible Gaussian;
+        # tile key + record id per duplicate
+        return "hbm", V * 16 + D * 8
+    if "k_sort_downsweep<false, false>" in name or "k_sort_onesweep<false, false>" in name:
+        # key + value read and written per element; 3 depth passes over the
+        # visible Gaussians and the tile passes over the duplicates, per launch
+        return "hbm", 16 * (3 * V + tile_passes * D) / (3 + tile_passes)
+    return None
+
+
+def roofline(v, n, storage):
+    """Roofline of the dominant kernel of the FP32 run: algorithmic work per
+    launch / average launch duration (HIP events around every launch)."""
+    w = v["work"]
+    tile_passes = v["sort_passes"] - 4
+    ranked = sorted(v["kernels"].items(), key=lambda kv: -kv[1]["ms_per_frame"])
+    for name, k in ranked:
+        m = kernel_work(name, w, n, storage, tile_passes)
+        if m is None:
+            continue
+        bound, amount = m
+        amount /= max(k["launches_per_frame"], 1e-9)
+        sec = k["avg_us"] * 1e-6
+        if bound == "alu":
+            ach = amount / sec / 1e12
+            return dict(kernel=name, bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=None, avg_us=k["avg_us"],
+                        per_launch=amount, dominant=ranked[0][0])
+        ach = amount / sec / 1e9
+        return dict(kernel=name, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                    traffic=None, avg_us=k["avg_us"], per_launch=amount, dominant=ranked[0][0])
+    return None
+
+
+def hbm_copy(torch, mib=1024, reps=20):
+    """A plain device-to-device copy of known size (torch's elementwise copy
+    kernel): the achievable HBM rate, and the reference that scales profiler
+    byte counters (FETCH_SIZE / WRITE_SIZE) into bytes."""
+    n = mib * 2 ** 20 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    moved = 2 * n * 4
+    del src, dst
+    return dict(bytes_read=n * 4, bytes_written=n * 4, us=sec * 1e6, gbps=moved / sec / 1e9)
 
 
 def cpu_baseline(scene, pose, k, W, H, n_pix=2048):
@@ -267,6 +316,8 @@ def main():
     traj = synth.c3_trajectory(300)
     k = synth.fov_intrinsics(W, H)
     ctx = tigas.Context(0)
+    copy = hbm_copy(torch)
+    print(f"# HBM copy: {copy['gbps']:.0f} GB/s", file=sys.stderr, flush=True)
     variants = {}
     for storage in args.variants.split(","):
         variants[storage] = run_variant(ctx, tigas, scene, storage, traj, k, W, H, args.steps, args.warmup, torch,
@@ -305,7 +356,9 @@ def main():
                                               "scene_bytes", "tile", "batch_depth", "pixels_per_lane")}
                      for kk, vv in variants.items()},
         "roofline": {x: rl[x] for x in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "roofline_kernel": rl["kernel"],
+        "roofline_kernel": {x: rl[x] for x in ("kernel", "avg_us", "per_launch", "dominant")},
+        "hbm_copy": copy,
+        "kernels": main_v["kernels"],
     }
     if not args.no_batched:
         line["batched"] = run_batched(ctx, scene, torch)

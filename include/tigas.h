@@ -127,7 +127,13 @@ typedef struct {
 
 /* Creates a context on HIP device `device`: a stream, workspaces and the
  * tuning cache (the autotuner's choices per workload shape; persisted in the
- * file named by the environment variable TIGAS_TUNE_CACHE when set).  *out is owned by the caller; free with tigas_context_destroy. */
+ * file named by the environment variable TIGAS_TUNE_CACHE when set).  *out
+ * is owned by the caller; free with tigas_context_destroy.
+ * Environment read here: TIGAS_GRAPHS=0 (no graph capture), TIGAS_SORT=1
+ * (single-pass sort), TIGAS_BLEND_CULL=0 (the blend keeps every list entry
+ * whose pixel box meets a wave's block, instead of also dropping those whose
+ * exponent stays below the skip threshold on the whole block; frames are
+ * identical either way). */
 tigas_status tigas_context_create(int device, tigas_context** out);
 void tigas_context_destroy(tigas_context* ctx);
 
@@ -192,6 +198,22 @@ tigas_status tigas_set_sort(tigas_context* ctx, int single_pass);
  * context). */
 int64_t tigas_sort_fallbacks(const tigas_context* ctx);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
+
+/* Kernel timing with HIP events recorded on the rendering stream around every
+ * kernel launch of every render on this context; while it is on, launch
+ * sequences run uncaptured.  tigas_profile_kernels switches it on or off and
+ * clears the totals; tigas_kernel_times copies up to `cap` entries (kernel
+ * instantiation name, launches, summed milliseconds) into the caller's
+ * array, sorted by name, and sets *count to the number of kernels timed
+ * (which may exceed cap).  TIGAS_E_INVALID for null pointers. */
+typedef struct {
+    char name[120];
+    int64_t launches;
+    double total_ms;
+} tigas_kernel_time;
+
+tigas_status tigas_profile_kernels(tigas_context* ctx, int enable);
+tigas_status tigas_kernel_times(tigas_context* ctx, tigas_kernel_time* out, int cap, int* count);
 
 /* Renders like tigas_render with a blend kernel that also counts the work it
  * does: *evaluations = (pixel, Gaussian) pairs whose alpha was evaluated

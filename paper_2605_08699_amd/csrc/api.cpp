@@ -22,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <cxxabi.h>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -30,6 +31,8 @@
 #include "tigas_internal.h"
 
 using namespace tigas;
+
+thread_local KernelTimer* tigas::g_kernel_timer = nullptr;
 
 namespace {
 
@@ -187,6 +190,58 @@ struct GraphEntry {
 
 }  // namespace
 
+// Events around every launch of one frame (kernel profiling); the pool is
+// reused frame after frame.
+struct EventTimer final : KernelTimer {
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<const void*, size_t>> recs;  // kernel handle, index of its start event
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void before(const void* kernel, hipStream_t st) override {
+        recs.emplace_back(kernel, used);
+        HIPCHK(hipEventRecord(next(), st));
+    }
+    void after(hipStream_t st) override { HIPCHK(hipEventRecord(next(), st)); }
+    void reset() {
+        used = 0;
+        recs.clear();
+    }
+    ~EventTimer() override {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// Demangled name of a kernel from its host-side handle, as profilers print it.
+std::string kernel_name(const void* kernel, hipStream_t st) {
+    static std::mutex mu;
+    static std::map<const void*, std::string> names;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(kernel);
+    if (it != names.end()) return it->second;
+    const char* m = hipKernelNameRefByPtr(kernel, st);
+    std::string name = m ? m : "?";
+    int status = 0;
+    char* d = m ? abi::__cxa_demangle(m, nullptr, nullptr, &status) : nullptr;
+    if (d && status == 0) name = d;
+    std::free(d);
+    names[kernel] = name;
+    return name;
+}
+
+// Installs a timer for the calling thread's launches for one scope.
+struct TimerScope {
+    KernelTimer* prev;
+    explicit TimerScope(KernelTimer* t) : prev(g_kernel_timer) { g_kernel_timer = t; }
+    ~TimerScope() { g_kernel_timer = prev; }
+};
+
 struct Workspace {
     hipStream_t stream = nullptr;
     std::mutex mu;  // one launch sequence at a time per workspace
@@ -208,6 +263,7 @@ struct Workspace {
     HostPinned host_views, host_counters;
     DevBuf work;            // blend work counters (evaluations, contributions)
     hipEvent_t ev[7] = {};  // stage boundaries when stage timing is on
+    EventTimer ktimer;      // per-launch events when kernel timing is on
     uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0, view_cap = 0;
     uint32_t last_D = 0;
     uint64_t gen = 1;  // bumped whenever a buffer is reallocated (captured graphs hold its pointers)
@@ -303,8 +359,11 @@ struct tigas_context {
     tigas_stats last{};
     std::mutex stats_mu;
     std::atomic<bool> profile{false};
+    std::atomic<bool> profile_kernels{false};
+    std::map<std::string, std::pair<int64_t, double>> kernel_ms;  // name -> (launches, total ms)
     std::atomic<bool> use_graphs{true};
     std::atomic<bool> sort_onepass{false};  // single-pass (look-back) radix sort
+    std::atomic<bool> blend_cull{true};     // blend: per-block threshold culling
     std::atomic<int64_t> sort_fallbacks{0};  // frames redone after a look-back wait gave up
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
@@ -487,8 +546,15 @@ void prepare(Workspace& ws, const Plan& plan, bool debug) {
 // that holds the sorted lists.
 //   preprocess -> scan visible -> compact -> depth passes (visible Gaussians)
 //   -> duplicate in depth order -> tile passes (duplicates) -> ranges -> blend
+// Per-context switches that change the launch sequence (not its results).
+struct LaunchOptions {
+    bool onepass = false;  // single-pass look-back radix sort
+    bool cull = true;      // blend: per-block threshold culling of list entries
+};
+
 int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks,
-            bool onepass) {
+            const LaunchOptions& opt) {
+    const bool onepass = opt.onepass;
     hipStream_t st = ws.stream;
     auto mark = [&](int i) {
         if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
@@ -556,7 +622,7 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
-                 plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, st);
+                 plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, opt.cull, st);
     mark(6);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ws.host_counters.p, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -573,10 +639,18 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     const int pblocks =
         plan.persistent ? ctx->cus * blend_persistent_occupancy(plan.tc.tw, plan.tc.th, plan.tc.bd, plan.tc.ppl) : 0;
     // stage timing needs events between the launches: that runs uncaptured
-    const bool onepass = ctx->sort_onepass.load();
-    const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof;
-    if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks, onepass);
-    const std::string key = shape_key(plan, true) + (onepass ? "s1" : "s3");
+    LaunchOptions opt;
+    opt.onepass = ctx->sort_onepass.load();
+    opt.cull = ctx->blend_cull.load();
+    const bool kprof = ctx->profile_kernels.load();
+    const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof && !kprof;
+    if (kprof) {
+        ws.ktimer.reset();
+        TimerScope ts(&ws.ktimer);
+        return enqueue(ws, plan, debug, prof, work, pblocks, opt);
+    }
+    if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks, opt);
+    const std::string key = shape_key(plan, true) + (opt.onepass ? "s1" : "s3") + (opt.cull ? "c1" : "c0");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
         if (g.exec) HIPCHK(hipGraphExecDestroy(g.exec));
@@ -589,7 +663,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         HIPCHK(hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal));
         int cur = 0;
         try {
-            cur = enqueue(ws, plan, debug, prof, work, pblocks, onepass);
+            cur = enqueue(ws, plan, debug, prof, work, pblocks, opt);
         } catch (...) {
             (void)hipStreamEndCapture(ws.stream, &graph_t);
             if (graph_t) (void)hipGraphDestroy(graph_t);
@@ -650,6 +724,16 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
             ctx->stage_ms[i] += ms;
         }
         ctx->stage_frames += 1;
+    }
+    if (ctx->profile_kernels.load()) {
+        for (const auto& r : ws.ktimer.recs) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ws.ktimer.pool[r.second], ws.ktimer.pool[r.second + 1]));
+            auto& e = ctx->kernel_ms[kernel_name(r.first, ws.stream)];
+            e.first += 1;
+            e.second += ms;
+        }
+        ws.ktimer.reset();
     }
     ctx->last.visible = c.visible;
     ctx->last.duplicates = c.D;
@@ -1148,6 +1232,7 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         if (const char* f = std::getenv("TIGAS_TUNE_CACHE")) c->tune_file = f;
         if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_SORT")) c->sort_onepass.store(std::atoi(g) != 0);
+        if (const char* g = std::getenv("TIGAS_BLEND_CULL")) c->blend_cull.store(std::atoi(g) != 0);
         load_tune_file(c.get());
         *out = c.release();
     });
@@ -1316,6 +1401,32 @@ tigas_status tigas_profile_stages(tigas_context* ctx, int enable) {
         for (double& x : ctx->stage_ms) x = 0.0;
         ctx->stage_frames = 0;
         ctx->profile.store(enable != 0);
+    });
+}
+
+tigas_status tigas_profile_kernels(tigas_context* ctx, int enable) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        ctx->kernel_ms.clear();
+        ctx->profile_kernels.store(enable != 0);
+    });
+}
+
+tigas_status tigas_kernel_times(tigas_context* ctx, tigas_kernel_time* out, int cap, int* count) {
+    return guard([&] {
+        if (!ctx || !count || cap < 0 || (cap > 0 && !out)) fail(TIGAS_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(ctx->stats_mu);
+        int i = 0;
+        for (const auto& kv : ctx->kernel_ms) {
+            if (i < cap) {
+                std::snprintf(out[i].name, sizeof out[i].name, "%s", kv.first.c_str());
+                out[i].launches = kv.second.first;
+                out[i].total_ms = kv.second.second;
+            }
+            ++i;
+        }
+        *count = i;
     });
 }
 

@@ -1093,6 +1093,7 @@ struct BlendArgs {
     const uint2* bbox;
     uint32_t nrec;
     unsigned long long* work;
+    int cull;  // drop entries below the skip threshold on the whole block (never changes a pixel)
 };
 
 // Per-wave LDS slice of staged Gaussians: block-relative centre (u, v of the
@@ -1105,14 +1106,49 @@ struct Stage {
     float2 c[64 * BD];  // b, v_rel1
 };
 
+// log2(1/255): below it, 2^e < 1/255 and a Gaussian is skipped at the pixel.
+constexpr float LOG2_ALPHA_MIN = -7.99435343685886f;
+
+// Does the Gaussian with exponent e(d) = A dx^2 + B dx dy + C dy^2 + L
+// (negative-definite quadratic part) stay below the skip threshold on the
+// whole rectangle [dx0, dx1] x [dy0, dy1] of offsets?  The maximum of a
+// concave quadratic over a rectangle is at the unconstrained maximum when
+// that lies inside, else on one of the four edges, where it is a 1D concave
+// quadratic maximised at a clamped stationary point.  The test is
+// conservative: it answers yes only with a margin far above the FP32
+// rounding of this bound and of the per-pixel exponent, so a Gaussian it
+// removes would have been skipped at every pixel of the rectangle.
+__device__ __forceinline__ bool below_threshold(float A, float B, float C, float L, float dx0, float dx1, float dy0,
+                                                float dy1) {
+    if (!(A < 0.0f && C < 0.0f && B * B < 4.0f * A * C)) return false;  // not concave: keep it
+    float q = 0.0f;
+    if (!(dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f)) {
+        const float ra = __builtin_amdgcn_rcpf(2.0f * A), rc = __builtin_amdgcn_rcpf(2.0f * C);
+        auto edge_x = [&](float cx) {  // dx = cx fixed, best dy
+            const float dy = fminf(fmaxf(-B * cx * rc, dy0), dy1);
+            return (A * cx + B * dy) * cx + C * dy * dy;
+        };
+        auto edge_y = [&](float cy) {  // dy = cy fixed, best dx
+            const float dx = fminf(fmaxf(-B * cy * ra, dx0), dx1);
+            return (C * cy + B * dx) * cy + A * dx * dx;
+        };
+        q = fmaxf(fmaxf(edge_x(dx0), edge_x(dx1)), fmaxf(edge_y(dy0), edge_y(dy1)));
+    }
+    const float r2 = fmaxf(dx0 * dx0, dx1 * dx1) + fmaxf(dy0 * dy0, dy1 * dy1);
+    const float margin = 0.02f + 1e-5f * (fabsf(A) + fabsf(B) + fabsf(C)) * r2;
+    return q + L < LOG2_ALPHA_MIN - margin;  // false for NaN
+}
+
 // One tile of TW x TH pixels.  Each wave owns a block of 8 x (8 PPL) pixels
 // (PPL pixels per lane, one per stacked 8x8 sub-block); wave w takes block
 // (w mod TW/8, w div TW/8).  The wave walks the tile's depth-sorted list in
 // batches of 64 * BD entries: every lane fetches entries, keeps those whose
-// pixel box meets the wave's block, compacts them into the wave's LDS slice
-// (ballot + mbcnt) and the 64 lanes then composite them front to back.  Each
-// pixel's operations (and their rounding) are the same for every tile shape
-// and PPL: offsets are taken from the 8x8 sub-block's own origin.  A wave
+// pixel box meets the wave's block (and, with culling on, whose exponent can
+// reach the skip threshold somewhere on it), compacts them into the wave's
+// LDS slice (ballot + mbcnt) and the 64 lanes then composite them front to
+// back.  Each pixel's operations (and their rounding) are the same for every
+// tile shape and PPL: offsets are taken from the 8x8 sub-block's own origin,
+// and the entries culling drops are ones every pixel of the block skips.  A wave
 // leaves as soon as all of its pixels have terminated; there is no barrier
 // between the waves of a tile.
 template <int TW, int TH, int BD, int PPL, bool COUNT>
@@ -1172,12 +1208,22 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
                 const int x1 = (int)(b.y & 0xffffu), y1 = (int)(b.y >> 16);
                 hit = !(x1 < sx || x0 > bx1 || y1 < sy || y0 > by1);
             }
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b1 = a, c2 = a;
+            float u = 0.f, v0 = 0.f;
+            if (hit) {
+                a = A.rec0[r];
+                b1 = A.rec1[r];
+                c2 = A.rec2[r];
+                // pixel centre relative to each 8x8 sub-block origin, hi and lo parts combined here
+                u = (a.x - fsx) + a.z;
+                v0 = (a.y - fsy[0]) + a.w;
+                hit = !(A.cull && below_threshold(b1.x, b1.y, b1.z, b1.w, 0.5f - u, 7.5f - u, 0.5f - v0,
+                                                  (float)(8 * PPL) - 0.5f - v0));
+            }
             const uint64_t m = ballot(hit);
             if (hit) {
                 const uint32_t slot = cnt + bits_below(m);
-                const float4 a = A.rec0[r], b1 = A.rec1[r], c2 = A.rec2[r];
-                // pixel centre relative to each 8x8 sub-block origin, hi and lo parts combined here
-                S.a[slot] = make_float4((a.x - fsx) + a.z, (a.y - fsy[0]) + a.w, b1.x, b1.y);
+                S.a[slot] = make_float4(u, v0, b1.x, b1.y);
                 S.b[slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
                 S.c[slot] = make_float2(c2.z, PPL > 1 ? (a.y - fsy[PPL - 1]) + a.w : 0.0f);
             }
@@ -1255,14 +1301,17 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
 }
 
 // One workgroup per tile.  XCD-aware mapping: consecutive workgroup ids go
-// round-robin to the 8 XCDs; each XCD gets a contiguous band of tiles so
-// neighbouring tiles (which share Gaussians) meet in the same L2.
+// round-robin to the 8 XCDs; XCD x takes the chunks of BLEND_CHUNK
+// consecutive tiles numbered x, x + 8, x + 16, ..., so neighbouring tiles
+// (which share Gaussians) meet in the same L2 while every XCD gets a share of
+// every part of the image (dense and sparse regions alike).
+constexpr uint32_t BLEND_CHUNK = 16;
 template <int TW, int TH, int BD, int PPL, bool COUNT>
 __global__ __launch_bounds__(TW* TH / PPL) void k_blend(BlendArgs A) {
     constexpr int NW = TW * TH / (64 * PPL);
     __shared__ Stage<BD> stage[NW];
-    const uint32_t per = (A.n_tiles + 7) / 8;
-    const uint32_t tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const uint32_t j = blockIdx.x >> 3, x = blockIdx.x & 7;
+    const uint32_t tile = ((j / BLEND_CHUNK) * 8u + x) * BLEND_CHUNK + (j % BLEND_CHUNK);
     if (tile >= A.n_tiles) return;
     blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, stage);
 }
@@ -1305,7 +1354,13 @@ __global__ void k_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n) {
 
 // ------------------------------------------------------------- launchers
 
-#define TIGAS_LAUNCH(kernel, grid, block, st, ...) hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__)
+#define TIGAS_LAUNCH(kernel, grid, block, st, ...)                                        \
+    do {                                                                                  \
+        KernelTimer* kt_ = g_kernel_timer;                                                \
+        if (kt_) kt_->before(reinterpret_cast<const void*>(kernel), st);                 \
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                      \
+        if (kt_) kt_->after(st);                                                          \
+    } while (0)
 
 template <int ST>
 static void preprocess_deg(int deg, dim3 grid, const SceneView& s, const ViewParams* v, int nv, uint32_t rb,
@@ -1428,7 +1483,8 @@ static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int pe
         TIGAS_LAUNCH((k_blend_persistent<TW, TH, BD, PPL>), dim3(persistent_blocks), dim3(TW * TH / PPL), st, A,
                      queue);
     } else {
-        const dim3 grid(((A.n_tiles + 7) / 8) * 8);
+        const uint32_t per_round = 8 * BLEND_CHUNK;  // one chunk for every XCD
+        const dim3 grid(((A.n_tiles + per_round - 1) / per_round) * per_round);
         if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, true>), grid, dim3(TW * TH / PPL), st, A);
         else TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, false>), grid, dim3(TW * TH / PPL), st, A);
     }
@@ -1445,9 +1501,9 @@ static void blend_bd(int bd, const BlendArgs& A, bool count, uint32_t* queue, in
 
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st) {
+                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st) {
     if (n_tiles == 0) return;
-    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work};
+    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work, cull ? 1 : 0};
     const bool count = work != nullptr;
     if (count) queue = nullptr;
     const bool two = ppl == 2 && tile_h >= 16;

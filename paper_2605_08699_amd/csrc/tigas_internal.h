@@ -133,11 +133,23 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, hipStream_t st);
+                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st);
 // With `queue` (8 counters cleared per frame) the blend runs as a persistent
 // kernel of persistent_blocks workgroups pulling tiles from work queues.
-// ppl: pixels per lane (1, or 2 for tiles at least 16 tall).
+// ppl: pixels per lane (1, or 2 for tiles at least 16 tall).  cull: drop,
+// per wave, the entries whose exponent stays below the skip threshold on the
+// wave's whole pixel block (they would be skipped at every pixel anyway).
 int blend_persistent_occupancy(int tile_w, int tile_h, int batch_depth, int ppl);
 void launch_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
+
+// Per-launch timing for profiling: while a timer is installed for the calling
+// host thread, every kernel launch is bracketed by two events on its stream
+// (never used for captured launches).
+struct KernelTimer {
+    virtual void before(const void* kernel, hipStream_t st) = 0;  // kernel: its host-side handle
+    virtual void after(hipStream_t st) = 0;
+    virtual ~KernelTimer() = default;
+};
+extern thread_local KernelTimer* g_kernel_timer;
 
 }  // namespace tigas

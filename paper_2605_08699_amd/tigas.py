@@ -73,11 +73,16 @@ class StageC(ctypes.Structure):
                 ("frames", ctypes.c_int64)]
 
 
+class KernelTimeC(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 120), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 # every symbol include/tigas.h declares
 EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
-           "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks")
+           "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks",
+           "tigas_profile_kernels", "tigas_kernel_times")
 
 _lib = None
 
@@ -115,12 +120,15 @@ def lib():
         L.tigas_sort_fallbacks.argtypes = [P]
         L.tigas_sort_fallbacks.restype = I64
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
+        L.tigas_profile_kernels.argtypes = [P, I]
+        L.tigas_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimeC), I, ctypes.POINTER(I)]
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
                                              ctypes.POINTER(I64), ctypes.POINTER(I64)]
         for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
-                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort"):
+                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort",
+                     "tigas_profile_kernels", "tigas_kernel_times"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -233,6 +241,18 @@ class Context:
         st = StageC()
         _check(lib().tigas_stage_times(self.handle, ctypes.byref(st)))
         return {f: (int(getattr(st, f)) if f == "frames" else float(getattr(st, f))) for f, _ in StageC._fields_}
+
+    def profile_kernels(self, enable: bool = True):
+        """Switch per-launch HIP-event timing of every kernel on/off (clears the sums)."""
+        _check(lib().tigas_profile_kernels(self.handle, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """{kernel name: (launches, summed ms)} since profile_kernels(True)."""
+        n = ctypes.c_int(0)
+        _check(lib().tigas_kernel_times(self.handle, None, 0, ctypes.byref(n)))
+        arr = (KernelTimeC * max(n.value, 1))()
+        _check(lib().tigas_kernel_times(self.handle, arr, n.value, ctypes.byref(n)))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
 
     def set_graphs(self, enable: bool):
         """Capture/replay launch sequences as HIP graphs (default on)."""

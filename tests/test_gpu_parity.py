@@ -209,3 +209,51 @@ def test_single_pass_sort_gives_the_same_lists_and_frames(ctx, c1):
     finally:
         ctx.set_sort(False)
         big.free()
+
+
+def test_kernel_timing_brackets_every_launch(ctx, c1):
+    scene, poses, k, W, H = c1
+    s = ctx.load_scene(scene)
+    ref = ctx.render(s, poses[0], k, W, H, fmt="f32")
+    ctx.profile_kernels(True)
+    try:
+        for _ in range(3):
+            got = ctx.render(s, poses[0], k, W, H, fmt="f32")
+        kt = ctx.kernel_times()
+    finally:
+        ctx.profile_kernels(False)
+    _say("kernel times", kt)
+    np.testing.assert_array_equal(got, ref)
+    pre = [n for n in kt if "k_preprocess<0, 3>" in n]
+    blend = [n for n in kt if "k_blend<" in n]
+    assert len(pre) == 1 and kt[pre[0]][0] == 3
+    assert len(blend) == 1 and kt[blend[0]][0] == 3
+    assert all(ms > 0 for _, ms in kt.values())
+
+
+def test_block_culling_never_changes_a_pixel(ctx, monkeypatch):
+    # the blend drops, per wave, entries whose exponent stays below the skip
+    # threshold on its whole block; frames must equal those rendered without it
+    scene = synth.c3_scene()
+    traj = synth.c3_trajectory(300)
+    k = synth.fov_intrinsics(1920, 1080)
+    monkeypatch.setenv("TIGAS_BLEND_CULL", "0")
+    plain = tigas.Context(0)
+    monkeypatch.delenv("TIGAS_BLEND_CULL")
+    try:
+        sa = ctx.load_scene(scene)
+        sb = plain.load_scene(scene)
+        for i in (0, 75, 150, 225):
+            for tile, ppl in (((16, 32), 1), ((16, 16), 2), ((8, 8), 1)):
+                _say("cull check pose", i, tile, ppl)
+                a = ctx.render(sa, traj[i], k, 1920, 1080, fmt="f32", tile=tile, batch_depth=64, ppl=ppl)
+                b = plain.render(sb, traj[i], k, 1920, 1080, fmt="f32", tile=tile, batch_depth=64, ppl=ppl)
+                np.testing.assert_array_equal(a, b, err_msg=f"pose {i} tile {tile} ppl {ppl}")
+        ea, ca = ctx.count_blend_work(sa, traj[0], k, 1920, 1080, tile=(16, 32), batch_depth=64, ppl=1)
+        eb, cb = plain.count_blend_work(sb, traj[0], k, 1920, 1080, tile=(16, 32), batch_depth=64, ppl=1)
+        _say("evaluations with / without culling", ea, eb, "contributions", ca, cb)
+        assert ca == cb and ea <= eb
+        sa.free()
+        sb.free()
+    finally:
+        plain.close()
