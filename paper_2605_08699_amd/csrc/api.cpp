@@ -100,13 +100,18 @@ struct HostPinned {
     ~HostPinned() {
         if (p) (void)hipHostFree(p);
     }
-    void ensure(size_t need) {
+    // coherent: fine-grained, so device stores reach host memory directly
+    void ensure(size_t need, bool coherent = false) {
         if (need <= bytes) return;
         if (p) HIPCHK(hipHostFree(p));
         p = nullptr;
         bytes = 0;
-        HIPCHK(hipHostMalloc(&p, std::max<size_t>(need, 256), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(&p, std::max<size_t>(need, 256), coherent ? hipHostMallocCoherent : hipHostMallocDefault));
         bytes = std::max<size_t>(need, 256);
+    }
+    template <typename T>
+    T* as() const {
+        return reinterpret_cast<T*>(p);
     }
 };
 
@@ -377,7 +382,7 @@ struct tigas_context {
         if (!p) {
             p.reset(new Workspace());
             p->stream = s;
-            p->host_counters.ensure(sizeof(Counters));
+            p->host_counters.ensure(sizeof(Counters), /*coherent=*/true);
             if (p->counters.ensure(sizeof(Counters))) HIPCHK(hipMemset(p->counters.p, 0, sizeof(Counters)));
         }
         return *p;
@@ -619,13 +624,12 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
                             : launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
                                           sort_blocks(ws.dup_cap), cd, debug, cnt, 4, nullptr, nullptr, st);
     mark(4);
-    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), st);
+    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.host_counters.as<Counters>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
                  plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, opt.cull, st);
     mark(6);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(ws.host_counters.p, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     return cur;
 }
 
@@ -680,6 +684,20 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     return g.cur;
 }
 
+// Waits for the stream: polls for up to ~2 ms (a frame's completion is then
+// seen within a microsecond or two instead of after a blocking wake-up), then
+// blocks.
+void wait_stream(hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) HIPCHK(e);
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) break;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
 // Runs the plan to completion (synchronous).  A first attempt whose
 // duplicates overflowed the buffers emitted nothing; it is detected here and
 // the frame is rendered again with buffers sized from the true count.
@@ -687,7 +705,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
     prepare(ws, plan, debug);
     const bool prof = ctx->profile.load();
     int cur = launch_plan(ctx, ws, plan, debug, prof, work);
-    HIPCHK(hipStreamSynchronize(ws.stream));
+    wait_stream(ws.stream);
     Counters c;
     std::memcpy(&c, ws.host_counters.p, sizeof(c));
     int rerenders = 0;
@@ -698,7 +716,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
         ctx->sort_onepass.store(false);
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
         cur = launch_plan(ctx, ws, plan, debug, prof, work);
-        HIPCHK(hipStreamSynchronize(ws.stream));
+        wait_stream(ws.stream);
         std::memcpy(&c, ws.host_counters.p, sizeof(c));
         rerenders = 1;
         ctx->sort_fallbacks.fetch_add(1);
@@ -710,7 +728,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
         if (debug) prepare(ws, plan, debug);
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
         cur = launch_plan(ctx, ws, plan, debug, prof, work);
-        HIPCHK(hipStreamSynchronize(ws.stream));
+        wait_stream(ws.stream);
         std::memcpy(&c, ws.host_counters.p, sizeof(c));
         if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
         rerenders += 1;
@@ -1288,14 +1306,13 @@ tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tig
                 for (int c = 0; c < 3; ++c) a[4 * n + 4 * i + c] = ls[3 * i + c];
                 a[4 * n + 4 * i + 3] = op[i];
             }
+            // SH: the np 16-byte words of a Gaussian are contiguous, so a
+            // culled Gaussian's coefficients are never fetched
             const int np = (ncoef + 3) / 4;
             std::vector<float> shp((size_t)np * 4 * nn, 0.f);
-            for (int p = 0; p < np; ++p)
-                for (int64_t i = 0; i < n; ++i)
-                    for (int c = 0; c < 4; ++c) {
-                        const int k = 4 * p + c;
-                        shp[((size_t)p * n + i) * 4 + c] = k < ncoef ? sh[48 * i + k] : 0.f;
-                    }
+            for (int64_t i = 0; i < n; ++i)
+                for (int k = 0; k < ncoef; ++k) shp[(size_t)i * np * 4 + k] = sh[48 * i + k];
+            s->view.sh_stride = np;
             s->attr.ensure(a.size() * 4);
             s->sh.ensure(shp.size() * 4);
             HIPCHK(hipMemcpy(s->attr.p, a.data(), (size_t)n * 32, hipMemcpyHostToDevice));
@@ -1311,12 +1328,9 @@ tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tig
             }
             const int np = (ncoef + 7) / 8;
             std::vector<uint16_t> shp((size_t)np * 8 * nn, 0);
-            for (int p = 0; p < np; ++p)
-                for (int64_t i = 0; i < n; ++i)
-                    for (int c = 0; c < 8; ++c) {
-                        const int k = 8 * p + c;
-                        shp[((size_t)p * n + i) * 8 + c] = k < ncoef ? cvt(sh[48 * i + k]) : 0;
-                    }
+            for (int64_t i = 0; i < n; ++i)
+                for (int k = 0; k < ncoef; ++k) shp[(size_t)i * np * 8 + k] = cvt(sh[48 * i + k]);
+            s->view.sh_stride = np;
             s->attr.ensure(a.size() * 2);
             s->sh.ensure(shp.size() * 2);
             HIPCHK(hipMemcpy(s->attr.p, a.data(), (size_t)n * 16, hipMemcpyHostToDevice));

@@ -221,7 +221,7 @@ __device__ __forceinline__ void cov2d_fp64(const float* q32, const float* ls32, 
     abc[2] = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2] + (double)DILATION;
 }
 
-// SH coefficients of Gaussian g (the planes of degree <= DEG) decoded to FP32.
+// SH coefficients of Gaussian g (the words of degree <= DEG) decoded to FP32.
 template <int ST, int DEG>
 __device__ __forceinline__ void load_sh(const SceneView& s, int64_t n, int64_t g, float* k) {
     if (ST == 0) {
@@ -229,7 +229,7 @@ __device__ __forceinline__ void load_sh(const SceneView& s, int64_t n, int64_t g
         constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 3) / 4;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const float4 t = sh[(int64_t)p * n + g];
+            const float4 t = sh[g * s.sh_stride + p];
             k[4 * p] = t.x;
             k[4 * p + 1] = t.y;
             k[4 * p + 2] = t.z;
@@ -239,7 +239,7 @@ __device__ __forceinline__ void load_sh(const SceneView& s, int64_t n, int64_t g
         const uint4* sh = reinterpret_cast<const uint4*>(s.sh);
         constexpr int NP = ((DEG + 1) * (DEG + 1) * 3 + 7) / 8;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) unpack8(sh[(int64_t)p * n + g], &k[8 * p], ST);
+        for (int p = 0; p < NP; ++p) unpack8(sh[g * s.sh_stride + p], &k[8 * p], ST);
     }
 }
 
@@ -1061,9 +1061,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
 // ------------------------------------------------------------------ ranges
 
 // Tile boundaries in the sorted tile words; the ranges array was cleared by
-// k_scan_visible, so tiles without entries stay [0, 0).
+// k_scan_visible, so tiles without entries stay [0, 0).  The frame's counters
+// are final here: one thread also stores them to the host-visible block the
+// host reads after the frame (no separate copy).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tile, const Counters* __restrict__ cnt,
-                                                uint32_t cap, uint2* __restrict__ ranges) {
+                                                uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t D = sort_count(cnt, 0, cap);
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < D; i += gridDim.x * 256) {
         const uint32_t t = tile[i];
@@ -1473,8 +1476,9 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
     return cur;
 }
 
-void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st) {
-    TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges);
+void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
+                   hipStream_t st) {
+    TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges, host_cnt);
 }
 
 template <int TW, int TH, int BD, int PPL>

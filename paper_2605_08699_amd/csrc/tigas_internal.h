@@ -27,7 +27,8 @@ struct SceneView {
     int sh_degree;
     const float* mean;
     const void* attr;
-    const void* sh;
+    const void* sh;  // per Gaussian: sh_stride contiguous 16-byte words (4 floats or 8 halves)
+    int sh_stride;
 };
 
 // Per-view camera and tiling parameters, computed on the host in FP64 and
@@ -130,7 +131,9 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
 int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
                          uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
                          const uint32_t* touched, unsigned long long* lookback, uint32_t* tickets, hipStream_t st);
-void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, hipStream_t st);
+// host_cnt: pinned host memory that receives a copy of the counters.
+void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
+                   hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
                   int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st);
