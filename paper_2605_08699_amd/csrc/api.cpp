@@ -314,7 +314,7 @@ struct Workspace {
             grow(val[i], (size_t)cap * 4);
             grow(ext[i], (size_t)cap * 4);
         }
-        grow(hist, (size_t)256 * SORT_MAX_BLOCKS * 4);
+        grow(hist, (size_t)2 * 256 * SORT_MAX_BLOCKS * 4);  // counts, then segment digit prefixes
         grow(totals, (size_t)256 * MAX_SORT_PASSES * 4);
         grow(queue, (8 + MAX_SORT_PASSES) * 4);  // blend band queues, then sort tickets
         if (lookback.ensure(((size_t)cap / SORT_CHUNK + 2) * 256 * 8)) {
@@ -478,10 +478,19 @@ size_t frame_bytes(const ViewParams& v) { return (size_t)v.width * v.height * 3 
 // Depth digits of the (tile | depth) key: positive FP32 bit patterns, bit 31 clear.
 const SortPass kDepthPasses[4] = {{0, 8}, {8, 8}, {16, 8}, {24, 7}};
 
+// The fewest passes of at most 8 bits, with the bits spread evenly over them
+// (e.g. 12 bits as 6 + 6): fewer digits per pass give longer runs of equal
+// digits per chunk, so the scatter writes whole cache lines more often.
 std::vector<SortPass> tile_passes(uint32_t n_tiles) {
     std::vector<SortPass> p;
     const int tb = ceil_log2(n_tiles);
-    for (int sh = 0; sh < tb; sh += 8) p.push_back({sh, std::min(8, tb - sh)});
+    const int np = (tb + 7) / 8;
+    int sh = 0;
+    for (int i = 0; i < np; ++i) {
+        const int b = (tb - sh + (np - i) - 1) / (np - i);
+        p.push_back({sh, b});
+        sh += b;
+    }
     return p;
 }
 

@@ -715,11 +715,17 @@ __device__ __forceinline__ void segment(uint32_t D, int nb, int b, uint32_t* beg
     *end = (uint32_t)min((uint64_t)D, s + per);
 }
 
+// Digit counts of one segment: hist[d * nb + b] = keys of digit d in segment
+// b, pre[d * nb + b] = keys of digits below d in segment b (the segment's
+// exclusive digit prefix).  Summed over segments, pre gives each digit's global
+// start, so no kernel needs device-wide atomics on the 256 digit totals.
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* __restrict__ keys,
                                                                const Counters* __restrict__ cnt, int which,
                                                                uint32_t cap, int shift, int bits,
                                                                uint32_t* __restrict__ hist,
-                                                               uint32_t* __restrict__ totals, int nb) {
+                                                               uint32_t* __restrict__ pre, int nb) {
+    static_assert(SORT_THREADS == 256, "one thread per digit");
+    __shared__ uint32_t red[SORT_THREADS / 64];
     __shared__ uint32_t h[SORT_THREADS / 64][256];
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < 256 * (SORT_THREADS / 64); i += SORT_THREADS) (&h[0][0])[i] = 0u;
@@ -754,34 +760,37 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     }
     __syncthreads();
     const int t = threadIdx.x;
-    if (t < 256) {
-        uint32_t s = 0;
+    uint32_t s = 0;
 #pragma unroll
-        for (int j = 0; j < SORT_THREADS / 64; ++j) s += h[j][t];
-        if (t <= (int)mask) {
-            hist[(size_t)t * nb + blockIdx.x] = s;
-            if (s) atomicAdd(&totals[t], s);
-        }
+    for (int j = 0; j < SORT_THREADS / 64; ++j) s += h[j][t];
+    if (t > (int)mask) s = 0;
+    uint32_t tot;
+    const uint32_t e = block_excl_scan<SORT_THREADS>(s, red, &tot);
+    if (t <= (int)mask) {
+        hist[(size_t)t * nb + blockIdx.x] = s;
+        pre[(size_t)t * nb + blockIdx.x] = e;
     }
 }
 
-// One wave per digit: exclusive offsets of that digit over all segments.
-__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals,
+// One wave per digit: the digit's global start (the sum of the segments'
+// exclusive digit prefixes), then its exclusive offsets over the segments.
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ pre,
                                                    int nb, int ndig) {
     const int lane = threadIdx.x & 63;
     const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (d >= ndig) return;  // whole wave exits together
-    uint32_t part = 0;
-    for (int j = lane; j < d; j += 64) part += totals[j];
-    uint32_t running = wave_sum(part);
     uint32_t* row = hist + (size_t)d * nb;
+    const uint32_t* prow = pre + (size_t)d * nb;
     constexpr int NJ = SORT_MAX_BLOCKS / 64;
     uint32_t x[NJ];
+    uint32_t part = 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
         const int j = q * 64 + lane;
         x[q] = j < nb ? row[j] : 0u;
+        part += j < nb ? prow[j] : 0u;
     }
+    uint32_t running = wave_sum(part);
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
         if (q * 64 >= nb) break;
@@ -1424,11 +1433,11 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
-        uint32_t* totals = b.totals + (totals_base + p) * 256;
+        uint32_t* pre = b.hist + (size_t)256 * SORT_MAX_BLOCKS;
         TIGAS_LAUNCH(k_sort_upsweep, dim3(nblocks), dim3(SORT_THREADS), st, (const uint32_t*)b.key[cur], cnt, which,
-                     cap, ps.shift, ps.bits, b.hist, totals, nblocks);
+                     cap, ps.shift, ps.bits, b.hist, pre, nblocks);
         const int ndig = 1 << ps.bits;
-        TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, totals, nblocks, ndig);
+        TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig);
         const bool sums = touched && p + 1 == npasses;
 #define TIGAS_DOWN(E, S)                                                                                        \
     TIGAS_LAUNCH((k_sort_downsweep<E, S>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],      \

@@ -83,8 +83,8 @@ struct SortBuffers {
     uint32_t* key[2];
     uint32_t* val[2];
     uint32_t* ext[2];
-    uint32_t* hist;    // [256][nblocks]
-    uint32_t* totals;  // [MAX_SORT_PASSES][256]
+    uint32_t* hist;    // [256][SORT_MAX_BLOCKS] digit counts per segment, then as many segment digit prefixes
+    uint32_t* totals;  // [MAX_SORT_PASSES][256] digit totals (single-pass sort only)
 };
 
 // Arrays cleared (as u32 words) by the first kernel after preprocess.
