@@ -491,28 +491,43 @@ __global__ __launch_bounds__(256) void k_conic_fp64(const uint2* __restrict__ li
     }
 }
 
-// ------------------------------------------------------------- block scans
-// Exclusive scan of n per-block counts by one workgroup (wave64 DPP scans,
-// SCAN_ITEMS consecutive counts per thread); returns the 64-bit total.
-__device__ uint64_t scan_counts(const uint32_t* __restrict__ in, int n, uint32_t* __restrict__ out, uint32_t* red) {
+// Exclusive scan of n counts by one workgroup, SCAN_THREADS * SCAN_ITEMS at a
+// time: coalesced loads into LDS, SCAN_ITEMS consecutive counts per thread
+// summed from LDS (one pad word per 32 keeps the strided reads free of bank
+// conflicts), a workgroup scan of the thread sums, and the offsets written
+// back through LDS and stored coalesced.  Returns the 64-bit total.
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+constexpr int SCAN_STAGE = SCAN_CHUNK + SCAN_CHUNK / 32;
+__device__ __forceinline__ int spad(int i) { return i + (i >> 5); }
+
+__device__ uint64_t scan_counts(const uint32_t* __restrict__ in, int n, uint32_t* __restrict__ out, uint32_t* red,
+                                uint32_t* stage) {
     uint64_t running = 0;
-    for (int base = 0; base < n; base += SCAN_THREADS * SCAN_ITEMS) {
-        const int i0 = base + threadIdx.x * SCAN_ITEMS;
+    for (int base = 0; base < n; base += SCAN_CHUNK) {
+#pragma unroll
+        for (int r = 0; r < SCAN_ITEMS; ++r) {
+            const int i = r * SCAN_THREADS + (int)threadIdx.x;
+            stage[spad(i)] = base + i < n ? in[base + i] : 0u;
+        }
+        __syncthreads();
         uint32_t loc[SCAN_ITEMS];
         uint32_t sum = 0;
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
-            const int i = i0 + j;
             loc[j] = sum;
-            sum += i < n ? in[i] : 0u;
+            sum += stage[spad((int)threadIdx.x * SCAN_ITEMS + j)];
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &tot);
 #pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            const int i = i0 + j;
-            if (i < n) out[i] = (uint32_t)running + ex + loc[j];
+        for (int j = 0; j < SCAN_ITEMS; ++j) stage[spad((int)threadIdx.x * SCAN_ITEMS + j)] = (uint32_t)running + ex + loc[j];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SCAN_ITEMS; ++r) {
+            const int i = r * SCAN_THREADS + (int)threadIdx.x;
+            if (base + i < n) out[base + i] = stage[spad(i)];
         }
+        __syncthreads();  // the next chunk reuses the stage
         running += tot;
     }
     return running;
@@ -540,30 +555,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
                                                                uint32_t cap, ZeroList zl) {
     __shared__ uint32_t red[SCAN_THREADS / 64];
     __shared__ unsigned long long red64[SCAN_THREADS / 64];
-    uint64_t running = 0, dsum = 0, fsum = 0;
-    for (int base = 0; base < nblk; base += SCAN_THREADS * SCAN_ITEMS) {
-        const int i0 = base + threadIdx.x * SCAN_ITEMS;
-        uint32_t loc[SCAN_ITEMS];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            const int i = i0 + j;
-            loc[j] = sum;
-            if (i < nblk) {
-                sum += blk_vis[i];
-                dsum += blk_sum[i];
-                fsum += blk_fb[i];
-            }
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &tot);
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            const int i = i0 + j;
-            if (i < nblk) blk_off[i] = (uint32_t)running + ex + loc[j];
-        }
-        running += tot;
+    __shared__ uint32_t stage[SCAN_STAGE];
+    uint64_t dsum = 0, fsum = 0;
+    for (int i = (int)threadIdx.x; i < nblk; i += SCAN_THREADS) {
+        dsum += blk_sum[i];
+        fsum += blk_fb[i];
     }
+    const uint64_t running = scan_counts(blk_vis, nblk, blk_off, red, stage);
     const uint64_t D = block_sum_u64(dsum, red64);
     const uint64_t fb = block_sum_u64(fsum, red64);
     if (threadIdx.x == 0) {
@@ -585,7 +583,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_dups(const uint32_t* __restrict__ blk_sum, int nblk,
                                                             uint32_t* __restrict__ blk_off) {
     __shared__ uint32_t red[SCAN_THREADS / 64];
-    scan_counts(blk_sum, nblk, blk_off, red);
+    __shared__ uint32_t stage[SCAN_STAGE];
+    scan_counts(blk_sum, nblk, blk_off, red, stage);
 }
 
 // Visible records, in record order, as (depth key, record) pairs.
@@ -629,7 +628,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __re
 // each finding its Gaussian by binary search over the LDS prefix sums.
 template <bool DEPTH>
 __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ sorted_rec,
-                                                          const uint32_t* __restrict__ touched,
+                                                          const uint32_t* __restrict__ sorted_touched,
                                                           const uint2* __restrict__ bbox,
                                                           const uint32_t* __restrict__ zkey,
                                                           const uint32_t* __restrict__ blk_off,
@@ -649,7 +648,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     uint32_t rec = 0, t = 0;
     if (i < V) {
         rec = sorted_rec[i];
-        t = touched[rec];
+        t = sorted_touched[i];  // tiles touched, gathered into depth order by the last depth pass
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<K1_THREADS>(t, red, &tot);
@@ -1420,10 +1419,10 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
     TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_touched, cnt, blk_sum2);
     TIGAS_LAUNCH(k_scan_dups, dim3(1), dim3(SCAN_THREADS), st, blk_sum2, nblk, blk_off2);
     if (depth_out)
-        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, o.bbox, o.zkey,
+        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, o.bbox, o.zkey,
                      (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
-        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, o.touched, o.bbox, o.zkey,
+        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, o.bbox, o.zkey,
                      (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
 }
 

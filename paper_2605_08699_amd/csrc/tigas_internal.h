@@ -12,7 +12,7 @@ constexpr int SORT_THREADS = 256;     // 4 wave64 per sort workgroup
 constexpr int SORT_CHUNK = 2048;      // keys ranked per workgroup step (4 waves x 8 rounds x 64)
 constexpr int SORT_MAX_BLOCKS = 1024; // workgroups per sort pass
 constexpr int SCAN_THREADS = 1024;
-constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_ITEMS = 8;
 constexpr int MAX_SORT_PASSES = 8;
 
 // Resident scene (device pointers).  Layout by storage precision:
