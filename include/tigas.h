@@ -154,6 +154,25 @@ size_t tigas_scene_bytes(const tigas_scene* scene);
 tigas_status tigas_render(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
                           int width, int height, const tigas_quality* q, tigas_frame* out, void* hip_stream);
 
+/* The same frame without waiting for it: the frame is launched on the stream
+ * (after everything already queued there) and *ticket names it.  At most two
+ * frames per stream are in flight: submitting a third first completes the
+ * oldest.  `out` must be device memory (out->is_device) that stays valid until
+ * the frame is waited for; stage and kernel timing must be off.  Frames on
+ * one stream still execute one after the other, so the host prepares and
+ * launches a frame while the previous one renders.  E_INVALID for a host
+ * output or timing on; the other errors as tigas_render. */
+tigas_status tigas_render_submit(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                                 int width, int height, const tigas_quality* q, tigas_frame* out, void* hip_stream,
+                                 int64_t* ticket);
+/* Waits for a submitted frame and collects it (once): its statistics
+ * (may be NULL) and its GPU time in milliseconds, from events recorded on
+ * the stream just before and after its launch sequence (may be NULL).  A
+ * frame whose duplicates overflowed is rendered again here (its GPU time is
+ * that of the first attempt).  E_INVALID for an unknown or collected ticket;
+ * the frame's own error otherwise. */
+tigas_status tigas_render_wait(tigas_context* ctx, int64_t ticket, tigas_stats* stats, float* gpu_ms);
+
 /* Renders n_views views, each with its own scene, pose, intrinsics, size and
  * quality q[i] (rung, SH degree, format, background; q may be NULL for
  * defaults; the tile size and batch depth of q[0] apply to all views), with one

@@ -187,6 +187,20 @@ struct Plan {
     bool allow_graph = true;  // capture/replay (off for one-off shapes such as serving batches)
 };
 
+// Per-frame host-visible state.  A workspace has two: a frame can be prepared
+// and launched while the previous one still runs on the stream, each slot's
+// launch sequence reading its own view parameters and writing its own counters.
+struct FrameSlot {
+    DevBuf views;
+    HostPinned host_views, host_counters;
+    uint32_t view_cap = 0;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // start / end of an asynchronous frame on the stream
+    bool pending = false;                    // launched asynchronously and not yet finished
+    int64_t ticket = -1;
+    Plan plan;
+    int cur = 0;
+};
+
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     uint64_t gen = 0;
@@ -263,13 +277,16 @@ struct Workspace {
     DevBuf dbg_key, dbg_val, dbg_ext;
     // per tile / per view
     DevBuf ranges;
-    DevBuf views;
     DevBuf frame_staging;
-    HostPinned host_views, host_counters;
+    static constexpr int NSLOT = 2;
+    FrameSlot slot[NSLOT];
+    int active = 0;      // slot used by the launch being prepared
+    int next_async = 0;  // slot for the next asynchronous frame
+    FrameSlot& fs() { return slot[active]; }
     DevBuf work;            // blend work counters (evaluations, contributions)
     hipEvent_t ev[7] = {};  // stage boundaries when stage timing is on
     EventTimer ktimer;      // per-launch events when kernel timing is on
-    uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0, view_cap = 0;
+    uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0;
     uint32_t last_D = 0;
     uint64_t gen = 1;  // bumped whenever a buffer is reallocated (captured graphs hold its pointers)
     std::map<std::string, GraphEntry> graphs;
@@ -330,13 +347,14 @@ struct Workspace {
         tile_cap = std::max<uint32_t>(n, 1);
     }
     void ensure_views(int n) {
-        if ((uint32_t)n <= view_cap && views.p) return;
-        grow(views, sizeof(ViewParams) * (size_t)n);
-        if (host_views.bytes < sizeof(ViewParams) * (size_t)n) {
-            host_views.ensure(sizeof(ViewParams) * (size_t)n);
+        FrameSlot& f = fs();
+        if ((uint32_t)n <= f.view_cap && f.views.p) return;
+        grow(f.views, sizeof(ViewParams) * (size_t)n);
+        if (f.host_views.bytes < sizeof(ViewParams) * (size_t)n) {
+            f.host_views.ensure(sizeof(ViewParams) * (size_t)n);
             ++gen;
         }
-        view_cap = (uint32_t)n;
+        f.view_cap = (uint32_t)n;
     }
     void ensure_events() {
         if (ev[0]) return;
@@ -349,6 +367,9 @@ struct Workspace {
         graphs.clear();
     }
     ~Workspace() {
+        for (FrameSlot& f : slot)
+            for (hipEvent_t e : {f.t0, f.t1})
+                if (e) (void)hipEventDestroy(e);
         drop_graphs();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -375,6 +396,17 @@ struct tigas_context {
     std::mutex tune_mu;
     std::map<std::string, TileCfg> tuned;  // shape -> best tile / batch depth
     std::string tune_file;
+    // asynchronous frames: ticket -> (workspace, slot) while in flight, then its outcome
+    struct AsyncDone {
+        tigas_status status = TIGAS_OK;
+        std::string error;
+        tigas_stats stats{};
+        float gpu_ms = 0.f;
+    };
+    std::mutex async_mu;
+    std::map<int64_t, std::pair<Workspace*, int>> async_pending;
+    std::map<int64_t, AsyncDone> async_done;
+    int64_t ticket_seq = 0;
 
     Workspace& workspace(hipStream_t s) {
         std::lock_guard<std::mutex> lk(mu);
@@ -382,7 +414,7 @@ struct tigas_context {
         if (!p) {
             p.reset(new Workspace());
             p->stream = s;
-            p->host_counters.ensure(sizeof(Counters), /*coherent=*/true);
+            for (FrameSlot& f : p->slot) f.host_counters.ensure(sizeof(Counters), /*coherent=*/true);
             if (p->counters.ensure(sizeof(Counters))) HIPCHK(hipMemset(p->counters.p, 0, sizeof(Counters)));
         }
         return *p;
@@ -574,9 +606,9 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
         if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
     };
     const int nv = (int)plan.views.size();
-    HIPCHK(hipMemcpyAsync(ws.views.p, ws.host_views.p, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.fs().views.p, ws.fs().host_views.p, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
     const PreOut o = ws.pre();
-    const ViewParams* vdev = ws.views.as<ViewParams>();
+    const ViewParams* vdev = ws.fs().views.as<ViewParams>();
     mark(0);
     for (const Group& g : plan.groups) {
         if (g.n_pad == 0) continue;
@@ -633,7 +665,7 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
                             : launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
                                           sort_blocks(ws.dup_cap), cd, debug, cnt, 4, nullptr, nullptr, st);
     mark(4);
-    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.host_counters.as<Counters>(), st);
+    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.fs().host_counters.as<Counters>(), st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
                  plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, opt.cull, st);
@@ -647,7 +679,7 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
 // eagerly.  Returns the sort buffer index.
 int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, bool prof,
                 unsigned long long* work) {
-    std::memcpy(ws.host_views.p, plan.views.data(), sizeof(ViewParams) * plan.views.size());
+    std::memcpy(ws.fs().host_views.p, plan.views.data(), sizeof(ViewParams) * plan.views.size());
     if (prof) ws.ensure_events();
     const int pblocks =
         plan.persistent ? ctx->cus * blend_persistent_occupancy(plan.tc.tw, plan.tc.th, plan.tc.bd, plan.tc.ppl) : 0;
@@ -663,7 +695,8 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         return enqueue(ws, plan, debug, prof, work, pblocks, opt);
     }
     if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks, opt);
-    const std::string key = shape_key(plan, true) + (opt.onepass ? "s1" : "s3") + (opt.cull ? "c1" : "c0");
+    const std::string key = shape_key(plan, true) + (opt.onepass ? "s1" : "s3") + (opt.cull ? "c1" : "c0") +
+                            (ws.active ? "f1" : "f0");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
         if (g.exec) HIPCHK(hipGraphExecDestroy(g.exec));
@@ -707,17 +740,15 @@ void wait_stream(hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
 }
 
-// Runs the plan to completion (synchronous).  A first attempt whose
-// duplicates overflowed the buffers emitted nothing; it is detected here and
-// the frame is rendered again with buffers sized from the true count.
-int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, unsigned long long* work = nullptr) {
-    prepare(ws, plan, debug);
-    const bool prof = ctx->profile.load();
-    int cur = launch_plan(ctx, ws, plan, debug, prof, work);
-    wait_stream(ws.stream);
+// After a launch of `plan` from the active slot has completed: a frame whose
+// single-pass sort gave up, or whose duplicates overflowed the buffers (it
+// then emitted nothing), is rendered again (synchronously); returns the
+// counters of the final attempt.
+Counters settle_frame(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, bool prof,
+                      unsigned long long* work, int& cur, int& rerenders) {
     Counters c;
-    std::memcpy(&c, ws.host_counters.p, sizeof(c));
-    int rerenders = 0;
+    std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
+    rerenders = 0;
     if (c.error) {
         // a bounded wait of the single-pass sort gave up: the lists may be
         // wrong.  Redo the frame with the three-kernel passes, which have no
@@ -726,7 +757,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
         cur = launch_plan(ctx, ws, plan, debug, prof, work);
         wait_stream(ws.stream);
-        std::memcpy(&c, ws.host_counters.p, sizeof(c));
+        std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
         rerenders = 1;
         ctx->sort_fallbacks.fetch_add(1);
     }
@@ -738,11 +769,34 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
         cur = launch_plan(ctx, ws, plan, debug, prof, work);
         wait_stream(ws.stream);
-        std::memcpy(&c, ws.host_counters.p, sizeof(c));
+        std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
         if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
         rerenders += 1;
     }
     ws.last_D = c.D;
+    return c;
+}
+
+tigas_stats frame_stats(const Plan& plan, const Counters& c, int rerenders) {
+    tigas_stats st{};
+    st.visible = c.visible;
+    st.duplicates = c.D;
+    st.fallbacks = c.fallbacks;
+    st.tiles = plan.n_tiles;
+    st.sort_passes = 4 + (int64_t)tile_passes(plan.n_tiles).size();
+    st.rerenders = rerenders;
+    st.tile_w = plan.tc.tw;
+    st.tile_h = plan.tc.th;
+    st.batch_depth = plan.tc.bd;
+    st.pixels_per_lane = plan.tc.ppl;
+    int64_t n = 0;
+    for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
+    st.n = n;
+    return st;
+}
+
+// Stage and kernel timings of the finished launch, and the context's stats.
+void record_stats(tigas_context* ctx, Workspace& ws, const tigas_stats& st, bool prof) {
     std::lock_guard<std::mutex> lk(ctx->stats_mu);
     if (prof) {
         for (int i = 0; i < 6; ++i) {
@@ -762,19 +816,68 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
         }
         ws.ktimer.reset();
     }
-    ctx->last.visible = c.visible;
-    ctx->last.duplicates = c.D;
-    ctx->last.fallbacks = c.fallbacks;
-    ctx->last.tiles = plan.n_tiles;
-    ctx->last.sort_passes = 4 + (int64_t)tile_passes(plan.n_tiles).size();
-    ctx->last.rerenders = rerenders;
-    ctx->last.tile_w = plan.tc.tw;
-    ctx->last.tile_h = plan.tc.th;
-    ctx->last.batch_depth = plan.tc.bd;
-    ctx->last.pixels_per_lane = plan.tc.ppl;
-    int64_t n = 0;
-    for (const Group& g : plan.groups) n += g.scene->view.n * g.nviews;
-    ctx->last.n = n;
+    ctx->last = st;
+}
+
+// Waits for an event: polls for up to ~2 ms, then blocks.
+void wait_event(hipEvent_t ev) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) HIPCHK(e);
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) break;
+    }
+    HIPCHK(hipEventSynchronize(ev));
+}
+
+// Completes the asynchronous frame of slot si (caller holds ws.mu): waits for
+// it, redoes it if it overflowed, records its outcome under its ticket.
+void finish_async(tigas_context* ctx, Workspace& ws, int si) {
+    FrameSlot& f = ws.slot[si];
+    if (!f.pending) return;
+    f.pending = false;
+    tigas_context::AsyncDone d;
+    try {
+        wait_event(f.t1);
+        HIPCHK(hipEventElapsedTime(&d.gpu_ms, f.t0, f.t1));
+        ws.active = si;
+        int cur = f.cur, rerenders = 0;
+        const Counters c = settle_frame(ctx, ws, f.plan, false, false, nullptr, cur, rerenders);
+        d.stats = frame_stats(f.plan, c, rerenders);
+        record_stats(ctx, ws, d.stats, false);
+    } catch (const Error& e) {
+        d.status = e.st;
+        d.error = e.what();
+    } catch (const std::exception& e) {
+        d.status = TIGAS_E_DEVICE;
+        d.error = e.what();
+    }
+    std::lock_guard<std::mutex> lk(ctx->async_mu);
+    ctx->async_pending.erase(f.ticket);
+    ctx->async_done[f.ticket] = d;
+}
+
+// Completes every asynchronous frame of the workspace, oldest first.
+void finish_all_async(tigas_context* ctx, Workspace& ws) {
+    int order[Workspace::NSLOT];
+    for (int i = 0; i < Workspace::NSLOT; ++i) order[i] = i;
+    std::sort(order, order + Workspace::NSLOT, [&](int a, int b) { return ws.slot[a].ticket < ws.slot[b].ticket; });
+    for (int i : order) finish_async(ctx, ws, i);
+}
+
+// Runs the plan to completion (synchronous) from slot 0, after any
+// asynchronous frames of the workspace.
+int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, unsigned long long* work = nullptr) {
+    finish_all_async(ctx, ws);
+    ws.active = 0;
+    prepare(ws, plan, debug);
+    const bool prof = ctx->profile.load();
+    int cur = launch_plan(ctx, ws, plan, debug, prof, work);
+    wait_stream(ws.stream);
+    int rerenders = 0;
+    const Counters c = settle_frame(ctx, ws, plan, debug, prof, work, cur, rerenders);
+    record_stats(ctx, ws, frame_stats(plan, c, rerenders), prof);
     return cur;
 }
 
@@ -926,9 +1029,84 @@ void render_one(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsi
     render_views(ctx, ws, plan, q, out, dbg, work_out);
 }
 
+// Launches one frame without waiting for it (see tigas_render_submit).
+void render_submit(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width, int height,
+                   const tigas_quality* q, tigas_frame* out, void* hip_stream, int64_t* ticket) {
+    if (!scene || !out || !ticket) fail(TIGAS_E_INVALID, "scene, frame and ticket are required");
+    if (!out->is_device) fail(TIGAS_E_INVALID, "an asynchronous frame needs a device output buffer");
+    tigas_context* ctx = scene->ctx;
+    if (ctx->profile.load() || ctx->profile_kernels.load())
+        fail(TIGAS_E_INVALID, "stage and kernel timing need synchronous frames");
+    HIPCHK(hipSetDevice(ctx->device));
+    Plan plan;
+    plan.views.push_back(make_view(scene, pose, intr, width, height, q));
+    const uint32_t n_pad = round_up((uint64_t)scene->view.n, K1_THREADS);
+    plan.groups.push_back({scene, 0, 1, 0, n_pad});
+    plan.nrec = n_pad;
+    Workspace& ws = ctx->workspace(pick_stream(ctx, hip_stream));
+    std::lock_guard<std::mutex> lk(ws.mu);
+    std::vector<size_t> stage_off;
+    bind_outputs(ws, plan, out, stage_off);
+    TileCfg tc = tile_cfg(q);
+    if (!tile_requested(q)) {
+        const TileCfg req = tc;
+        tc = autotune(ctx, ws, plan);  // renders synchronously (after earlier frames) the first time only
+        if (q && q->batch_depth != 0) tc.bd = req.bd;
+        if (q && q->pixels_per_lane != 0 && tc.th >= 16) tc.ppl = req.ppl;
+    }
+    set_tiles(plan, tc);
+    const int si = ws.next_async;
+    FrameSlot& f = ws.slot[si];
+    if (f.pending) finish_async(ctx, ws, si);  // two frames in flight at most
+    ws.next_async = (si + 1) % Workspace::NSLOT;
+    ws.active = si;
+    prepare(ws, plan, false);
+    if (!f.t0) HIPCHK(hipEventCreate(&f.t0));
+    if (!f.t1) HIPCHK(hipEventCreate(&f.t1));
+    HIPCHK(hipEventRecord(f.t0, ws.stream));
+    f.cur = launch_plan(ctx, ws, plan, false, false, nullptr);
+    HIPCHK(hipEventRecord(f.t1, ws.stream));
+    f.plan = plan;
+    f.pending = true;
+    std::lock_guard<std::mutex> lk2(ctx->async_mu);
+    f.ticket = ++ctx->ticket_seq;
+    ctx->async_pending[f.ticket] = {&ws, si};
+    *ticket = f.ticket;
+}
+
+void render_wait(tigas_context* ctx, int64_t ticket, tigas_stats* stats, float* gpu_ms) {
+    Workspace* ws = nullptr;
+    int si = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->async_mu);
+        auto it = ctx->async_pending.find(ticket);
+        if (it != ctx->async_pending.end()) {
+            ws = it->second.first;
+            si = it->second.second;
+        } else if (!ctx->async_done.count(ticket)) {
+            fail(TIGAS_E_INVALID, "unknown or already collected ticket");
+        }
+    }
+    if (ws) {
+        std::lock_guard<std::mutex> lk(ws->mu);
+        if (ws->slot[si].pending && ws->slot[si].ticket == ticket) finish_async(ctx, *ws, si);
+    }
+    tigas_context::AsyncDone d;
+    {
+        std::lock_guard<std::mutex> lk(ctx->async_mu);
+        auto it = ctx->async_done.find(ticket);
+        if (it == ctx->async_done.end()) fail(TIGAS_E_INVALID, "unknown or already collected ticket");
+        d = it->second;
+        ctx->async_done.erase(it);
+    }
+    if (d.status != TIGAS_OK) fail(d.status, d.error);
+    if (stats) *stats = d.stats;
+    if (gpu_ms) *gpu_ms = d.gpu_ms;
+}
+
 void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_pad, tigas_debug_out* dbg) {
     Counters c;
-    std::memcpy(&c, ws.host_counters.p, sizeof(c));
+    std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
     dbg->n_dup = c.D;
     dbg->n_tiles = plan.n_tiles;
     hipStream_t st = ws.stream;
@@ -1464,6 +1642,19 @@ tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out) {
         out->ranges = ctx->stage_ms[4];
         out->blend = ctx->stage_ms[5];
         out->frames = ctx->stage_frames;
+    });
+}
+
+tigas_status tigas_render_submit(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width,
+                                 int height, const tigas_quality* q, tigas_frame* out, void* hip_stream,
+                                 int64_t* ticket) {
+    return guard([&] { render_submit(scene, pose, intr, width, height, q, out, hip_stream, ticket); });
+}
+
+tigas_status tigas_render_wait(tigas_context* ctx, int64_t ticket, tigas_stats* stats, float* gpu_ms) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        render_wait(ctx, ticket, stats, gpu_ms);
     });
 }
 

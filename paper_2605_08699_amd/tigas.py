@@ -82,7 +82,7 @@ EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", 
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
            "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks",
-           "tigas_profile_kernels", "tigas_kernel_times")
+           "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait")
 
 _lib = None
 
@@ -121,6 +121,9 @@ def lib():
         L.tigas_sort_fallbacks.restype = I64
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
         L.tigas_profile_kernels.argtypes = [P, I]
+        L.tigas_render_submit.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
+                                          ctypes.POINTER(QualityC), ctypes.POINTER(FrameC), P, ctypes.POINTER(I64)]
+        L.tigas_render_wait.argtypes = [P, I64, ctypes.POINTER(StatsC), ctypes.POINTER(ctypes.c_float)]
         L.tigas_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimeC), I, ctypes.POINTER(I)]
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
@@ -128,7 +131,8 @@ def lib():
         for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
                      "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort",
-                     "tigas_profile_kernels", "tigas_kernel_times"):
+                     "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit",
+                     "tigas_render_wait"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -293,6 +297,29 @@ class Context:
         _check(lib().tigas_render(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
                                   int(width), int(height), ctypes.byref(q), ctypes.byref(fr), st))
         return out
+
+    def render_async(self, scene: Scene, pose, intr, width, height, out, res_scale=1.0, fmt="rgb8", bg=(0, 0, 0),
+                     tile=None, batch_depth=None, sh_degree=-1, stream=None, ppl=None) -> int:
+        """Launch one frame into the GPU tensor ``out`` and return its ticket
+        without waiting; collect it with wait().  Two frames per stream may be
+        in flight."""
+        q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth, ppl)
+        fr = FrameC(ctypes.c_void_p(int(out.data_ptr())), out.numel() * out.element_size(), 1, 0, 0)
+        st = ctypes.c_void_p(stream) if stream else None
+        t = ctypes.c_int64(0)
+        _check(lib().tigas_render_submit(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
+                                         int(width), int(height), ctypes.byref(q), ctypes.byref(fr), st,
+                                         ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int) -> dict:
+        """Wait for a submitted frame; its stats plus ``gpu_ms``."""
+        st = StatsC()
+        ms = ctypes.c_float(0.0)
+        _check(lib().tigas_render_wait(self.handle, int(ticket), ctypes.byref(st), ctypes.byref(ms)))
+        d = {f: int(getattr(st, f)) for f, _ in StatsC._fields_}
+        d["gpu_ms"] = float(ms.value)
+        return d
 
     def render_debug(self, scene: Scene, pose, intr, width, height, res_scale=1.0, fmt="f32", bg=(0, 0, 0),
                      tile=(16, 16), batch_depth=64, sh_degree=-1, cap_dup=None):
