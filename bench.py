@@ -36,12 +36,12 @@ def _stats(ts):
     return float(np.median(a)), float(np.percentile(a, 99))
 
 
-def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch, count_work):
+def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch, count_work, tile_kw):
     s = ctx.load_scene(scene, storage)
     out = torch.empty((H, W, 3), dtype=torch.uint8, device="cuda")
     # warm-up: the first frame of this shape runs the autotuner and captures the graph
     for i in range(warmup):
-        ctx.render(s, traj[i % len(traj)], k, W, H, out=out)
+        ctx.render(s, traj[i % len(traj)], k, W, H, out=out, **tile_kw)
     torch.cuda.synchronize()
 
     def timed(label):
@@ -50,7 +50,7 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
         t0 = time.perf_counter()
         for i in range(steps):
             t = time.perf_counter()
-            ctx.render(s, traj[i % len(traj)], k, W, H, out=out)
+            ctx.render(s, traj[i % len(traj)], k, W, H, out=out, **tile_kw)
             lat.append(time.perf_counter() - t)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
@@ -60,6 +60,22 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
     # headline: the product path (graph replay per frame), no instrumentation
     head = timed("graph")
     cfg = ctx.stats()
+    # the same frames submitted asynchronously (the next frame is launched
+    # while the previous one renders; frames still run one after the other)
+    outs = [out, torch.empty_like(out)]
+    res, prev = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        t = ctx.render_async(s, traj[i % len(traj)], k, W, H, outs[i % 2], **tile_kw)
+        if prev is not None:
+            res.append(ctx.wait(prev))
+        prev = t
+    res.append(ctx.wait(prev))
+    total = time.perf_counter() - t0
+    g = np.array([r["gpu_ms"] for r in res])
+    pipelined = dict(frames_per_s=steps / total, gpu_ms_p50=float(np.median(g)), gpu_ms_p99=float(np.percentile(g, 99)),
+                     gpu_ms_mean=float(g.mean()))
     # the same frames again with HIP events between the stages (uncaptured launches)
     ctx.profile_stages(True)
     prof = timed("stages")
@@ -87,7 +103,7 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
             work["contributions"] += c
             for f in ("visible", "duplicates", "fallbacks"):
                 work[f] += st[f]
-    res = dict(head, tile=f"{cfg['tile_w']}x{cfg['tile_h']}", batch_depth=cfg["batch_depth"],
+    res = dict(head, pipelined=pipelined, tile=f"{cfg['tile_w']}x{cfg['tile_h']}", batch_depth=cfg["batch_depth"],
                sort_passes=cfg["sort_passes"],
                pixels_per_lane=cfg["pixels_per_lane"],
                stage_pass=prof, gpu_ms_per_frame=sum(v for kk, v in stages.items() if kk != "frames") / nfr,
@@ -227,6 +243,19 @@ def kernel_work(name, w, n, storage, tile_passes):
     return None
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3M_1080p_f32.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile, or
+    None when it was measured on other kernel source (or not at all)."""
+    from paper_2605_08699_amd import profiling
+    sha, t = profiling.read_traffic(TRAFFIC_FILE)
+    if sha != profiling.source_sha1():
+        return None
+    return t.get(kernel)
+
+
 def roofline(v, n, storage):
     """Roofline of the dominant kernel of the FP32 run: algorithmic work per
     launch / average launch duration (HIP events around every launch)."""
@@ -240,14 +269,15 @@ def roofline(v, n, storage):
         bound, amount = m
         amount /= max(k["launches_per_frame"], 1e-9)
         sec = k["avg_us"] * 1e-6
+        traffic = measured_traffic(name)
         if bound == "alu":
             ach = amount / sec / 1e12
             return dict(kernel=name, bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                        frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=None, avg_us=k["avg_us"],
+                        frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=traffic, avg_us=k["avg_us"],
                         per_launch=amount, dominant=ranked[0][0])
         ach = amount / sec / 1e9
         return dict(kernel=name, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                    traffic=None, avg_us=k["avg_us"], per_launch=amount, dominant=ranked[0][0])
+                    traffic=traffic, avg_us=k["avg_us"], per_launch=amount, dominant=ranked[0][0])
     return None
 
 
@@ -273,7 +303,7 @@ def hbm_copy(torch, mib=1024, reps=20):
     return dict(bytes_read=n * 4, bytes_written=n * 4, us=sec * 1e6, gbps=moved / sec / 1e9)
 
 
-def cpu_baseline(scene, pose, k, W, H, n_pix=2048):
+def cpu_baseline(scene, pose, k, W, H, n_pix=100_000):
     """The FP64 oracle, untuned, on a bounded sample of one frame."""
     from oracle import oracle as orc
     rng = np.random.default_rng(0)
@@ -302,6 +332,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--tile", default=None,
+                    help="W,H,batch_depth,pixels_per_lane for the single-view variants (default: autotuned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py renders on one GPU only: the rasterizer has no multi-GPU path in this build "
@@ -320,8 +352,12 @@ def main():
     print(f"# HBM copy: {copy['gbps']:.0f} GB/s", file=sys.stderr, flush=True)
     variants = {}
     for storage in args.variants.split(","):
+        tile_kw = {}
+        if args.tile:
+            tw, th, bd, ppl = (int(x) for x in args.tile.split(","))
+            tile_kw = dict(tile=(tw, th), batch_depth=bd, ppl=ppl)
         variants[storage] = run_variant(ctx, tigas, scene, storage, traj, k, W, H, args.steps, args.warmup, torch,
-                                        count_work=(storage == "f32"))
+                                        count_work=(storage == "f32"), tile_kw=tile_kw)
         print(f"# {storage}: {variants[storage]['frames_per_s']:.1f} frames/s, p50 "
               f"{variants[storage]['p50_ms']:.3f} ms, p99 {variants[storage]['p99_ms']:.3f} ms", file=sys.stderr,
               flush=True)
@@ -352,8 +388,9 @@ def main():
         "work_per_frame": {x: main_v["work"][x] / max(main_v["work"]["frames"], 1)
                            for x in ("visible", "duplicates", "evaluations", "contributions", "fallbacks")},
         "stage_pass": main_v["stage_pass"],
+        "pipelined": main_v["pipelined"],
         "variants": {kk: {x: vv[x] for x in ("frames_per_s", "p50_ms", "p99_ms", "gpu_ms_per_frame", "stage_ms",
-                                              "scene_bytes", "tile", "batch_depth", "pixels_per_lane")}
+                                              "scene_bytes", "tile", "batch_depth", "pixels_per_lane", "pipelined")}
                      for kk, vv in variants.items()},
         "roofline": {x: rl[x] for x in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": {x: rl[x] for x in ("kernel", "avg_us", "per_launch", "dominant")},
