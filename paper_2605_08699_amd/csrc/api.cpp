@@ -265,7 +265,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     std::mutex mu;  // one launch sequence at a time per workspace
     // per record
-    DevBuf rec0, rec1, rec2, bbox, zkey, touched;
+    DevBuf recs, zkey, touched;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf fb_list;  // near-singular Gaussians for the FP64 conic kernel
     DevBuf counters;
@@ -293,10 +293,7 @@ struct Workspace {
 
     PreOut pre() const {
         PreOut o;
-        o.rec0 = rec0.as<float4>();
-        o.rec1 = rec1.as<float4>();
-        o.rec2 = rec2.as<float4>();
-        o.bbox = bbox.as<uint2>();
+        o.rec = recs.as<Rec>();
         o.zkey = zkey.as<uint32_t>();
         o.touched = touched.as<uint32_t>();
         o.blk_sum = blk_sum.as<uint32_t>();
@@ -312,10 +309,9 @@ struct Workspace {
         if (b.ensure(bytes)) ++gen;
     }
     void ensure_records(uint32_t nrec) {
-        if (nrec <= rec_cap && rec0.p) return;
+        if (nrec <= rec_cap && recs.p) return;
         const size_t r = std::max<uint32_t>(nrec, 256);
-        for (DevBuf* b : {&rec0, &rec1, &rec2}) grow(*b, r * 16);
-        grow(bbox, r * 8);
+        grow(recs, r * sizeof(Rec));
         grow(zkey, r * 4);
         grow(touched, r * 4);
         const size_t nb = r / K1_THREADS + 1;
@@ -423,6 +419,7 @@ struct tigas_context {
 
 struct tigas_scene {
     tigas_context* ctx = nullptr;
+    uint64_t uid = 0;  // unique over the process: a captured graph holds this scene's device pointers
     SceneView view{};
     DevBuf mean, attr, sh;
     size_t bytes = 0;
@@ -545,12 +542,17 @@ void set_tiles(Plan& plan, const TileCfg& tc) {
 
 // Everything about a plan that a captured graph depends on, except the view
 // parameters themselves (copied from pinned memory by the graph each replay).
+// Key of a plan's shape.  with_tiles (a captured graph's key): also the
+// tile configuration and the identity of each scene, whose device pointers
+// the graph holds (a scene loaded after another was freed may reuse its host
+// address, never its uid).  Without: only sizes (the autotuner's key).
 std::string shape_key(const Plan& plan, bool with_tiles) {
     std::string k;
     char buf[160];
     for (const Group& g : plan.groups) {
-        std::snprintf(buf, sizeof buf, "g%p:%lld:%d:%d:%d:%u:%u;", (void*)g.scene, (long long)g.scene->view.n,
-                      g.scene->view.storage, g.first_view, g.nviews, g.rec_base, g.n_pad);
+        std::snprintf(buf, sizeof buf, "g%llu:%lld:%d:%d:%d:%d:%u:%u;",
+                      with_tiles ? (unsigned long long)g.scene->uid : 0ull, (long long)g.scene->view.n,
+                      g.scene->view.storage, g.scene->view.sh_degree, g.first_view, g.nviews, g.rec_base, g.n_pad);
         k += buf;
     }
     for (const ViewParams& v : plan.views) {
@@ -1111,14 +1113,12 @@ void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_
     dbg->n_tiles = plan.n_tiles;
     hipStream_t st = ws.stream;
     if (dbg->rec) {
-        std::vector<float4> a(n_pad), b(n_pad), cc(n_pad);
-        HIPCHK(hipMemcpyAsync(a.data(), ws.rec0.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(b.data(), ws.rec1.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(cc.data(), ws.rec2.p, 16 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        std::vector<Rec> a(n_pad);
+        HIPCHK(hipMemcpyAsync(a.data(), ws.recs.p, sizeof(Rec) * (size_t)n_pad, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         for (int64_t i = 0; i < n; ++i) {
             float* r = dbg->rec + 12 * i;
-            const float4 x = a[i], y = b[i], z = cc[i];
+            const float4 x = a[i].r0, y = a[i].r1, z = a[i].r2;
             r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
             r[4] = y.x; r[5] = y.y; r[6] = y.z; r[7] = y.w;
             r[8] = z.x; r[9] = z.y; r[10] = z.z; r[11] = z.w;
@@ -1130,9 +1130,11 @@ void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_
     if (dbg->touched && n) std::memcpy(dbg->touched, touched.data(), 4 * (size_t)n);
     if (dbg->zkey && n) HIPCHK(hipMemcpyAsync(dbg->zkey, ws.zkey.p, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
     if (dbg->bbox) {
-        std::vector<uint2> bb(n_pad);
-        if (n_pad) HIPCHK(hipMemcpyAsync(bb.data(), ws.bbox.p, 8 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+        std::vector<Rec> rr(n_pad);
+        if (n_pad) HIPCHK(hipMemcpyAsync(rr.data(), ws.recs.p, sizeof(Rec) * (size_t)n_pad, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        std::vector<uint2> bb(n_pad);
+        for (uint32_t i = 0; i < n_pad; ++i) bb[i] = rr[i].bbox;
         for (int64_t i = 0; i < n; ++i) {
             int32_t* r = dbg->bbox + 4 * i;
             if (touched[i]) {
@@ -1226,6 +1228,10 @@ double request_pixels(const tigas_request& r) {
     return std::floor(r.width * s + 0.5) * std::floor(r.height * s + 0.5);
 }
 
+// Workspace bytes per record: the 64-byte record, depth key, tiles touched,
+// FP64-list entry.
+constexpr size_t kBytesPerRecord = sizeof(Rec) + 4 + 4 + 8;
+
 size_t request_need(const tigas_server* sv, const tigas_request& r) {
     const double rec = (double)request_records(r);
     const double dup = std::max(4.0, sv->dup_per_rec) * 1.25 * rec;
@@ -1235,7 +1241,7 @@ size_t request_need(const tigas_server* sv, const tigas_request& r) {
         frame = (size_t)((double)r.width * s + 1) * (size_t)((double)r.height * s + 1) * 3 *
                 (r.q.fmt == TIGAS_OUT_RGBF32 ? 4 : 1);
     }
-    return (size_t)(rec * 72.0 + dup * 24.0) + frame;
+    return (size_t)(rec * (double)kBytesPerRecord + dup * 24.0) + frame;
 }
 
 void server_render(tigas_server* sv, tigas_server::Slot& slot) {
@@ -1476,6 +1482,8 @@ tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tig
         fetch(op, d->opacity_logits, (size_t)n);
         fetch(sh, d->sh, (size_t)n * 48);
         std::unique_ptr<tigas_scene> s(new tigas_scene());
+        static std::atomic<uint64_t> next_uid{0};
+        s->uid = ++next_uid;
         s->ctx = ctx;
         const int deg = d->sh_degree;
         const int ncoef = 3 * (deg + 1) * (deg + 1);
@@ -1734,7 +1742,7 @@ tigas_status tigas_server_create(tigas_context* ctx, const tigas_server_config* 
             // reserve each slot's workspace for its whole share up front, so
             // serving never reallocates (a reallocation waits for the device)
             const size_t share = sv->cfg.hbm_budget / sv->slots.size();
-            const uint64_t recs = share / (72 + 5 * 24 + 1);
+            const uint64_t recs = share / (kBytesPerRecord + 5 * 24 + 1);
             for (auto& sl : sv->slots) {
                 Workspace& ws = ctx->workspace(sl->stream);
                 std::lock_guard<std::mutex> lk(ws.mu);

@@ -421,10 +421,13 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
         o.zkey[rec] = __float_as_uint(z32);
         o.touched[rec] = touched;
         if (touched) {
-            o.rec0[rec] = r0;
-            o.rec1[rec] = r1;
-            o.rec2[rec] = r2;
-            o.bbox[rec] = bb;
+            Rec out;
+            out.r0 = r0;
+            out.r1 = r1;
+            out.r2 = r2;
+            out.bbox = bb;
+            out.pad = make_uint2(0u, 0u);
+            o.rec[rec] = out;
         }
         // per-block counts: wave sums, then one barrier (LDS slots alternate
         // between views so the next view cannot overwrite unread sums)
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
 // coefficients of the record are overwritten (log2 opacity kept).
 __global__ __launch_bounds__(256) void k_conic_fp64(const uint2* __restrict__ list, Counters* cnt, uint32_t cap,
                                                     const ViewParams* __restrict__ views,
-                                                    const uint32_t* __restrict__ blk_view, float4* __restrict__ rec1) {
+                                                    const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
     const uint32_t n = min(cnt->fb_list, cap);
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const uint2 e = list[i];
@@ -483,11 +486,11 @@ __global__ __launch_bounds__(256) void k_conic_fp64(const uint2* __restrict__ li
         double abc[3];
         cov2d_fp64(q, ls, mx, my, mz, v, abc);
         const double d64 = abc[0] * abc[2] - abc[1] * abc[1];
-        float4 r = rec1[rec];
+        float4 r = recs[rec].r1;
         r.x = -0.5f * LOG2E * (float)(abc[2] / d64);
         r.y = -LOG2E * (float)(-abc[1] / d64);
         r.z = -0.5f * LOG2E * (float)(abc[0] / d64);
-        rec1[rec] = r;
+        recs[rec].r1 = r;
     }
 }
 
@@ -629,7 +632,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __re
 template <bool DEPTH>
 __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ sorted_rec,
                                                           const uint32_t* __restrict__ sorted_touched,
-                                                          const uint2* __restrict__ bbox,
+                                                          const Rec* __restrict__ recs,
                                                           const uint32_t* __restrict__ zkey,
                                                           const uint32_t* __restrict__ blk_off,
                                                           const uint32_t* __restrict__ blk_view,
@@ -658,7 +661,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     srec[threadIdx.x] = rec;
     if (t) {
         const ViewParams& v = views[blk_view[rec / K1_THREADS]];
-        const uint2 b = bbox[rec];
+        const uint2 b = recs[rec].bbox;
         const int tx0 = (int)(b.x & 0xffffu) / v.tile_w, ty0 = (int)(b.x >> 16) / v.tile_h;
         const int tx1 = (int)(b.y & 0xffffu) / v.tile_w;
         sx0[threadIdx.x] = (uint32_t)tx0;
@@ -1098,10 +1101,7 @@ struct BlendArgs {
     uint32_t n_tiles;
     const uint2* ranges;
     const uint32_t* vals;
-    const float4* rec0;
-    const float4* rec1;
-    const float4* rec2;
-    const uint2* bbox;
+    const Rec* rec;
     uint32_t nrec;
     unsigned long long* work;
     int cull;  // drop entries below the skip threshold on the whole block (never changes a pixel)
@@ -1112,7 +1112,7 @@ struct BlendArgs {
 // exponent coefficients and the colour.
 template <int BD>
 struct Stage {
-    float4 a[64 * BD];  // u_rel, v_rel0, A, B
+    float4 a[64 * BD];  // u_rel, A, v_rel0, B
     float4 b[64 * BD];  // C, L, r, g
     float2 c[64 * BD];  // b, v_rel1
 };
@@ -1163,7 +1163,7 @@ __device__ __forceinline__ bool below_threshold(float A, float B, float C, float
 // leaves as soon as all of its pixels have terminated; there is no barrier
 // between the waves of a tile.
 template <int TW, int TH, int BD, int PPL, bool COUNT>
-__device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, Stage<BD>* stage) {
+__device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, int w, Stage<BD>& S) {
     constexpr int BX = TW / 8;
     constexpr int BATCH = 64 * BD;
     int vi = 0;
@@ -1178,8 +1178,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
     const ViewParams& v = A.views[vi];
     const uint32_t lt = tile - v.tile_base;
     const int tx = (int)(lt % (uint32_t)v.tiles_x), ty = (int)(lt / (uint32_t)v.tiles_x);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Stage<BD>& S = stage[w];
+    const int lane = threadIdx.x & 63;
     const int sx = tx * TW + (w % BX) * 8, sy = ty * TH + (w / BX) * 8 * PPL;
     const int px = sx + (lane & 7);
     const float pxr = (float)(lane & 7) + 0.5f, pyr = (float)(lane >> 3) + 0.5f;
@@ -1214,7 +1213,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
             uint32_t r = 0;
             if (i < rg.y) r = A.vals[i];
             if (i < rg.y && r < A.nrec) {
-                const uint2 b = A.bbox[r];
+                const uint2 b = A.rec[r].bbox;
                 const int x0 = (int)(b.x & 0xffffu), y0 = (int)(b.x >> 16);
                 const int x1 = (int)(b.y & 0xffffu), y1 = (int)(b.y >> 16);
                 hit = !(x1 < sx || x0 > bx1 || y1 < sy || y0 > by1);
@@ -1222,9 +1221,9 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
             float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b1 = a, c2 = a;
             float u = 0.f, v0 = 0.f;
             if (hit) {
-                a = A.rec0[r];
-                b1 = A.rec1[r];
-                c2 = A.rec2[r];
+                a = A.rec[r].r0;
+                b1 = A.rec[r].r1;
+                c2 = A.rec[r].r2;
                 // pixel centre relative to each 8x8 sub-block origin, hi and lo parts combined here
                 u = (a.x - fsx) + a.z;
                 v0 = (a.y - fsy[0]) + a.w;
@@ -1234,7 +1233,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
             const uint64_t m = ballot(hit);
             if (hit) {
                 const uint32_t slot = cnt + bits_below(m);
-                S.a[slot] = make_float4(u, v0, b1.x, b1.y);
+                S.a[slot] = make_float4(u, b1.x, v0, b1.y);
                 S.b[slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
                 S.c[slot] = make_float2(c2.z, PPL > 1 ? (a.y - fsy[PPL - 1]) + a.w : 0.0f);
             }
@@ -1243,7 +1242,56 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (alive) {
+        if (PPL == 1) {
+            // Eight entries at a time.  Lane l forms, for entry j0 + l/8 and
+            // pixel row l mod 8, the row terms B dy and C dy^2 + L (the very
+            // products and sums of the per-pixel exponent, so every pixel's
+            // arithmetic is unchanged); the lanes of a row then fetch theirs
+            // with a cross-lane permute, which leaves dx and two FMAs per
+            // (pixel, Gaussian) pair.  The permutes run on every lane.
+            const float yrow = (float)(lane & 7) + 0.5f;
+            for (uint32_t j0 = 0; j0 < cnt; j0 += 8) {
+                if (ballot(!done[0]) == 0) break;
+                const uint32_t jg = min(j0 + (uint32_t)(lane >> 3), cnt - 1);
+                const float4 ga = S.a[jg];
+                const float4 gb = S.b[jg];
+                const float dyg = yrow - ga.z;
+                const float pg = ga.w * dyg;
+                const float qg = __builtin_fmaf(gb.x * dyg, dyg, gb.y);
+                const uint32_t nk = min(8u, cnt - j0);
+#pragma unroll
+                for (uint32_t k = 0; k < 8; ++k) {
+                    if (k >= nk) break;
+                    const int src = (int)(k * 8) + (lane >> 3);
+                    const float P = __shfl(pg, src, 64);
+                    const float Q = __shfl(qg, src, 64);
+                    // straight-line update (no branches per pair): a pixel
+                    // that is done, or an alpha below the threshold, or a
+                    // stop, leaves the colour and T exactly as they are
+                    const float2 ua = *reinterpret_cast<const float2*>(&S.a[j0 + k]);
+                    const float4 b = S.b[j0 + k];
+                    const float cz = S.c[j0 + k].x;
+                    const float dx = pxr - ua.x;
+                    const float e = __builtin_fmaf(__builtin_fmaf(ua.y, dx, P), dx, Q);
+                    const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
+                    const float t0 = T[0];
+                    const float tn = t0 * (1.0f - alpha);
+                    const bool use = alpha >= ALPHA_MIN;
+                    const bool stop = use && tn < T_MIN;
+                    const bool acc = use && !stop && !done[0];
+                    if (COUNT) {
+                        n_eval += done[0] ? 0u : 1u;
+                        n_contrib += acc ? 1u : 0u;
+                    }
+                    const float wgt = alpha * t0;
+                    cr[0] = acc ? __builtin_fmaf(wgt, b.z, cr[0]) : cr[0];
+                    cg[0] = acc ? __builtin_fmaf(wgt, b.w, cg[0]) : cg[0];
+                    cb[0] = acc ? __builtin_fmaf(wgt, cz, cb[0]) : cb[0];
+                    T[0] = acc ? tn : t0;
+                    done[0] = done[0] || stop;
+                }
+            }
+        } else if (alive) {
             for (uint32_t j = 0; j < cnt; ++j) {
                 const float4 a = S.a[j];
                 const float4 b = S.b[j];
@@ -1252,9 +1300,9 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, St
                 bool all_done = true;
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    const float vrel = p == 0 ? a.y : c.y;
+                    const float vrel = p == 0 ? a.z : c.y;
                     const float dy = pyr - vrel;
-                    const float e = __builtin_fmaf(__builtin_fmaf(a.z, dx, a.w * dy), dx,
+                    const float e = __builtin_fmaf(__builtin_fmaf(a.y, dx, a.w * dy), dx,
                                                    __builtin_fmaf(b.x * dy, dy, b.y));
                     const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
                     if (!done[p]) {
@@ -1324,7 +1372,25 @@ __global__ __launch_bounds__(TW* TH / PPL) void k_blend(BlendArgs A) {
     const uint32_t j = blockIdx.x >> 3, x = blockIdx.x & 7;
     const uint32_t tile = ((j / BLEND_CHUNK) * 8u + x) * BLEND_CHUNK + (j % BLEND_CHUNK);
     if (tile >= A.n_tiles) return;
-    blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, stage);
+    blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, threadIdx.x >> 6, stage[threadIdx.x >> 6]);
+}
+
+// One wave per workgroup: workgroup = one 8 x (8 PPL) block of a tile.  The
+// blocks of a tile finish at very different times (a block may terminate
+// early or walk a long list); as workgroups of their own, a finished block
+// frees its slot at once instead of when the tile's slowest block ends.  The
+// blocks of a tile stay on one XCD (consecutive workgroup ids go round-robin
+// to the 8 XCDs; XCD x takes the chunks of BLEND_CHUNK tiles numbered
+// x, x + 8, ..., block by block).
+template <int TW, int TH, int BD, int PPL, bool COUNT>
+__global__ __launch_bounds__(64) void k_blend_block(BlendArgs A) {
+    constexpr uint32_t NB = TW * TH / (64 * PPL);  // blocks per tile
+    __shared__ Stage<BD> stage;
+    const uint32_t j = blockIdx.x >> 3, x = blockIdx.x & 7;
+    const uint32_t k = j / NB, w = j % NB;  // k-th tile of this XCD, block w of it
+    const uint32_t tile = ((k / BLEND_CHUNK) * 8u + x) * BLEND_CHUNK + (k % BLEND_CHUNK);
+    if (tile >= A.n_tiles) return;
+    blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, (int)w, stage);
 }
 
 // Persistent form for many views of uneven size: a fixed grid of resident
@@ -1351,7 +1417,7 @@ __global__ __launch_bounds__(TW* TH / PPL) void k_blend_persistent(BlendArgs A, 
             const uint32_t tile = next;
             __syncthreads();
             if (tile >= band_end) break;
-            blend_tile<TW, TH, BD, PPL, false>(A, tile, stage);
+            blend_tile<TW, TH, BD, PPL, false>(A, tile, threadIdx.x >> 6, stage[threadIdx.x >> 6]);
         }
     }
 }
@@ -1397,7 +1463,7 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
 
 void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t st) {
     TIGAS_LAUNCH(k_conic_fp64, dim3(64), dim3(256), st, (const uint2*)o.fb_list, o.cnt, o.fb_cap, views_dev,
-                 (const uint32_t*)o.blk_view, o.rec1);
+                 (const uint32_t*)o.blk_view, o.rec);
 }
 
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
@@ -1419,11 +1485,11 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
     TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_touched, cnt, blk_sum2);
     TIGAS_LAUNCH(k_scan_dups, dim3(1), dim3(SCAN_THREADS), st, blk_sum2, nblk, blk_off2);
     if (depth_out)
-        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, o.bbox, o.zkey,
-                     (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const Rec*)o.rec,
+                     o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
-        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, o.bbox, o.zkey,
-                     (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const Rec*)o.rec,
+                     o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
 }
 
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
@@ -1489,6 +1555,12 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
     TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges, host_cnt);
 }
 
+// Experiment switch: one wave per blend workgroup (set from the environment).
+static bool g_blend_block_waves = [] {
+    const char* e = std::getenv("TIGAS_BLEND_WAVE_WG");
+    return e && std::atoi(e) != 0;
+}();
+
 template <int TW, int TH, int BD, int PPL>
 static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int persistent_blocks, hipStream_t st) {
     if (queue) {
@@ -1496,9 +1568,16 @@ static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int pe
                      queue);
     } else {
         const uint32_t per_round = 8 * BLEND_CHUNK;  // one chunk for every XCD
-        const dim3 grid(((A.n_tiles + per_round - 1) / per_round) * per_round);
-        if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, true>), grid, dim3(TW * TH / PPL), st, A);
-        else TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, false>), grid, dim3(TW * TH / PPL), st, A);
+        const uint32_t tiles = ((A.n_tiles + per_round - 1) / per_round) * per_round;
+        if (g_blend_block_waves) {
+            const dim3 grid(tiles * (TW * TH / (64 * PPL)));
+            if (count) TIGAS_LAUNCH((k_blend_block<TW, TH, BD, PPL, true>), grid, dim3(64), st, A);
+            else TIGAS_LAUNCH((k_blend_block<TW, TH, BD, PPL, false>), grid, dim3(64), st, A);
+        } else {
+            const dim3 grid(tiles);
+            if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, true>), grid, dim3(TW * TH / PPL), st, A);
+            else TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, false>), grid, dim3(TW * TH / PPL), st, A);
+        }
     }
 }
 
@@ -1515,7 +1594,7 @@ void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, con
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
                   int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st) {
     if (n_tiles == 0) return;
-    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec0, o.rec1, o.rec2, o.bbox, nrec, work, cull ? 1 : 0};
+    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec, nrec, work, cull ? 1 : 0};
     const bool count = work != nullptr;
     if (count) queue = nullptr;
     const bool two = ppl == 2 && tile_h >= 16;

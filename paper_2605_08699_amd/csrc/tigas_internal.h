@@ -62,11 +62,19 @@ struct Counters {
 
 // Preprocess outputs, one slot per record (record = view-local index of a
 // Gaussian, padded per view to a multiple of 256).
+// One projected Gaussian (record), 64 bytes: all that the blend gathers for
+// a list entry lies in one 64-byte segment.
+struct alignas(64) Rec {
+    float4 r0;   // u_hi, v_hi, u_lo, v_lo
+    float4 r1;   // A, B, C, L: alpha = 2^(A dx^2 + B dx dy + C dy^2 + L)
+    float4 r2;   // r, g, b, opacity
+    uint2 bbox;  // inclusive pixel box: x0 | y0 << 16, x1 | y1 << 16
+    uint2 pad;
+};
+static_assert(sizeof(Rec) == 64, "record is one 64-byte segment");
+
 struct PreOut {
-    float4* rec0;       // u_hi, v_hi, u_lo, v_lo
-    float4* rec1;       // A, B, C, L: alpha = 2^(A dx^2 + B dx dy + C dy^2 + L)
-    float4* rec2;       // r, g, b, opacity
-    uint2* bbox;        // inclusive pixel box: x0 | y0 << 16, x1 | y1 << 16
+    Rec* rec;           // records (written only for Gaussians that touch a tile)
     uint32_t* zkey;     // FP32 depth-key bits
     uint32_t* touched;  // tiles overlapped
     uint32_t* blk_sum;  // per 256-record block: sum of touched

@@ -134,3 +134,27 @@ def test_batched_3m_scene_32_views_matches_single(ctx):
                           batch_depth=64)
         np.testing.assert_array_equal(got[i], want, err_msg=f"view {i}")
     s.free()
+
+
+def test_scene_reloaded_after_free_renders_its_own_data(ctx, c2small):
+    # captured graphs hold a scene's device pointers: a scene loaded after
+    # another was freed (possibly at the same host address) must never replay
+    # the freed scene's graph
+    scene, traj, k = c2small
+    other = synth.scene_clusters(seed=77, n=scene.n, n_clusters=16, surface_frac=0.2)
+    fresh = tigas.Context(0)
+    try:
+        for rep in range(3):
+            sa = ctx.load_scene(scene)
+            a = ctx.render(sa, traj[1], k, 1280, 720, fmt="f32", tile=(16, 16), batch_depth=64)
+            sa.free()
+            sb = ctx.load_scene(other)
+            b = ctx.render(sb, traj[1], k, 1280, 720, fmt="f32", tile=(16, 16), batch_depth=64)
+            sb.free()
+            fb = fresh.load_scene(other)
+            want = fresh.render(fb, traj[1], k, 1280, 720, fmt="f32", tile=(16, 16), batch_depth=64)
+            fb.free()
+            np.testing.assert_array_equal(b, want, err_msg=f"reload {rep}")
+            assert not np.array_equal(a, b)
+    finally:
+        fresh.close()
