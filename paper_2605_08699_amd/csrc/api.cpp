@@ -265,7 +265,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     std::mutex mu;  // one launch sequence at a time per workspace
     // per record
-    DevBuf recs, zkey, touched;
+    DevBuf recs, bbox, zkey, touched;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf fb_list;  // near-singular Gaussians for the FP64 conic kernel
     DevBuf counters;
@@ -294,6 +294,7 @@ struct Workspace {
     PreOut pre() const {
         PreOut o;
         o.rec = recs.as<Rec>();
+        o.bbox = bbox.as<uint2>();
         o.zkey = zkey.as<uint32_t>();
         o.touched = touched.as<uint32_t>();
         o.blk_sum = blk_sum.as<uint32_t>();
@@ -312,6 +313,7 @@ struct Workspace {
         if (nrec <= rec_cap && recs.p) return;
         const size_t r = std::max<uint32_t>(nrec, 256);
         grow(recs, r * sizeof(Rec));
+        grow(bbox, r * 8);
         grow(zkey, r * 4);
         grow(touched, r * 4);
         const size_t nb = r / K1_THREADS + 1;
@@ -1228,9 +1230,9 @@ double request_pixels(const tigas_request& r) {
     return std::floor(r.width * s + 0.5) * std::floor(r.height * s + 0.5);
 }
 
-// Workspace bytes per record: the 64-byte record, depth key, tiles touched,
-// FP64-list entry.
-constexpr size_t kBytesPerRecord = sizeof(Rec) + 4 + 4 + 8;
+// Workspace bytes per record: the 64-byte record, its pixel box again, depth
+// key, tiles touched, FP64-list entry.
+constexpr size_t kBytesPerRecord = sizeof(Rec) + 8 + 4 + 4 + 8;
 
 size_t request_need(const tigas_server* sv, const tigas_request& r) {
     const double rec = (double)request_records(r);

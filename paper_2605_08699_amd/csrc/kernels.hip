@@ -429,6 +429,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             out.pad = make_uint2(0u, 0u);
             o.rec[rec] = out;
         }
+        o.bbox[rec] = touched ? bb : make_uint2(0u, 0u);  // every record: whole-line, coalesced stores
         // per-block counts: wave sums, then one barrier (LDS slots alternate
         // between views so the next view cannot overwrite unread sums)
         const uint32_t s0 = wave_sum(touched), s1 = wave_sum(touched ? 1u : 0u), s2 = wave_sum(touched ? fb : 0u);
@@ -632,7 +633,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __re
 template <bool DEPTH>
 __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ sorted_rec,
                                                           const uint32_t* __restrict__ sorted_touched,
-                                                          const Rec* __restrict__ recs,
+                                                          const uint2* __restrict__ bbox,
                                                           const uint32_t* __restrict__ zkey,
                                                           const uint32_t* __restrict__ blk_off,
                                                           const uint32_t* __restrict__ blk_view,
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     srec[threadIdx.x] = rec;
     if (t) {
         const ViewParams& v = views[blk_view[rec / K1_THREADS]];
-        const uint2 b = recs[rec].bbox;
+        const uint2 b = bbox[rec];
         const int tx0 = (int)(b.x & 0xffffu) / v.tile_w, ty0 = (int)(b.x >> 16) / v.tile_h;
         const int tx1 = (int)(b.y & 0xffffu) / v.tile_w;
         sx0[threadIdx.x] = (uint32_t)tx0;
@@ -1375,24 +1376,6 @@ __global__ __launch_bounds__(TW* TH / PPL) void k_blend(BlendArgs A) {
     blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, threadIdx.x >> 6, stage[threadIdx.x >> 6]);
 }
 
-// One wave per workgroup: workgroup = one 8 x (8 PPL) block of a tile.  The
-// blocks of a tile finish at very different times (a block may terminate
-// early or walk a long list); as workgroups of their own, a finished block
-// frees its slot at once instead of when the tile's slowest block ends.  The
-// blocks of a tile stay on one XCD (consecutive workgroup ids go round-robin
-// to the 8 XCDs; XCD x takes the chunks of BLEND_CHUNK tiles numbered
-// x, x + 8, ..., block by block).
-template <int TW, int TH, int BD, int PPL, bool COUNT>
-__global__ __launch_bounds__(64) void k_blend_block(BlendArgs A) {
-    constexpr uint32_t NB = TW * TH / (64 * PPL);  // blocks per tile
-    __shared__ Stage<BD> stage;
-    const uint32_t j = blockIdx.x >> 3, x = blockIdx.x & 7;
-    const uint32_t k = j / NB, w = j % NB;  // k-th tile of this XCD, block w of it
-    const uint32_t tile = ((k / BLEND_CHUNK) * 8u + x) * BLEND_CHUNK + (k % BLEND_CHUNK);
-    if (tile >= A.n_tiles) return;
-    blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, (int)w, stage);
-}
-
 // Persistent form for many views of uneven size: a fixed grid of resident
 // workgroups pulls tiles from 8 device work queues, one per band of
 // consecutive tiles; a workgroup starts on the band of its XCD (id mod 8) and
@@ -1485,10 +1468,10 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
     TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_touched, cnt, blk_sum2);
     TIGAS_LAUNCH(k_scan_dups, dim3(1), dim3(SCAN_THREADS), st, blk_sum2, nblk, blk_off2);
     if (depth_out)
-        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const Rec*)o.rec,
+        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const uint2*)o.bbox,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
-        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const Rec*)o.rec,
+        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const uint2*)o.bbox,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
 }
 
@@ -1555,12 +1538,6 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
     TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges, host_cnt);
 }
 
-// Experiment switch: one wave per blend workgroup (set from the environment).
-static bool g_blend_block_waves = [] {
-    const char* e = std::getenv("TIGAS_BLEND_WAVE_WG");
-    return e && std::atoi(e) != 0;
-}();
-
 template <int TW, int TH, int BD, int PPL>
 static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int persistent_blocks, hipStream_t st) {
     if (queue) {
@@ -1569,15 +1546,9 @@ static void blend_launch(const BlendArgs& A, bool count, uint32_t* queue, int pe
     } else {
         const uint32_t per_round = 8 * BLEND_CHUNK;  // one chunk for every XCD
         const uint32_t tiles = ((A.n_tiles + per_round - 1) / per_round) * per_round;
-        if (g_blend_block_waves) {
-            const dim3 grid(tiles * (TW * TH / (64 * PPL)));
-            if (count) TIGAS_LAUNCH((k_blend_block<TW, TH, BD, PPL, true>), grid, dim3(64), st, A);
-            else TIGAS_LAUNCH((k_blend_block<TW, TH, BD, PPL, false>), grid, dim3(64), st, A);
-        } else {
-            const dim3 grid(tiles);
-            if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, true>), grid, dim3(TW * TH / PPL), st, A);
-            else TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, false>), grid, dim3(TW * TH / PPL), st, A);
-        }
+        const dim3 grid(tiles);
+        if (count) TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, true>), grid, dim3(TW * TH / PPL), st, A);
+        else TIGAS_LAUNCH((k_blend<TW, TH, BD, PPL, false>), grid, dim3(TW * TH / PPL), st, A);
     }
 }
 

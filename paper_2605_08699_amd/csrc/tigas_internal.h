@@ -75,6 +75,7 @@ static_assert(sizeof(Rec) == 64, "record is one 64-byte segment");
 
 struct PreOut {
     Rec* rec;           // records (written only for Gaussians that touch a tile)
+    uint2* bbox;        // the records' pixel boxes again, densely (read by k_duplicate)
     uint32_t* zkey;     // FP32 depth-key bits
     uint32_t* touched;  // tiles overlapped
     uint32_t* blk_sum;  // per 256-record block: sum of touched

@@ -72,7 +72,7 @@ def test_results_identical_alone_and_in_the_mix(ctx, scenes):
 def test_small_budget_defers_requests_but_renders_them_all(ctx, scenes):
     reqs, outs, meta = _requests(scenes, 20, seed=22)
     # room for about two requests of the largest scene per slot
-    budget = 2 * 2 * (150_016 * 80 + 150_016 * 5 * 24) + (1 << 20)
+    budget = 2 * 2 * (150_016 * 88 + 150_016 * 5 * 24) + (1 << 20)
     with tigas.Server(ctx, slots=2, max_batch=64, hbm_budget=budget) as sv:
         for r in reqs:
             sv.submit(r)
