@@ -504,14 +504,29 @@ constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
 constexpr int SCAN_STAGE = SCAN_CHUNK + SCAN_CHUNK / 32;
 __device__ __forceinline__ int spad(int i) { return i + (i >> 5); }
 
+// sum_a / sum_b (optional): per-thread sums of two more count arrays of the
+// same length, loaded alongside (all loads of a chunk are in flight at once).
 __device__ uint64_t scan_counts(const uint32_t* __restrict__ in, int n, uint32_t* __restrict__ out, uint32_t* red,
-                                uint32_t* stage) {
+                                uint32_t* stage, const uint32_t* __restrict__ in_a = nullptr, uint64_t* sum_a = nullptr,
+                                const uint32_t* __restrict__ in_b = nullptr, uint64_t* sum_b = nullptr) {
     uint64_t running = 0;
     for (int base = 0; base < n; base += SCAN_CHUNK) {
+        uint32_t va[SCAN_ITEMS], vb[SCAN_ITEMS];
 #pragma unroll
         for (int r = 0; r < SCAN_ITEMS; ++r) {
             const int i = r * SCAN_THREADS + (int)threadIdx.x;
-            stage[spad(i)] = base + i < n ? in[base + i] : 0u;
+            const bool ok = base + i < n;
+            stage[spad(i)] = ok ? in[base + i] : 0u;
+            va[r] = (in_a && ok) ? in_a[base + i] : 0u;
+            vb[r] = (in_b && ok) ? in_b[base + i] : 0u;
+        }
+        if (in_a) {
+#pragma unroll
+            for (int r = 0; r < SCAN_ITEMS; ++r) *sum_a += va[r];
+        }
+        if (in_b) {
+#pragma unroll
+            for (int r = 0; r < SCAN_ITEMS; ++r) *sum_b += vb[r];
         }
         __syncthreads();
         uint32_t loc[SCAN_ITEMS];
@@ -561,11 +576,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
     __shared__ unsigned long long red64[SCAN_THREADS / 64];
     __shared__ uint32_t stage[SCAN_STAGE];
     uint64_t dsum = 0, fsum = 0;
-    for (int i = (int)threadIdx.x; i < nblk; i += SCAN_THREADS) {
-        dsum += blk_sum[i];
-        fsum += blk_fb[i];
-    }
-    const uint64_t running = scan_counts(blk_vis, nblk, blk_off, red, stage);
+    const uint64_t running = scan_counts(blk_vis, nblk, blk_off, red, stage, blk_sum, &dsum, blk_fb, &fsum);
     const uint64_t D = block_sum_u64(dsum, red64);
     const uint64_t fb = block_sum_u64(fsum, red64);
     if (threadIdx.x == 0) {
@@ -1080,7 +1091,8 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ til
                                                 uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t D = sort_count(cnt, 0, cap);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < D; i += gridDim.x * 256) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;  // one element per thread (grid covers the capacity)
+    if (i < D) {
         const uint32_t t = tile[i];
         if (i == 0 || tile[i - 1] != t) ranges[t].x = i;
         if (i + 1 == D || tile[i + 1] != t) ranges[t].y = i + 1;
@@ -1125,8 +1137,8 @@ constexpr float LOG2_ALPHA_MIN = -7.99435343685886f;
 // (negative-definite quadratic part) stay below the skip threshold on the
 // whole rectangle [dx0, dx1] x [dy0, dy1] of offsets?  The maximum of a
 // concave quadratic over a rectangle is at the unconstrained maximum when
-// that lies inside, else on one of the four edges, where it is a 1D concave
-// quadratic maximised at a clamped stationary point.  The test is
+// that lies inside, else on an edge facing the centre, where it is a 1D
+// concave quadratic maximised at a clamped stationary point.  The test is
 // conservative: it answers yes only with a margin far above the FP32
 // rounding of this bound and of the per-pixel exponent, so a Gaussian it
 // removes would have been skipped at every pixel of the rectangle.
@@ -1144,7 +1156,10 @@ __device__ __forceinline__ bool below_threshold(float A, float B, float C, float
             const float dx = fminf(fmaxf(-B * cy * ra, dx0), dx1);
             return (C * cy + B * dx) * cy + A * dx * dx;
         };
-        q = fmaxf(fmaxf(edge_x(dx0), edge_x(dx1)), fmaxf(edge_y(dy0), edge_y(dy1)));
+        // the maximum lies on a face visible from the centre (visibility is
+        // affine-invariant, so it holds in the quadratic's own metric): the
+        // x-face and the y-face on the centre's side suffice
+        q = fmaxf(edge_x(dx1 < 0.0f ? dx1 : dx0), edge_y(dy1 < 0.0f ? dy1 : dy0));
     }
     const float r2 = fmaxf(dx0 * dx0, dx1 * dx1) + fmaxf(dy0 * dy0, dy1 * dy1);
     const float margin = 0.02f + 1e-5f * (fabsf(A) + fabsf(B) + fabsf(C)) * r2;
@@ -1535,7 +1550,8 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
 
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    hipStream_t st) {
-    TIGAS_LAUNCH(k_ranges, dim3(1024), dim3(256), st, tile_sorted, cnt, cap, ranges, host_cnt);
+    TIGAS_LAUNCH(k_ranges, dim3(std::max<uint32_t>(1u, (cap + 255) / 256)), dim3(256), st, tile_sorted, cnt, cap, ranges,
+                 host_cnt);
 }
 
 template <int TW, int TH, int BD, int PPL>
