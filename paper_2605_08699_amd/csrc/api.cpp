@@ -929,7 +929,7 @@ TileCfg autotune(tigas_context* ctx, Workspace& ws, Plan& plan) {
         set_tiles(plan, tc);
         run_plan(ctx, ws, plan, false);  // capture + warm
         double t_min = 1e30;
-        for (int r = 0; r < 3; ++r) {
+        for (int r = 0; r < 5; ++r) {
             const auto t0 = std::chrono::steady_clock::now();
             run_plan(ctx, ws, plan, false);
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

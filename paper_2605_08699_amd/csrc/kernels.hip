@@ -1091,8 +1091,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ til
                                                 uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t D = sort_count(cnt, 0, cap);
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;  // one element per thread (grid covers the capacity)
-    if (i < D) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < D; i += gridDim.x * 256) {
         const uint32_t t = tile[i];
         if (i == 0 || tile[i - 1] != t) ranges[t].x = i;
         if (i + 1 == D || tile[i + 1] != t) ranges[t].y = i + 1;
@@ -1550,8 +1549,10 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
 
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    hipStream_t st) {
-    TIGAS_LAUNCH(k_ranges, dim3(std::max<uint32_t>(1u, (cap + 255) / 256)), dim3(256), st, tile_sorted, cnt, cap, ranges,
-                 host_cnt);
+    // a few elements per thread at most, but no more workgroups than a large
+    // frame needs (the capacity may have been sized by a much larger frame)
+    TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(4096u, std::max<uint32_t>(1u, (cap + 255) / 256))), dim3(256), st,
+                 tile_sorted, cnt, cap, ranges, host_cnt);
 }
 
 template <int TW, int TH, int BD, int PPL>
