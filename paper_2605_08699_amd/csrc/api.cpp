@@ -268,6 +268,7 @@ struct Workspace {
     DevBuf recs, bbox, zkey, touched;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf fb_list;  // near-singular Gaussians for the FP64 conic kernel
+    DevBuf chunk_vis, chunk_dup, chunk_fb, chunk_dups;  // totals per chunk of block counts
     DevBuf counters;
     // per duplicate (also holds the visible Gaussians during the depth passes)
     DevBuf key[2], val[2], ext[2];
@@ -302,6 +303,10 @@ struct Workspace {
         o.blk_fb = blk_fb.as<uint32_t>();
         o.blk_view = blk_view.as<uint32_t>();
         o.fb_list = fb_list.as<uint2>();
+        o.chunk_vis = chunk_vis.as<uint32_t>();
+        o.chunk_dup = chunk_dup.as<unsigned long long>();
+        o.chunk_fb = chunk_fb.as<uint32_t>();
+        o.chunk_dups = chunk_dups.as<uint32_t>();
         o.fb_cap = rec_cap;
         o.cnt = counters.as<Counters>();
         return o;
@@ -319,6 +324,9 @@ struct Workspace {
         const size_t nb = r / K1_THREADS + 1;
         for (DevBuf* b : {&blk_sum, &blk_vis, &blk_fb, &blk_view, &blk_off, &blk_sum2, &blk_off2}) grow(*b, nb * 4);
         grow(fb_list, r * 8);
+        const size_t nch = nb / SCAN_CHUNK + 2;
+        for (DevBuf* b : {&chunk_vis, &chunk_fb, &chunk_dups}) grow(*b, nch * 4);
+        grow(chunk_dup, nch * 8);
         rec_cap = (uint32_t)r;
     }
     void ensure_dups(uint32_t cap) {
@@ -525,7 +533,14 @@ std::vector<SortPass> tile_passes(uint32_t n_tiles) {
     return p;
 }
 
-int sort_blocks(uint64_t n) { return (int)std::min<uint64_t>(SORT_MAX_BLOCKS, std::max<uint64_t>(1, n / 4096)); }
+// Workgroups of a sort pass: one per 4096 keys, at most 1024 up to 16M keys
+// (more only lengthen the scans there) and up to SORT_MAX_BLOCKS beyond, so
+// that a batch's hundred million duplicates do not queue 60 chunks per
+// workgroup.
+int sort_blocks(uint64_t n) {
+    const uint64_t cap = n <= (16ull << 20) ? 1024 : SORT_MAX_BLOCKS;
+    return (int)std::min<uint64_t>(cap, std::max<uint64_t>(1, n / 4096));
+}
 
 // Tile layout of a plan for a tile configuration (tile ids are global:
 // view tile offset + row-major local id).

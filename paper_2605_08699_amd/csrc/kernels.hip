@@ -495,62 +495,12 @@ __global__ __launch_bounds__(256) void k_conic_fp64(const uint2* __restrict__ li
     }
 }
 
-// Exclusive scan of n counts by one workgroup, SCAN_THREADS * SCAN_ITEMS at a
-// time: coalesced loads into LDS, SCAN_ITEMS consecutive counts per thread
-// summed from LDS (one pad word per 32 keeps the strided reads free of bank
-// conflicts), a workgroup scan of the thread sums, and the offsets written
-// back through LDS and stored coalesced.  Returns the 64-bit total.
-constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+// Counts are staged through LDS for the scans: coalesced loads, SCAN_ITEMS
+// consecutive counts per thread summed from LDS (one pad word per 32 keeps
+// those strided reads free of bank conflicts), offsets written back through
+// LDS and stored coalesced.
 constexpr int SCAN_STAGE = SCAN_CHUNK + SCAN_CHUNK / 32;
 __device__ __forceinline__ int spad(int i) { return i + (i >> 5); }
-
-// sum_a / sum_b (optional): per-thread sums of two more count arrays of the
-// same length, loaded alongside (all loads of a chunk are in flight at once).
-__device__ uint64_t scan_counts(const uint32_t* __restrict__ in, int n, uint32_t* __restrict__ out, uint32_t* red,
-                                uint32_t* stage, const uint32_t* __restrict__ in_a = nullptr, uint64_t* sum_a = nullptr,
-                                const uint32_t* __restrict__ in_b = nullptr, uint64_t* sum_b = nullptr) {
-    uint64_t running = 0;
-    for (int base = 0; base < n; base += SCAN_CHUNK) {
-        uint32_t va[SCAN_ITEMS], vb[SCAN_ITEMS];
-#pragma unroll
-        for (int r = 0; r < SCAN_ITEMS; ++r) {
-            const int i = r * SCAN_THREADS + (int)threadIdx.x;
-            const bool ok = base + i < n;
-            stage[spad(i)] = ok ? in[base + i] : 0u;
-            va[r] = (in_a && ok) ? in_a[base + i] : 0u;
-            vb[r] = (in_b && ok) ? in_b[base + i] : 0u;
-        }
-        if (in_a) {
-#pragma unroll
-            for (int r = 0; r < SCAN_ITEMS; ++r) *sum_a += va[r];
-        }
-        if (in_b) {
-#pragma unroll
-            for (int r = 0; r < SCAN_ITEMS; ++r) *sum_b += vb[r];
-        }
-        __syncthreads();
-        uint32_t loc[SCAN_ITEMS];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            loc[j] = sum;
-            sum += stage[spad((int)threadIdx.x * SCAN_ITEMS + j)];
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &tot);
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) stage[spad((int)threadIdx.x * SCAN_ITEMS + j)] = (uint32_t)running + ex + loc[j];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < SCAN_ITEMS; ++r) {
-            const int i = r * SCAN_THREADS + (int)threadIdx.x;
-            if (base + i < n) out[base + i] = stage[spad(i)];
-        }
-        __syncthreads();  // the next chunk reuses the stage
-        running += tot;
-    }
-    return running;
-}
 
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, unsigned long long* lds) {
 #pragma unroll
@@ -563,43 +513,122 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, unsigned long long
     return t;
 }
 
-// After preprocess: compaction offsets of the visible records, the totals
-// V, D and FP64-fallback count, the overflow flag; clears the per-frame
-// accumulators of later kernels (digit totals, per-block duplicate sums,
-// tile ranges).
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* __restrict__ blk_sum,
-                                                               const uint32_t* __restrict__ blk_vis,
-                                                               const uint32_t* __restrict__ blk_fb, int nblk,
+// Multi-workgroup exclusive scans of per-block counts, chunk by chunk
+// (SCAN_CHUNK counts per workgroup), in two kernels: chunk totals, then each
+// chunk scanned from the sum of the totals before it.
+
+// Totals of chunk blockIdx.x of `in` (and optionally of two more count arrays).
+__global__ __launch_bounds__(SCAN_THREADS) void k_chunk_totals(const uint32_t* __restrict__ in, int n,
+                                                               const uint32_t* __restrict__ in_a,
+                                                               const uint32_t* __restrict__ in_b,
+                                                               uint32_t* __restrict__ tot,
+                                                               unsigned long long* __restrict__ tot_a,
+                                                               uint32_t* __restrict__ tot_b) {
+    __shared__ unsigned long long red64[SCAN_THREADS / 64];
+    const int base = (int)blockIdx.x * SCAN_CHUNK;
+    uint64_t s = 0, sa = 0, sb = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const int i = base + r * SCAN_THREADS + (int)threadIdx.x;
+        if (i < n) {
+            s += in[i];
+            if (in_a) sa += in_a[i];
+            if (in_b) sb += in_b[i];
+        }
+    }
+    s = block_sum_u64(s, red64);
+    if (in_a) sa = block_sum_u64(sa, red64);
+    if (in_b) sb = block_sum_u64(sb, red64);
+    if (threadIdx.x == 0) {
+        tot[blockIdx.x] = (uint32_t)s;
+        if (tot_a) tot_a[blockIdx.x] = sa;
+        if (tot_b) tot_b[blockIdx.x] = (uint32_t)sb;
+    }
+}
+
+// Exclusive scan of chunk blockIdx.x of `in` into `out`, starting from the
+// sum of the totals of the chunks before it.
+__device__ void scan_chunk(const uint32_t* __restrict__ in, int n, const uint32_t* __restrict__ tot,
+                           uint32_t* __restrict__ out, uint32_t* red, unsigned long long* red64, uint32_t* stage) {
+    uint64_t p = 0;
+    for (int c = (int)threadIdx.x; c < (int)blockIdx.x; c += SCAN_THREADS) p += tot[c];
+    const uint32_t prefix = (uint32_t)block_sum_u64(p, red64);
+    const int base = (int)blockIdx.x * SCAN_CHUNK;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const int i = r * SCAN_THREADS + (int)threadIdx.x;
+        stage[spad(i)] = base + i < n ? in[base + i] : 0u;
+    }
+    __syncthreads();
+    uint32_t loc[SCAN_ITEMS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        loc[j] = sum;
+        sum += stage[spad((int)threadIdx.x * SCAN_ITEMS + j)];
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &total);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) stage[spad((int)threadIdx.x * SCAN_ITEMS + j)] = prefix + ex + loc[j];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const int i = r * SCAN_THREADS + (int)threadIdx.x;
+        if (base + i < n) out[base + i] = stage[spad(i)];
+    }
+}
+
+// After preprocess (second kernel of the chunked scan): compaction offsets of
+// the visible records; workgroup 0 also sets the totals V, D and FP64-fallback
+// count and the overflow flag; every workgroup clears part of the per-frame
+// accumulators of later kernels (digit totals, work queues, tile ranges).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* __restrict__ blk_vis, int nblk,
+                                                               const uint32_t* __restrict__ tot_vis,
+                                                               const unsigned long long* __restrict__ tot_dup,
+                                                               const uint32_t* __restrict__ tot_fb, int nchunks,
                                                                uint32_t* __restrict__ blk_off, Counters* cnt,
                                                                uint32_t cap, ZeroList zl) {
     __shared__ uint32_t red[SCAN_THREADS / 64];
     __shared__ unsigned long long red64[SCAN_THREADS / 64];
     __shared__ uint32_t stage[SCAN_STAGE];
-    uint64_t dsum = 0, fsum = 0;
-    const uint64_t running = scan_counts(blk_vis, nblk, blk_off, red, stage, blk_sum, &dsum, blk_fb, &fsum);
-    const uint64_t D = block_sum_u64(dsum, red64);
-    const uint64_t fb = block_sum_u64(fsum, red64);
-    if (threadIdx.x == 0) {
-        cnt->D = D > 0xffffffffull ? 0xffffffffu : (uint32_t)D;
-        cnt->visible = (uint32_t)running;
-        cnt->fallbacks = (uint32_t)fb;
-        cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
-        cnt->fb_list = 0u;  // consumed by k_conic_fp64, which ran before this kernel
-        cnt->epoch += MAX_SORT_PASSES;  // look-back entries of earlier frames never match
-        cnt->error = 0u;
+    scan_chunk(blk_vis, nblk, tot_vis, blk_off, red, red64, stage);
+    if (blockIdx.x == 0) {
+        uint64_t V = 0, D = 0, F = 0;
+        for (int c = (int)threadIdx.x; c < nchunks; c += SCAN_THREADS) {
+            V += tot_vis[c];
+            D += tot_dup[c];
+            F += tot_fb[c];
+        }
+        V = block_sum_u64(V, red64);
+        D = block_sum_u64(D, red64);
+        F = block_sum_u64(F, red64);
+        if (threadIdx.x == 0) {
+            cnt->D = D > 0xffffffffull ? 0xffffffffu : (uint32_t)D;
+            cnt->visible = (uint32_t)V;
+            cnt->fallbacks = (uint32_t)F;
+            cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
+            cnt->fb_list = 0u;  // consumed by k_conic_fp64, which ran before this kernel
+            cnt->epoch += MAX_SORT_PASSES;  // look-back entries of earlier frames never match
+            cnt->error = 0u;
+        }
     }
 #pragma unroll
     for (int k = 0; k < ZeroList::N; ++k)
-        for (uint32_t i = threadIdx.x; i < zl.n[k]; i += SCAN_THREADS) zl.p[k][i] = 0u;
+        for (uint32_t i = blockIdx.x * SCAN_THREADS + threadIdx.x; i < zl.n[k]; i += gridDim.x * SCAN_THREADS)
+            zl.p[k][i] = 0u;
 }
 
 // Emission offsets: exclusive scan of the duplicate counts of the
-// depth-sorted visible Gaussians, per 256-element block.
+// depth-sorted visible Gaussians, per 256-element block (second kernel of the
+// chunked scan).
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_dups(const uint32_t* __restrict__ blk_sum, int nblk,
+                                                            const uint32_t* __restrict__ tot,
                                                             uint32_t* __restrict__ blk_off) {
     __shared__ uint32_t red[SCAN_THREADS / 64];
+    __shared__ unsigned long long red64[SCAN_THREADS / 64];
     __shared__ uint32_t stage[SCAN_STAGE];
-    scan_counts(blk_sum, nblk, blk_off, red, stage);
+    scan_chunk(blk_sum, nblk, tot, blk_off, red, red64, stage);
 }
 
 // Visible records, in record order, as (depth key, record) pairs.
@@ -1465,8 +1494,12 @@ void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t
 
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st) {
-    TIGAS_LAUNCH(k_scan_visible, dim3(1), dim3(SCAN_THREADS), st, o.blk_sum, o.blk_vis, o.blk_fb, nblk, blk_off, cnt,
-                 cap, zl);
+    const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)o.blk_vis, nblk,
+                 (const uint32_t*)o.blk_sum, (const uint32_t*)o.blk_fb, o.chunk_vis, o.chunk_dup, o.chunk_fb);
+    TIGAS_LAUNCH(k_scan_visible, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)o.blk_vis, nblk,
+                 (const uint32_t*)o.chunk_vis, (const unsigned long long*)o.chunk_dup, (const uint32_t*)o.chunk_fb,
+                 nchunks, blk_off, cnt, cap, zl);
 }
 
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st) {
@@ -1480,7 +1513,12 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
                       hipStream_t st) {
     if (nblk == 0) return;
     TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_touched, cnt, blk_sum2);
-    TIGAS_LAUNCH(k_scan_dups, dim3(1), dim3(SCAN_THREADS), st, blk_sum2, nblk, blk_off2);
+    const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
+                 (const uint32_t*)nullptr, (const uint32_t*)nullptr, o.chunk_dups, (unsigned long long*)nullptr,
+                 (uint32_t*)nullptr);
+    TIGAS_LAUNCH(k_scan_dups, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
+                 (const uint32_t*)o.chunk_dups, blk_off2);
     if (depth_out)
         TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const uint2*)o.bbox,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
@@ -1551,7 +1589,7 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
                    hipStream_t st) {
     // a few elements per thread at most, but no more workgroups than a large
     // frame needs (the capacity may have been sized by a much larger frame)
-    TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(4096u, std::max<uint32_t>(1u, (cap + 255) / 256))), dim3(256), st,
+    TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(16384u, std::max<uint32_t>(1u, (cap + 255) / 256))), dim3(256), st,
                  tile_sorted, cnt, cap, ranges, host_cnt);
 }
 

@@ -10,9 +10,10 @@ namespace tigas {
 constexpr int K1_THREADS = 256;       // one Gaussian per thread in preprocess / duplicate
 constexpr int SORT_THREADS = 256;     // 4 wave64 per sort workgroup
 constexpr int SORT_CHUNK = 2048;      // keys ranked per workgroup step (4 waves x 8 rounds x 64)
-constexpr int SORT_MAX_BLOCKS = 1024; // workgroups per sort pass
+constexpr int SORT_MAX_BLOCKS = 4096; // workgroups per sort pass (at most)
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;  // counts per workgroup of the chunked scans
 constexpr int MAX_SORT_PASSES = 8;
 
 // Resident scene (device pointers).  Layout by storage precision:
@@ -82,6 +83,10 @@ struct PreOut {
     uint32_t* blk_vis;  // per block: records with touched > 0
     uint32_t* blk_fb;   // per block: FP64 fallbacks
     uint32_t* blk_view; // per block: view index
+    uint32_t* chunk_vis;            // per SCAN_CHUNK block counts: visible records,
+    unsigned long long* chunk_dup;  // duplicates,
+    uint32_t* chunk_fb;             // FP64 fallbacks,
+    uint32_t* chunk_dups;           // and (later) depth-ordered duplicate counts
     uint2* fb_list;     // (record, Gaussian) pairs whose conic is recomputed in FP64
     uint32_t fb_cap;
     Counters* cnt;
