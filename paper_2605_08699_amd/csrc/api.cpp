@@ -265,7 +265,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     std::mutex mu;  // one launch sequence at a time per workspace
     // per record
-    DevBuf recs, bbox, zkey, touched;
+    DevBuf recs, rect, srect, zkey, touched;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf fb_list;  // near-singular Gaussians for the FP64 conic kernel
     DevBuf chunk_vis, chunk_dup, chunk_fb, chunk_dups;  // totals per chunk of block counts
@@ -295,7 +295,8 @@ struct Workspace {
     PreOut pre() const {
         PreOut o;
         o.rec = recs.as<Rec>();
-        o.bbox = bbox.as<uint2>();
+        o.rect = rect.as<uint2>();
+        o.srect = srect.as<uint2>();
         o.zkey = zkey.as<uint32_t>();
         o.touched = touched.as<uint32_t>();
         o.blk_sum = blk_sum.as<uint32_t>();
@@ -318,7 +319,8 @@ struct Workspace {
         if (nrec <= rec_cap && recs.p) return;
         const size_t r = std::max<uint32_t>(nrec, 256);
         grow(recs, r * sizeof(Rec));
-        grow(bbox, r * 8);
+        grow(rect, r * 8);
+        grow(srect, r * 8);
         grow(zkey, r * 4);
         grow(touched, r * 4);
         const size_t nb = r / K1_THREADS + 1;
@@ -662,13 +664,13 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     unsigned long long* lb = ws.lookback.as<unsigned long long>();
     uint32_t* tickets = ws.queue.as<uint32_t>() + 8;
     const int cv = onepass ? launch_sort_onesweep(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap,
-                                                  std::min(plan.nrec, ws.dup_cap), 0, false, cnt, 0, o.touched, lb,
+                                                  std::min(plan.nrec, ws.dup_cap), 0, false, cnt, 0, o.rect, o.srect, lb,
                                                   tickets, st)
                            : launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0,
-                                         false, cnt, 0, o.touched, nullptr, st);
+                                         false, cnt, 0, o.rect, o.srect, st);
     // duplicates in depth order
     const int cd = cv ^ 1;
-    launch_duplicate(o, nblk, sb.val[cv], sb.ext[cv], ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
+    launch_duplicate(o, nblk, sb.val[cv], o.srect, ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
                      ws.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
     mark(3);
     if (debug) {
@@ -680,7 +682,7 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     // tile digits, on the duplicates
     const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
     const int cur = onepass ? launch_sort_onesweep(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
-                                                   ws.dup_cap, cd, debug, cnt, 4, nullptr, lb, tickets, st)
+                                                   ws.dup_cap, cd, debug, cnt, 4, nullptr, nullptr, lb, tickets, st)
                             : launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
                                           sort_blocks(ws.dup_cap), cd, debug, cnt, 4, nullptr, nullptr, st);
     mark(4);

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
         bool vis = ok && z32 > NEAR_Z;
         uint32_t touched = 0, fb = 0;
         float4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, r2 = {0, 0, 0, 0};
-        uint2 bb = {0u, 0u};
+        uint2 bb = {0u, 0u}, tr = {0u, 0u};
         if (vis) {
             // camera-space centre, double-float: d = mu - t exactly, p = V d
             const df dX = two_sum(mx, -v.cam[0]), dY = two_sum(my, -v.cam[1]), dZ = two_sum(mz, -v.cam[2]);
@@ -388,6 +388,8 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
                     const int ty0 = y0 / v.tile_h, ty1 = y1 / v.tile_h;
                     touched = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
                     bb = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+                    tr = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
+                                    (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16));
                 }
             }
             if (touched) {
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             out.pad = make_uint2(0u, 0u);
             o.rec[rec] = out;
         }
-        o.bbox[rec] = touched ? bb : make_uint2(0u, 0u);  // every record: whole-line, coalesced stores
+        o.rect[rec] = tr;  // every record: whole-line, coalesced stores
         // per-block counts: wave sums, then one barrier (LDS slots alternate
         // between views so the next view cannot overwrite unread sums)
         const uint32_t s0 = wave_sum(touched), s1 = wave_sum(touched ? 1u : 0u), s2 = wave_sum(touched ? fb : 0u);
@@ -648,8 +650,11 @@ __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restri
     }
 }
 
+// Tiles in a tile rectangle (tx0 | ty0 << 16, nx | ny << 16).
+__device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu) * (r.y >> 16); }
+
 // Per 256 depth-sorted visible Gaussians: the sum of their tile counts.
-__global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __restrict__ sorted_touched,
+__global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint2* __restrict__ sorted_rect,
                                                             const Counters* __restrict__ cnt,
                                                             uint32_t* __restrict__ blk_sum) {
     __shared__ uint32_t red[K1_THREADS / 64];
@@ -659,7 +664,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __re
         if (threadIdx.x == 0) blk_sum[blockIdx.x] = 0u;
         return;
     }
-    const uint32_t s = block_sum<K1_THREADS>(i < V ? sorted_touched[i] : 0u, red);
+    const uint32_t s = block_sum<K1_THREADS>(i < V ? rect_tiles(sorted_rect[i]) : 0u, red);
     if (threadIdx.x == 0) blk_sum[blockIdx.x] = s;
 }
 
@@ -672,8 +677,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint32_t* __re
 // each finding its Gaussian by binary search over the LDS prefix sums.
 template <bool DEPTH>
 __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ sorted_rec,
-                                                          const uint32_t* __restrict__ sorted_touched,
-                                                          const uint2* __restrict__ bbox,
+                                                          const uint2* __restrict__ sorted_rect,
                                                           const uint32_t* __restrict__ zkey,
                                                           const uint32_t* __restrict__ blk_off,
                                                           const uint32_t* __restrict__ blk_view,
@@ -690,9 +694,11 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
     const uint32_t V = cnt->visible;
     uint32_t rec = 0, t = 0;
+    uint2 tr = make_uint2(0u, 0u);
     if (i < V) {
         rec = sorted_rec[i];
-        t = sorted_touched[i];  // tiles touched, gathered into depth order by the last depth pass
+        tr = sorted_rect[i];  // tile rectangle, gathered into depth order by the last depth pass
+        t = rect_tiles(tr);
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<K1_THREADS>(t, red, &tot);
@@ -702,15 +708,13 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     srec[threadIdx.x] = rec;
     if (t) {
         const ViewParams& v = views[blk_view[rec / K1_THREADS]];
-        const uint2 b = bbox[rec];
-        const int tx0 = (int)(b.x & 0xffffu) / v.tile_w, ty0 = (int)(b.x >> 16) / v.tile_h;
-        const int tx1 = (int)(b.y & 0xffffu) / v.tile_w;
-        sx0[threadIdx.x] = (uint32_t)tx0;
-        snx[threadIdx.x] = (uint32_t)(tx1 - tx0 + 1);
-        sinx[threadIdx.x] = 1.0f / (float)(tx1 - tx0 + 1);
+        const uint32_t nx = tr.y & 0xffffu;
+        sx0[threadIdx.x] = tr.x & 0xffffu;
+        snx[threadIdx.x] = nx;
+        sinx[threadIdx.x] = 1.0f / (float)nx;
         stb[threadIdx.x] = v.tile_base;
         // tiles_x of the view, packed with the first row
-        stx[threadIdx.x] = (uint32_t)ty0 | ((uint32_t)v.tiles_x << 16);
+        stx[threadIdx.x] = (tr.x >> 16) | ((uint32_t)v.tiles_x << 16);
     }
     __syncthreads();
     const uint32_t base = blk_off[blockIdx.x];
@@ -847,16 +851,15 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
 // Chunks of 2048 keys are ranked (per-wave ballot match + per-wave digit
 // counters), staged in LDS in chunk-local digit order, and written out so that
 // consecutive threads store consecutive positions of each digit run.
-// SUMS (last depth pass): the extra output word is the tile count of each
-// Gaussian (gathered once here), so the emission offsets of k_duplicate can be
-// summed from a contiguous array.
+// SUMS (last depth pass): each Gaussian's tile rectangle is gathered once
+// here and written in depth order, so that k_sorted_sums and k_duplicate read
+// it contiguously instead of gathering by record.
 template <bool EXTRA, bool SUMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext,
     const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits,
-    const uint32_t* __restrict__ hist, int nb, const uint32_t* __restrict__ touched,
-    uint32_t* __restrict__ blk_sum) {
+    const uint32_t* __restrict__ hist, int nb, const uint2* __restrict__ rsrc, uint2* __restrict__ rdst) {
     static_assert(SORT_THREADS == 256, "one thread per digit");
     constexpr int NW = SORT_THREADS / 64;
     constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
@@ -866,7 +869,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     __shared__ uint32_t red[NW];
     __shared__ uint32_t lkey[SORT_CHUNK];
     __shared__ uint32_t lval[SORT_CHUNK];
-    __shared__ uint32_t lext[(EXTRA || SUMS) ? SORT_CHUNK : 1];
+    __shared__ uint32_t lext[EXTRA ? SORT_CHUNK : 1];
+    __shared__ uint2 lrect[SUMS ? SORT_CHUNK : 1];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -879,6 +883,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
         for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
         __syncthreads();
         uint32_t dig[ROUNDS], rank[ROUNDS], ek[ROUNDS], ev[ROUNDS], ee[ROUNDS];
+        uint2 er[ROUNDS];
         bool ok[ROUNDS];
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
@@ -887,7 +892,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             const uint32_t ic = ok[r] ? idx : chunk;  // clamped: loads never depend on a branch
             const uint32_t key = skey[ic];
             ev[r] = sval[ic];
-            ee[r] = EXTRA ? sext[ic] : (SUMS ? touched[ev[r]] : 0u);
+            ee[r] = EXTRA ? sext[ic] : 0u;
+            if constexpr (SUMS) er[r] = rsrc[ev[r]];
             ek[r] = key;
             const uint32_t d = (key >> shift) & mask;
             dig[r] = d;
@@ -925,7 +931,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
                 const uint32_t l = wcnt[w][dig[r]] + rank[r];
                 lkey[l] = ek[r];
                 lval[l] = ev[r];
-                if (EXTRA || SUMS) lext[l] = ee[r];
+                if (EXTRA) lext[l] = ee[r];
+                if constexpr (SUMS) lrect[l] = er[r];
             }
         }
         __syncthreads();
@@ -937,7 +944,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
                 const uint32_t vv = lval[l];
                 dkey[pos] = k;
                 dval[pos] = vv;
-                if (EXTRA || SUMS) dext[pos] = lext[l];
+                if (EXTRA) dext[pos] = lext[l];
+                if constexpr (SUMS) rdst[pos] = lrect[l];
             }
         }
         __syncthreads();
@@ -990,7 +998,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
     const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext, Counters* cnt, int which,
     uint32_t cap, int shift, int bits, const uint32_t* __restrict__ ghist, unsigned long long* lookback,
-    uint32_t* ticket, uint32_t epoch_add, const uint32_t* __restrict__ touched) {
+    uint32_t* ticket, uint32_t epoch_add, const uint2* __restrict__ rsrc, uint2* __restrict__ rdst) {
     static_assert(SORT_THREADS == 256, "one thread per digit");
     constexpr int NW = SORT_THREADS / 64;
     constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
@@ -1000,7 +1008,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
     __shared__ uint32_t red[NW];
     __shared__ uint32_t lkey[SORT_CHUNK];
     __shared__ uint32_t lval[SORT_CHUNK];
-    __shared__ uint32_t lext[(EXTRA || SUMS) ? SORT_CHUNK : 1];
+    __shared__ uint32_t lext[EXTRA ? SORT_CHUNK : 1];
+    __shared__ uint2 lrect[SUMS ? SORT_CHUNK : 1];
     __shared__ uint32_t chunk_id;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t mask = (1u << bits) - 1u;
@@ -1020,6 +1029,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
     uint32_t tot_all;
     const uint32_t gstart = block_excl_scan<SORT_THREADS>(t <= (int)mask ? ghist[t] : 0u, red, &tot_all);
     uint32_t dig[ROUNDS], rank[ROUNDS], ek[ROUNDS], ev[ROUNDS], ee[ROUNDS];
+    uint2 er[ROUNDS];
     bool ok[ROUNDS];
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
@@ -1028,7 +1038,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
         const uint32_t ic = ok[r] ? idx : chunk;
         const uint32_t key = skey[ic];
         ev[r] = sval[ic];
-        ee[r] = EXTRA ? sext[ic] : (SUMS ? touched[ev[r]] : 0u);
+        ee[r] = EXTRA ? sext[ic] : 0u;
+        if constexpr (SUMS) er[r] = rsrc[ev[r]];
         ek[r] = key;
         const uint32_t d = (key >> shift) & mask;
         dig[r] = d;
@@ -1094,7 +1105,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
             const uint32_t l = wcnt[w][dig[r]] + rank[r];
             lkey[l] = ek[r];
             lval[l] = ev[r];
-            if (EXTRA || SUMS) lext[l] = ee[r];
+            if (EXTRA) lext[l] = ee[r];
+            if constexpr (SUMS) lrect[l] = er[r];
         }
     }
     __syncthreads();
@@ -1105,7 +1117,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
         if (pos < D) {
             dkey[pos] = k;
             dval[pos] = lval[l];
-            if (EXTRA || SUMS) dext[pos] = lext[l];
+            if (EXTRA) dext[pos] = lext[l];
+            if constexpr (SUMS) rdst[pos] = lrect[l];
         }
     }
 }
@@ -1507,12 +1520,12 @@ void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t
     TIGAS_LAUNCH(k_compact, dim3(nblk), dim3(K1_THREADS), st, o.touched, o.zkey, blk_off, key, val);
 }
 
-void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint32_t* sorted_touched,
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
                       uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
                       const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
                       hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_touched, cnt, blk_sum2);
+    TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_rect, cnt, blk_sum2);
     const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
     TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
                  (const uint32_t*)nullptr, (const uint32_t*)nullptr, o.chunk_dups, (unsigned long long*)nullptr,
@@ -1520,16 +1533,16 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
     TIGAS_LAUNCH(k_scan_dups, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
                  (const uint32_t*)o.chunk_dups, blk_off2);
     if (depth_out)
-        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const uint2*)o.bbox,
+        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
-        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_touched, (const uint2*)o.bbox,
+        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
 }
 
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, int totals_base, const uint32_t* touched,
-                uint32_t* blk_sum, hipStream_t st) {
+                int start, bool extra, const Counters* cnt, int totals_base, const uint2* rect_src,
+                uint2* rect_dst, hipStream_t st) {
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
@@ -1538,11 +1551,11 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
                      cap, ps.shift, ps.bits, b.hist, pre, nblocks);
         const int ndig = 1 << ps.bits;
         TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig);
-        const bool sums = touched && p + 1 == npasses;
+        const bool sums = rect_src && p + 1 == npasses;
 #define TIGAS_DOWN(E, S)                                                                                        \
     TIGAS_LAUNCH((k_sort_downsweep<E, S>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],      \
                  b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits, \
-                 (const uint32_t*)b.hist, nblocks, touched, blk_sum)
+                 (const uint32_t*)b.hist, nblocks, rect_src, rect_dst)
         if (extra && sums) TIGAS_DOWN(true, true);
         else if (extra) TIGAS_DOWN(true, false);
         else if (sums) TIGAS_DOWN(false, true);
@@ -1555,7 +1568,8 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
 
 int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
                          uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
-                         const uint32_t* touched, unsigned long long* lookback, uint32_t* tickets, hipStream_t st) {
+                         const uint2* rect_src, uint2* rect_dst, unsigned long long* lookback, uint32_t* tickets,
+                         hipStream_t st) {
     PassList pl{};
     pl.n = npasses;
     for (int p = 0; p < npasses; ++p) {
@@ -1569,12 +1583,12 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
-        const bool sums = touched && p + 1 == npasses;
+        const bool sums = rect_src && p + 1 == npasses;
 #define TIGAS_ONE(E, S)                                                                                            \
     TIGAS_LAUNCH((k_sort_onesweep<E, S>), dim3(grid), dim3(SORT_THREADS), st, b.key[cur], b.val[cur], b.ext[cur], \
                  b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits,               \
                  (const uint32_t*)(ghist + p * 256), lookback, tickets + totals_base + p,                        \
-                 (uint32_t)(totals_base + p), touched)
+                 (uint32_t)(totals_base + p), rect_src, rect_dst)
         if (extra && sums) TIGAS_ONE(true, true);
         else if (extra) TIGAS_ONE(true, false);
         else if (sums) TIGAS_ONE(false, true);

@@ -76,7 +76,8 @@ static_assert(sizeof(Rec) == 64, "record is one 64-byte segment");
 
 struct PreOut {
     Rec* rec;           // records (written only for Gaussians that touch a tile)
-    uint2* bbox;        // the records' pixel boxes again, densely (read by k_duplicate)
+    uint2* rect;        // per record: tile rectangle tx0 | ty0 << 16, nx | ny << 16 (0 when no tile)
+    uint2* srect;       // the visible records' tile rectangles in depth order (last depth pass)
     uint32_t* zkey;     // FP32 depth-key bits
     uint32_t* touched;  // tiles overlapped
     uint32_t* blk_sum;  // per 256-record block: sum of touched
@@ -128,23 +129,25 @@ void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st);
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st);
-void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint32_t* sorted_touched,
+void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
                       uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
                       const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
                       hipStream_t st);
 // Runs LSD passes over the count selected by `which` (0 duplicates, 1 visible)
 // starting in buffer `start`; returns the buffer index holding the result.
-// With `touched`, the last pass also writes touched[value] as the extra word.
+// With `rect_src`, the last pass also writes rect_src[value] to rect_dst in
+// sorted order.
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, int totals_base, const uint32_t* touched,
-                uint32_t* blk_sum, hipStream_t st);
+                int start, bool extra, const Counters* cnt, int totals_base, const uint2* rect_src,
+                uint2* rect_dst, hipStream_t st);
 // The same passes with one kernel each (look-back chained scan) after one
 // histogram kernel; tickets[totals_base + p] must be zero, lookback holds
 // 256 entries per 2048-key chunk of max_items (the most keys the count can
 // reach).
 int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
                          uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
-                         const uint32_t* touched, unsigned long long* lookback, uint32_t* tickets, hipStream_t st);
+                         const uint2* rect_src, uint2* rect_dst, unsigned long long* lookback, uint32_t* tickets,
+                         hipStream_t st);
 // host_cnt: pinned host memory that receives a copy of the counters.
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    hipStream_t st);
