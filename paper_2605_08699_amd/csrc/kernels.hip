@@ -772,44 +772,38 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
                                                                uint32_t* __restrict__ hist,
                                                                uint32_t* __restrict__ pre, int nb) {
     static_assert(SORT_THREADS == 256, "one thread per digit");
-    __shared__ uint32_t red[SORT_THREADS / 64];
-    __shared__ uint32_t h[SORT_THREADS / 64][256];
-    const int w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 256 * (SORT_THREADS / 64); i += SORT_THREADS) (&h[0][0])[i] = 0u;
+    // NH sub-histograms (one per wave and lane residue mod 4), rows of 257
+    // words so that the copies of one digit sit in different LDS banks: keys
+    // of one digit in one row of 64 (the leading depth digit is nearly
+    // constant) meet at most 16 to an address
+    constexpr int NW = SORT_THREADS / 64, NH = NW * 4, ROW = 257;
+    __shared__ uint32_t red[NW];
+    __shared__ uint32_t h[NH * ROW];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < NH * ROW; i += SORT_THREADS) h[i] = 0u;
     __syncthreads();
     uint32_t beg, end;
     segment(sort_count(cnt, which, cap), nb, blockIdx.x, &beg, &end);
     const uint32_t mask = (1u << bits) - 1u;
-    const uint64_t lt = (threadIdx.x & 63) == 0 ? 0ull : (~0ull >> (64 - (threadIdx.x & 63)));
-    // each wave walks blocks of 8 rows of 64 keys (8 loads in flight per
-    // lane); equal digits of a row are counted once by their leading lane
-    // (ballot match) instead of one LDS atomic per key
+    uint32_t* hrow = h + (w * 4 + (lane & 3)) * ROW;
+    // each wave walks blocks of 8 rows of 64 keys (8 loads in flight per lane)
     constexpr int U = 8;
     for (uint32_t blk = beg + (uint32_t)w * 64 * U; blk < end; blk += SORT_THREADS * U) {
         uint32_t kk[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = blk + u * 64 + (threadIdx.x & 63);
+            const uint32_t i = blk + u * 64 + lane;
             kk[u] = keys[i < end ? i : beg];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = blk + u * 64 + (threadIdx.x & 63) < end;
-            const uint32_t d = (kk[u] >> shift) & mask;
-            uint64_t m = ballot(ok);
-            for (int b = 0; b < bits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bl = ballot(bit);
-                m &= bit ? bl : ~bl;
-            }
-            if (ok && (m & lt) == 0) h[w][d] += (uint32_t)__builtin_popcountll(m);
-        }
+        for (int u = 0; u < U; ++u)
+            if (blk + u * 64 + lane < end) atomicAdd(&hrow[(kk[u] >> shift) & mask], 1u);
     }
     __syncthreads();
     const int t = threadIdx.x;
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < SORT_THREADS / 64; ++j) s += h[j][t];
+    for (int j = 0; j < NH; ++j) s += h[j * ROW + t];
     if (t > (int)mask) s = 0;
     uint32_t tot;
     const uint32_t e = block_excl_scan<SORT_THREADS>(s, red, &tot);
@@ -821,6 +815,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
 
 // One wave per digit: the digit's global start (the sum of the segments'
 // exclusive digit prefixes), then its exclusive offsets over the segments.
+template <int NJ>
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ pre,
                                                    int nb, int ndig) {
     const int lane = threadIdx.x & 63;
@@ -828,8 +823,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
     if (d >= ndig) return;  // whole wave exits together
     uint32_t* row = hist + (size_t)d * nb;
     const uint32_t* prow = pre + (size_t)d * nb;
-    constexpr int NJ = SORT_MAX_BLOCKS / 64;
-    uint32_t x[NJ];
+    uint32_t x[NJ];  // NJ * 64 >= nb
     uint32_t part = 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
@@ -1550,7 +1544,12 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
         TIGAS_LAUNCH(k_sort_upsweep, dim3(nblocks), dim3(SORT_THREADS), st, (const uint32_t*)b.key[cur], cnt, which,
                      cap, ps.shift, ps.bits, b.hist, pre, nblocks);
         const int ndig = 1 << ps.bits;
-        TIGAS_LAUNCH(k_sort_scan, dim3((ndig + 3) / 4), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig);
+        if (nblocks <= 1024)
+            TIGAS_LAUNCH(k_sort_scan<16>, dim3((ndig + 3) / 4), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks,
+                         ndig);
+        else
+            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 64>), dim3((ndig + 3) / 4), dim3(256), st, b.hist,
+                         (const uint32_t*)pre, nblocks, ndig);
         const bool sums = rect_src && p + 1 == npasses;
 #define TIGAS_DOWN(E, S)                                                                                        \
     TIGAS_LAUNCH((k_sort_downsweep<E, S>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],      \
