@@ -243,6 +243,20 @@ __device__ __forceinline__ void load_sh(const SceneView& s, int64_t n, int64_t g
     }
 }
 
+// Bit d set when the SH coefficients of degrees 0..d are all finite.
+__host__ __device__ constexpr int sh_degree_of(int i) {  // float i of the [16][3] coefficient block
+    return i < 3 ? 0 : i < 12 ? 1 : i < 27 ? 2 : 3;
+}
+template <int DEG>
+__device__ __forceinline__ uint32_t sh_finite(const float* k) {
+    uint32_t bad = 0;  // bit d: a coefficient of degree d is not finite
+#pragma unroll
+    for (int i = 0; i < 3 * (DEG + 1) * (DEG + 1); ++i)
+        bad |= __builtin_isfinite(k[i]) ? 0u : (1u << sh_degree_of(i));
+    // lowest bad degree b: degrees below b are fine
+    return (bad & (0u - bad)) - 1u;
+}
+
 template <int ST, int DEG>
 __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const ViewParams* __restrict__ views,
                                                            int nviews, uint32_t rec_base, uint32_t n_pad,
@@ -303,6 +317,8 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
 
     float k[48];
     bool sh_loaded = false;
+    uint32_t sh_fin = 0;  // bit d: the coefficients of degrees 0..d are all finite
+    bool sh_checked = false;
 
     for (int vi = 0; vi < nviews; ++vi) {
         const ViewParams& v = views[vi];
@@ -402,6 +418,20 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
                 const float dn = 1.0f / sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
                 float rgb[3];
                 sh_colour<DEG>(k, dx * dn, dy * dn, dz * dn, v.sh_degree, rgb);
+                if (!sh_checked) {  // once per Gaussian, where the loads have landed
+                    sh_fin = sh_finite<DEG>(k);
+                    sh_checked = true;
+                }
+                // a non-finite SH coefficient of the degree in use drops the
+                // Gaussian, as any other non-finite attribute does (and so
+                // does a colour that overflows): every record's colour is finite
+                const bool fin = ((sh_fin >> v.sh_degree) & 1u) && __builtin_isfinite(rgb[0]) &&
+                                 __builtin_isfinite(rgb[1]) && __builtin_isfinite(rgb[2]);
+                if (!fin) {
+                    touched = 0;
+                    fb = 0;
+                    tr = make_uint2(0u, 0u);
+                }
                 r0 = make_float4(u.hi, w.hi, u.lo, w.lo);
                 r1 = make_float4(-0.5f * LOG2E * ca, -LOG2E * cb, -0.5f * LOG2E * cc, L);
                 r2 = make_float4(rgb[0], rgb[1], rgb[2], op);
@@ -1334,10 +1364,12 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, in
                         n_eval += done[0] ? 0u : 1u;
                         n_contrib += acc ? 1u : 0u;
                     }
-                    const float wgt = alpha * t0;
-                    cr[0] = acc ? __builtin_fmaf(wgt, b.z, cr[0]) : cr[0];
-                    cg[0] = acc ? __builtin_fmaf(wgt, b.w, cg[0]) : cg[0];
-                    cb[0] = acc ? __builtin_fmaf(wgt, cz, cb[0]) : cb[0];
+                    // a weight of zero leaves the (finite) colour sums exactly
+                    // as they are, with one select instead of three
+                    const float wgt = acc ? alpha * t0 : 0.0f;
+                    cr[0] = __builtin_fmaf(wgt, b.z, cr[0]);
+                    cg[0] = __builtin_fmaf(wgt, b.w, cg[0]);
+                    cb[0] = __builtin_fmaf(wgt, cz, cb[0]);
                     T[0] = acc ? tn : t0;
                     done[0] = done[0] || stop;
                 }

@@ -135,16 +135,22 @@ def test_empty_scene_and_all_culled_render_background(ctx):
 
 
 def test_nan_and_zero_quaternion_are_dropped(ctx):
-    sc = make_scene([[0, 0, 3], [0.1, 0, 3], [0, 0.1, 3], [0, 0, 4]], log_scales=[[math.log(0.2)] * 3] * 4,
-                    logits=[2, 2, 2, 2], colors=[[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]])
+    sc = make_scene([[0, 0, 3], [0.1, 0, 3], [0, 0.1, 3], [0, 0, 4], [0.05, 0.05, 3], [-0.1, 0, 3.5],
+                     [0, -0.1, 3.5]], log_scales=[[math.log(0.2)] * 3] * 7,
+                    logits=[2] * 7, colors=[[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]] + [[0.5, 0.5, 0.5]] * 3,
+                    sh_degree=3)
     sc.quats[1] = 0
     sc.means[2, 1] = np.nan
     sc.log_scales[3, 0] = np.inf
+    sc.sh[4, 12, 1] = np.nan          # a degree-3 coefficient
+    sc.sh[5, 0, 2] = -np.inf          # the DC term
+    sc.opacity_logits[6] = np.inf
     s = ctx.load_scene(sc)
     k = intr(60, 16, 16)
     img = ctx.render(s, eye_pose(), k, 32, 32, fmt="f32")
     proj = orc.preprocess(sc, eye_pose(), k, 32, 32)
-    np.testing.assert_array_equal(proj.valid, [True, False, False, False])
+    np.testing.assert_array_equal(proj.valid, [True, False, False, False, False, False, False])
+    assert np.isfinite(img).all()
     br, nb = orc.render_frame(proj)
     res = gc.check_frame_pixels(img.reshape(-1, 3), br.reshape(-1, br.shape[2], 4), nb.reshape(-1))
     assert res["n_bad"] == 0, res
