@@ -636,7 +636,6 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
         launch_preprocess(g.scene->view, vdev + g.first_view, plan.views.data() + g.first_view, g.nviews,
                           g.rec_base, g.n_pad, (uint32_t)g.first_view, o, st);
     }
-    if (plan.nrec) launch_conic_fp64(o, vdev, st);
     mark(1);
     const int nblk = (int)(plan.nrec / K1_THREADS);
     Counters* cnt = ws.counters.as<Counters>();
@@ -686,7 +685,8 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
                             : launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
                                           sort_blocks(ws.dup_cap), cd, debug, cnt, 4, nullptr, nullptr, st);
     mark(4);
-    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.fs().host_counters.as<Counters>(), st);
+    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.fs().host_counters.as<Counters>(), o, vdev,
+                  st);
     mark(5);
     launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
                  plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, opt.cull, st);

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             float ca, cb, cc;
             if (!(det > ac * KAPPA_INV)) {
                 // near-singular 2D covariance: its conic is recomputed in FP64
-                // by k_conic_fp64 (listed below); a and c are sums of squares
+                // by conic_fp64 (listed below); a and c are sums of squares
                 // and exact enough for the footprint
                 ca = cb = cc = 0.0f;
                 fb = 1;
@@ -489,15 +489,13 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
     }
 }
 
-// Conic of the listed near-singular Gaussians, recomputed in FP64 from the
+// Conic of a listed near-singular Gaussian, recomputed in FP64 from the
 // FP32 inputs: Sigma2D, its determinant and its inverse; the exponent
-// coefficients of the record are overwritten (log2 opacity kept).
-__global__ __launch_bounds__(256) void k_conic_fp64(const uint2* __restrict__ list, Counters* cnt, uint32_t cap,
-                                                    const ViewParams* __restrict__ views,
-                                                    const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
-    const uint32_t n = min(cnt->fb_list, cap);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const uint2 e = list[i];
+// coefficients of the record are overwritten (log2 opacity kept).  Run by
+// k_ranges: nothing between preprocess and the blend reads the coefficients.
+__device__ void conic_fp64(const uint2 e, const ViewParams* __restrict__ views, const uint32_t* __restrict__ blk_view,
+                           Rec* __restrict__ recs) {
+    {
         const uint32_t rec = e.x;
         const int64_t g = e.y;
         const ViewParams& v = views[blk_view[rec / K1_THREADS]];
@@ -640,7 +638,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
             cnt->visible = (uint32_t)V;
             cnt->fallbacks = (uint32_t)F;
             cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
-            cnt->fb_list = 0u;  // consumed by k_conic_fp64, which ran before this kernel
+            cnt->fb_listed = cnt->fb_list;  // every preprocess launch has appended
+            cnt->fb_list = 0u;                // the next frame appends from zero
             cnt->epoch += MAX_SORT_PASSES;  // look-back entries of earlier frames never match
             cnt->error = 0u;
         }
@@ -1154,7 +1153,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
 // are final here: one thread also stores them to the host-visible block the
 // host reads after the frame (no separate copy).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tile, const Counters* __restrict__ cnt,
-                                                uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt) {
+                                                uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt,
+                                                const uint2* __restrict__ fb_list, uint32_t fb_cap,
+                                                const ViewParams* __restrict__ views,
+                                                const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t D = sort_count(cnt, 0, cap);
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < D; i += gridDim.x * 256) {
@@ -1162,6 +1164,10 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ til
         if (i == 0 || tile[i - 1] != t) ranges[t].x = i;
         if (i + 1 == D || tile[i + 1] != t) ranges[t].y = i + 1;
     }
+    // the FP64 conics of the near-singular Gaussians (a few hundred per frame)
+    const uint32_t nfb = min(cnt->fb_listed, fb_cap);
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nfb; i += gridDim.x * 256)
+        conic_fp64(fb_list[i], views, blk_view, recs);
 }
 
 // ------------------------------------------------------------------- blend
@@ -1526,10 +1532,6 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
     else preprocess_deg<2>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
 }
 
-void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t st) {
-    TIGAS_LAUNCH(k_conic_fp64, dim3(64), dim3(256), st, (const uint2*)o.fb_list, o.cnt, o.fb_cap, views_dev,
-                 (const uint32_t*)o.blk_view, o.rec);
-}
 
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st) {
@@ -1631,11 +1633,12 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
 }
 
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
-                   hipStream_t st) {
+                   const PreOut& o, const ViewParams* views_dev, hipStream_t st) {
     // a few elements per thread at most, but no more workgroups than a large
     // frame needs (the capacity may have been sized by a much larger frame)
     TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(16384u, std::max<uint32_t>(1u, (cap + 255) / 256))), dim3(256), st,
-                 tile_sorted, cnt, cap, ranges, host_cnt);
+                 tile_sorted, cnt, cap, ranges, host_cnt, (const uint2*)o.fb_list, o.fb_cap, views_dev,
+                 (const uint32_t*)o.blk_view, o.rec);
 }
 
 template <int TW, int TH, int BD, int PPL>

@@ -55,10 +55,10 @@ struct Counters {
     uint32_t visible;
     uint32_t fallbacks;
     uint32_t overflow;  // D exceeded the duplicate capacity: nothing was emitted
-    uint32_t fb_list;   // entries in the FP64-fallback list (cleared after use)
+    uint32_t fb_list;   // append cursor of the FP64-fallback list (cleared once counted)
     uint32_t epoch;     // advanced every frame: tags the single-pass sort's look-back entries
     uint32_t error;     // a bounded wait of the single-pass sort timed out (frame must be redone)
-    uint32_t pad;
+    uint32_t fb_listed; // entries in the FP64-fallback list this frame
 };
 
 // Preprocess outputs, one slot per record (record = view-local index of a
@@ -123,9 +123,6 @@ struct SortPass {
 // ---- launchers (kernels.hip) ----
 void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
                        uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
-// Recomputes, in FP64, the conic of every Gaussian preprocess listed as
-// near-singular (one launch after all preprocess launches of a frame).
-void launch_conic_fp64(const PreOut& o, const ViewParams* views_dev, hipStream_t st);
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st);
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st);
@@ -148,9 +145,11 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
                          uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
                          const uint2* rect_src, uint2* rect_dst, unsigned long long* lookback, uint32_t* tickets,
                          hipStream_t st);
-// host_cnt: pinned host memory that receives a copy of the counters.
+// Tile ranges of the sorted list; the same launch recomputes, in FP64, the
+// conic of every Gaussian preprocess listed as near-singular.  host_cnt:
+// pinned host memory that receives a copy of the counters.
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
-                   hipStream_t st);
+                   const PreOut& o, const ViewParams* views_dev, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
                   int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st);
