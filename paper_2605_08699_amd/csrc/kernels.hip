@@ -662,39 +662,52 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_dups(const uint32_t* __re
     scan_chunk(blk_sum, nblk, tot, blk_off, red, red64, stage);
 }
 
-// Visible records, in record order, as (depth key, record) pairs.
+// Visible records, in record order, as (depth key, record) pairs.  Four
+// records per thread (16-byte loads): a workgroup covers four preprocess
+// blocks, whose first compaction offset it starts from.
 __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restrict__ touched,
                                                         const uint32_t* __restrict__ zkey,
-                                                        const uint32_t* __restrict__ blk_off,
+                                                        const uint32_t* __restrict__ blk_off, int nblk,
                                                         uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
     __shared__ uint32_t red[K1_THREADS / 64];
-    const uint32_t rec = blockIdx.x * K1_THREADS + threadIdx.x;
-    const bool vis = touched[rec] != 0u;
+    const uint32_t nrec = (uint32_t)nblk * K1_THREADS;  // a multiple of 4
+    const uint32_t r0 = (blockIdx.x * K1_THREADS + threadIdx.x) * 4u;
+    uint4 t = make_uint4(0u, 0u, 0u, 0u), z = t;
+    if (r0 < nrec) {
+        t = *reinterpret_cast<const uint4*>(touched + r0);
+        z = *reinterpret_cast<const uint4*>(zkey + r0);
+    }
+    const uint32_t c = (t.x != 0u) + (t.y != 0u) + (t.z != 0u) + (t.w != 0u);
     uint32_t tot;
-    const uint32_t ex = block_excl_scan<K1_THREADS>(vis ? 1u : 0u, red, &tot);
-    if (vis) {
-        const uint32_t pos = blk_off[blockIdx.x] + ex;
-        key[pos] = zkey[rec];
-        val[pos] = rec;
+    const uint32_t ex = block_excl_scan<K1_THREADS>(c, red, &tot);
+    if (c) {
+        uint32_t pos = blk_off[blockIdx.x * 4] + ex;
+        if (t.x) { key[pos] = z.x; val[pos] = r0; ++pos; }
+        if (t.y) { key[pos] = z.y; val[pos] = r0 + 1; ++pos; }
+        if (t.z) { key[pos] = z.z; val[pos] = r0 + 2; ++pos; }
+        if (t.w) { key[pos] = z.w; val[pos] = r0 + 3; }
     }
 }
 
 // Tiles in a tile rectangle (tx0 | ty0 << 16, nx | ny << 16).
 __device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
-// Per 256 depth-sorted visible Gaussians: the sum of their tile counts.
+// Per 256 depth-sorted visible Gaussians: the sum of their tile counts (zero
+// past the visible count); workgroups stride over the nblk blocks.
 __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint2* __restrict__ sorted_rect,
-                                                            const Counters* __restrict__ cnt,
+                                                            const Counters* __restrict__ cnt, int nblk,
                                                             uint32_t* __restrict__ blk_sum) {
     __shared__ uint32_t red[K1_THREADS / 64];
-    const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
     const uint32_t V = cnt->visible;
-    if (blockIdx.x * K1_THREADS >= V) {  // uniform: empty block
-        if (threadIdx.x == 0) blk_sum[blockIdx.x] = 0u;
-        return;
+    for (uint32_t b = blockIdx.x; b < (uint32_t)nblk; b += gridDim.x) {
+        if (b * K1_THREADS >= V) {  // uniform: empty block
+            if (threadIdx.x == 0) blk_sum[b] = 0u;
+            continue;
+        }
+        const uint32_t i = b * K1_THREADS + threadIdx.x;
+        const uint32_t s = block_sum<K1_THREADS>(i < V ? rect_tiles(sorted_rect[i]) : 0u, red);
+        if (threadIdx.x == 0) blk_sum[b] = s;
     }
-    const uint32_t s = block_sum<K1_THREADS>(i < V ? rect_tiles(sorted_rect[i]) : 0u, red);
-    if (threadIdx.x == 0) blk_sum[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------- duplicate
@@ -1159,10 +1172,34 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ til
                                                 const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t D = sort_count(cnt, 0, cap);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < D; i += gridDim.x * 256) {
-        const uint32_t t = tile[i];
-        if (i == 0 || tile[i - 1] != t) ranges[t].x = i;
-        if (i + 1 == D || tile[i + 1] != t) ranges[t].y = i + 1;
+    // each wave takes 256 consecutive words per step, four per lane (one
+    // 16-byte load); neighbours come from the adjacent lanes, and across the
+    // step's edges from one extra load
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwaves = gridDim.x * 4u;
+    for (uint32_t c = ((blockIdx.x * 256u + threadIdx.x) >> 6) * 256u; c < D; c += nwaves * 256u) {
+        const uint32_t i0 = c + (uint32_t)lane * 4u;
+        uint32_t e[4];
+        if (i0 + 3u < D) {
+            const uint4 q = *reinterpret_cast<const uint4*>(tile + i0);
+            e[0] = q.x; e[1] = q.y; e[2] = q.z; e[3] = q.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e[k] = i0 + k < D ? tile[i0 + k] : 0xffffffffu;
+        }
+        uint32_t prev = __shfl_up(e[3], 1, 64), next = __shfl_down(e[0], 1, 64);
+        if (lane == 0) prev = c > 0u ? tile[c - 1u] : 0xffffffffu;
+        if (lane == 63) next = c + 256u < D ? tile[c + 256u] : 0xffffffffu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = i0 + (uint32_t)k;
+            if (i < D) {
+                const uint32_t t = e[k];
+                const uint32_t p = k > 0 ? e[k - 1] : prev, n = k < 3 ? e[k + 1] : next;
+                if (i == 0u || p != t) ranges[t].x = i;
+                if (i + 1u == D || n != t) ranges[t].y = i + 1u;
+            }
+        }
     }
     // the FP64 conics of the near-singular Gaussians (a few hundred per frame)
     const uint32_t nfb = min(cnt->fb_listed, fb_cap);
@@ -1545,7 +1582,7 @@ void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters*
 
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_compact, dim3(nblk), dim3(K1_THREADS), st, o.touched, o.zkey, blk_off, key, val);
+    TIGAS_LAUNCH(k_compact, dim3((nblk + 3) / 4), dim3(K1_THREADS), st, o.touched, o.zkey, blk_off, nblk, key, val);
 }
 
 void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
@@ -1553,7 +1590,7 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
                       const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
                       hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_sorted_sums, dim3(nblk), dim3(K1_THREADS), st, sorted_rect, cnt, blk_sum2);
+    TIGAS_LAUNCH(k_sorted_sums, dim3(std::min(nblk, 8192)), dim3(K1_THREADS), st, sorted_rect, cnt, nblk, blk_sum2);
     const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
     TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
                  (const uint32_t*)nullptr, (const uint32_t*)nullptr, o.chunk_dups, (unsigned long long*)nullptr,
@@ -1634,9 +1671,10 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
 
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    const PreOut& o, const ViewParams* views_dev, hipStream_t st) {
-    // a few elements per thread at most, but no more workgroups than a large
-    // frame needs (the capacity may have been sized by a much larger frame)
-    TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(16384u, std::max<uint32_t>(1u, (cap + 255) / 256))), dim3(256), st,
+    // one 1024-word step per workgroup at capacity, but no more workgroups
+    // than a large frame needs (the capacity may have been sized by a much
+    // larger frame)
+    TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(16384u, std::max<uint32_t>(1u, (cap + 1023) / 1024))), dim3(256), st,
                  tile_sorted, cnt, cap, ranges, host_cnt, (const uint2*)o.fb_list, o.fb_cap, views_dev,
                  (const uint32_t*)o.blk_view, o.rec);
 }
