@@ -265,7 +265,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     std::mutex mu;  // one launch sequence at a time per workspace
     // per record
-    DevBuf recs, rect, srect, zkey, touched;
+    DevBuf recs, rect, srect, zkey;
     DevBuf blk_sum, blk_vis, blk_fb, blk_view, blk_off, blk_sum2, blk_off2;
     DevBuf fb_list;  // near-singular Gaussians for the FP64 conic kernel
     DevBuf chunk_vis, chunk_dup, chunk_fb, chunk_dups;  // totals per chunk of block counts
@@ -298,7 +298,6 @@ struct Workspace {
         o.rect = rect.as<uint2>();
         o.srect = srect.as<uint2>();
         o.zkey = zkey.as<uint32_t>();
-        o.touched = touched.as<uint32_t>();
         o.blk_sum = blk_sum.as<uint32_t>();
         o.blk_vis = blk_vis.as<uint32_t>();
         o.blk_fb = blk_fb.as<uint32_t>();
@@ -322,7 +321,6 @@ struct Workspace {
         grow(rect, r * 8);
         grow(srect, r * 8);
         grow(zkey, r * 4);
-        grow(touched, r * 4);
         const size_t nb = r / K1_THREADS + 1;
         for (DevBuf* b : {&blk_sum, &blk_vis, &blk_fb, &blk_view, &blk_off, &blk_sum2, &blk_off2}) grow(*b, nb * 4);
         grow(fb_list, r * 8);
@@ -658,18 +656,23 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     }
     sb.hist = ws.hist.as<uint32_t>();
     sb.totals = ws.totals.as<uint32_t>();
-    // depth digits, on the visible Gaussians (record order in, depth order out)
-    launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], st);
+    // depth digits, on the visible Gaussians (record order in, depth order
+    // out); the tile rectangles travel packed with them when every view has
+    // at most 256 x 256 tiles, else the last pass gathers them
+    bool packed = true;
+    for (const ViewParams& v : plan.views) packed = packed && v.tiles_x <= 256 && v.tiles_y <= 256;
+    launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, st);
     unsigned long long* lb = ws.lookback.as<unsigned long long>();
     uint32_t* tickets = ws.queue.as<uint32_t>() + 8;
     const int cv = onepass ? launch_sort_onesweep(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap,
-                                                  std::min(plan.nrec, ws.dup_cap), 0, false, cnt, 0, o.rect, o.srect, lb,
+                                                  std::min(plan.nrec, ws.dup_cap), 0, packed, cnt, 0,
+                                                  packed ? nullptr : o.rect, packed ? nullptr : o.srect, lb,
                                                   tickets, st)
                            : launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0,
-                                         false, cnt, 0, o.rect, o.srect, st);
+                                         packed, cnt, 0, packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
     // duplicates in depth order
     const int cd = cv ^ 1;
-    launch_duplicate(o, nblk, sb.val[cv], o.srect, ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
+    launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
                      ws.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
     mark(3);
     if (debug) {
@@ -1143,9 +1146,12 @@ void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_
             r[8] = z.x; r[9] = z.y; r[10] = z.z; r[11] = z.w;
         }
     }
-    std::vector<uint32_t> touched(n_pad);
-    if (n_pad) HIPCHK(hipMemcpyAsync(touched.data(), ws.touched.p, 4 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
+    // tiles touched per record, from the tile rectangles
+    std::vector<uint2> rect(n_pad);
+    if (n_pad) HIPCHK(hipMemcpyAsync(rect.data(), ws.rect.p, 8 * (size_t)n_pad, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    std::vector<uint32_t> touched(n_pad);
+    for (uint32_t i = 0; i < n_pad; ++i) touched[i] = (rect[i].y & 0xffffu) * (rect[i].y >> 16);
     if (dbg->touched && n) std::memcpy(dbg->touched, touched.data(), 4 * (size_t)n);
     if (dbg->zkey && n) HIPCHK(hipMemcpyAsync(dbg->zkey, ws.zkey.p, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
     if (dbg->bbox) {

@@ -451,7 +451,6 @@ __global__ __launch_bounds__(K1_THREADS) void k_preprocess(SceneView s, const Vi
             }
         }
         o.zkey[rec] = __float_as_uint(z32);
-        o.touched[rec] = touched;
         if (touched) {
             Rec out;
             out.r0 = r0;
@@ -662,30 +661,53 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_dups(const uint32_t* __re
     scan_chunk(blk_sum, nblk, tot, blk_off, red, red64, stage);
 }
 
-// Visible records, in record order, as (depth key, record) pairs.  Four
-// records per thread (16-byte loads): a workgroup covers four preprocess
-// blocks, whose first compaction offset it starts from.
-__global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restrict__ touched,
-                                                        const uint32_t* __restrict__ zkey,
+// Tile rectangle (tx0 | ty0 << 16, nx | ny << 16) packed into one word as
+// tx0 | ty0 << 8 | tx1 << 16 | ty1 << 24 (views of at most 256 x 256 tiles),
+// and back.
+__device__ __forceinline__ uint32_t pack_rect(uint2 r) {
+    const uint32_t tx0 = r.x & 0xffffu, ty0 = r.x >> 16;
+    return tx0 | (ty0 << 8) | ((tx0 + (r.y & 0xffffu) - 1u) << 16) | ((ty0 + (r.y >> 16) - 1u) << 24);
+}
+__device__ __forceinline__ uint2 unpack_rect(uint32_t p) {
+    const uint32_t tx0 = p & 0xffu, ty0 = (p >> 8) & 0xffu, tx1 = (p >> 16) & 0xffu, ty1 = p >> 24;
+    return make_uint2(tx0 | (ty0 << 16), (tx1 - tx0 + 1u) | ((ty1 - ty0 + 1u) << 16));
+}
+
+// Visible records, in record order, as (depth key, record) pairs, and with
+// `ext` the packed tile rectangle as a third word that the depth passes carry
+// along.  Four records per thread (16-byte loads): a workgroup covers four
+// preprocess blocks, whose first compaction offset it starts from.
+__global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restrict__ zkey,
+                                                        const uint2* __restrict__ rect,
                                                         const uint32_t* __restrict__ blk_off, int nblk,
-                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                        uint32_t* __restrict__ ext) {
     __shared__ uint32_t red[K1_THREADS / 64];
     const uint32_t nrec = (uint32_t)nblk * K1_THREADS;  // a multiple of 4
     const uint32_t r0 = (blockIdx.x * K1_THREADS + threadIdx.x) * 4u;
-    uint4 t = make_uint4(0u, 0u, 0u, 0u), z = t;
-    if (r0 < nrec) {
-        t = *reinterpret_cast<const uint4*>(touched + r0);
+    uint4 z = make_uint4(0u, 0u, 0u, 0u), ra = z, rb = z;
+    if (r0 < nrec) {  // a record is visible when its rectangle has tiles
         z = *reinterpret_cast<const uint4*>(zkey + r0);
+        ra = *reinterpret_cast<const uint4*>(rect + r0);
+        rb = *reinterpret_cast<const uint4*>(rect + r0 + 2);
     }
-    const uint32_t c = (t.x != 0u) + (t.y != 0u) + (t.z != 0u) + (t.w != 0u);
+    const bool v0 = ra.y != 0u, v1 = ra.w != 0u, v2 = rb.y != 0u, v3 = rb.w != 0u;
+    const uint32_t c = (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2 + (uint32_t)v3;
     uint32_t tot;
     const uint32_t ex = block_excl_scan<K1_THREADS>(c, red, &tot);
     if (c) {
         uint32_t pos = blk_off[blockIdx.x * 4] + ex;
-        if (t.x) { key[pos] = z.x; val[pos] = r0; ++pos; }
-        if (t.y) { key[pos] = z.y; val[pos] = r0 + 1; ++pos; }
-        if (t.z) { key[pos] = z.z; val[pos] = r0 + 2; ++pos; }
-        if (t.w) { key[pos] = z.w; val[pos] = r0 + 3; }
+        if (ext) {
+            if (v0) { key[pos] = z.x; val[pos] = r0; ext[pos] = pack_rect(make_uint2(ra.x, ra.y)); ++pos; }
+            if (v1) { key[pos] = z.y; val[pos] = r0 + 1; ext[pos] = pack_rect(make_uint2(ra.z, ra.w)); ++pos; }
+            if (v2) { key[pos] = z.z; val[pos] = r0 + 2; ext[pos] = pack_rect(make_uint2(rb.x, rb.y)); ++pos; }
+            if (v3) { key[pos] = z.w; val[pos] = r0 + 3; ext[pos] = pack_rect(make_uint2(rb.z, rb.w)); }
+        } else {
+            if (v0) { key[pos] = z.x; val[pos] = r0; ++pos; }
+            if (v1) { key[pos] = z.y; val[pos] = r0 + 1; ++pos; }
+            if (v2) { key[pos] = z.z; val[pos] = r0 + 2; ++pos; }
+            if (v3) { key[pos] = z.w; val[pos] = r0 + 3; }
+        }
     }
 }
 
@@ -693,8 +715,10 @@ __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restri
 __device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu) * (r.y >> 16); }
 
 // Per 256 depth-sorted visible Gaussians: the sum of their tile counts (zero
-// past the visible count); workgroups stride over the nblk blocks.
+// past the visible count); workgroups stride over the nblk blocks.  The
+// rectangles come packed (sorted_packed) or as two words (sorted_rect).
 __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint2* __restrict__ sorted_rect,
+                                                            const uint32_t* __restrict__ sorted_packed,
                                                             const Counters* __restrict__ cnt, int nblk,
                                                             uint32_t* __restrict__ blk_sum) {
     __shared__ uint32_t red[K1_THREADS / 64];
@@ -705,7 +729,9 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint2* __restr
             continue;
         }
         const uint32_t i = b * K1_THREADS + threadIdx.x;
-        const uint32_t s = block_sum<K1_THREADS>(i < V ? rect_tiles(sorted_rect[i]) : 0u, red);
+        uint32_t t = 0;
+        if (i < V) t = rect_tiles(sorted_packed ? unpack_rect(sorted_packed[i]) : sorted_rect[i]);
+        const uint32_t s = block_sum<K1_THREADS>(t, red);
         if (threadIdx.x == 0) blk_sum[b] = s;
     }
 }
@@ -720,6 +746,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_sorted_sums(const uint2* __restr
 template <bool DEPTH>
 __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __restrict__ sorted_rec,
                                                           const uint2* __restrict__ sorted_rect,
+                                                          const uint32_t* __restrict__ sorted_packed,
                                                           const uint32_t* __restrict__ zkey,
                                                           const uint32_t* __restrict__ blk_off,
                                                           const uint32_t* __restrict__ blk_view,
@@ -739,7 +766,9 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     uint2 tr = make_uint2(0u, 0u);
     if (i < V) {
         rec = sorted_rec[i];
-        tr = sorted_rect[i];  // tile rectangle, gathered into depth order by the last depth pass
+        // tile rectangle in depth order: carried packed through the depth
+        // passes, or gathered by the last one
+        tr = sorted_packed ? unpack_rect(sorted_packed[i]) : sorted_rect[i];
         t = rect_tiles(tr);
     }
     uint32_t tot;
@@ -1580,17 +1609,21 @@ void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters*
                  nchunks, blk_off, cnt, cap, zl);
 }
 
-void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st) {
+void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, uint32_t* ext,
+                    hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_compact, dim3((nblk + 3) / 4), dim3(K1_THREADS), st, o.touched, o.zkey, blk_off, nblk, key, val);
+    TIGAS_LAUNCH(k_compact, dim3((nblk + 3) / 4), dim3(K1_THREADS), st, o.zkey, (const uint2*)o.rect,
+                 blk_off, nblk, key, val, ext);
 }
 
 void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
+                      const uint32_t* sorted_packed,
                       uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
                       const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
                       hipStream_t st) {
     if (nblk == 0) return;
-    TIGAS_LAUNCH(k_sorted_sums, dim3(std::min(nblk, 8192)), dim3(K1_THREADS), st, sorted_rect, cnt, nblk, blk_sum2);
+    TIGAS_LAUNCH(k_sorted_sums, dim3(std::min(nblk, 8192)), dim3(K1_THREADS), st, sorted_rect, sorted_packed, cnt, nblk,
+                 blk_sum2);
     const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
     TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
                  (const uint32_t*)nullptr, (const uint32_t*)nullptr, o.chunk_dups, (unsigned long long*)nullptr,
@@ -1598,10 +1631,10 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
     TIGAS_LAUNCH(k_scan_dups, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
                  (const uint32_t*)o.chunk_dups, blk_off2);
     if (depth_out)
-        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect,
+        TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect, sorted_packed,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
-        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect,
+        TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect, sorted_packed,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
 }
 

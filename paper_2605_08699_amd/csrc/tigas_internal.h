@@ -76,10 +76,10 @@ static_assert(sizeof(Rec) == 64, "record is one 64-byte segment");
 
 struct PreOut {
     Rec* rec;           // records (written only for Gaussians that touch a tile)
-    uint2* rect;        // per record: tile rectangle tx0 | ty0 << 16, nx | ny << 16 (0 when no tile)
+    uint2* rect;        // per record: tile rectangle tx0 | ty0 << 16, nx | ny << 16 (0 when no tile;
+                        // a record is visible when nx ny > 0)
     uint2* srect;       // the visible records' tile rectangles in depth order (last depth pass)
     uint32_t* zkey;     // FP32 depth-key bits
-    uint32_t* touched;  // tiles overlapped
     uint32_t* blk_sum;  // per 256-record block: sum of touched
     uint32_t* blk_vis;  // per block: records with touched > 0
     uint32_t* blk_fb;   // per block: FP64 fallbacks
@@ -125,8 +125,14 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
                        uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st);
-void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, hipStream_t st);
+// Visible records as (depth key, record) pairs; with ext, also each one's
+// tile rectangle packed into one word (views of at most 256 x 256 tiles).
+void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, uint32_t* ext,
+                    hipStream_t st);
+// The depth-ordered tile rectangles come packed (sorted_packed, carried by the
+// depth passes) or, when that is null, as two words (sorted_rect).
 void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
+                      const uint32_t* sorted_packed,
                       uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
                       const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
                       hipStream_t st);

@@ -121,6 +121,31 @@ def test_ragged_and_tiny_images(ctx, size):
         assert res["n_bad"] == 0, res
 
 
+@pytest.mark.parametrize("size", [(2048, 24), (2072, 24), (24, 2072)])
+def test_wide_views_both_rectangle_encodings(ctx, size):
+    # up to 256 x 256 tiles a view's tile rectangles travel packed in one word
+    # through the depth passes; beyond that (here 259 tiles of 8 px) the last
+    # depth pass gathers them: lists and pixels must match either way
+    W, H = size
+    rng = np.random.default_rng(W + 7 * H)
+    scene = random_tiny_scene(rng, n=400, extent=1.0)
+    axis = 0 if W > H else 1
+    scene.means[:, axis] *= 7.0
+    k = intr(700.0, W / 2, H / 2)
+    s = ctx.load_scene(scene)
+    _say("wide", size)
+    dbg = ctx.render_debug(s, eye_pose(), k, W, H, tile=(8, 8))
+    gc.check_tiles(dbg, 8, 8)
+    proj = orc.preprocess(scene, eye_pose(), k, W, H)
+    gc.check_preprocess(dbg, proj, W, H)
+    br, nb = orc.render_frame(proj)
+    res = gc.check_frame_pixels(dbg["image"].reshape(-1, 3), br.reshape(-1, br.shape[2], 4), nb.reshape(-1))
+    assert res["n_bad"] == 0, res
+    assert dbg["n_dup"] > 0
+    if max(W, H) > 2048:  # Gaussians reach the tiles past 255
+        assert dbg["bbox"][:, 2 + axis].max() >= 2048
+
+
 def test_empty_scene_and_all_culled_render_background(ctx):
     bg = (0.25, 0.5, 0.75)
     empty = make_scene(np.zeros((0, 3)))
