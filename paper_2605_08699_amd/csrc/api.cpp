@@ -167,8 +167,9 @@ struct TileCfg {
     int tw, th, bd, ppl;  // tile width/height, staged entries per wave batch, pixels per lane
 };
 
-const TileCfg kTileCandidates[] = {{8, 8, 64, 1},   {8, 8, 128, 1},   {16, 16, 64, 1}, {16, 16, 64, 2},
-                                   {16, 16, 128, 2}, {16, 32, 64, 1}, {16, 32, 64, 2}, {16, 32, 128, 2},
+const TileCfg kTileCandidates[] = {{8, 8, 64, 1},    {8, 8, 128, 1},   {16, 16, 64, 1},  {16, 16, 128, 1},
+                                   {16, 16, 64, 2},  {16, 16, 128, 2}, {16, 32, 64, 1},  {16, 32, 128, 1},
+                                   {16, 32, 64, 2},  {16, 32, 128, 2}, {32, 16, 64, 1},  {32, 16, 128, 1},
                                    {32, 16, 64, 2}};
 
 // A group of views of one scene inside a launch sequence.
@@ -932,8 +933,8 @@ void save_tune_file(tigas_context* ctx) {
 }
 
 // Picks the tile shape and batch depth for the plan's shape: each candidate
-// is rendered (graph captured, one warm-up) and timed over a few replays; the
-// fastest is cached per shape (and in the file named by TIGAS_TUNE_CACHE).
+// is rendered (graph captured, two warm-ups) and timed by the median of seven
+// replays; the fastest is cached per shape (and in the file named by TIGAS_TUNE_CACHE).
 // Frames are identical for every candidate, so tuning changes only speed.
 TileCfg autotune(tigas_context* ctx, Workspace& ws, Plan& plan) {
     const std::string key = shape_key(plan, false) + (plan.persistent ? "|P" : "|G");
@@ -948,15 +949,16 @@ TileCfg autotune(tigas_context* ctx, Workspace& ws, Plan& plan) {
     for (const TileCfg& tc : kTileCandidates) {
         set_tiles(plan, tc);
         run_plan(ctx, ws, plan, false);  // capture + warm
-        double t_min = 1e30;
-        for (int r = 0; r < 5; ++r) {
+        run_plan(ctx, ws, plan, false);
+        double ts[7];
+        for (double& t : ts) {
             const auto t0 = std::chrono::steady_clock::now();
             run_plan(ctx, ws, plan, false);
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            t_min = std::min(t_min, ms);
+            t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
-        if (t_min < best_ms) {
-            best_ms = t_min;
+        std::sort(ts, ts + 7);
+        if (ts[3] < best_ms) {  // median: one slow or lucky replay does not decide
+            best_ms = ts[3];
             best = tc;
         }
     }
