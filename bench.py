@@ -218,9 +218,10 @@ def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.
 
 
 def kernel_work(name, w, n, storage, tile_passes):
-    """Algorithmic work of ONE launch of a kernel, averaged over the frames of
-    the work pass: (bound, amount, unit) with bytes for HBM-bound kernels and
-    FP32 flops for the blend, or None for a kernel without a model."""
+    """Algorithmic work of a kernel per FRAME (all its launches of the frame),
+    averaged over the frames of the work pass: (bound, amount) with bytes for
+    HBM-bound kernels and FP32 flops for the blend, or None for a kernel
+    without a model."""
     nf = max(w["frames"], 1)
     D = w["duplicates"] / nf
     V = w["visible"] / nf
@@ -228,18 +229,20 @@ def kernel_work(name, w, n, storage, tile_passes):
         return "alu", (FLOPS_EVAL * w["evaluations"] + FLOPS_CONTRIB * w["contributions"]) / nf
     if "k_preprocess" in name:
         # attributes of every Gaussian, SH of the visible ones, depth key +
-        # touched count of every record, three float4 records + box per visible
+        # tile rectangle of every record, one 64-byte record per visible
         attr = 44 if storage == "f32" else 28
         shb = 192 if storage == "f32" else 96
-        return "hbm", n * attr + V * shb + n * 8 + V * 56
+        return "hbm", n * attr + V * shb + n * 12 + V * 64
     if "k_duplicate" in name:
-        # sorted record id, sorted touched count and box per visible Gaussian;
-        # tile key + record id per duplicate
-        return "hbm", V * 16 + D * 8
+        # sorted record id and packed tile rectangle per visible Gaussian;
+        # tile word + record id per duplicate
+        return "hbm", V * 8 + D * 8
+    if "k_sort_downsweep<true, false>" in name or "k_sort_onesweep<true, false>" in name:
+        # the 4 depth passes: key, record and packed rectangle read and written
+        return "hbm", 4 * 24 * V
     if "k_sort_downsweep<false, false>" in name or "k_sort_onesweep<false, false>" in name:
-        # key + value read and written per element; 3 depth passes over the
-        # visible Gaussians and the tile passes over the duplicates, per launch
-        return "hbm", 16 * (3 * V + tile_passes * D) / (3 + tile_passes)
+        # the tile passes: key + value read and written per duplicate
+        return "hbm", tile_passes * 16 * D
     return None
 
 
