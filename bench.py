@@ -159,7 +159,7 @@ def run_batched(ctx, scene, torch, steps=30, warmup=3):
                 tiles=st["tiles"])
 
 
-def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0), budget_gb=48,
+def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0, 50.0), budget_gb=48,
                 batch_mpx=6.0):
     """The serving form: 64 clients (Poisson arrivals, random rungs of
     1920x1080, their own 6DoF walks) on 4 resident FP16 scenes of 0.5/1/3/6M
