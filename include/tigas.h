@@ -349,6 +349,29 @@ tigas_status tigas_render_debug(tigas_scene* scene, const tigas_pose* pose, cons
                                 int width, int height, const tigas_quality* q, tigas_frame* out,
                                 tigas_debug_out* dbg);
 
+/* Baseline JPEG of an RGB8 frame in device memory: the per-frame payload of
+ * the paper's transport (Section 3: one stateless JPEG per request), at a
+ * quality factor of its bitrate ladder (Table 1: 10, 35, 65, 90).  Format:
+ * JFIF, YCbCr 4:4:4, the Annex K quantisation tables of ITU-T T.81 scaled by
+ * quality (5000/q percent below 50, else 200 - 2q, clamped to 1..255) and its
+ * Annex K Huffman tables, one restart interval per row of 8x8 blocks.
+ *   rgb: device pointer, `height` rows of 3 * `width` bytes, top row first (the
+ *        RGB8 layout tigas_render writes); width 1..4096, height 1..65535;
+ *   quality: 1..100;
+ *   out: device buffer of `capacity` bytes (tigas_jpeg_max_bytes bounds the
+ *        stream); *out_len (host) receives the stream length.  A stream longer
+ *        than `capacity` returns TIGAS_E_BUFFER with *out_len set and only a
+ *        prefix written;
+ *   hip_stream: NULL = the context stream.  The call returns when the stream
+ *        has finished (the length is read back).  Scratch buffers belong to
+ *        the stream's workspace; calls on one stream run one after another.
+ * Errors: TIGAS_E_INVALID for null pointers or out-of-range sizes/quality. */
+tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, int height, int quality,
+                               void* out, size_t capacity, size_t* out_len, void* hip_stream);
+/* Upper bound on the stream length of a width x height frame (0 for
+ * non-positive sizes). */
+size_t tigas_jpeg_max_bytes(int width, int height);
+
 /* Self-test of the wave64 DPP prefix scan used by the scan and sort kernels:
  * inclusive scan of n u32 host values in groups of 64 lanes, result to host. */
 tigas_status tigas_selftest_wave_scan(const uint32_t* in, uint32_t* out, int n);

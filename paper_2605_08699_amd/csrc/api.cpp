@@ -286,6 +286,10 @@ struct Workspace {
     int next_async = 0;  // slot for the next asynchronous frame
     FrameSlot& fs() { return slot[active]; }
     DevBuf work;            // blend work counters (evaluations, contributions)
+    // JPEG encoder: coefficients, per-row bit buffers (all zero between
+    // calls), per-row bit counts and output lengths, code tables, length
+    DevBuf jpeg_coef, jpeg_bits, jpeg_row_bits, jpeg_seg_len, jpeg_huff, jpeg_len;
+    HostPinned jpeg_len_host;
     hipEvent_t ev[7] = {};  // stage boundaries when stage timing is on
     EventTimer ktimer;      // per-launch events when kernel timing is on
     uint32_t rec_cap = 0, dup_cap = 0, tile_cap = 0;
@@ -821,6 +825,19 @@ tigas_stats frame_stats(const Plan& plan, const Counters& c, int rerenders) {
 }
 
 // Stage and kernel timings of the finished launch, and the context's stats.
+// Adds the per-launch event times of the workspace's kernel timer to the
+// context's per-kernel totals (the stream has completed).
+void record_kernel_times(tigas_context* ctx, Workspace& ws) {
+    for (const auto& r : ws.ktimer.recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ws.ktimer.pool[r.second], ws.ktimer.pool[r.second + 1]));
+        auto& e = ctx->kernel_ms[kernel_name(r.first, ws.stream)];
+        e.first += 1;
+        e.second += ms;
+    }
+    ws.ktimer.reset();
+}
+
 void record_stats(tigas_context* ctx, Workspace& ws, const tigas_stats& st, bool prof) {
     std::lock_guard<std::mutex> lk(ctx->stats_mu);
     if (prof) {
@@ -831,16 +848,7 @@ void record_stats(tigas_context* ctx, Workspace& ws, const tigas_stats& st, bool
         }
         ctx->stage_frames += 1;
     }
-    if (ctx->profile_kernels.load()) {
-        for (const auto& r : ws.ktimer.recs) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ws.ktimer.pool[r.second], ws.ktimer.pool[r.second + 1]));
-            auto& e = ctx->kernel_ms[kernel_name(r.first, ws.stream)];
-            e.first += 1;
-            e.second += ms;
-        }
-        ws.ktimer.reset();
-    }
+    if (ctx->profile_kernels.load()) record_kernel_times(ctx, ws);
     ctx->last = st;
 }
 
@@ -1450,6 +1458,149 @@ int64_t submit_locked(tigas_server* sv, const tigas_request* r, double arrival) 
 
 // ================================================================== C ABI
 
+namespace {
+
+// ITU-T T.81 Annex K: quantisation tables (Tables K.1, K.2, row-major) and
+// Huffman tables (K.3 to K.6: code counts per length 1..16, then symbols).
+const uint8_t kQLuma[64] = {16, 11, 10, 16, 24,  40,  51,  61,  12, 12, 14, 19, 26,  58,  60,  55,
+                            14, 13, 16, 24, 40,  57,  69,  56,  14, 17, 22, 29, 51,  87,  80,  62,
+                            18, 22, 37, 56, 68,  109, 103, 77,  24, 35, 55, 64, 81,  104, 113, 92,
+                            49, 64, 78, 87, 103, 121, 120, 101, 72, 92, 95, 98, 112, 100, 103, 99};
+const uint8_t kQChroma[64] = {17, 18, 24, 47, 99, 99, 99, 99, 18, 21, 26, 66, 99, 99, 99, 99,
+                              24, 26, 56, 99, 99, 99, 99, 99, 47, 66, 99, 99, 99, 99, 99, 99,
+                              99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99,
+                              99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99};
+struct HuffSpec {
+    uint8_t counts[16];
+    uint8_t syms[162];
+};
+const HuffSpec kHuff[4] = {
+    // DC luminance
+    {{0, 1, 5, 1, 1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0}, {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11}},
+    // AC luminance
+    {{0, 2, 1, 3, 3, 2, 4, 3, 5, 5, 4, 4, 0, 0, 1, 0x7d},
+     {0x01, 0x02, 0x03, 0x00, 0x04, 0x11, 0x05, 0x12, 0x21, 0x31, 0x41, 0x06, 0x13, 0x51, 0x61, 0x07, 0x22, 0x71,
+      0x14, 0x32, 0x81, 0x91, 0xa1, 0x08, 0x23, 0x42, 0xb1, 0xc1, 0x15, 0x52, 0xd1, 0xf0, 0x24, 0x33, 0x62, 0x72,
+      0x82, 0x09, 0x0a, 0x16, 0x17, 0x18, 0x19, 0x1a, 0x25, 0x26, 0x27, 0x28, 0x29, 0x2a, 0x34, 0x35, 0x36, 0x37,
+      0x38, 0x39, 0x3a, 0x43, 0x44, 0x45, 0x46, 0x47, 0x48, 0x49, 0x4a, 0x53, 0x54, 0x55, 0x56, 0x57, 0x58, 0x59,
+      0x5a, 0x63, 0x64, 0x65, 0x66, 0x67, 0x68, 0x69, 0x6a, 0x73, 0x74, 0x75, 0x76, 0x77, 0x78, 0x79, 0x7a, 0x83,
+      0x84, 0x85, 0x86, 0x87, 0x88, 0x89, 0x8a, 0x92, 0x93, 0x94, 0x95, 0x96, 0x97, 0x98, 0x99, 0x9a, 0xa2, 0xa3,
+      0xa4, 0xa5, 0xa6, 0xa7, 0xa8, 0xa9, 0xaa, 0xb2, 0xb3, 0xb4, 0xb5, 0xb6, 0xb7, 0xb8, 0xb9, 0xba, 0xc2, 0xc3,
+      0xc4, 0xc5, 0xc6, 0xc7, 0xc8, 0xc9, 0xca, 0xd2, 0xd3, 0xd4, 0xd5, 0xd6, 0xd7, 0xd8, 0xd9, 0xda, 0xe1, 0xe2,
+      0xe3, 0xe4, 0xe5, 0xe6, 0xe7, 0xe8, 0xe9, 0xea, 0xf1, 0xf2, 0xf3, 0xf4, 0xf5, 0xf6, 0xf7, 0xf8, 0xf9, 0xfa}},
+    // DC chrominance
+    {{0, 3, 1, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0, 0, 0, 0}, {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11}},
+    // AC chrominance
+    {{0, 2, 1, 2, 4, 4, 3, 4, 7, 5, 4, 4, 0, 1, 2, 0x77},
+     {0x00, 0x01, 0x02, 0x03, 0x11, 0x04, 0x05, 0x21, 0x31, 0x06, 0x12, 0x41, 0x51, 0x07, 0x61, 0x71, 0x13, 0x22,
+      0x32, 0x81, 0x08, 0x14, 0x42, 0x91, 0xa1, 0xb1, 0xc1, 0x09, 0x23, 0x33, 0x52, 0xf0, 0x15, 0x62, 0x72, 0xd1,
+      0x0a, 0x16, 0x24, 0x34, 0xe1, 0x25, 0xf1, 0x17, 0x18, 0x19, 0x1a, 0x26, 0x27, 0x28, 0x29, 0x2a, 0x35, 0x36,
+      0x37, 0x38, 0x39, 0x3a, 0x43, 0x44, 0x45, 0x46, 0x47, 0x48, 0x49, 0x4a, 0x53, 0x54, 0x55, 0x56, 0x57, 0x58,
+      0x59, 0x5a, 0x63, 0x64, 0x65, 0x66, 0x67, 0x68, 0x69, 0x6a, 0x73, 0x74, 0x75, 0x76, 0x77, 0x78, 0x79, 0x7a,
+      0x82, 0x83, 0x84, 0x85, 0x86, 0x87, 0x88, 0x89, 0x8a, 0x92, 0x93, 0x94, 0x95, 0x96, 0x97, 0x98, 0x99, 0x9a,
+      0xa2, 0xa3, 0xa4, 0xa5, 0xa6, 0xa7, 0xa8, 0xa9, 0xaa, 0xb2, 0xb3, 0xb4, 0xb5, 0xb6, 0xb7, 0xb8, 0xb9, 0xba,
+      0xc2, 0xc3, 0xc4, 0xc5, 0xc6, 0xc7, 0xc8, 0xc9, 0xca, 0xd2, 0xd3, 0xd4, 0xd5, 0xd6, 0xd7, 0xd8, 0xd9, 0xda,
+      0xe2, 0xe3, 0xe4, 0xe5, 0xe6, 0xe7, 0xe8, 0xe9, 0xea, 0xf2, 0xf3, 0xf4, 0xf5, 0xf6, 0xf7, 0xf8, 0xf9, 0xfa}},
+};
+
+int huff_count(const HuffSpec& h) {
+    int n = 0;
+    for (uint8_t c : h.counts) n += c;
+    return n;
+}
+
+// Quality scaling of a base table: 5000/q below 50, else 200 - 2q percent,
+// rounded, within 1..255 (8-bit tables).
+void scaled_qtable(const uint8_t* base, int quality, uint8_t* out) {
+    const long s = quality < 50 ? 5000 / quality : 200 - 2 * quality;
+    for (int i = 0; i < 64; ++i) out[i] = (uint8_t)std::min(255L, std::max(1L, ((long)base[i] * s + 50) / 100));
+}
+
+// Row-major index of each zig-zag scan position.
+void zigzag_order(int* zz) {
+    int i = 0;
+    for (int d = 0; d < 15; ++d)
+        for (int j = std::min(d, 7); j >= std::max(0, d - 7); --j) {
+            const int row = (d & 1) ? d - j : j;
+            zz[i++] = row * 8 + (d - row);
+        }
+}
+
+// Canonical codes (Annex C) of a table, as length << 16 | code per symbol.
+void huff_codes(const HuffSpec& h, uint32_t* out) {
+    std::fill(out, out + 256, 0u);
+    uint32_t code = 0;
+    int k = 0;
+    for (int len = 1; len <= 16; ++len) {
+        for (int i = 0; i < h.counts[len - 1]; ++i, ++k) out[h.syms[k]] = ((uint32_t)len << 16) | code++;
+        code <<= 1;
+    }
+}
+
+// SOI, JFIF APP0, DQT, SOF0 (4:4:4), DHT, DRI (one MCU row), SOS.
+std::vector<uint8_t> jpeg_header(int W, int H, const uint8_t* ql, const uint8_t* qc) {
+    std::vector<uint8_t> h;
+    auto b = [&](unsigned v) { h.push_back((uint8_t)v); };
+    auto w16 = [&](unsigned v) {
+        b(v >> 8);
+        b(v & 0xff);
+    };
+    int zz[64];
+    zigzag_order(zz);
+    w16(0xFFD8);
+    w16(0xFFE0);
+    w16(16);
+    const uint8_t jfif[14] = {'J', 'F', 'I', 'F', 0, 1, 1, 0, 0, 1, 0, 1, 0, 0};  // version 1.01, no density units
+    for (uint8_t v : jfif) b(v);
+    w16(0xFFDB);
+    w16(2 + 2 * 65);
+    b(0);
+    for (int i = 0; i < 64; ++i) b(ql[zz[i]]);
+    b(1);
+    for (int i = 0; i < 64; ++i) b(qc[zz[i]]);
+    w16(0xFFC0);
+    w16(17);
+    b(8);
+    w16((unsigned)H);
+    w16((unsigned)W);
+    b(3);
+    for (int c = 0; c < 3; ++c) {
+        b(c + 1);
+        b(0x11);
+        b(c ? 1 : 0);
+    }
+    int len = 2;
+    for (const HuffSpec& t : kHuff) len += 17 + huff_count(t);
+    w16(0xFFC4);
+    w16((unsigned)len);
+    const unsigned cls_id[4] = {0x00, 0x10, 0x01, 0x11};
+    for (int t = 0; t < 4; ++t) {
+        b(cls_id[t]);
+        for (uint8_t c : kHuff[t].counts) b(c);
+        for (int i = 0; i < huff_count(kHuff[t]); ++i) b(kHuff[t].syms[i]);
+    }
+    w16(0xFFDD);
+    w16(4);
+    w16((unsigned)((W + 7) / 8));
+    w16(0xFFDA);
+    w16(12);
+    b(3);
+    for (int c = 0; c < 3; ++c) {
+        b(c + 1);
+        b(c ? 0x11 : 0x00);
+    }
+    b(0);
+    b(63);
+    b(0);
+    return h;
+}
+
+// Bound on the entropy-coded bits of one block: DC 11 + 11, 63 AC symbols of
+// at most 16 + 10 bits.
+constexpr uint32_t kBlockMaxBits = 22 + 63 * 26;
+
+}  // namespace
+
 extern "C" {
 
 const char* tigas_last_error(void) { return g_err.c_str(); }
@@ -1718,6 +1869,82 @@ tigas_status tigas_count_blend_work(tigas_scene* scene, const tigas_pose* pose, 
         render_one(scene, pose, intr, width, height, q, out, nullptr, nullptr, w);
         *evaluations = w[0];
         *contributions = w[1];
+    });
+}
+
+size_t tigas_jpeg_max_bytes(int width, int height) {
+    if (width < 1 || height < 1) return 0;
+    const size_t w8 = ((size_t)width + 7) / 8, h8 = ((size_t)height + 7) / 8;
+    const size_t row = (3 * w8 * kBlockMaxBits + 7) / 8;
+    return 1024 + h8 * (2 * row + 2);  // every byte stuffed at worst, plus the marker
+}
+
+tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, int height, int quality, void* out,
+                               size_t capacity, size_t* out_len, void* hip_stream) {
+    return guard([&] {
+        if (!ctx || !rgb || !out || !out_len) fail(TIGAS_E_INVALID, "null argument");
+        if (width < 1 || width > 8 * (JPEG_MAX_BLOCKS / 3) || height < 1 || height > 65535)
+            fail(TIGAS_E_INVALID, "jpeg: width must be 1..4096 and height 1..65535");
+        if (quality < 1 || quality > 100) fail(TIGAS_E_INVALID, "jpeg: quality must be 1..100");
+        HIPCHK(hipSetDevice(ctx->device));
+        hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+        Workspace& ws = ctx->workspace(st);
+        std::lock_guard<std::mutex> lk(ws.mu);
+        JpegArgs a{};
+        a.rgb = (const uint8_t*)rgb;
+        a.width = width;
+        a.height = height;
+        a.w8 = (width + 7) / 8;
+        a.h8 = (height + 7) / 8;
+        const size_t nb = 3 * (size_t)a.w8;
+        a.row_words = (uint32_t)((nb * kBlockMaxBits + 31) / 32 + 1);
+        ws.jpeg_coef.ensure((size_t)a.h8 * nb * 64 * 2);
+        const size_t bits_bytes = (size_t)a.h8 * a.row_words * 4;
+        if (ws.jpeg_bits.ensure(bits_bytes)) HIPCHK(hipMemset(ws.jpeg_bits.p, 0, ws.jpeg_bits.bytes));
+        ws.jpeg_row_bits.ensure((size_t)a.h8 * 4);
+        ws.jpeg_seg_len.ensure((size_t)a.h8 * 4);
+        ws.jpeg_huff.ensure(4 * 256 * 4);
+        ws.jpeg_len.ensure(8);
+        ws.jpeg_len_host.ensure(8);
+        // tables: quantisation steps as FP32 reciprocals, the DCT matrix
+        // rounded once from FP64, the canonical Huffman codes
+        uint8_t ql[64], qc[64];
+        scaled_qtable(kQLuma, quality, ql);
+        scaled_qtable(kQChroma, quality, qc);
+        for (int i = 0; i < 64; ++i) {
+            a.rq_luma[i] = 1.0f / (float)ql[i];
+            a.rq_chroma[i] = 1.0f / (float)qc[i];
+        }
+        for (int k = 0; k < 8; ++k)
+            for (int n = 0; n < 8; ++n) {
+                const double ck = k == 0 ? std::sqrt(0.5) : 1.0;
+                a.dct[k * 8 + n] = (float)(0.5 * ck * std::cos((2 * n + 1) * k * 3.14159265358979323846 / 16.0));
+            }
+        uint32_t codes[4 * 256];
+        for (int t = 0; t < 4; ++t) huff_codes(kHuff[t], codes + 256 * t);
+        HIPCHK(hipMemcpyAsync(ws.jpeg_huff.p, codes, sizeof codes, hipMemcpyHostToDevice, st));
+        const std::vector<uint8_t> hdr = jpeg_header(width, height, ql, qc);
+        HIPCHK(hipMemcpyAsync(out, hdr.data(), std::min(hdr.size(), capacity), hipMemcpyHostToDevice, st));
+        a.huff = ws.jpeg_huff.as<uint32_t>();
+        a.coef = ws.jpeg_coef.as<int16_t>();
+        a.bits = ws.jpeg_bits.as<uint32_t>();
+        a.row_bits = ws.jpeg_row_bits.as<uint32_t>();
+        a.seg_len = ws.jpeg_seg_len.as<uint32_t>();
+        a.out = (uint8_t*)out;
+        a.capacity = capacity;
+        a.header_len = hdr.size();
+        a.out_len = ws.jpeg_len.as<uint64_t>();
+        if (ctx->profile_kernels.load()) ws.ktimer.reset();
+        TimerScope ts(ctx->profile_kernels.load() ? &ws.ktimer : nullptr);
+        launch_jpeg(a, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(ws.jpeg_len_host.p, ws.jpeg_len.p, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (ctx->profile_kernels.load()) record_kernel_times(ctx, ws);
+        uint64_t n = 0;
+        std::memcpy(&n, ws.jpeg_len_host.p, 8);
+        *out_len = (size_t)n;
+        if (n > capacity) fail(TIGAS_E_BUFFER, "jpeg: output buffer smaller than the stream");
     });
 }
 

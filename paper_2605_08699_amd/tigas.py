@@ -82,7 +82,8 @@ EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", 
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
            "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks",
-           "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait")
+           "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait",
+           "tigas_jpeg_encode", "tigas_jpeg_max_bytes")
 
 _lib = None
 
@@ -93,6 +94,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_2605_08699_amd.build.build()")
+        try:  # one HIP runtime per process: torch's, loaded first so that the library binds to it
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
         L.tigas_context_create.argtypes = [I, ctypes.POINTER(P)]
@@ -125,6 +130,9 @@ def lib():
                                           ctypes.POINTER(QualityC), ctypes.POINTER(FrameC), P, ctypes.POINTER(I64)]
         L.tigas_render_wait.argtypes = [P, I64, ctypes.POINTER(StatsC), ctypes.POINTER(ctypes.c_float)]
         L.tigas_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimeC), I, ctypes.POINTER(I)]
+        L.tigas_jpeg_encode.argtypes = [P, P, I, I, I, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
+        L.tigas_jpeg_max_bytes.argtypes = [I, I]
+        L.tigas_jpeg_max_bytes.restype = ctypes.c_size_t
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
                                              ctypes.POINTER(I64), ctypes.POINTER(I64)]
@@ -132,7 +140,7 @@ def lib():
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
                      "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort",
                      "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit",
-                     "tigas_render_wait"):
+                     "tigas_render_wait", "tigas_jpeg_encode"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -297,6 +305,27 @@ class Context:
         _check(lib().tigas_render(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
                                   int(width), int(height), ctypes.byref(q), ctypes.byref(fr), st))
         return out
+
+    def jpeg_encode(self, rgb, quality, out=None, stream=None):
+        """Baseline JPEG of an RGB8 frame held in a GPU tensor [H, W, 3] (uint8).
+        ``out``: a GPU uint8 tensor receiving the stream (sized by
+        jpeg_max_bytes when None).  Returns (out, length)."""
+        import torch
+        assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.dim() == 3 and rgb.shape[2] == 3
+        assert rgb.is_contiguous()
+        H, W = int(rgb.shape[0]), int(rgb.shape[1])
+        if out is None:
+            out = torch.empty(int(lib().tigas_jpeg_max_bytes(W, H)), dtype=torch.uint8, device=rgb.device)
+        n = ctypes.c_size_t(0)
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(lib().tigas_jpeg_encode(self.handle, ctypes.c_void_p(int(rgb.data_ptr())), W, H, int(quality),
+                                       ctypes.c_void_p(int(out.data_ptr())), out.numel(), ctypes.byref(n), st))
+        return out, int(n.value)
+
+    def jpeg_bytes(self, rgb, quality, stream=None) -> bytes:
+        """The JPEG stream of jpeg_encode copied to host memory."""
+        out, n = self.jpeg_encode(rgb, quality, stream=stream)
+        return out[:n].cpu().numpy().tobytes()
 
     def render_async(self, scene: Scene, pose, intr, width, height, out, res_scale=1.0, fmt="rgb8", bg=(0, 0, 0),
                      tile=None, batch_depth=None, sh_degree=-1, stream=None, ppl=None) -> int:
