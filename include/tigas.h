@@ -354,9 +354,9 @@ tigas_status tigas_render_debug(tigas_scene* scene, const tigas_pose* pose, cons
  * quality factor of its bitrate ladder (Table 1: 10, 35, 65, 90).  Format:
  * JFIF, YCbCr 4:4:4, the Annex K quantisation tables of ITU-T T.81 scaled by
  * quality (5000/q percent below 50, else 200 - 2q, clamped to 1..255) and its
- * Annex K Huffman tables, one restart interval per row of 8x8 blocks.
+ * Annex K Huffman tables, restart intervals of 40 MCUs (8x8 pixel blocks).
  *   rgb: device pointer, `height` rows of 3 * `width` bytes, top row first (the
- *        RGB8 layout tigas_render writes); width 1..4096, height 1..65535;
+ *        RGB8 layout tigas_render writes); width and height 1..65535;
  *   quality: 1..100;
  *   out: device buffer of `capacity` bytes (tigas_jpeg_max_bytes bounds the
  *        stream); *out_len (host) receives the stream length.  A stream longer

@@ -24,13 +24,15 @@
  *   - entropy coding of Annex F (DC difference category + magnitude bits;
  *     AC run/size symbols with ZRL and EOB), 0xFF bytes followed by 0x00,
  *     pad bits set to 1;
- *   - one restart interval per MCU row (DRI), RSTn after every row but the
- *     last, DC predictions reset to zero at each interval.
+ *   - restart intervals of 40 MCUs in raster order (DRI), RSTn after every
+ *     interval but the last, DC predictions reset to zero at each interval.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#define ORC_RESTART_MCUS 40
 
 /* Annex K, Table K.1 and K.2, rows of the 8x8 block (natural order) */
 static const uint8_t QL[64] = {16, 11, 10, 16, 24,  40,  51,  61,  12, 12, 14, 19, 26,  58,  60,  55,
@@ -254,10 +256,10 @@ int64_t orc_jpeg(const uint8_t* rgb, int W, int H, int quality, uint8_t* out, in
             for (int i = 0; i < m; ++i) put_byte(&w, s[i]);
         }
     }
-    /* DRI: one MCU row per interval */
+    /* DRI: 40 MCUs per interval */
     put16(&w, 0xFFDD);
     put16(&w, 4);
-    put16(&w, (unsigned)W8);
+    put16(&w, ORC_RESTART_MCUS);
     /* SOS: three components, full spectral range */
     put16(&w, 0xFFDA);
     put16(&w, 12);
@@ -270,9 +272,16 @@ int64_t orc_jpeg(const uint8_t* rgb, int W, int H, int quality, uint8_t* out, in
     put_byte(&w, 63);
     put_byte(&w, 0);
 
-    for (int by = 0; by < H8; ++by) {
-        int pred[3] = {0, 0, 0};
-        for (int bx = 0; bx < W8; ++bx) {
+    int pred[3] = {0, 0, 0};
+    const int64_t n_mcu = (int64_t)W8 * H8;
+    for (int64_t m = 0; m < n_mcu; ++m) {
+        if (m > 0 && m % ORC_RESTART_MCUS == 0) { /* end of an interval */
+            pad_ones(&w);
+            put16(&w, 0xFFD0u + (unsigned)((m / ORC_RESTART_MCUS - 1) % 8));
+            pred[0] = pred[1] = pred[2] = 0;
+        }
+        const int by = (int)(m / W8), bx = (int)(m % W8);
+        {
             for (int comp = 0; comp < 3; ++comp) {
                 float f[64];
                 for (int r = 0; r < 8; ++r)
@@ -315,9 +324,8 @@ int64_t orc_jpeg(const uint8_t* rgb, int W, int H, int quality, uint8_t* out, in
                 if (run > 0) put_symbol(&w, ha, 0x00);
             }
         }
-        pad_ones(&w);
-        if (by + 1 < H8) put16(&w, 0xFFD0u + (unsigned)(by % 8));
     }
+    pad_ones(&w);
     put16(&w, 0xFFD9);
     return w.n;
 }

@@ -286,9 +286,9 @@ struct Workspace {
     int next_async = 0;  // slot for the next asynchronous frame
     FrameSlot& fs() { return slot[active]; }
     DevBuf work;            // blend work counters (evaluations, contributions)
-    // JPEG encoder: coefficients, per-row bit buffers (all zero between
-    // calls), per-row bit counts and output lengths, code tables, length
-    DevBuf jpeg_coef, jpeg_bits, jpeg_row_bits, jpeg_seg_len, jpeg_huff, jpeg_len;
+    // JPEG encoder: coefficients, per-interval bit buffers (all zero between
+    // calls), per-interval bit counts and output lengths, code tables, length
+    DevBuf jpeg_coef, jpeg_bits, jpeg_seg_bits, jpeg_seg_len, jpeg_huff, jpeg_len;
     HostPinned jpeg_len_host;
     hipEvent_t ev[7] = {};  // stage boundaries when stage timing is on
     EventTimer ktimer;      // per-launch events when kernel timing is on
@@ -1537,7 +1537,7 @@ void huff_codes(const HuffSpec& h, uint32_t* out) {
     }
 }
 
-// SOI, JFIF APP0, DQT, SOF0 (4:4:4), DHT, DRI (one MCU row), SOS.
+// SOI, JFIF APP0, DQT, SOF0 (4:4:4), DHT, DRI (JPEG_SEG_MCUS MCUs), SOS.
 std::vector<uint8_t> jpeg_header(int W, int H, const uint8_t* ql, const uint8_t* qc) {
     std::vector<uint8_t> h;
     auto b = [&](unsigned v) { h.push_back((uint8_t)v); };
@@ -1581,7 +1581,7 @@ std::vector<uint8_t> jpeg_header(int W, int H, const uint8_t* ql, const uint8_t*
     }
     w16(0xFFDD);
     w16(4);
-    w16((unsigned)((W + 7) / 8));
+    w16((unsigned)JPEG_SEG_MCUS);
     w16(0xFFDA);
     w16(12);
     b(3);
@@ -1874,17 +1874,18 @@ tigas_status tigas_count_blend_work(tigas_scene* scene, const tigas_pose* pose, 
 
 size_t tigas_jpeg_max_bytes(int width, int height) {
     if (width < 1 || height < 1) return 0;
-    const size_t w8 = ((size_t)width + 7) / 8, h8 = ((size_t)height + 7) / 8;
-    const size_t row = (3 * w8 * kBlockMaxBits + 7) / 8;
-    return 1024 + h8 * (2 * row + 2);  // every byte stuffed at worst, plus the marker
+    const size_t n_mcu = (((size_t)width + 7) / 8) * (((size_t)height + 7) / 8);
+    const size_t nseg = (n_mcu + JPEG_SEG_MCUS - 1) / JPEG_SEG_MCUS;
+    const size_t seg = (3 * JPEG_SEG_MCUS * (size_t)kBlockMaxBits + 7) / 8;
+    return 1024 + nseg * (2 * seg + 2);  // every byte stuffed at worst, plus the marker
 }
 
 tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, int height, int quality, void* out,
                                size_t capacity, size_t* out_len, void* hip_stream) {
     return guard([&] {
         if (!ctx || !rgb || !out || !out_len) fail(TIGAS_E_INVALID, "null argument");
-        if (width < 1 || width > 8 * (JPEG_MAX_BLOCKS / 3) || height < 1 || height > 65535)
-            fail(TIGAS_E_INVALID, "jpeg: width must be 1..4096 and height 1..65535");
+        if (width < 1 || width > 65535 || height < 1 || height > 65535)
+            fail(TIGAS_E_INVALID, "jpeg: width and height must be 1..65535");
         if (quality < 1 || quality > 100) fail(TIGAS_E_INVALID, "jpeg: quality must be 1..100");
         HIPCHK(hipSetDevice(ctx->device));
         hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
@@ -1896,13 +1897,15 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
         a.height = height;
         a.w8 = (width + 7) / 8;
         a.h8 = (height + 7) / 8;
-        const size_t nb = 3 * (size_t)a.w8;
-        a.row_words = (uint32_t)((nb * kBlockMaxBits + 31) / 32 + 1);
-        ws.jpeg_coef.ensure((size_t)a.h8 * nb * 64 * 2);
-        const size_t bits_bytes = (size_t)a.h8 * a.row_words * 4;
+        a.n_mcu = (int64_t)a.w8 * a.h8;
+        a.nseg = (int)((a.n_mcu + JPEG_SEG_MCUS - 1) / JPEG_SEG_MCUS);
+        const size_t nb = 3 * (size_t)JPEG_SEG_MCUS;
+        a.seg_words = (uint32_t)((nb * kBlockMaxBits + 31) / 32 + 1);
+        ws.jpeg_coef.ensure((size_t)a.nseg * nb * 64 * 2);
+        const size_t bits_bytes = (size_t)a.nseg * a.seg_words * 4;
         if (ws.jpeg_bits.ensure(bits_bytes)) HIPCHK(hipMemset(ws.jpeg_bits.p, 0, ws.jpeg_bits.bytes));
-        ws.jpeg_row_bits.ensure((size_t)a.h8 * 4);
-        ws.jpeg_seg_len.ensure((size_t)a.h8 * 4);
+        ws.jpeg_seg_bits.ensure((size_t)a.nseg * 4);
+        ws.jpeg_seg_len.ensure((size_t)a.nseg * 4);
         ws.jpeg_huff.ensure(4 * 256 * 4);
         ws.jpeg_len.ensure(8);
         ws.jpeg_len_host.ensure(8);
@@ -1928,7 +1931,7 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
         a.huff = ws.jpeg_huff.as<uint32_t>();
         a.coef = ws.jpeg_coef.as<int16_t>();
         a.bits = ws.jpeg_bits.as<uint32_t>();
-        a.row_bits = ws.jpeg_row_bits.as<uint32_t>();
+        a.seg_bits = ws.jpeg_seg_bits.as<uint32_t>();
         a.seg_len = ws.jpeg_seg_len.as<uint32_t>();
         a.out = (uint8_t*)out;
         a.capacity = capacity;

@@ -2,23 +2,23 @@
 // paper's backend (Section 3 transport: one stateless JPEG per request; the
 // bitrate ladder of Table 1 pairs each resolution with a quality factor).
 //
-//   k_jpeg_rows   one workgroup per MCU row (one restart interval): colour
-//                 transform, forward DCT and quantisation of every 8x8 block
-//                 of the row (one thread per block), the entropy-coded length
-//                 of each block (DC prediction inside the row), a workgroup
-//                 scan of those lengths, then each block's Huffman codes ORed
-//                 into the row's bit buffer at its offset
-//   k_jpeg_count  per row: bytes after padding with 1-bits, plus one 0x00
-//                 for every 0xFF byte, plus the restart marker
-//   k_jpeg_pack   per row: output offset = header + the rows before it; the
-//                 bytes with stuffing, the RSTn marker (EOI after the last
-//                 row); clears the consumed bit-buffer words for the next call
+//   k_jpeg_seg    one workgroup per restart interval (40 MCUs in raster
+//                 order, one thread per 8x8 block): colour transform, forward
+//                 DCT and quantisation, the entropy-coded length of each block
+//                 (DC prediction inside the interval), a workgroup scan of
+//                 those lengths, then each block's Huffman codes ORed into the
+//                 interval's bit buffer at its offset
+//   k_jpeg_count  per interval: bytes after padding with 1-bits, plus one
+//                 0x00 for every 0xFF byte, plus the restart marker
+//   k_jpeg_pack   per interval: output offset = header + the intervals before
+//                 it; the bytes with stuffing, the RSTn marker (EOI after the
+//                 last); clears the consumed bit-buffer words for the next call
 //
 // Format choices (the standard leaves them open; the JPEG oracle makes the
 // same ones): JFIF full-range YCbCr, 4:4:4, orthonormal DCT-II as two FP32
 // FMA chains (columns of each row first, then rows), quantisation
 // x = F (1/Q), q = trunc(x + copysign(1/2, x)), AC clamped to +-1023, the
-// Annex K tables scaled by quality, one restart interval per MCU row.
+// Annex K tables scaled by quality, restart intervals of 40 MCUs.
 #include "tigas_internal.h"
 
 namespace tigas {
@@ -51,7 +51,7 @@ struct BitCount {
     __device__ void put(uint32_t, int nb) { n += (uint32_t)nb; }
 };
 struct BitWrite {
-    uint32_t* buf;  // the row's words, stream bit i at bit 31 - i % 32 of word i / 32
+    uint32_t* buf;  // the interval's words, stream bit i at bit 31 - i % 32 of word i / 32
     uint64_t acc;   // pending bits, left-aligned
     int n;          // pending bit count
     uint32_t w;     // word the pending bits start in
@@ -108,7 +108,7 @@ __device__ void code_block(const int16_t* zq, int pred, const uint32_t* hdc, con
     if (run > 0) put_symbol(s, hac, 0x00);
 }
 
-// Workgroup exclusive scan (256 threads) through LDS.
+// Workgroup exclusive scan (JPEG_THREADS threads) through LDS.
 __device__ uint32_t wg_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
     const int t = threadIdx.x;
     lds[t] = v;
@@ -134,20 +134,22 @@ __device__ __forceinline__ uint32_t row_byte(const uint32_t* buf, uint32_t j, ui
 
 }  // namespace
 
-__global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_rows(JpegArgs a) {
-    __shared__ int32_t s_dc[JPEG_MAX_BLOCKS];
-    __shared__ uint32_t s_off[JPEG_MAX_BLOCKS];
+__global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
+    static_assert(3 * JPEG_SEG_MCUS <= JPEG_THREADS, "one thread per block of an interval");
+    __shared__ int32_t s_dc[3 * JPEG_SEG_MCUS];
     __shared__ uint32_t s_huff[4 * 256];
     __shared__ uint32_t s_scan[JPEG_THREADS];
-    const int row = blockIdx.x, t = threadIdx.x;
-    const int nb = 3 * a.w8;
+    const int seg = blockIdx.x, t = threadIdx.x;
+    const int64_t m0 = (int64_t)seg * JPEG_SEG_MCUS;
+    const int nb = 3 * (int)min((int64_t)JPEG_SEG_MCUS, a.n_mcu - m0);
     for (int i = t; i < 4 * 256; i += JPEG_THREADS) s_huff[i] = a.huff[i];
-    int16_t* coef = a.coef + (size_t)row * nb * 64;
+    int16_t* zq = a.coef + ((size_t)seg * 3 * JPEG_SEG_MCUS + t) * 64;
+    const int comp = t % 3;
 
-    // transform and quantise; one thread per block (Y, Cb, Cr of each MCU)
-    for (int b = t; b < nb; b += JPEG_THREADS) {
-        const int mcu = b / 3, comp = b - 3 * mcu;
-        const int x0 = mcu * 8, y0 = row * 8;
+    // transform and quantise block t (Y, Cb, Cr of each MCU)
+    if (t < nb) {
+        const int64_t mcu = m0 + t / 3;
+        const int x0 = (int)(mcu % a.w8) * 8, y0 = (int)(mcu / a.w8) * 8;
         float tr[64];  // rows transformed along x: tr[r][l]
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -173,7 +175,6 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_rows(JpegArgs a) {
             }
         }
         const float* rq = comp ? a.rq_chroma : a.rq_luma;
-        int16_t* zq = coef + (size_t)b * 64;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -185,72 +186,59 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_rows(JpegArgs a) {
                 int v = (int)__builtin_truncf(x + __builtin_copysignf(0.5f, x));
                 if (k + l > 0) v = max(-1023, min(1023, v));
                 zq[kZigZag.pos[k * 8 + l]] = (int16_t)v;
-                if (k + l == 0) s_dc[b] = v;
+                if (k + l == 0) s_dc[t] = v;
             }
     }
     __syncthreads();
 
-    // entropy-coded length of each block; DC predicted from the previous
-    // block of the same component in the row (the interval starts at zero)
-    for (int b = t; b < nb; b += JPEG_THREADS) {
-        const int16_t* zq = coef + (size_t)b * 64;  // written by this thread above
-        const int comp = b % 3;
+    // entropy-coded length of the block; DC predicted from the previous block
+    // of the same component in the interval (the interval starts at zero)
+    const uint32_t* hdc = s_huff + (comp ? 512 : 0);
+    const uint32_t* hac = s_huff + (comp ? 768 : 256);
+    const int pred = t >= 3 && t < nb ? s_dc[t - 3] : 0;
+    uint32_t len = 0;
+    if (t < nb) {
         BitCount c;
-        code_block(zq, b >= 3 ? s_dc[b - 3] : 0, s_huff + (comp ? 512 : 0), s_huff + (comp ? 768 : 256), c);
-        s_off[b] = c.n;
+        code_block(zq, pred, hdc, hac, c);  // coefficients written by this thread above
+        len = c.n;
     }
-    __syncthreads();
-    // exclusive offsets: each thread scans a contiguous run of blocks
-    const int per = (nb + JPEG_THREADS - 1) / JPEG_THREADS;
-    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
-    uint32_t sum = 0;
-    for (int b = b0; b < b1; ++b) sum += s_off[b];
     uint32_t total;
-    uint32_t off = wg_excl_scan(sum, s_scan, &total);
-    for (int b = b0; b < b1; ++b) {
-        const uint32_t len = s_off[b];
-        s_off[b] = off;
-        off += len;
-    }
-    if (t == 0) a.row_bits[row] = total;
-    __syncthreads();
+    const uint32_t off = wg_excl_scan(len, s_scan, &total);
+    if (t == 0) a.seg_bits[seg] = total;
 
-    // the codes, ORed into the (cleared) bit buffer of the row
-    uint32_t* buf = a.bits + (size_t)row * a.row_words;
-    for (int b = t; b < nb; b += JPEG_THREADS) {
-        const int16_t* zq = coef + (size_t)b * 64;
-        const int comp = b % 3;
-        BitWrite w(buf, s_off[b]);
-        code_block(zq, b >= 3 ? s_dc[b - 3] : 0, s_huff + (comp ? 512 : 0), s_huff + (comp ? 768 : 256), w);
+    // the codes, ORed into the (cleared) bit buffer of the interval
+    if (t < nb) {
+        BitWrite w(a.bits + (size_t)seg * a.seg_words, off);
+        code_block(zq, pred, hdc, hac, w);
         w.flush();
     }
 }
 
 __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_count(JpegArgs a) {
     __shared__ uint32_t s_scan[JPEG_THREADS];
-    const int row = blockIdx.x;
-    const uint32_t bits = a.row_bits[row];
+    const int seg = blockIdx.x;
+    const uint32_t bits = a.seg_bits[seg];
     const uint32_t nbytes = (bits + 7) / 8;
-    const uint32_t* buf = a.bits + (size_t)row * a.row_words;
+    const uint32_t* buf = a.bits + (size_t)seg * a.seg_words;
     uint32_t ff = 0;
     for (uint32_t j = threadIdx.x; j < nbytes; j += JPEG_THREADS) ff += row_byte(buf, j, bits) == 0xffu ? 1u : 0u;
     uint32_t total;
     wg_excl_scan(ff, s_scan, &total);
-    if (threadIdx.x == 0) a.seg_len[row] = nbytes + total + (row + 1 < a.h8 ? 2u : 0u);
+    if (threadIdx.x == 0) a.seg_len[seg] = nbytes + total + (seg + 1 < a.nseg ? 2u : 0u);
 }
 
 __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_pack(JpegArgs a) {
     __shared__ uint32_t s_scan[JPEG_THREADS];
-    const int row = blockIdx.x, t = threadIdx.x;
-    // output offset of the row: the header and every row before it
+    const int seg = blockIdx.x, t = threadIdx.x;
+    // output offset of the interval: the header and every interval before it
     uint32_t before = 0;
-    for (int r = t; r < row; r += JPEG_THREADS) before += a.seg_len[r];
+    for (int r = t; r < seg; r += JPEG_THREADS) before += a.seg_len[r];
     uint32_t tot_before;
     wg_excl_scan(before, s_scan, &tot_before);
     const uint64_t base = a.header_len + (uint64_t)tot_before;
-    const uint32_t bits = a.row_bits[row];
+    const uint32_t bits = a.seg_bits[seg];
     const uint32_t nbytes = (bits + 7) / 8;
-    uint32_t* buf = a.bits + (size_t)row * a.row_words;
+    uint32_t* buf = a.bits + (size_t)seg * a.seg_words;
     // a contiguous run of bytes per thread; its 0xFF count places it
     const uint32_t per = (nbytes + JPEG_THREADS - 1) / JPEG_THREADS;
     const uint32_t j0 = min(nbytes, (uint32_t)t * per), j1 = min(nbytes, j0 + per);
@@ -270,8 +258,8 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_pack(JpegArgs a) {
     }
     const uint64_t end = base + nbytes + ff_total;
     if (t == 0) {
-        const bool last = row + 1 == a.h8;
-        const uint8_t m = last ? 0xD9 : (uint8_t)(0xD0 + (row & 7));  // RSTn, or EOI after the last row
+        const bool last = seg + 1 == a.nseg;
+        const uint8_t m = last ? 0xD9 : (uint8_t)(0xD0 + (seg & 7));  // RSTn, or EOI after the last interval
         if (end < a.capacity) a.out[end] = 0xFF;
         if (end + 1 < a.capacity) a.out[end + 1] = m;
         if (last) *a.out_len = end + 2;
@@ -290,9 +278,9 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_pack(JpegArgs a) {
     } while (0)
 
 void launch_jpeg(const JpegArgs& a, hipStream_t st) {
-    TIGAS_JPEG_LAUNCH(k_jpeg_rows, a.h8, st, a);
-    TIGAS_JPEG_LAUNCH(k_jpeg_count, a.h8, st, a);
-    TIGAS_JPEG_LAUNCH(k_jpeg_pack, a.h8, st, a);
+    TIGAS_JPEG_LAUNCH(k_jpeg_seg, a.nseg, st, a);
+    TIGAS_JPEG_LAUNCH(k_jpeg_count, a.nseg, st, a);
+    TIGAS_JPEG_LAUNCH(k_jpeg_pack, a.nseg, st, a);
 }
 
 }  // namespace tigas

@@ -156,26 +156,28 @@ int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npass
 // pinned host memory that receives a copy of the counters.
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    const PreOut& o, const ViewParams* views_dev, hipStream_t st);
-// Baseline JPEG of an RGB8 frame: one workgroup per MCU row (restart
-// interval); the header is written by the host.
-constexpr int JPEG_THREADS = 256;
-constexpr int JPEG_MAX_BLOCKS = 3 * 512;  // blocks of one MCU row: widths up to 4096 pixels
+// Baseline JPEG of an RGB8 frame: one workgroup per restart interval of
+// JPEG_SEG_MCUS MCUs; the header is written by the host.
+constexpr int JPEG_THREADS = 128;
+constexpr int JPEG_SEG_MCUS = 40;  // 120 blocks: one thread each
 struct JpegArgs {
     const uint8_t* rgb;  // H x W x 3, row-major
     int width, height, w8, h8;
+    int64_t n_mcu;  // w8 h8
+    int nseg;       // restart intervals
     float dct[64];        // M[k][n] = c(k)/2 cos((2n+1) k pi/16), FP32
     float rq_luma[64];    // 1/Q, row-major
     float rq_chroma[64];
     const uint32_t* huff;  // [4][256] length << 16 | code: DC luma, AC luma, DC chroma, AC chroma
-    int16_t* coef;         // [h8][3 w8][64] quantised coefficients, zig-zag order
-    uint32_t* bits;        // [h8][row_words] entropy-coded bits of each row (all zero between calls)
-    uint32_t row_words;
-    uint32_t* row_bits;  // [h8] bits of each row
-    uint32_t* seg_len;   // [h8] output bytes of each row (stuffing and marker included)
+    int16_t* coef;         // [nseg][3 JPEG_SEG_MCUS][64] quantised coefficients, zig-zag order
+    uint32_t* bits;        // [nseg][seg_words] entropy-coded bits of each interval (all zero between calls)
+    uint32_t seg_words;
+    uint32_t* seg_bits;  // [nseg] bits of each interval
+    uint32_t* seg_len;   // [nseg] output bytes of each interval (stuffing and marker included)
     uint8_t* out;
     uint64_t capacity;
     uint64_t header_len;
-    uint64_t* out_len;  // total length (written by the last row)
+    uint64_t* out_len;  // total length (written by the last interval)
 };
 void launch_jpeg(const JpegArgs& a, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,

@@ -53,11 +53,11 @@ def test_stream_equals_oracle(ctx, size, q):
     assert got == want
 
 
-def test_wide_rows_and_repeated_calls(ctx):
-    # a 4096-pixel row (the widest: 1536 blocks in one workgroup), then a
-    # smaller frame on the same buffers, then the large one again: the row bit
-    # buffers must come back cleared
-    for H, W, q in ((24, 4096, 90), (16, 40, 35), (24, 4096, 90), (1, 4096, 100)):
+def test_wide_frames_and_repeated_calls(ctx):
+    # wide frames (intervals wrap across MCU rows), then a smaller frame on the
+    # same buffers, then the large one again: the interval bit buffers must
+    # come back cleared
+    for H, W, q in ((24, 4096, 90), (16, 40, 35), (24, 4096, 90), (1, 6000, 100), (300, 9, 65)):
         img = _image(H, W, seed=W + H)
         _say("jpeg", (H, W), q)
         assert ctx.jpeg_bytes(_gpu(img), q) == oj.encode(img, q)
@@ -100,6 +100,6 @@ def test_invalid_arguments(ctx):
     for q in (0, 101):
         with pytest.raises(tigas.TigasError):
             ctx.jpeg_encode(img, q)
-    wide = _gpu(np.zeros((1, 4104, 3), np.uint8))
+    wide = _gpu(np.zeros((1, 65536, 3), np.uint8))
     with pytest.raises(tigas.TigasError):
         ctx.jpeg_encode(wide, 90)

@@ -141,7 +141,9 @@ def test_cosine_pattern_gives_one_coefficient(freq, vertical):
 
 
 def test_restart_markers_and_byte_stuffing():
-    img = _test_image(40, 64, seed=5)
+    img = _test_image(40, 64, seed=5)  # 40 MCUs: no restart marker
+    assert oj.encode(img, 90).count(b"\xff\xd0") == 0
+    img = _test_image(40, 136, seed=5)
     img[:8] = 255  # saturated rows push 0xFF bytes into the entropy-coded data
     b = oj.encode(img, 100)
     _, i = _segments(b)
@@ -157,7 +159,7 @@ def test_restart_markers_and_byte_stuffing():
             j += 2
         else:
             j += 1
-    H8 = (40 + 7) // 8
-    assert rst == [r % 8 for r in range(H8 - 1)]
+    n_mcu = ((40 + 7) // 8) * ((136 + 7) // 8)
+    assert rst == [r % 8 for r in range((n_mcu + 39) // 40 - 1)]  # intervals of 40 MCUs
     assert data.count(b"\xff\x00") > 0
     assert _psnr(_decode(b), img) > 40.0
