@@ -159,6 +159,53 @@ def run_batched(ctx, scene, torch, steps=30, warmup=3):
                 tiles=st["tiles"])
 
 
+def run_jpeg(ctx, tigas, scene, traj, torch, steps=40):
+    """The per-frame payload: each rung of the paper's bitrate ladder (Table 1:
+    320x180 q10, 640x360 q35, 960x540 q65, 1280x720 q90, plus 1920x1080 q90)
+    rendered from the 3M-Gaussian scene and encoded on the GPU.  Per rung:
+    stream bytes, host time per encode call (launches + length read-back),
+    per-kernel GPU times (HIP events), render + encode frames/s, and the JPEG
+    oracle's single-thread time for the same frame."""
+    from oracle import jpeg as oj
+    from paper_2605_08699_amd import synth
+    s = ctx.load_scene(scene, "f32")
+    rungs = []
+    for (w, h, q) in ((320, 180, 10), (640, 360, 35), (960, 540, 65), (1280, 720, 90), (1920, 1080, 90)):
+        k = synth.fov_intrinsics(w, h)
+        frame = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+        out = torch.empty(int(tigas.lib().tigas_jpeg_max_bytes(w, h)), dtype=torch.uint8, device="cuda")
+        for i in range(3):
+            ctx.render(s, traj[i], k, w, h, out=frame)
+            ctx.jpeg_encode(frame, q, out=out)
+        torch.cuda.synchronize()
+        sizes, enc = [], 0.0
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ctx.render(s, traj[i % len(traj)], k, w, h, out=frame)
+            t = time.perf_counter()
+            _, n = ctx.jpeg_encode(frame, q, out=out)
+            enc += time.perf_counter() - t
+            sizes.append(n)
+        total = time.perf_counter() - t0
+        ctx.profile_kernels(True)
+        for _ in range(10):
+            ctx.jpeg_encode(frame, q, out=out)
+        kt = ctx.kernel_times()
+        ctx.profile_kernels(False)
+        kern = {n_: 1e3 * ms / l for n_, (l, ms) in kt.items() if "jpeg" in n_}
+        img = frame.cpu().numpy()
+        t = time.perf_counter()
+        want = oj.encode(img, q)
+        cpu_s = time.perf_counter() - t
+        rungs.append(dict(width=w, height=h, quality=q, bytes_mean=float(np.mean(sizes)),
+                          stream_equals_oracle=ctx.jpeg_bytes(frame, q) == want,
+                          encode_ms=1e3 * enc / steps, kernel_us=kern, kernel_us_total=sum(kern.values()),
+                          render_encode_frames_per_s=steps / total,
+                          cpu_oracle_encode_ms=1e3 * cpu_s))
+    s.free()
+    return dict(rungs=rungs, cpu_oracle_threads=1)
+
+
 def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0, 50.0), budget_gb=48,
                 batch_mpx=6.0):
     """The serving form: 64 clients (Poisson arrivals, random rungs of
@@ -334,6 +381,7 @@ def main():
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-jpeg", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--tile", default=None,
                     help="W,H,batch_depth,pixels_per_lane for the single-view variants (default: autotuned)")
@@ -404,6 +452,11 @@ def main():
         line["batched"] = run_batched(ctx, scene, torch)
         print(f"# batched: {line['batched']['views_per_s']:.0f} views/s "
               f"(one by one: {line['batched']['sequential_views_per_s']:.0f})", file=sys.stderr, flush=True)
+    if not args.no_jpeg:
+        line["jpeg"] = run_jpeg(ctx, tigas, scene, traj, torch)
+        r = line["jpeg"]["rungs"][3]
+        print(f"# jpeg 1280x720 q90: {r['bytes_mean'] / 1024:.0f} KiB, encode {r['encode_ms']:.3f} ms per call, "
+              f"render+encode {r['render_encode_frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
     if not args.no_serving:
         line["serving"] = run_serving(ctx, torch, tigas, seconds=args.serve_seconds)
         f = line["serving"]["full_load_latest_pose_wins"]
