@@ -286,9 +286,9 @@ struct Workspace {
     int next_async = 0;  // slot for the next asynchronous frame
     FrameSlot& fs() { return slot[active]; }
     DevBuf work;            // blend work counters (evaluations, contributions)
-    // JPEG encoder: coefficients, per-interval bit buffers (all zero between
-    // calls), per-interval bit counts and output lengths, code tables, length
-    DevBuf jpeg_coef, jpeg_bits, jpeg_seg_bits, jpeg_seg_len, jpeg_huff, jpeg_len;
+    // JPEG encoder: per-interval bit buffers (all zero between calls),
+    // per-interval bit counts and output lengths, code tables, length
+    DevBuf jpeg_bits, jpeg_seg_bits, jpeg_seg_len, jpeg_huff, jpeg_len;
     HostPinned jpeg_len_host;
     hipEvent_t ev[7] = {};  // stage boundaries when stage timing is on
     EventTimer ktimer;      // per-launch events when kernel timing is on
@@ -1901,7 +1901,6 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
         a.nseg = (int)((a.n_mcu + JPEG_SEG_MCUS - 1) / JPEG_SEG_MCUS);
         const size_t nb = 3 * (size_t)JPEG_SEG_MCUS;
         a.seg_words = (uint32_t)((nb * kBlockMaxBits + 31) / 32 + 1);
-        ws.jpeg_coef.ensure((size_t)a.nseg * nb * 64 * 2);
         const size_t bits_bytes = (size_t)a.nseg * a.seg_words * 4;
         if (ws.jpeg_bits.ensure(bits_bytes)) HIPCHK(hipMemset(ws.jpeg_bits.p, 0, ws.jpeg_bits.bytes));
         ws.jpeg_seg_bits.ensure((size_t)a.nseg * 4);
@@ -1929,7 +1928,6 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
         const std::vector<uint8_t> hdr = jpeg_header(width, height, ql, qc);
         HIPCHK(hipMemcpyAsync(out, hdr.data(), std::min(hdr.size(), capacity), hipMemcpyHostToDevice, st));
         a.huff = ws.jpeg_huff.as<uint32_t>();
-        a.coef = ws.jpeg_coef.as<int16_t>();
         a.bits = ws.jpeg_bits.as<uint32_t>();
         a.seg_bits = ws.jpeg_seg_bits.as<uint32_t>();
         a.seg_len = ws.jpeg_seg_len.as<uint32_t>();

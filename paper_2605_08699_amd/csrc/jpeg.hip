@@ -4,7 +4,7 @@
 //
 //   k_jpeg_seg    one workgroup per restart interval (40 MCUs in raster
 //                 order, one thread per 8x8 block): colour transform, forward
-//                 DCT and quantisation, the entropy-coded length of each block
+//                 DCT and quantisation into LDS, the entropy-coded length of each block
 //                 (DC prediction inside the interval), a workgroup scan of
 //                 those lengths, then each block's Huffman codes ORed into the
 //                 interval's bit buffer at its offset
@@ -136,6 +136,11 @@ __device__ __forceinline__ uint32_t row_byte(const uint32_t* buf, uint32_t j, ui
 
 __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     static_assert(3 * JPEG_SEG_MCUS <= JPEG_THREADS, "one thread per block of an interval");
+    // quantised coefficients of the interval in zig-zag order, one block per
+    // thread; rows of 66 halves (33 words) so that the 64 lanes reading
+    // coefficient i of their blocks meet in different LDS banks
+    constexpr int ZS = 66;
+    __shared__ int16_t s_coef[3 * JPEG_SEG_MCUS * ZS];
     __shared__ int32_t s_dc[3 * JPEG_SEG_MCUS];
     __shared__ uint32_t s_huff[4 * 256];
     __shared__ uint32_t s_scan[JPEG_THREADS];
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     const int64_t m0 = (int64_t)seg * JPEG_SEG_MCUS;
     const int nb = 3 * (int)min((int64_t)JPEG_SEG_MCUS, a.n_mcu - m0);
     for (int i = t; i < 4 * 256; i += JPEG_THREADS) s_huff[i] = a.huff[i];
-    int16_t* zq = a.coef + ((size_t)seg * 3 * JPEG_SEG_MCUS + t) * 64;
+    int16_t* zq = s_coef + (t < 3 * JPEG_SEG_MCUS ? t : 0) * ZS;
     const int comp = t % 3;
 
     // transform and quantise block t (Y, Cb, Cr of each MCU)
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     uint32_t len = 0;
     if (t < nb) {
         BitCount c;
-        code_block(zq, pred, hdc, hac, c);  // coefficients written by this thread above
+        code_block(zq, pred, hdc, hac, c);  // this thread's own block
         len = c.n;
     }
     uint32_t total;

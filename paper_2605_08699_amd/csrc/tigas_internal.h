@@ -169,7 +169,6 @@ struct JpegArgs {
     float rq_luma[64];    // 1/Q, row-major
     float rq_chroma[64];
     const uint32_t* huff;  // [4][256] length << 16 | code: DC luma, AC luma, DC chroma, AC chroma
-    int16_t* coef;         // [nseg][3 JPEG_SEG_MCUS][64] quantised coefficients, zig-zag order
     uint32_t* bits;        // [nseg][seg_words] entropy-coded bits of each interval (all zero between calls)
     uint32_t seg_words;
     uint32_t* seg_bits;  // [nseg] bits of each interval

@@ -3,8 +3,13 @@
     python -m paper_2605_08699_amd.profiling stats KERNEL_STATS_CSV OUT_MD --command CMD [--title T]
     python -m paper_2605_08699_amd.profiling traffic FETCH_CSV WRITE_CSV OUT_MD --fetch-command CMD
         --write-command CMD [--copy-bytes N]
+    python -m paper_2605_08699_amd.profiling launches KERNEL_TRACE_CSV OUT_MD --match SUBSTR --command CMD
+        [--title T]
 
 `stats` turns a `--kernel-trace --stats` kernel_stats.csv into a table.
+`launches` groups the dispatches of the kernels whose name contains SUBSTR
+in a kernel_trace.csv by (kernel, workgroups): one launch shape per frame
+size, so sizes that share a kernel get a row each.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` counter_collection
 CSVs into HBM bytes per launch of every kernel.  The counters are scaled by
 what they read for the plain device-to-device copies of known size that
@@ -44,6 +49,21 @@ def stats(src, dst, command, title):
             name = short(r["Name"]).replace("|", "/")
             f.write(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |\n")
+
+
+def launches(src, dst, match, command, title):
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(src)):
+        n = r["Kernel_Name"]
+        if match not in n:
+            continue
+        wg = int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1)
+        acc[(short(n), wg)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    with open(dst, "w") as f:
+        f.write(f"# {title}\n\nCommand (run from the repository root on one MI355X):\n\n```\n{command}\n```\n\n")
+        f.write("| kernel | workgroups | launches | avg us | min us | max us |\n|---|---:|---:|---:|---:|---:|\n")
+        for (n, wg), ts in sorted(acc.items(), key=lambda kv: (kv[0][1], kv[0][0])):
+            f.write(f"| `{n}` | {wg} | {len(ts)} | {sum(ts) / len(ts):.1f} | {min(ts):.1f} | {max(ts):.1f} |\n")
 
 
 def per_dispatch(path):
@@ -134,9 +154,17 @@ def main():
     b.add_argument("--fetch-command", required=True)
     b.add_argument("--write-command", required=True)
     b.add_argument("--copy-bytes", type=int, default=1 << 30)
+    c = sub.add_parser("launches")
+    c.add_argument("src")
+    c.add_argument("dst")
+    c.add_argument("--match", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="rocprofv3 launches")
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.src, args.dst, args.command, args.title)
+    elif args.cmd == "launches":
+        launches(args.src, args.dst, args.match, args.command, args.title)
     else:
         traffic(args.fetch, args.write, args.dst, args.fetch_command, args.write_command, args.copy_bytes)
 
