@@ -144,26 +144,38 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     __shared__ int32_t s_dc[3 * JPEG_SEG_MCUS];
     __shared__ uint32_t s_huff[4 * 256];
     __shared__ uint32_t s_scan[JPEG_THREADS];
+    __shared__ uint8_t s_pix[JPEG_SEG_MCUS * 64 * 3];  // the interval's 8x8 pixel blocks, edges repeated
     const int seg = blockIdx.x, t = threadIdx.x;
     const int64_t m0 = (int64_t)seg * JPEG_SEG_MCUS;
-    const int nb = 3 * (int)min((int64_t)JPEG_SEG_MCUS, a.n_mcu - m0);
+    const int nm = (int)min((int64_t)JPEG_SEG_MCUS, a.n_mcu - m0);
+    const int nb = 3 * nm;
     for (int i = t; i < 4 * 256; i += JPEG_THREADS) s_huff[i] = a.huff[i];
+    // the pixels of the interval, staged once: consecutive threads read
+    // consecutive pixels of a block row (the three component threads of an
+    // MCU share them)
+    for (int i = t; i < nm * 64; i += JPEG_THREADS) {
+        const int64_t mcu = m0 + i / 64;
+        const int x = min((int)(mcu % a.w8) * 8 + (i & 7), a.width - 1);
+        const int y = min((int)(mcu / a.w8) * 8 + ((i >> 3) & 7), a.height - 1);
+        const uint8_t* p = a.rgb + ((size_t)y * a.width + x) * 3;
+        s_pix[3 * i] = p[0];
+        s_pix[3 * i + 1] = p[1];
+        s_pix[3 * i + 2] = p[2];
+    }
+    __syncthreads();
     int16_t* zq = s_coef + (t < 3 * JPEG_SEG_MCUS ? t : 0) * ZS;
     const int comp = t % 3;
 
     // transform and quantise block t (Y, Cb, Cr of each MCU)
     if (t < nb) {
-        const int64_t mcu = m0 + t / 3;
-        const int x0 = (int)(mcu % a.w8) * 8, y0 = (int)(mcu / a.w8) * 8;
+        const uint8_t* px = s_pix + (t / 3) * 64 * 3;
         float tr[64];  // rows transformed along x: tr[r][l]
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int y = min(y0 + r, a.height - 1);
             float f[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const int x = min(x0 + c, a.width - 1);
-                const uint8_t* p = a.rgb + ((size_t)y * a.width + x) * 3;
+                const uint8_t* p = px + (r * 8 + c) * 3;
                 const float R = (float)p[0], G = (float)p[1], B = (float)p[2];
                 float v;
                 if (comp == 0) v = __builtin_fmaf(0.114f, B, __builtin_fmaf(0.587f, G, 0.299f * R)) - 128.0f;
