@@ -350,8 +350,9 @@ tigas_status tigas_render_debug(tigas_scene* scene, const tigas_pose* pose, cons
                                 tigas_debug_out* dbg);
 
 /* Baseline JPEG of an RGB8 frame in device memory: the per-frame payload of
- * the paper's transport (Section 3: one stateless JPEG per request), at a
- * quality factor of its bitrate ladder (Table 1: 10, 35, 65, 90).  Format:
+ * the paper's backend (Section 5.1: frames leave as 8-bit JPEG; Sections 4.2
+ * and 5.2: one stateless JPEG per request), at a quality factor of its
+ * bitrate ladder (Table 1: 10, 35, 65, 90).  Format:
  * JFIF, YCbCr 4:4:4, the Annex K quantisation tables of ITU-T T.81 scaled by
  * quality (5000/q percent below 50, else 200 - 2q, clamped to 1..255) and its
  * Annex K Huffman tables, restart intervals of 40 MCUs (8x8 pixel blocks).

@@ -1,6 +1,7 @@
 // Baseline JPEG encoder for CDNA4 (gfx950): the per-frame payload of the
-// paper's backend (Section 3 transport: one stateless JPEG per request; the
-// bitrate ladder of Table 1 pairs each resolution with a quality factor).
+// paper's backend (Section 5.1, Rendering Engine: frames leave as 8-bit JPEG;
+// Sections 4.2 and 5.2: one stateless JPEG per request; Table 1 pairs each
+// resolution of the bitrate ladder with a quality factor).
 //
 //   k_jpeg_seg    one workgroup per restart interval (40 MCUs in raster
 //                 order, one thread per 8x8 block): colour transform, forward
