@@ -214,25 +214,29 @@ def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.
     server (2 slots, memory budget).  Full offered load (60 req/s per client)
     with latest-pose-wins, then a rate sweep without supersession to find the
     largest per-client rate whose p99 latency for 1080p frames of the 3M scene
-    stays within 10 ms."""
+    stays within 10 ms; then full load and 40 req/s per client again with each
+    frame also encoded as its JPEG payload."""
     from paper_2605_08699_amd import synth
     scenes = [ctx.load_scene(sc, "f16") for sc in synth.serving_scenes()]
     k = synth.fov_intrinsics(1920, 1080)
     outs = [torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda") for _ in range(64)]
+    jpeg_outs = [torch.empty(8 << 20, dtype=torch.uint8, device="cuda") for _ in range(64)]
+    ladder_q = {0.25: 10, 0.5: 35, 0.75: 65, 1.0: 90}
 
-    def trace(rate):
+    def trace(rate, jpeg=False):
         clients = synth.serving_clients(64, rate_hz=rate, duration_s=seconds)
         reqs, meta = [], []
         for c, cl in enumerate(clients):
             for j in range(len(cl.arrivals_s)):
                 reqs.append((cl.arrivals_s[j], c, cl.scene_id, cl.poses[j], float(cl.rungs[j])))
         reqs.sort(key=lambda r: r[0])
-        cs = [tigas.request_c(scenes[sid], pose, k, 1920, 1080, outs[c], client=c, arrival_s=t, res_scale=rung)
+        cs = [tigas.request_c(scenes[sid], pose, k, 1920, 1080, outs[c], client=c, arrival_s=t, res_scale=rung,
+                              jpeg_quality=ladder_q[rung] if jpeg else 0, jpeg_out=jpeg_outs[c] if jpeg else None)
               for t, c, sid, pose, rung in reqs]
         return cs, reqs
 
-    def run(rate, supersede):
-        cs, reqs = trace(rate)
+    def run(rate, supersede, jpeg=False):
+        cs, reqs = trace(rate, jpeg)
         with tigas.Server(ctx, slots=2, max_batch=64, hbm_budget=int(budget_gb * 2 ** 30), supersede=supersede,
                           max_batch_pixels=int(batch_mpx * 1e6)) as sv:
             done = sv.replay(cs)
@@ -246,21 +250,30 @@ def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.
             if r[2] == 2 and r[4] == 1.0:
                 lat_hd.append(ms)
         rendered = sum(1 for d, r in zip(done, reqs) if d["status"] == 0 and r[0] >= warm)
+        jb = [d["jpeg_bytes"] for d, r in zip(done, reqs) if d["status"] == 0 and r[0] >= warm and jpeg]
         pct = lambda a, q: float(np.percentile(a, q)) if a else None
         return dict(rate_per_client=rate, offered_req_per_s=len(reqs) / seconds, rendered_frames_per_s=rendered /
                     (seconds - warm), p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p50_ms_1080p_3M=pct(lat_hd, 50),
                     p99_ms_1080p_3M=pct(lat_hd, 99), superseded=st["superseded"], deferred=st["deferred"],
                     admitted=st["admitted"], batches=st["batches"],
-                    mean_batch=st["admitted"] / max(st["batches"], 1), failed=st["failed"])
+                    mean_batch=st["admitted"] / max(st["batches"], 1), failed=st["failed"],
+                    jpeg_mean_bytes=float(np.mean(jb)) if jb else None,
+                    jpeg_over_capacity=sum(1 for b in jb if b > (8 << 20)))
 
     full = run(60.0, True)
     sweep = [run(r, False) for r in rates]
+    # the same with the per-request payload: every frame also encoded as the
+    # JPEG of its rung's quality (Table 1), done when the payload is
+    full_jpeg = run(60.0, True, jpeg=True)
+    at40_jpeg = run(40.0, False, jpeg=True)
     ok = [x["rate_per_client"] for x in sweep if x["p99_ms_1080p_3M"] is not None and x["p99_ms_1080p_3M"] <= 10.0]
     for s_ in scenes:
         s_.free()
     return dict(seconds=seconds, warmup_s=warm, clients=64, hbm_budget_gb=budget_gb, slots=2,
                 max_batch_megapixels=batch_mpx,
                 full_load_latest_pose_wins=full, sweep_no_supersede=sweep,
+                with_jpeg={"full_load_latest_pose_wins": full_jpeg, "rate_40_no_supersede": at40_jpeg,
+                           "quality_by_rung": {str(k_): v for k_, v in ladder_q.items()}},
                 max_rate_per_client_p99_1080p_3M_within_10ms=max(ok) if ok else None)
 
 
@@ -462,6 +475,10 @@ def main():
         f = line["serving"]["full_load_latest_pose_wins"]
         print(f"# serving at {f['offered_req_per_s']:.0f} req/s offered: {f['rendered_frames_per_s']:.0f} frames/s, "
               f"p50 {f['p50_ms']:.2f} ms p99 {f['p99_ms']:.2f} ms (1080p 3M: p99 {f['p99_ms_1080p_3M']})",
+              file=sys.stderr, flush=True)
+        j = line["serving"]["with_jpeg"]["rate_40_no_supersede"]
+        print(f"# serving with JPEG payloads at 40 req/s per client: {j['rendered_frames_per_s']:.0f} frames/s, "
+              f"p99 {j['p99_ms']:.2f} ms (1080p 3M: p99 {j['p99_ms_1080p_3M']}), mean {j['jpeg_mean_bytes']:.0f} B",
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, traj[0], k, W, H)

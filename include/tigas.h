@@ -267,7 +267,10 @@ typedef struct {
 } tigas_server_config;
 
 /* One request.  The output frame must stay valid until its completion is
- * reported; `arrival_s` is used only by tigas_server_replay. */
+ * reported; `arrival_s` is used only by tigas_server_replay.  With
+ * jpeg_quality 1..100 the frame (RGB8, device memory) is also encoded as the
+ * per-request payload (tigas_jpeg_encode's format) into the device buffer
+ * jpeg_out of jpeg_capacity bytes; 0 = no JPEG. */
 typedef struct {
     tigas_scene* scene;
     tigas_pose pose;
@@ -277,6 +280,9 @@ typedef struct {
     tigas_frame out;
     int client;
     double arrival_s;
+    int jpeg_quality;
+    void* jpeg_out;
+    size_t jpeg_capacity;
 } tigas_request;
 
 /* status: 0 rendered, 1 superseded (not rendered), < 0 a tigas_status error.
@@ -285,8 +291,9 @@ typedef struct {
     int64_t id;
     int client;
     int status;
-    double arrival_s, dispatch_s, done_s;
+    double arrival_s, dispatch_s, done_s; /* done: frame and payload complete */
     int batch_size;
+    int64_t jpeg_bytes; /* stream length (above jpeg_capacity: only a prefix was written); 0 without JPEG */
 } tigas_completion;
 
 typedef struct {

@@ -1215,6 +1215,19 @@ void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_
 
 // ================================================================ serving
 
+// One JPEG of an RGB8 device frame (the result: the stream length).
+struct JpegJob {
+    const uint8_t* rgb;
+    int width, height, quality;
+    uint8_t* out;
+    size_t capacity;
+    uint64_t bytes;
+};
+void check_jpeg_args(int width, int height, int quality);
+// Encodes the jobs one after another on `st` with the workspace's scratch
+// buffers, then waits for the stream and fills in the lengths.
+void jpeg_encode_jobs(tigas_context* ctx, Workspace& ws, hipStream_t st, JpegJob* jobs, int n);
+
 struct tigas_server {
     tigas_context* ctx = nullptr;
     tigas_server_config cfg{};
@@ -1225,6 +1238,7 @@ struct tigas_server {
         tigas_request r;
         double arrival, dispatch = 0, done = 0;
         size_t need = 0;
+        int64_t jpeg_bytes = 0;
     };
     struct Slot {
         hipStream_t stream = nullptr;
@@ -1311,6 +1325,22 @@ void server_render(tigas_server* sv, tigas_server::Slot& slot) {
     q.pixels_per_lane = sv->cfg.pixels_per_lane;
     Workspace& ws = ctx->workspace(slot.stream);
     render_views(ctx, ws, plan, &q, outs.data(), nullptr, nullptr);
+    // the payload: a JPEG of each frame that asks for one, on the same stream
+    std::vector<JpegJob> jobs;
+    std::vector<size_t> job_req;
+    for (size_t i = 0; i < b.size(); ++i) {
+        const tigas_request& r = b[i].r;
+        if (r.jpeg_quality <= 0) continue;
+        const tigas_frame& f = outs[i];  // out_w / out_h filled in by the render
+        jobs.push_back({(const uint8_t*)f.data, f.out_w, f.out_h, r.jpeg_quality, (uint8_t*)r.jpeg_out,
+                        r.jpeg_capacity, 0});
+        job_req.push_back(i);
+    }
+    if (!jobs.empty()) {
+        std::lock_guard<std::mutex> wl(ws.mu);
+        jpeg_encode_jobs(ctx, ws, slot.stream, jobs.data(), (int)jobs.size());
+        for (size_t k = 0; k < jobs.size(); ++k) b[job_req[k]].jpeg_bytes = (int64_t)jobs[k].bytes;
+    }
     std::lock_guard<std::mutex> lk(sv->mu);
     const double dpr = (double)ws.last_D / std::max<double>(1.0, (double)plan.nrec);
     sv->dup_per_rec = std::max(sv->dup_per_rec, dpr);
@@ -1347,6 +1377,7 @@ void slot_main(tigas_server* sv, tigas_server::Slot* slot) {
             c.dispatch_s = r.dispatch;
             c.done_s = t_done;
             c.batch_size = (int)slot->batch.size();
+            c.jpeg_bytes = r.jpeg_bytes;
             sv->completed.push_back(c);
         }
         sv->finished += (int64_t)slot->batch.size();
@@ -1421,6 +1452,13 @@ void validate_request(tigas_server* sv, const tigas_request* r) {
     if (r->scene->ctx != sv->ctx) fail(TIGAS_E_INVALID, "scene belongs to another context");
     (void)make_view(r->scene, &r->pose, &r->intr, r->width, r->height, &r->q);
     if (!r->out.data) fail(TIGAS_E_INVALID, "request without an output frame");
+    if (r->jpeg_quality != 0) {
+        if (!r->out.is_device || r->q.fmt != TIGAS_OUT_RGB8)
+            fail(TIGAS_E_INVALID, "a JPEG needs an RGB8 frame in device memory");
+        if (!r->jpeg_out || r->jpeg_capacity == 0) fail(TIGAS_E_INVALID, "request without a JPEG buffer");
+        const float s = r->q.res_scale != 0.f ? r->q.res_scale : 1.f;
+        check_jpeg_args((int)std::lround(r->width * (double)s), (int)std::lround(r->height * (double)s), r->jpeg_quality);
+    }
     if (sv->cfg.hbm_budget && request_need(sv, *r) > sv->cfg.hbm_budget / sv->slots.size())
         fail(TIGAS_E_BUDGET, "request needs more workspace than a slot's share of the memory budget");
 }
@@ -1600,6 +1638,77 @@ std::vector<uint8_t> jpeg_header(int W, int H, const uint8_t* ql, const uint8_t*
 constexpr uint32_t kBlockMaxBits = 22 + 63 * 26;
 
 }  // namespace
+
+void check_jpeg_args(int width, int height, int quality) {
+    if (width < 1 || width > 65535 || height < 1 || height > 65535)
+        fail(TIGAS_E_INVALID, "jpeg: width and height must be 1..65535");
+    if (quality < 1 || quality > 100) fail(TIGAS_E_INVALID, "jpeg: quality must be 1..100");
+}
+
+void jpeg_encode_jobs(tigas_context* ctx, Workspace& ws, hipStream_t st, JpegJob* jobs, int n) {
+    if (n <= 0) return;
+    const uint32_t seg_words = (uint32_t)((3 * JPEG_SEG_MCUS * (size_t)kBlockMaxBits + 31) / 32 + 1);
+    int max_seg = 1;
+    for (int i = 0; i < n; ++i) {
+        const int64_t n_mcu = (int64_t)((jobs[i].width + 7) / 8) * ((jobs[i].height + 7) / 8);
+        max_seg = std::max(max_seg, (int)((n_mcu + JPEG_SEG_MCUS - 1) / JPEG_SEG_MCUS));
+    }
+    if (ws.jpeg_bits.ensure((size_t)max_seg * seg_words * 4)) HIPCHK(hipMemset(ws.jpeg_bits.p, 0, ws.jpeg_bits.bytes));
+    ws.jpeg_seg_bits.ensure((size_t)max_seg * 4);
+    ws.jpeg_seg_len.ensure((size_t)max_seg * 4);
+    ws.jpeg_huff.ensure(4 * 256 * 4);
+    ws.jpeg_len.ensure((size_t)n * 8);
+    ws.jpeg_len_host.ensure((size_t)n * 8);
+    uint32_t codes[4 * 256];
+    for (int t = 0; t < 4; ++t) huff_codes(kHuff[t], codes + 256 * t);
+    HIPCHK(hipMemcpyAsync(ws.jpeg_huff.p, codes, sizeof codes, hipMemcpyHostToDevice, st));
+    float dct[64];
+    for (int k = 0; k < 8; ++k)
+        for (int m = 0; m < 8; ++m) {  // rounded once from FP64
+            const double ck = k == 0 ? std::sqrt(0.5) : 1.0;
+            dct[k * 8 + m] = (float)(0.5 * ck * std::cos((2 * m + 1) * k * 3.14159265358979323846 / 16.0));
+        }
+    const bool kprof = ctx->profile_kernels.load();
+    if (kprof) ws.ktimer.reset();
+    TimerScope ts(kprof ? &ws.ktimer : nullptr);
+    std::vector<std::vector<uint8_t>> hdrs(n);  // alive until the stream has finished
+    for (int i = 0; i < n; ++i) {
+        const JpegJob& j = jobs[i];
+        JpegArgs a{};
+        a.rgb = j.rgb;
+        a.width = j.width;
+        a.height = j.height;
+        a.w8 = (j.width + 7) / 8;
+        a.h8 = (j.height + 7) / 8;
+        a.n_mcu = (int64_t)a.w8 * a.h8;
+        a.nseg = (int)((a.n_mcu + JPEG_SEG_MCUS - 1) / JPEG_SEG_MCUS);
+        a.seg_words = seg_words;
+        uint8_t ql[64], qc[64];
+        scaled_qtable(kQLuma, j.quality, ql);
+        scaled_qtable(kQChroma, j.quality, qc);
+        for (int k = 0; k < 64; ++k) {
+            a.rq_luma[k] = 1.0f / (float)ql[k];
+            a.rq_chroma[k] = 1.0f / (float)qc[k];
+            a.dct[k] = dct[k];
+        }
+        hdrs[i] = jpeg_header(j.width, j.height, ql, qc);
+        HIPCHK(hipMemcpyAsync(j.out, hdrs[i].data(), std::min(hdrs[i].size(), j.capacity), hipMemcpyHostToDevice, st));
+        a.huff = ws.jpeg_huff.as<uint32_t>();
+        a.bits = ws.jpeg_bits.as<uint32_t>();
+        a.seg_bits = ws.jpeg_seg_bits.as<uint32_t>();
+        a.seg_len = ws.jpeg_seg_len.as<uint32_t>();
+        a.out = j.out;
+        a.capacity = j.capacity;
+        a.header_len = hdrs[i].size();
+        a.out_len = ws.jpeg_len.as<uint64_t>() + i;
+        launch_jpeg(a, st);  // jobs run one after another on the stream and share the scratch buffers
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ws.jpeg_len_host.p, ws.jpeg_len.p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (kprof) record_kernel_times(ctx, ws);
+    for (int i = 0; i < n; ++i) std::memcpy(&jobs[i].bytes, (const uint8_t*)ws.jpeg_len_host.p + 8 * i, 8);
+}
 
 extern "C" {
 
@@ -1884,68 +1993,15 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
                                size_t capacity, size_t* out_len, void* hip_stream) {
     return guard([&] {
         if (!ctx || !rgb || !out || !out_len) fail(TIGAS_E_INVALID, "null argument");
-        if (width < 1 || width > 65535 || height < 1 || height > 65535)
-            fail(TIGAS_E_INVALID, "jpeg: width and height must be 1..65535");
-        if (quality < 1 || quality > 100) fail(TIGAS_E_INVALID, "jpeg: quality must be 1..100");
+        check_jpeg_args(width, height, quality);
         HIPCHK(hipSetDevice(ctx->device));
         hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
         Workspace& ws = ctx->workspace(st);
         std::lock_guard<std::mutex> lk(ws.mu);
-        JpegArgs a{};
-        a.rgb = (const uint8_t*)rgb;
-        a.width = width;
-        a.height = height;
-        a.w8 = (width + 7) / 8;
-        a.h8 = (height + 7) / 8;
-        a.n_mcu = (int64_t)a.w8 * a.h8;
-        a.nseg = (int)((a.n_mcu + JPEG_SEG_MCUS - 1) / JPEG_SEG_MCUS);
-        const size_t nb = 3 * (size_t)JPEG_SEG_MCUS;
-        a.seg_words = (uint32_t)((nb * kBlockMaxBits + 31) / 32 + 1);
-        const size_t bits_bytes = (size_t)a.nseg * a.seg_words * 4;
-        if (ws.jpeg_bits.ensure(bits_bytes)) HIPCHK(hipMemset(ws.jpeg_bits.p, 0, ws.jpeg_bits.bytes));
-        ws.jpeg_seg_bits.ensure((size_t)a.nseg * 4);
-        ws.jpeg_seg_len.ensure((size_t)a.nseg * 4);
-        ws.jpeg_huff.ensure(4 * 256 * 4);
-        ws.jpeg_len.ensure(8);
-        ws.jpeg_len_host.ensure(8);
-        // tables: quantisation steps as FP32 reciprocals, the DCT matrix
-        // rounded once from FP64, the canonical Huffman codes
-        uint8_t ql[64], qc[64];
-        scaled_qtable(kQLuma, quality, ql);
-        scaled_qtable(kQChroma, quality, qc);
-        for (int i = 0; i < 64; ++i) {
-            a.rq_luma[i] = 1.0f / (float)ql[i];
-            a.rq_chroma[i] = 1.0f / (float)qc[i];
-        }
-        for (int k = 0; k < 8; ++k)
-            for (int n = 0; n < 8; ++n) {
-                const double ck = k == 0 ? std::sqrt(0.5) : 1.0;
-                a.dct[k * 8 + n] = (float)(0.5 * ck * std::cos((2 * n + 1) * k * 3.14159265358979323846 / 16.0));
-            }
-        uint32_t codes[4 * 256];
-        for (int t = 0; t < 4; ++t) huff_codes(kHuff[t], codes + 256 * t);
-        HIPCHK(hipMemcpyAsync(ws.jpeg_huff.p, codes, sizeof codes, hipMemcpyHostToDevice, st));
-        const std::vector<uint8_t> hdr = jpeg_header(width, height, ql, qc);
-        HIPCHK(hipMemcpyAsync(out, hdr.data(), std::min(hdr.size(), capacity), hipMemcpyHostToDevice, st));
-        a.huff = ws.jpeg_huff.as<uint32_t>();
-        a.bits = ws.jpeg_bits.as<uint32_t>();
-        a.seg_bits = ws.jpeg_seg_bits.as<uint32_t>();
-        a.seg_len = ws.jpeg_seg_len.as<uint32_t>();
-        a.out = (uint8_t*)out;
-        a.capacity = capacity;
-        a.header_len = hdr.size();
-        a.out_len = ws.jpeg_len.as<uint64_t>();
-        if (ctx->profile_kernels.load()) ws.ktimer.reset();
-        TimerScope ts(ctx->profile_kernels.load() ? &ws.ktimer : nullptr);
-        launch_jpeg(a, st);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(ws.jpeg_len_host.p, ws.jpeg_len.p, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (ctx->profile_kernels.load()) record_kernel_times(ctx, ws);
-        uint64_t n = 0;
-        std::memcpy(&n, ws.jpeg_len_host.p, 8);
-        *out_len = (size_t)n;
-        if (n > capacity) fail(TIGAS_E_BUFFER, "jpeg: output buffer smaller than the stream");
+        JpegJob job{(const uint8_t*)rgb, width, height, quality, (uint8_t*)out, capacity, 0};
+        jpeg_encode_jobs(ctx, ws, st, &job, 1);
+        *out_len = (size_t)job.bytes;
+        if (job.bytes > capacity) fail(TIGAS_E_BUFFER, "jpeg: output buffer smaller than the stream");
     });
 }
 

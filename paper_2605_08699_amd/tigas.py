@@ -432,13 +432,14 @@ class ServerConfigC(ctypes.Structure):
 class RequestC(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_void_p), ("pose", PoseC), ("intr", IntrC), ("width", ctypes.c_int),
                 ("height", ctypes.c_int), ("q", QualityC), ("out", FrameC), ("client", ctypes.c_int),
-                ("arrival_s", ctypes.c_double)]
+                ("arrival_s", ctypes.c_double), ("jpeg_quality", ctypes.c_int), ("jpeg_out", ctypes.c_void_p),
+                ("jpeg_capacity", ctypes.c_size_t)]
 
 
 class CompletionC(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("client", ctypes.c_int), ("status", ctypes.c_int),
                 ("arrival_s", ctypes.c_double), ("dispatch_s", ctypes.c_double), ("done_s", ctypes.c_double),
-                ("batch_size", ctypes.c_int)]
+                ("batch_size", ctypes.c_int), ("jpeg_bytes", ctypes.c_int64)]
 
 
 class ServerStatsC(ctypes.Structure):
@@ -471,9 +472,11 @@ def _server_lib():
 
 
 def request_c(scene: Scene, pose, intr, width, height, out, client=0, arrival_s=0.0, res_scale=1.0, fmt="rgb8",
-              bg=(0, 0, 0)):
+              bg=(0, 0, 0), jpeg_quality=0, jpeg_out=None):
     """One request; ``out`` is a torch GPU tensor or a host numpy array of the
-    output frame (kept alive by the caller until it completes)."""
+    output frame (kept alive by the caller until it completes).  With
+    ``jpeg_quality`` the frame is also encoded into the GPU uint8 tensor
+    ``jpeg_out``."""
     r = RequestC()
     r.scene = scene.handle.value if isinstance(scene.handle, ctypes.c_void_p) else scene.handle
     r.pose = pose_c(pose)
@@ -486,6 +489,10 @@ def request_c(scene: Scene, pose, intr, width, height, out, client=0, arrival_s=
         r.out = FrameC(ctypes.c_void_p(int(out.data_ptr())), out.numel() * out.element_size(), 1, 0, 0)
     r.client = int(client)
     r.arrival_s = float(arrival_s)
+    if jpeg_quality:
+        r.jpeg_quality = int(jpeg_quality)
+        r.jpeg_out = ctypes.c_void_p(int(jpeg_out.data_ptr()))
+        r.jpeg_capacity = jpeg_out.numel()
     return r
 
 
@@ -541,4 +548,5 @@ class Server:
 
 def _completion_dict(c):
     return dict(id=int(c.id), client=int(c.client), status=int(c.status), arrival_s=c.arrival_s,
-                dispatch_s=c.dispatch_s, done_s=c.done_s, batch_size=int(c.batch_size))
+                dispatch_s=c.dispatch_s, done_s=c.done_s, batch_size=int(c.batch_size),
+                jpeg_bytes=int(c.jpeg_bytes))

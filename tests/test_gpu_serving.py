@@ -3,7 +3,9 @@ under a memory budget.  Every rendered frame must be identical to rendering
 the request alone."""
 import numpy as np
 import pytest
+import torch
 
+from oracle import jpeg as oj
 from paper_2605_08699_amd import synth, tigas
 from tests.handmade import random_tiny_scene
 
@@ -67,6 +69,44 @@ def test_results_identical_alone_and_in_the_mix(ctx, scenes):
     assert st["batches"] < 40 and st["max_batch_seen"] > 1      # requests were batched together
     for i in range(40):
         np.testing.assert_array_equal(outs[i], _alone(ctx, meta[i]), err_msg=f"request {i}")
+
+
+def test_jpeg_payloads_in_the_mix(ctx, scenes):
+    # RGB8 frames in device memory, each encoded as its request's JPEG at the
+    # quality of its rung (the ladder pairs 10/35/65/90 with rising size)
+    quality = {0.25: 10, 0.5: 35, 0.75: 65, 1.0: 90}
+    rng = np.random.default_rng(31)
+    traj = synth.trajectory(seed=31, n_poses=24)
+    k = synth.fov_intrinsics(W, H)
+    reqs, frames, jpegs, meta = [], [], [], []
+    for i in range(24):
+        sc = scenes[int(rng.integers(0, len(scenes)))]
+        rung = float(rng.choice(synth.RUNG_SCALES))
+        ow, oh = tigas.output_size(W, H, rung)
+        frame = torch.zeros((oh, ow, 3), dtype=torch.uint8, device="cuda")
+        jpeg = torch.zeros(int(tigas.lib().tigas_jpeg_max_bytes(ow, oh)), dtype=torch.uint8, device="cuda")
+        reqs.append(tigas.request_c(sc, traj[i], k, W, H, frame, client=i % 6, res_scale=rung,
+                                    jpeg_quality=quality[rung], jpeg_out=jpeg))
+        frames.append(frame)
+        jpegs.append(jpeg)
+        meta.append((sc, traj[i], rung))
+    with tigas.Server(ctx, slots=2, max_batch=8) as sv:
+        for r in reqs:
+            sv.submit(r)
+        sv.drain()
+        done = {d["id"]: d for d in sv.poll()}
+        st = sv.stats()
+    _say("jpeg mix", st)
+    assert len(done) == 24 and st["max_batch_seen"] > 1
+    for i in range(24):
+        d = done[i]
+        assert d["status"] == 0 and d["jpeg_bytes"] > 0
+        img = frames[i].cpu().numpy()
+        sc, pose, rung = meta[i]
+        alone = ctx.render(sc, pose, k, W, H, res_scale=rung, tile=(16, 32), batch_depth=64)
+        np.testing.assert_array_equal(img, alone, err_msg=f"frame {i}")
+        got = bytes(jpegs[i][:d["jpeg_bytes"]].cpu().numpy())
+        assert got == oj.encode(img, quality[rung]), f"payload {i}"
 
 
 def test_small_budget_defers_requests_but_renders_them_all(ctx, scenes):
