@@ -380,6 +380,41 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
  * non-positive sizes). */
 size_t tigas_jpeg_max_bytes(int width, int height);
 
+/* Latency ABR controller of the adaptive client (Section 5.3, Throughput
+ * Monitoring and ABR Controller): per completed request the client reports
+ * the payload size and its download time; the controller keeps an
+ * exponential moving average (factor alpha) of the throughput over the last
+ * `history` requests and picks the next request's level of the bitrate
+ * ladder.  With T_l = expected_bytes[l] / (average in KB/s * 1024): up one
+ * level when T_{l+1} <= t_target_s, down one when T_l > t_margin_s, each only
+ * after its condition held on `hold` consecutive requests, except a downgrade
+ * during rapid panning, which is immediate.  Levels are numbered by rising
+ * quality (0 = the smallest rung).  Host-only; no GPU work. */
+typedef struct {
+    int n_levels;              /* 1..8 */
+    double expected_bytes[8];  /* expected payload per level, rising */
+    double t_target_s;         /* upgrade target */
+    double t_margin_s;         /* downgrade margin, above the target */
+    double alpha;              /* moving-average factor, 0 < alpha <= 1 */
+    int history;               /* requests in the average, 1..64 */
+    int hold;                  /* consecutive requests before a change, >= 1 */
+    int start_level;
+} tigas_abr_config;
+typedef struct tigas_abr tigas_abr;
+
+/* Defaults: the four rungs of Table 1 with the middles of its size ranges
+ * (7, 20, 55, 240 KB), 100 ms target, 150 ms margin, alpha 0.3, history 5,
+ * hold 3, start at level 0. */
+void tigas_abr_default_config(tigas_abr_config* cfg);
+/* E_INVALID for out-of-range fields (cfg NULL = the defaults). */
+tigas_status tigas_abr_create(const tigas_abr_config* cfg, tigas_abr** out);
+void tigas_abr_destroy(tigas_abr* abr);
+/* One completed request: payload bytes and download seconds (both > 0);
+ * *level receives the level of the next request. */
+tigas_status tigas_abr_observe(tigas_abr* abr, double bytes, double seconds, int rapid_pan, int* level);
+/* The current throughput average in KB/s (0 before the first request). */
+tigas_status tigas_abr_rate(const tigas_abr* abr, double* kbytes_per_s);
+
 /* Self-test of the wave64 DPP prefix scan used by the scan and sort kernels:
  * inclusive scan of n u32 host values in groups of 64 lanes, result to host. */
 tigas_status tigas_selftest_wave_scan(const uint32_t* in, uint32_t* out, int n);

@@ -1710,6 +1710,45 @@ void jpeg_encode_jobs(tigas_context* ctx, Workspace& ws, hipStream_t st, JpegJob
     for (int i = 0; i < n; ++i) std::memcpy(&jobs[i].bytes, (const uint8_t*)ws.jpeg_len_host.p + 8 * i, 8);
 }
 
+// Latency ABR controller state (tigas_abr_*): the throughput samples of the
+// window in arrival order, the average, the level and the hold counter.
+struct tigas_abr {
+    tigas_abr_config cfg{};
+    std::deque<double> samples;  // KB/s, oldest first
+    double rate_kbps = 0.0;
+    int level = 0;
+    int direction = 0;  // +1 / -1: the condition of the last requests
+    int streak = 0;
+
+    double expected_time(int l) const { return cfg.expected_bytes[l] / (rate_kbps * 1024.0); }
+    int observe(double bytes, double seconds, bool rapid_pan) {
+        samples.push_back(bytes / seconds / 1024.0);
+        while ((int)samples.size() > cfg.history) samples.pop_front();
+        double e = samples.front();  // the window's oldest sample, then the newer ones
+        for (size_t i = 1; i < samples.size(); ++i) e = cfg.alpha * samples[i] + (1.0 - cfg.alpha) * e;
+        rate_kbps = e;
+        int want = 0;
+        if (level + 1 < cfg.n_levels && expected_time(level + 1) <= cfg.t_target_s) want = 1;
+        else if (level > 0 && expected_time(level) > cfg.t_margin_s) want = -1;
+        if (want == -1 && rapid_pan) {  // panning: downgrade at once
+            --level;
+            direction = streak = 0;
+            return level;
+        }
+        if (want != 0 && want == direction) {
+            ++streak;
+        } else {
+            direction = want;
+            streak = want ? 1 : 0;
+        }
+        if (want != 0 && streak >= cfg.hold) {
+            level += want;
+            direction = streak = 0;
+        }
+        return level;
+    }
+};
+
 extern "C" {
 
 const char* tigas_last_error(void) { return g_err.c_str(); }
@@ -2002,6 +2041,60 @@ tigas_status tigas_jpeg_encode(tigas_context* ctx, const void* rgb, int width, i
         jpeg_encode_jobs(ctx, ws, st, &job, 1);
         *out_len = (size_t)job.bytes;
         if (job.bytes > capacity) fail(TIGAS_E_BUFFER, "jpeg: output buffer smaller than the stream");
+    });
+}
+
+void tigas_abr_default_config(tigas_abr_config* cfg) {
+    if (!cfg) return;
+    *cfg = tigas_abr_config{};
+    cfg->n_levels = 4;
+    const double kb[4] = {7, 20, 55, 240};  // Table 1: middles of the size ranges
+    for (int i = 0; i < 4; ++i) cfg->expected_bytes[i] = kb[i] * 1024.0;
+    cfg->t_target_s = 0.100;
+    cfg->t_margin_s = 0.150;
+    cfg->alpha = 0.3;
+    cfg->history = 5;
+    cfg->hold = 3;
+    cfg->start_level = 0;
+}
+
+tigas_status tigas_abr_create(const tigas_abr_config* cfg, tigas_abr** out) {
+    return guard([&] {
+        if (!out) fail(TIGAS_E_INVALID, "null output");
+        tigas_abr_config c;
+        if (cfg) c = *cfg;
+        else tigas_abr_default_config(&c);
+        if (c.n_levels < 1 || c.n_levels > 8) fail(TIGAS_E_INVALID, "abr: n_levels must be 1..8");
+        for (int i = 0; i < c.n_levels; ++i)
+            if (!(c.expected_bytes[i] > 0) || (i > 0 && !(c.expected_bytes[i] > c.expected_bytes[i - 1])))
+                fail(TIGAS_E_INVALID, "abr: expected sizes must be positive and rising");
+        if (!(c.t_target_s > 0) || !(c.t_margin_s > c.t_target_s))
+            fail(TIGAS_E_INVALID, "abr: need 0 < t_target < t_margin");
+        if (!(c.alpha > 0 && c.alpha <= 1)) fail(TIGAS_E_INVALID, "abr: alpha must be in (0, 1]");
+        if (c.history < 1 || c.history > 64 || c.hold < 1) fail(TIGAS_E_INVALID, "abr: history 1..64, hold >= 1");
+        if (c.start_level < 0 || c.start_level >= c.n_levels) fail(TIGAS_E_INVALID, "abr: bad start level");
+        tigas_abr* a = new tigas_abr;
+        a->cfg = c;
+        a->level = c.start_level;
+        *out = a;
+    });
+}
+
+void tigas_abr_destroy(tigas_abr* abr) { delete abr; }
+
+tigas_status tigas_abr_observe(tigas_abr* abr, double bytes, double seconds, int rapid_pan, int* level) {
+    return guard([&] {
+        if (!abr || !level) fail(TIGAS_E_INVALID, "null argument");
+        if (!(bytes > 0) || !(seconds > 0) || !std::isfinite(bytes) || !std::isfinite(seconds))
+            fail(TIGAS_E_INVALID, "abr: bytes and seconds must be positive");
+        *level = abr->observe(bytes, seconds, rapid_pan != 0);
+    });
+}
+
+tigas_status tigas_abr_rate(const tigas_abr* abr, double* kbytes_per_s) {
+    return guard([&] {
+        if (!abr || !kbytes_per_s) fail(TIGAS_E_INVALID, "null argument");
+        *kbytes_per_s = abr->rate_kbps;
     });
 }
 

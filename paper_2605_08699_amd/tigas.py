@@ -77,13 +77,20 @@ class KernelTimeC(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 120), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class AbrConfigC(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("expected_bytes", ctypes.c_double * 8), ("t_target_s", ctypes.c_double),
+                ("t_margin_s", ctypes.c_double), ("alpha", ctypes.c_double), ("history", ctypes.c_int),
+                ("hold", ctypes.c_int), ("start_level", ctypes.c_int)]
+
+
 # every symbol include/tigas.h declares
 EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
            "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks",
            "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait",
-           "tigas_jpeg_encode", "tigas_jpeg_max_bytes")
+           "tigas_jpeg_encode", "tigas_jpeg_max_bytes", "tigas_abr_default_config", "tigas_abr_create",
+           "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate")
 
 _lib = None
 
@@ -132,6 +139,13 @@ def lib():
         L.tigas_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimeC), I, ctypes.POINTER(I)]
         L.tigas_jpeg_encode.argtypes = [P, P, I, I, I, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
         L.tigas_jpeg_max_bytes.argtypes = [I, I]
+        L.tigas_abr_default_config.argtypes = [ctypes.POINTER(AbrConfigC)]
+        L.tigas_abr_default_config.restype = None
+        L.tigas_abr_create.argtypes = [ctypes.POINTER(AbrConfigC), ctypes.POINTER(P)]
+        L.tigas_abr_destroy.argtypes = [P]
+        L.tigas_abr_destroy.restype = None
+        L.tigas_abr_observe.argtypes = [P, ctypes.c_double, ctypes.c_double, I, ctypes.POINTER(I)]
+        L.tigas_abr_rate.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
         L.tigas_jpeg_max_bytes.restype = ctypes.c_size_t
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
@@ -140,7 +154,8 @@ def lib():
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
                      "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort",
                      "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit",
-                     "tigas_render_wait", "tigas_jpeg_encode"):
+                     "tigas_render_wait", "tigas_jpeg_encode", "tigas_abr_create", "tigas_abr_observe",
+                     "tigas_abr_rate"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -550,3 +565,51 @@ def _completion_dict(c):
     return dict(id=int(c.id), client=int(c.client), status=int(c.status), arrival_s=c.arrival_s,
                 dispatch_s=c.dispatch_s, done_s=c.done_s, batch_size=int(c.batch_size),
                 jpeg_bytes=int(c.jpeg_bytes))
+
+
+class ABR:
+    """The library's latency ABR controller (tigas_abr_*): observe() takes a
+    completed request's payload bytes and download seconds and returns the
+    level of the next request (0 = the smallest rung)."""
+
+    def __init__(self, expected_bytes=None, t_target=None, t_margin=None, alpha=None, history=None, hold=None,
+                 level=None):
+        L = lib()
+        cfg = AbrConfigC()
+        L.tigas_abr_default_config(ctypes.byref(cfg))
+        if expected_bytes is not None:
+            cfg.n_levels = len(expected_bytes)
+            for i, b in enumerate(expected_bytes):
+                cfg.expected_bytes[i] = float(b)
+        for name, v in (("t_target_s", t_target), ("t_margin_s", t_margin), ("alpha", alpha)):
+            if v is not None:
+                setattr(cfg, name, float(v))
+        for name, v in (("history", history), ("hold", hold), ("start_level", level)):
+            if v is not None:
+                setattr(cfg, name, int(v))
+        h = ctypes.c_void_p()
+        _check(L.tigas_abr_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def observe(self, nbytes, seconds, rapid_pan=False) -> int:
+        lv = ctypes.c_int()
+        _check(lib().tigas_abr_observe(self.handle, float(nbytes), float(seconds), 1 if rapid_pan else 0,
+                                       ctypes.byref(lv)))
+        return int(lv.value)
+
+    @property
+    def rate_kbps(self) -> float:
+        r = ctypes.c_double()
+        _check(lib().tigas_abr_rate(self.handle, ctypes.byref(r)))
+        return float(r.value)
+
+    def close(self):
+        if self.handle:
+            lib().tigas_abr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
