@@ -12,6 +12,7 @@ device buffer.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -206,6 +207,78 @@ def run_jpeg(ctx, tigas, scene, traj, torch, steps=40):
     return dict(rungs=rungs, cpu_oracle_threads=1)
 
 
+def run_abr_clients(ctx, torch, tigas, seconds=4.0, n_clients=16):
+    """Closed-loop clients on the serving loop, each driven by the library's
+    latency ABR (Section 5.3): a client sends its next request when it has
+    received the previous payload, at the ladder level the ABR picked (Table
+    1: 1280x720 scaled by 0.25/0.5/0.75/1 at JPEG quality 10/35/65/90); the
+    server renders and encodes it; the payload then takes a simulated
+    download: bytes / bandwidth + one RTT, the bandwidth a per-client mean
+    (log-uniform 2..200 Mbit/s, seeded) times a log-normal factor per request.
+    Rapid panning (rotation above 90 deg/s between requests) allows immediate
+    downgrades.  Reports levels, latency (server + network) and switches."""
+    from paper_2605_08699_amd import synth
+    scenes = [ctx.load_scene(sc, "f16") for sc in synth.serving_scenes()]
+    ladder = ((0.25, 10), (0.5, 35), (0.75, 65), (1.0, 90))
+    k = synth.fov_intrinsics(1280, 720)
+    rng = np.random.default_rng(4000)
+    mean_bw = np.exp(rng.uniform(np.log(2e6), np.log(200e6), n_clients))  # bit/s
+    rtt = rng.uniform(0.01, 0.06, n_clients)
+    clients = synth.serving_clients(n_clients, rate_hz=60.0, duration_s=seconds + 2)
+    frames = [torch.empty((720, 1280, 3), dtype=torch.uint8, device="cuda") for _ in range(n_clients)]
+    jpegs = [torch.empty(8 << 20, dtype=torch.uint8, device="cuda") for _ in range(n_clients)]
+    abrs = [tigas.ABR() for _ in range(n_clients)]
+    level = [0] * n_clients
+    step = [0] * n_clients
+    next_send = [0.0] * n_clients
+    inflight = {}
+    recs = []
+    with tigas.Server(ctx, slots=2, max_batch=64, hbm_budget=48 << 30) as sv:
+        t0 = time.perf_counter()
+        while True:
+            now = time.perf_counter() - t0
+            if now > seconds and not inflight:
+                break
+            for c in range(n_clients):
+                if now >= next_send[c] and c not in [v[0] for v in inflight.values()] and now <= seconds:
+                    cl = clients[c]
+                    pose = cl.poses[min(step[c], len(cl.poses) - 1)]
+                    sc, q = ladder[level[c]]
+                    rid = sv.submit(tigas.request_c(scenes[cl.scene_id], pose, k, 1280, 720, frames[c], client=c,
+                                                    res_scale=sc, jpeg_quality=q, jpeg_out=jpegs[c]))
+                    inflight[rid] = (c, now, level[c], step[c])
+            for d in sv.poll():
+                c, sent, lv, st_ = inflight.pop(d["id"])
+                server_s = d["done_s"] - d["arrival_s"]
+                bw = mean_bw[c] * float(np.exp(rng.normal(0, 0.3)))
+                dl = d["jpeg_bytes"] * 8.0 / bw
+                total = server_s + rtt[c] + dl
+                # rotation between this pose and the next: degrees per second of the walk
+                cl = clients[c]
+                p0, p1 = cl.poses[min(st_, len(cl.poses) - 1)], cl.poses[min(st_ + 1, len(cl.poses) - 1)]
+                cosang = np.clip((np.trace(p0.R.T @ p1.R) - 1) / 2, -1, 1)
+                pan = math.degrees(math.acos(cosang)) / max(total, 1e-3) > 90.0
+                level[c] = abrs[c].observe(d["jpeg_bytes"], dl, pan)
+                step[c] = st_ + 1
+                next_send[c] = (time.perf_counter() - t0) + rtt[c] + dl  # the frame arrives, the next request leaves
+                recs.append((c, lv, server_s, total, d["jpeg_bytes"], level[c] != lv))
+            time.sleep(0.0002)
+    for a in abrs:
+        a.close()
+    for s_ in scenes:
+        s_.free()
+    tot = np.array([r[3] for r in recs]) * 1e3
+    srv = np.array([r[2] for r in recs]) * 1e3
+    lv = np.array([r[1] for r in recs])
+    return dict(clients=n_clients, seconds=seconds, requests=len(recs),
+                level_share={str(l): float((lv == l).mean()) for l in range(4)},
+                latency_ms_p50=float(np.median(tot)), latency_ms_p99=float(np.percentile(tot, 99)),
+                within_100ms=float((tot <= 100.0).mean()), server_ms_p50=float(np.median(srv)),
+                server_ms_p99=float(np.percentile(srv, 99)), mean_payload_bytes=float(np.mean([r[4] for r in recs])),
+                switches_per_client=sum(r[5] for r in recs) / n_clients,
+                bandwidth_mbps=[round(float(b) / 1e6, 1) for b in mean_bw])
+
+
 def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0, 50.0), budget_gb=48,
                 batch_mpx=6.0):
     """The serving form: 64 clients (Poisson arrivals, random rungs of
@@ -395,6 +468,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-jpeg", action="store_true")
+    ap.add_argument("--no-abr", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--tile", default=None,
                     help="W,H,batch_depth,pixels_per_lane for the single-view variants (default: autotuned)")
@@ -480,6 +554,12 @@ def main():
         print(f"# serving with JPEG payloads at 40 req/s per client: {j['rendered_frames_per_s']:.0f} frames/s, "
               f"p99 {j['p99_ms']:.2f} ms (1080p 3M: p99 {j['p99_ms_1080p_3M']}), mean {j['jpeg_mean_bytes']:.0f} B",
               file=sys.stderr, flush=True)
+    if not args.no_abr:
+        line["abr_clients"] = run_abr_clients(ctx, torch, tigas)
+        a = line["abr_clients"]
+        print(f"# ABR clients: {a['requests']} requests, levels {a['level_share']}, latency p50 "
+              f"{a['latency_ms_p50']:.1f} ms p99 {a['latency_ms_p99']:.1f} ms, {100 * a['within_100ms']:.0f}% "
+              f"within 100 ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, traj[0], k, W, H)
     print(json.dumps(line), flush=True)
