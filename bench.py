@@ -207,7 +207,7 @@ def run_jpeg(ctx, tigas, scene, traj, torch, steps=40):
     return dict(rungs=rungs, cpu_oracle_threads=1)
 
 
-def run_abr_clients(ctx, torch, tigas, seconds=4.0, n_clients=16):
+def run_abr_clients(ctx, torch, tigas, serving_scenes, seconds=4.0, n_clients=16):
     """Closed-loop clients on the serving loop, each driven by the library's
     latency ABR (Section 5.3): a client sends its next request when it has
     received the previous payload, at the ladder level the ABR picked (Table
@@ -218,7 +218,7 @@ def run_abr_clients(ctx, torch, tigas, seconds=4.0, n_clients=16):
     Rapid panning (rotation above 90 deg/s between requests) allows immediate
     downgrades.  Reports levels, latency (server + network) and switches."""
     from paper_2605_08699_amd import synth
-    scenes = [ctx.load_scene(sc, "f16") for sc in synth.serving_scenes()]
+    scenes = [ctx.load_scene(sc, "f16") for sc in serving_scenes]
     ladder = ((0.25, 10), (0.5, 35), (0.75, 65), (1.0, 90))
     k = synth.fov_intrinsics(1280, 720)
     rng = np.random.default_rng(4000)
@@ -279,8 +279,8 @@ def run_abr_clients(ctx, torch, tigas, seconds=4.0, n_clients=16):
                 bandwidth_mbps=[round(float(b) / 1e6, 1) for b in mean_bw])
 
 
-def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0, 50.0), budget_gb=48,
-                batch_mpx=6.0):
+def run_serving(ctx, torch, tigas, serving_scenes, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0, 50.0),
+                budget_gb=48, batch_mpx=6.0):
     """The serving form: 64 clients (Poisson arrivals, random rungs of
     1920x1080, their own 6DoF walks) on 4 resident FP16 scenes of 0.5/1/3/6M
     Gaussians, replayed open-loop into the library's continuous-batching
@@ -290,7 +290,7 @@ def run_serving(ctx, torch, tigas, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.
     stays within 10 ms; then full load and 40 req/s per client again with each
     frame also encoded as its JPEG payload."""
     from paper_2605_08699_amd import synth
-    scenes = [ctx.load_scene(sc, "f16") for sc in synth.serving_scenes()]
+    scenes = [ctx.load_scene(sc, "f16") for sc in serving_scenes]
     k = synth.fov_intrinsics(1920, 1080)
     outs = [torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda") for _ in range(64)]
     jpeg_outs = [torch.empty(8 << 20, dtype=torch.uint8, device="cuda") for _ in range(64)]
@@ -544,8 +544,9 @@ def main():
         r = line["jpeg"]["rungs"][3]
         print(f"# jpeg 1280x720 q90: {r['bytes_mean'] / 1024:.0f} KiB, encode {r['encode_ms']:.3f} ms per call, "
               f"render+encode {r['render_encode_frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
+    serving_scenes = synth.serving_scenes() if not (args.no_serving and args.no_abr) else None
     if not args.no_serving:
-        line["serving"] = run_serving(ctx, torch, tigas, seconds=args.serve_seconds)
+        line["serving"] = run_serving(ctx, torch, tigas, serving_scenes, seconds=args.serve_seconds)
         f = line["serving"]["full_load_latest_pose_wins"]
         print(f"# serving at {f['offered_req_per_s']:.0f} req/s offered: {f['rendered_frames_per_s']:.0f} frames/s, "
               f"p50 {f['p50_ms']:.2f} ms p99 {f['p99_ms']:.2f} ms (1080p 3M: p99 {f['p99_ms_1080p_3M']})",
@@ -555,7 +556,7 @@ def main():
               f"p99 {j['p99_ms']:.2f} ms (1080p 3M: p99 {j['p99_ms_1080p_3M']}), mean {j['jpeg_mean_bytes']:.0f} B",
               file=sys.stderr, flush=True)
     if not args.no_abr:
-        line["abr_clients"] = run_abr_clients(ctx, torch, tigas)
+        line["abr_clients"] = run_abr_clients(ctx, torch, tigas, serving_scenes)
         a = line["abr_clients"]
         print(f"# ABR clients: {a['requests']} requests, levels {a['level_share']}, latency p50 "
               f"{a['latency_ms_p50']:.1f} ms p99 {a['latency_ms_p99']:.1f} ms, {100 * a['within_100ms']:.0f}% "
