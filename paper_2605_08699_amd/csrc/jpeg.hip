@@ -84,29 +84,30 @@ __device__ __forceinline__ void put_value(S& s, int v, int nb) {  // negative va
 
 // Entropy coding of one block (Annex F): DC difference category and bits,
 // then AC run/size symbols with ZRL for 16 zeros and EOB before trailing zeros.
+// nz has bit i set when scan position i holds a non-zero value, so the loop
+// visits the non-zero AC values only (the runs are the gaps between them).
 template <class S>
-__device__ void code_block(const int16_t* zq, int pred, const uint32_t* hdc, const uint32_t* hac, S& s) {
+__device__ void code_block(const int16_t* zq, uint64_t nz, int pred, const uint32_t* hdc, const uint32_t* hac,
+                           S& s) {
     const int diff = zq[0] - pred;
     const int nd = magnitude_bits(diff);
     put_symbol(s, hdc, nd);
     put_value(s, diff, nd);
-    int run = 0;
-    for (int i = 1; i < 64; ++i) {
-        const int v = zq[i];
-        if (v == 0) {
-            ++run;
-            continue;
-        }
+    int prev = 0;
+    for (uint64_t m = nz & ~1ull; m; m &= m - 1) {
+        const int i = __builtin_ctzll(m);
+        int run = i - prev - 1;
         while (run > 15) {
             put_symbol(s, hac, 0xF0);
             run -= 16;
         }
+        const int v = zq[i];
         const int nb = magnitude_bits(v);
         put_symbol(s, hac, (run << 4) | nb);
         put_value(s, v, nb);
-        run = 0;
+        prev = i;
     }
-    if (run > 0) put_symbol(s, hac, 0x00);
+    if (prev < 63) put_symbol(s, hac, 0x00);
 }
 
 // Workgroup exclusive scan (JPEG_THREADS threads) through LDS.
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     constexpr int ZS = 66;
     __shared__ int16_t s_coef[3 * JPEG_SEG_MCUS * ZS];
     __shared__ int32_t s_dc[3 * JPEG_SEG_MCUS];
+    __shared__ uint64_t s_nz[3 * JPEG_SEG_MCUS];  // non-zero scan positions of each block
     __shared__ uint32_t s_huff[4 * 256];
     __shared__ uint32_t s_scan[JPEG_THREADS];
     __shared__ uint8_t s_pix[JPEG_SEG_MCUS * 64 * 3];  // the interval's 8x8 pixel blocks, edges repeated
@@ -193,6 +195,7 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
             }
         }
         const float* rq = comp ? a.rq_chroma : a.rq_luma;
+        uint64_t nz = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -203,9 +206,12 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
                 const float x = acc * rq[k * 8 + l];
                 int v = (int)__builtin_truncf(x + __builtin_copysignf(0.5f, x));
                 if (k + l > 0) v = max(-1023, min(1023, v));
-                zq[kZigZag.pos[k * 8 + l]] = (int16_t)v;
+                const int p = kZigZag.pos[k * 8 + l];
+                zq[p] = (int16_t)v;
+                nz |= v != 0 ? 1ull << p : 0ull;
                 if (k + l == 0) s_dc[t] = v;
             }
+        s_nz[t] = nz;
     }
     __syncthreads();
 
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     uint32_t len = 0;
     if (t < nb) {
         BitCount c;
-        code_block(zq, pred, hdc, hac, c);  // this thread's own block
+        code_block(zq, s_nz[t], pred, hdc, hac, c);  // this thread's own block
         len = c.n;
     }
     uint32_t total;
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(JPEG_THREADS) void k_jpeg_seg(JpegArgs a) {
     // the codes, ORed into the (cleared) bit buffer of the interval
     if (t < nb) {
         BitWrite w(a.bits + (size_t)seg * a.seg_words, off);
-        code_block(zq, pred, hdc, hac, w);
+        code_block(zq, s_nz[t], pred, hdc, hac, w);
         w.flush();
     }
 }
