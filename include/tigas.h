@@ -389,7 +389,8 @@ size_t tigas_jpeg_max_bytes(int width, int height);
  * level when T_{l+1} <= t_target_s, down one when T_l > t_margin_s, each only
  * after its condition held on `hold` consecutive requests, except a downgrade
  * during rapid panning, which is immediate.  Levels are numbered by rising
- * quality (0 = the smallest rung).  Host-only; no GPU work. */
+ * quality (0 = the smallest rung).  Host-only; no GPU work.  A controller
+ * serves one client: calls on one controller must not overlap. */
 typedef struct {
     int n_levels;              /* 1..8 */
     double expected_bytes[8];  /* expected payload per level, rising */
