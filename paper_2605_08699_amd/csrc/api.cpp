@@ -1277,9 +1277,9 @@ double request_pixels(const tigas_request& r) {
     return std::floor(r.width * s + 0.5) * std::floor(r.height * s + 0.5);
 }
 
-// Workspace bytes per record: the 64-byte record, its pixel box again, depth
-// key, tiles touched, FP64-list entry.
-constexpr size_t kBytesPerRecord = sizeof(Rec) + 8 + 4 + 4 + 8;
+// Workspace bytes per record: the 64-byte record, its tile rectangle (index
+// order and depth order), depth key, FP64-list entry.
+constexpr size_t kBytesPerRecord = sizeof(Rec) + 8 + 8 + 4 + 8;
 
 size_t request_need(const tigas_server* sv, const tigas_request& r) {
     const double rec = (double)request_records(r);

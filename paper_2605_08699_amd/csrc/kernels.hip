@@ -3,15 +3,20 @@
 //   k_preprocess   per Gaussian (x views): activation, 3D covariance, camera
 //                  transform, projection, EWA 2D covariance + conic (FP64
 //                  fallback when near-singular), SH colour, screen footprint
-//   k_scan_*       exclusive scans of per-block counts (wave64 DPP)
-//   k_compact      visible Gaussians as (depth key, record) pairs
+//   k_chunk_totals, k_scan_*
+//                  exclusive scans of per-block counts (chunk totals, then
+//                  each chunk; wave64 DPP scans)
+//   k_compact      visible Gaussians as (depth key, record, packed tile
+//                  rectangle) triples
 //   k_sort_*       LSD radix sort passes, 8-bit digits, reduce-then-scan,
-//                  ballot/mbcnt ranking inside a wave, DPP scans; the depth
-//                  digits of the (tile | depth) keys are sorted on the
-//                  visible Gaussians before duplication, the tile digits on
-//                  the duplicates after it
+//                  LDS-atomic digit counts, ballot/mbcnt ranking inside a
+//                  wave, DPP scans; the depth digits of the (tile | depth)
+//                  keys are sorted on the visible Gaussians before
+//                  duplication, the tile digits on the duplicates after it
+//   k_sorted_sums  tile counts per 256 depth-ordered Gaussians
 //   k_duplicate    one (tile | depth) key per (Gaussian, overlapped tile)
-//   k_ranges       [start, end) of every tile in the sorted list
+//   k_ranges       [start, end) of every tile in the sorted list, and the
+//                  FP64 conics of the near-singular Gaussians
 //   k_blend        front-to-back compositing, one wave64 per 8x8 pixel block,
 //                  Gaussians staged per wave in LDS, per-wave early exit
 //

@@ -80,8 +80,8 @@ struct PreOut {
                         // a record is visible when nx ny > 0)
     uint2* srect;       // the visible records' tile rectangles in depth order (last depth pass)
     uint32_t* zkey;     // FP32 depth-key bits
-    uint32_t* blk_sum;  // per 256-record block: sum of touched
-    uint32_t* blk_vis;  // per block: records with touched > 0
+    uint32_t* blk_sum;  // per 256-record block: tiles touched
+    uint32_t* blk_vis;  // per block: records that touch a tile
     uint32_t* blk_fb;   // per block: FP64 fallbacks
     uint32_t* blk_view; // per block: view index
     uint32_t* chunk_vis;            // per SCAN_CHUNK block counts: visible records,
