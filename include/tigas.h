@@ -416,6 +416,95 @@ tigas_status tigas_abr_observe(tigas_abr* abr, double bytes, double seconds, int
 /* The current throughput average in KB/s (0 before the first request). */
 tigas_status tigas_abr_rate(const tigas_abr* abr, double* kbytes_per_s);
 
+/* ---- Scene registry (Section 4.1, GPU Backend; Section 5.1, PLY Model and
+ * Primitives and Dynamic Multi-Model Runtime) ----
+ *
+ * A registry scans a root directory once, at creation, for models: every
+ * sub-folder holding a 3DGS PLY file (point_cloud.ply in the folder, else
+ * point_cloud/iteration_<k>/point_cloud.ply with the highest k, else the
+ * first *.ply in the folder by name) and every *.ply directly under the root.
+ * A model's id is its folder's name (or the file's name without ".ply"); its
+ * preview image is preview.{png,jpg,jpeg,webp} in the folder (or
+ * <id>.{png,...} beside a root-level file).  Folders and files without a
+ * readable 3DGS PLY header are not registered.
+ *
+ * Models are loaded on first access (acquire or load), stay resident while
+ * clients hold references, and are unloaded once unreferenced and idle for at
+ * least idle_timeout_s, by a sweep: tigas_registry_evict_idle, or a thread
+ * of the registry every sweep_period_s.  Every function of one registry may be
+ * called from any thread at any time, except destroy, which must not overlap
+ * any other call on the registry.
+ *
+ * PLY layout read (the 3DGS training output; ascii, binary_little_endian or
+ * binary_big_endian, any scalar property types): element "vertex", one per
+ * Gaussian, with x y z, f_dc_0..2, f_rest_0..K-1 (K = 0, 9, 24 or 45 gives SH
+ * degree 0..3; channel-major: f_rest_{c*(K/3) + k - 1} is coefficient k of
+ * colour channel c), opacity (logit), scale_0..2 (log-scales) and rot_0..3
+ * (w, x, y, z).  Other vertex properties and other elements are skipped;
+ * vertex list properties are an error.  Values are converted to FP32 with
+ * round-to-nearest. */
+typedef struct tigas_registry tigas_registry;
+
+typedef struct {
+    double idle_timeout_s; /* unload after this long unreferenced; < 0: never by a sweep.  Default 300 */
+    double sweep_period_s; /* > 0: a registry thread sweeps this often; 0: sweeps only on request.  Default 0 */
+    tigas_attr storage;    /* resident precision of loaded models.  Default F32 */
+} tigas_registry_config;
+
+typedef struct {
+    const char* id;           /* strings owned by the registry, valid until destroy */
+    const char* ply_path;
+    const char* preview_path; /* "" when there is none */
+    int64_t n;                /* Gaussians (from the header; refreshed at each load) */
+    int sh_degree;
+    int loaded;               /* resident now */
+    int refs;                 /* references held */
+    int64_t loads;            /* times loaded since the registry was created */
+    size_t device_bytes;      /* resident bytes, 0 when not loaded */
+    double idle_s;            /* seconds since the last acquire, load or release (loaded models) */
+} tigas_model_info;
+
+/* Reads the header of a 3DGS PLY file: vertex count and SH degree.  Host
+ * only.  E_INVALID for a missing or malformed file. */
+tigas_status tigas_ply_info(const char* path, int64_t* n, int* sh_degree);
+/* Reads a 3DGS PLY file into host arrays in the tigas_scene_desc layout
+ * (means [n][3], log_scales [n][3], quats_wxyz [n][4], opacity_logits [n],
+ * sh [n][16][3] with the coefficients above the file's degree set to 0).  n
+ * must be the file's vertex count.  Host only; the caller owns the arrays.
+ * E_INVALID for a malformed or truncated file (arrays then unspecified). */
+tigas_status tigas_ply_read(const char* path, int64_t n, float* means, float* log_scales, float* quats_wxyz,
+                            float* opacity_logits, float* sh);
+
+void tigas_registry_default_config(tigas_registry_config* cfg);
+/* Creates a registry of the models under root (cfg null: defaults).  ctx is
+ * the context models load into; null gives a discovery-only registry (info
+ * works, acquire and load fail with E_INVALID).  *out is owned by the
+ * caller; tigas_registry_destroy before the context. */
+tigas_status tigas_registry_create(tigas_context* ctx, const char* root, const tigas_registry_config* cfg,
+                                   tigas_registry** out);
+/* Stops the sweeping thread and frees every resident model, referenced or
+ * not: scenes acquired from the registry are invalid afterwards. */
+void tigas_registry_destroy(tigas_registry* reg);
+/* Models registered (ordered by id). */
+int64_t tigas_registry_count(const tigas_registry* reg);
+tigas_status tigas_registry_info(tigas_registry* reg, int64_t index, tigas_model_info* info);
+/* Returns model `id` resident, loading it first if it is not (a concurrent
+ * first access waits for the one load), and takes a reference: the scene
+ * stays valid until the matching tigas_registry_release.  Release only after
+ * the renders of the scene have completed (serving: after their completion
+ * was polled).  E_INVALID for an unknown id or a malformed file; E_OOM. */
+tigas_status tigas_registry_acquire(tigas_registry* reg, const char* id, tigas_scene** out);
+/* Makes model `id` resident without taking a reference (explicit loading);
+ * it is then evictable once idle. */
+tigas_status tigas_registry_load(tigas_registry* reg, const char* id);
+/* Drops one reference taken by acquire.  E_INVALID for a scene that is not a
+ * resident model of the registry or has no reference left. */
+tigas_status tigas_registry_release(tigas_registry* reg, tigas_scene* scene);
+/* One sweep: unloads every resident model that has no reference and was idle
+ * for at least idle_timeout_s; *evicted (may be null) = models unloaded.  A
+ * model is freed after the device has finished all queued work. */
+tigas_status tigas_registry_evict_idle(tigas_registry* reg, int* evicted);
+
 /* Self-test of the wave64 DPP prefix scan used by the scan and sort kernels:
  * inclusive scan of n u32 host values in groups of 64 lanes, result to host. */
 tigas_status tigas_selftest_wave_scan(const uint32_t* in, uint32_t* out, int n);

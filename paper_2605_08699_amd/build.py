@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtigas.so")
-SOURCES = ["kernels.hip", "jpeg.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "jpeg.hip", "api.cpp", "registry.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -38,6 +38,12 @@ namespace {
 
 thread_local std::string g_err;
 
+}  // namespace
+
+void tigas::set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
+namespace {
+
 struct Error : std::runtime_error {
     tigas_status st;
     Error(tigas_status s, const std::string& m) : std::runtime_error(m), st(s) {}

@@ -200,4 +200,7 @@ struct KernelTimer {
 };
 extern thread_local KernelTimer* g_kernel_timer;
 
+// Sets the message tigas_last_error() returns on the calling thread.
+void set_last_error(const char* msg);
+
 }  // namespace tigas

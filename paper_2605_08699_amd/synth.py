@@ -327,3 +327,30 @@ def serving_clients(n_clients: int = 64, rate_hz: float = 60.0, duration_s: floa
 
 def serving_scenes(sizes=(500_000, 1_000_000, 3_000_000, 6_000_000), seeds=(50, 51, 52, 53)):
     return [scene_clusters(seed=s, n=n, n_clusters=64, surface_frac=0.4) for n, s in zip(sizes, seeds)]
+
+
+def write_ply(path, scene: Scene, fmt: str = "binary_little_endian") -> None:
+    """Writes ``scene`` as a 3DGS model file (the vertex layout of the 3DGS
+    training output: x y z nx ny nz f_dc_0..2 f_rest_* opacity scale_0..2
+    rot_0..3, FP32, normals zero; f_rest channel-major), in ``fmt``: ascii,
+    binary_little_endian or binary_big_endian."""
+    d = int(scene.sh_degree)
+    m = (d + 1) ** 2 - 1
+    names = ["x", "y", "z", "nx", "ny", "nz", "f_dc_0", "f_dc_1", "f_dc_2"]
+    names += [f"f_rest_{j}" for j in range(3 * m)]
+    names += ["opacity", "scale_0", "scale_1", "scale_2", "rot_0", "rot_1", "rot_2", "rot_3"]
+    n = scene.n
+    rest = np.asarray(scene.sh, F32)[:, 1:m + 1, :].transpose(0, 2, 1).reshape(n, 3 * m)  # [n, channel, coef]
+    cols = np.concatenate([np.asarray(scene.means, F32), np.zeros((n, 3), F32), np.asarray(scene.sh, F32)[:, 0, :],
+                           rest, np.asarray(scene.opacity_logits, F32).reshape(n, 1),
+                           np.asarray(scene.log_scales, F32), np.asarray(scene.quats, F32)], 1)
+    head = "ply\nformat %s 1.0\nelement vertex %d\n" % (fmt, n)
+    head += "".join("property float %s\n" % p for p in names) + "end_header\n"
+    with open(path, "wb") as f:
+        f.write(head.encode("ascii"))
+        if fmt == "ascii":
+            for row in cols:
+                f.write((" ".join(repr(float(v)) for v in row) + "\n").encode("ascii"))
+        else:
+            f.write(np.ascontiguousarray(cols.astype("<f4" if fmt == "binary_little_endian" else ">f4")).tobytes())
+

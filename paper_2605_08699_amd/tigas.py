@@ -204,11 +204,15 @@ def output_size(width, height, res_scale=1.0):
 
 
 class Scene:
-    def __init__(self, ctx, handle, n, storage):
+    """A resident scene.  ``borrowed`` scenes belong to a registry: free()
+    only forgets the handle (the registry releases and unloads them)."""
+
+    def __init__(self, ctx, handle, n, storage, borrowed=False):
         self.ctx = ctx
         self.handle = handle
         self.n = n
         self.storage = storage
+        self.borrowed = borrowed
 
     @property
     def bytes(self) -> int:
@@ -216,7 +220,8 @@ class Scene:
 
     def free(self):
         if self.handle:
-            lib().tigas_scene_free(self.handle)
+            if not self.borrowed:
+                lib().tigas_scene_free(self.handle)
             self.handle = None
 
 
@@ -613,3 +618,133 @@ class ABR:
             self.close()
         except Exception:
             pass
+
+
+class RegistryConfigC(ctypes.Structure):
+    _fields_ = [("idle_timeout_s", ctypes.c_double), ("sweep_period_s", ctypes.c_double), ("storage", ctypes.c_int)]
+
+
+class ModelInfoC(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_char_p), ("ply_path", ctypes.c_char_p), ("preview_path", ctypes.c_char_p),
+                ("n", ctypes.c_int64), ("sh_degree", ctypes.c_int), ("loaded", ctypes.c_int), ("refs", ctypes.c_int),
+                ("loads", ctypes.c_int64), ("device_bytes", ctypes.c_size_t), ("idle_s", ctypes.c_double)]
+
+
+REGISTRY_EXPORTS = ("tigas_ply_info", "tigas_ply_read", "tigas_registry_default_config", "tigas_registry_create",
+                    "tigas_registry_destroy", "tigas_registry_count", "tigas_registry_info", "tigas_registry_acquire",
+                    "tigas_registry_load", "tigas_registry_release", "tigas_registry_evict_idle")
+EXPORTS = EXPORTS + REGISTRY_EXPORTS
+
+
+def _registry_lib():
+    L = lib()
+    if not getattr(L, "_registry_bound", False):
+        P, I, I64, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_char_p
+        L.tigas_ply_info.argtypes = [S, ctypes.POINTER(I64), ctypes.POINTER(I)]
+        L.tigas_ply_read.argtypes = [S, I64, P, P, P, P, P]
+        L.tigas_registry_default_config.argtypes = [ctypes.POINTER(RegistryConfigC)]
+        L.tigas_registry_default_config.restype = None
+        L.tigas_registry_create.argtypes = [P, S, ctypes.POINTER(RegistryConfigC), ctypes.POINTER(P)]
+        L.tigas_registry_destroy.argtypes = [P]
+        L.tigas_registry_destroy.restype = None
+        L.tigas_registry_count.argtypes = [P]
+        L.tigas_registry_count.restype = I64
+        L.tigas_registry_info.argtypes = [P, I64, ctypes.POINTER(ModelInfoC)]
+        L.tigas_registry_acquire.argtypes = [P, S, ctypes.POINTER(P)]
+        L.tigas_registry_load.argtypes = [P, S]
+        L.tigas_registry_release.argtypes = [P, P]
+        L.tigas_registry_evict_idle.argtypes = [P, ctypes.POINTER(I)]
+        for name in ("tigas_ply_info", "tigas_ply_read", "tigas_registry_create", "tigas_registry_info",
+                     "tigas_registry_acquire", "tigas_registry_load", "tigas_registry_release",
+                     "tigas_registry_evict_idle"):
+            getattr(L, name).restype = I
+        L._registry_bound = True
+    return L
+
+
+def ply_info(path) -> tuple:
+    """(vertex count, SH degree) of a 3DGS PLY file (tigas_ply_info; host only)."""
+    L = _registry_lib()
+    n, d = ctypes.c_int64(), ctypes.c_int()
+    _check(L.tigas_ply_info(os.fsencode(path), ctypes.byref(n), ctypes.byref(d)))
+    return int(n.value), int(d.value)
+
+
+def ply_read(path) -> dict:
+    """The scene arrays of a 3DGS PLY file as read by the library
+    (tigas_ply_read; host only): means, log_scales, quats (w, x, y, z),
+    opacity_logits, sh [n, 16, 3] and sh_degree."""
+    L = _registry_lib()
+    n, deg = ply_info(path)
+    out = dict(means=np.empty((n, 3), np.float32), log_scales=np.empty((n, 3), np.float32),
+               quats=np.empty((n, 4), np.float32), opacity_logits=np.empty(n, np.float32),
+               sh=np.empty((n, 16, 3), np.float32))
+    _check(L.tigas_ply_read(os.fsencode(path), n, *[_ptr(out[k]) for k in
+                                                   ("means", "log_scales", "quats", "opacity_logits", "sh")]))
+    out["sh_degree"] = deg
+    return out
+
+
+class Registry:
+    """The library's scene registry (tigas_registry_*): models found under
+    ``root`` at creation, loaded on first access, reference-counted while
+    acquired and unloaded by sweeps once idle for ``idle_timeout_s``.  With
+    ``ctx`` None it only lists the models.  Close it before its context."""
+
+    def __init__(self, ctx, root, idle_timeout_s=300.0, sweep_period_s=0.0, storage="f32"):
+        L = _registry_lib()
+        cfg = RegistryConfigC(float(idle_timeout_s), float(sweep_period_s), ATTR[storage])
+        h = ctypes.c_void_p()
+        _check(L.tigas_registry_create(ctx.handle if ctx is not None else None, os.fsencode(root),
+                                       ctypes.byref(cfg), ctypes.byref(h)))
+        self.ctx = ctx
+        self.storage = storage
+        self.handle = h
+
+    def __len__(self):
+        return int(_registry_lib().tigas_registry_count(self.handle))
+
+    def _info(self, i) -> dict:
+        c = ModelInfoC()
+        _check(_registry_lib().tigas_registry_info(self.handle, int(i), ctypes.byref(c)))
+        return dict(id=c.id.decode(), ply_path=c.ply_path.decode(), preview_path=c.preview_path.decode(),
+                    n=int(c.n), sh_degree=int(c.sh_degree), loaded=bool(c.loaded), refs=int(c.refs),
+                    loads=int(c.loads), device_bytes=int(c.device_bytes), idle_s=float(c.idle_s))
+
+    def models(self) -> list:
+        return [self._info(i) for i in range(len(self))]
+
+    def info(self, model_id) -> dict:
+        for m in self.models():
+            if m["id"] == model_id:
+                return m
+        raise KeyError(model_id)
+
+    def acquire(self, model_id) -> Scene:
+        """The resident scene of model ``model_id`` (loaded now if needed),
+        with a reference held until ``release``."""
+        h = ctypes.c_void_p()
+        _check(_registry_lib().tigas_registry_acquire(self.handle, model_id.encode(), ctypes.byref(h)))
+        return Scene(self.ctx, h, self.info(model_id)["n"], self.storage, borrowed=True)
+
+    def release(self, scene: Scene):
+        _check(_registry_lib().tigas_registry_release(self.handle, scene.handle))
+
+    def load(self, model_id):
+        _check(_registry_lib().tigas_registry_load(self.handle, model_id.encode()))
+
+    def evict_idle(self) -> int:
+        k = ctypes.c_int()
+        _check(_registry_lib().tigas_registry_evict_idle(self.handle, ctypes.byref(k)))
+        return int(k.value)
+
+    def close(self):
+        if self.handle:
+            _registry_lib().tigas_registry_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
