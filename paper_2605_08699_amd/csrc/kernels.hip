@@ -1267,8 +1267,8 @@ struct BlendArgs {
 // exponent coefficients and the colour.
 template <int BD>
 struct Stage {
-    float4 a[64 * BD];  // u_rel, A, v_rel0, B
-    float4 b[64 * BD];  // C, L, r, g
+    float4 a[64 * BD];  // u_rel, A, r, g   (what the per-pair loop reads)
+    float4 b[64 * BD];  // v_rel0, B, C, L (what the row terms read)
     float2 c[64 * BD];  // b, v_rel1
 };
 
@@ -1391,8 +1391,8 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, in
             const uint64_t m = ballot(hit);
             if (hit) {
                 const uint32_t slot = cnt + bits_below(m);
-                S.a[slot] = make_float4(u, b1.x, v0, b1.y);
-                S.b[slot] = make_float4(b1.z, b1.w, c2.x, c2.y);
+                S.a[slot] = make_float4(u, b1.x, c2.x, c2.y);
+                S.b[slot] = make_float4(v0, b1.y, b1.z, b1.w);
                 S.c[slot] = make_float2(c2.z, PPL > 1 ? (a.y - fsy[PPL - 1]) + a.w : 0.0f);
             }
             cnt += (uint32_t)__builtin_popcountll(m);
@@ -1409,47 +1409,61 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, in
             // (pixel, Gaussian) pair.  The permutes run on every lane.
             const float yrow = (float)(lane & 7) + 0.5f;
             for (uint32_t j0 = 0; j0 < cnt; j0 += 8) {
-                if (ballot(!done[0]) == 0) break;
+                // the pixels still compositing, as a wave mask: the per-pair
+                // decisions are combined in scalar registers and applied
+                // with one select each
+                uint64_t live = ballot(!done[0]);
+                if (live == 0) break;
                 const uint32_t jg = min(j0 + (uint32_t)(lane >> 3), cnt - 1);
-                const float4 ga = S.a[jg];
                 const float4 gb = S.b[jg];
-                const float dyg = yrow - ga.z;
-                const float pg = ga.w * dyg;
-                const float qg = __builtin_fmaf(gb.x * dyg, dyg, gb.y);
+                const float dyg = yrow - gb.x;
+                const float pg = gb.y * dyg;
+                const float qg = __builtin_fmaf(gb.z * dyg, dyg, gb.w);
                 const uint32_t nk = min(8u, cnt - j0);
-#pragma unroll
-                for (uint32_t k = 0; k < 8; ++k) {
-                    if (k >= nk) break;
+                auto pair = [&](uint32_t k) {
                     const int src = (int)(k * 8) + (lane >> 3);
                     const float P = __shfl(pg, src, 64);
                     const float Q = __shfl(qg, src, 64);
                     // straight-line update (no branches per pair): a pixel
                     // that is done, or an alpha below the threshold, or a
                     // stop, leaves the colour and T exactly as they are
-                    const float2 ua = *reinterpret_cast<const float2*>(&S.a[j0 + k]);
-                    const float4 b = S.b[j0 + k];
+                    const float4 ua = S.a[j0 + k];
                     const float cz = S.c[j0 + k].x;
                     const float dx = pxr - ua.x;
                     const float e = __builtin_fmaf(__builtin_fmaf(ua.y, dx, P), dx, Q);
                     const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
                     const float t0 = T[0];
-                    const float tn = t0 * (1.0f - alpha);
-                    const bool use = alpha >= ALPHA_MIN;
-                    const bool stop = use && tn < T_MIN;
-                    const bool acc = use && !stop && !done[0];
+                    const float at = alpha * t0;
+                    const float tn = t0 - at;
+                    const uint64_t use = ballot(alpha >= ALPHA_MIN) & live;
+                    const uint64_t stop = use & ballot(tn < T_MIN);
+                    const bool acc = __builtin_amdgcn_inverse_ballot_w64(use & ~stop);
                     if (COUNT) {
-                        n_eval += done[0] ? 0u : 1u;
+                        n_eval += __builtin_amdgcn_inverse_ballot_w64(live) ? 1u : 0u;
                         n_contrib += acc ? 1u : 0u;
                     }
+                    live &= ~stop;
                     // a weight of zero leaves the (finite) colour sums exactly
                     // as they are, with one select instead of three
-                    const float wgt = acc ? alpha * t0 : 0.0f;
-                    cr[0] = __builtin_fmaf(wgt, b.z, cr[0]);
-                    cg[0] = __builtin_fmaf(wgt, b.w, cg[0]);
+                    const float wgt = acc ? at : 0.0f;
+                    cr[0] = __builtin_fmaf(wgt, ua.z, cr[0]);
+                    cg[0] = __builtin_fmaf(wgt, ua.w, cg[0]);
                     cb[0] = __builtin_fmaf(wgt, cz, cb[0]);
                     T[0] = acc ? tn : t0;
-                    done[0] = done[0] || stop;
+                };
+                if (nk == 8) {
+                    // a full group: no branch between the pairs, so the
+                    // LDS reads of later pairs are issued ahead
+#pragma unroll
+                    for (uint32_t k = 0; k < 8; ++k) pair(k);
+                } else {
+#pragma unroll
+                    for (uint32_t k = 0; k < 8; ++k) {
+                        if (k >= nk) break;
+                        pair(k);
+                    }
                 }
+                done[0] = !__builtin_amdgcn_inverse_ballot_w64(live);
             }
         } else if (alive) {
             for (uint32_t j = 0; j < cnt; ++j) {
@@ -1460,21 +1474,21 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, in
                 bool all_done = true;
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    const float vrel = p == 0 ? a.z : c.y;
+                    const float vrel = p == 0 ? b.x : c.y;
                     const float dy = pyr - vrel;
-                    const float e = __builtin_fmaf(__builtin_fmaf(a.y, dx, a.w * dy), dx,
-                                                   __builtin_fmaf(b.x * dy, dy, b.y));
+                    const float e = __builtin_fmaf(__builtin_fmaf(a.y, dx, b.y * dy), dx,
+                                                   __builtin_fmaf(b.z * dy, dy, b.w));
                     const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(e));
                     if (!done[p]) {
                         if (COUNT) ++n_eval;
                         if (alpha >= ALPHA_MIN) {
-                            const float Tn = T[p] * (1.0f - alpha);
+                            const float wgt = alpha * T[p];
+                            const float Tn = T[p] - wgt;
                             if (Tn < T_MIN) {
                                 done[p] = true;
                             } else {
-                                const float wgt = alpha * T[p];
-                                cr[p] = __builtin_fmaf(wgt, b.z, cr[p]);
-                                cg[p] = __builtin_fmaf(wgt, b.w, cg[p]);
+                                cr[p] = __builtin_fmaf(wgt, a.z, cr[p]);
+                                cg[p] = __builtin_fmaf(wgt, a.w, cg[p]);
                                 cb[p] = __builtin_fmaf(wgt, c.x, cb[p]);
                                 T[p] = Tn;
                                 if (COUNT) ++n_contrib;
