@@ -889,29 +889,42 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     }
 }
 
-// One wave per digit: the digit's global start (the sum of the segments'
-// exclusive digit prefixes), then its exclusive offsets over the segments.
+// One workgroup per digit: the digit's global start (the sum of the
+// segments' exclusive digit prefixes), then its exclusive offsets over the
+// segments.  The four waves take consecutive quarters of the digit's row
+// (NJ * 64 segments each) and learn the totals of the quarters before theirs
+// through LDS.
 template <int NJ>
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ pre,
                                                    int nb, int ndig) {
-    const int lane = threadIdx.x & 63;
-    const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (d >= ndig) return;  // whole wave exits together
+    __shared__ uint32_t qsum[4], qpre[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int d = blockIdx.x;
+    if (d >= ndig) return;  // whole workgroup exits together
     uint32_t* row = hist + (size_t)d * nb;
     const uint32_t* prow = pre + (size_t)d * nb;
-    uint32_t x[NJ];  // NJ * 64 >= nb
-    uint32_t part = 0;
+    const int j0 = w * NJ * 64;
+    uint32_t x[NJ];  // 4 * NJ * 64 >= nb
+    uint32_t part = 0, mine = 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
-        const int j = q * 64 + lane;
+        const int j = j0 + q * 64 + lane;
         x[q] = j < nb ? row[j] : 0u;
+        mine += x[q];
         part += j < nb ? prow[j] : 0u;
     }
-    uint32_t running = wave_sum(part);
+    const uint32_t ws = wave_sum(mine), wp = wave_sum(part);
+    if (lane == 0) {
+        qsum[w] = ws;
+        qpre[w] = wp;
+    }
+    __syncthreads();
+    uint32_t running = qpre[0] + qpre[1] + qpre[2] + qpre[3];
+    for (int v = 0; v < w; ++v) running += qsum[v];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
-        if (q * 64 >= nb) break;
-        const int j = q * 64 + lane;
+        if (j0 + q * 64 >= nb) break;
+        const int j = j0 + q * 64 + lane;
         const uint32_t inc = wave_incl_scan(x[q]);
         if (j < nb) row[j] = running + inc - x[q];
         running += readlane(inc, 63);
@@ -1668,10 +1681,9 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
                      cap, ps.shift, ps.bits, b.hist, pre, nblocks);
         const int ndig = 1 << ps.bits;
         if (nblocks <= 1024)
-            TIGAS_LAUNCH(k_sort_scan<16>, dim3((ndig + 3) / 4), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks,
-                         ndig);
+            TIGAS_LAUNCH(k_sort_scan<4>, dim3(ndig), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig);
         else
-            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 64>), dim3((ndig + 3) / 4), dim3(256), st, b.hist,
+            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 256>), dim3(ndig), dim3(256), st, b.hist,
                          (const uint32_t*)pre, nblocks, ndig);
         const bool sums = rect_src && p + 1 == npasses;
 #define TIGAS_DOWN(E, S)                                                                                        \
