@@ -1800,19 +1800,19 @@ tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tig
         if (n > 0 && (!d->means || !d->log_scales || !d->quats_wxyz || !d->opacity_logits || !d->sh))
             fail(TIGAS_E_INVALID, "attribute array is null");
         HIPCHK(hipSetDevice(ctx->device));
-        // bring the inputs to the host
-        std::vector<float> m, ls, q, op, sh;
-        auto fetch = [&](std::vector<float>& dst, const float* src, size_t cnt) {
+        // device inputs come to the host first; host inputs are read in place
+        std::vector<float> mv, lsv, qv, opv, shv;
+        auto fetch = [&](std::vector<float>& dst, const float* src, size_t cnt) -> const float* {
+            if (!d->is_device || cnt == 0) return src;
             dst.resize(cnt);
-            if (cnt == 0) return;
-            if (d->is_device) HIPCHK(hipMemcpy(dst.data(), src, cnt * 4, hipMemcpyDeviceToHost));
-            else std::memcpy(dst.data(), src, cnt * 4);
+            HIPCHK(hipMemcpy(dst.data(), src, cnt * 4, hipMemcpyDeviceToHost));
+            return dst.data();
         };
-        fetch(m, d->means, (size_t)n * 3);
-        fetch(ls, d->log_scales, (size_t)n * 3);
-        fetch(q, d->quats_wxyz, (size_t)n * 4);
-        fetch(op, d->opacity_logits, (size_t)n);
-        fetch(sh, d->sh, (size_t)n * 48);
+        const float* m = fetch(mv, d->means, (size_t)n * 3);
+        const float* ls = fetch(lsv, d->log_scales, (size_t)n * 3);
+        const float* q = fetch(qv, d->quats_wxyz, (size_t)n * 4);
+        const float* op = fetch(opv, d->opacity_logits, (size_t)n);
+        const float* sh = fetch(shv, d->sh, (size_t)n * 48);
         std::unique_ptr<tigas_scene> s(new tigas_scene());
         static std::atomic<uint64_t> next_uid{0};
         s->uid = ++next_uid;

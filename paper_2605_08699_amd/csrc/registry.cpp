@@ -366,17 +366,45 @@ void read_body(FILE* f, const PlyHeader& h, const VertexMap& m, const std::strin
     }
     const PlyElem& e = h.elems[(size_t)m.elem];
     const size_t stride = e.stride;
-    constexpr int64_t kChunk = 1 << 16;
+    // FP32 properties in the host's byte order are copied as they are
+    std::vector<char> plain(e.props.size());
+    for (size_t j = 0; j < e.props.size(); ++j) plain[j] = e.props[j].type == PType::F32 && !swap;
+    // records are read in chunks and decoded by up to 16 host threads
+    constexpr int64_t kChunk = 1 << 20, kPerThread = 1 << 15;
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
     std::vector<unsigned char> buf((size_t)std::min<int64_t>(std::max<int64_t>(m.n, 1), kChunk) * stride);
     for (int64_t i0 = 0; i0 < m.n; i0 += kChunk) {
         const int64_t cnt = std::min(kChunk, m.n - i0);
         if (std::fread(buf.data(), stride, (size_t)cnt, f) != (size_t)cnt)
             rfail(TIGAS_E_INVALID, path + ": file ends before the last vertex");
-        for (int64_t r = 0; r < cnt; ++r) {
-            const unsigned char* rec = buf.data() + (size_t)r * stride;
-            store_vertex(m, i0 + r, [&](int j) { return decode(rec + e.props[(size_t)j].offset, e.props[(size_t)j].type, swap); },
-                         out);
+        auto decode_range = [&](int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r) {
+                const unsigned char* rec = buf.data() + (size_t)r * stride;
+                store_vertex(m, i0 + r,
+                             [&](int j) -> double {
+                                 const PlyProp& p = e.props[(size_t)j];
+                                 if (plain[(size_t)j]) {
+                                     float v;
+                                     std::memcpy(&v, rec + p.offset, 4);
+                                     return v;
+                                 }
+                                 return decode(rec + p.offset, p.type, swap);
+                             },
+                             out);
+            }
+        };
+        const int64_t nt = std::min<int64_t>({16, hw, (cnt + kPerThread - 1) / kPerThread});
+        if (nt <= 1) {
+            decode_range(0, cnt);
+            continue;
         }
+        std::vector<std::thread> pool;
+        const int64_t per = (cnt + nt - 1) / nt;
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t r0 = t * per, r1 = std::min(cnt, r0 + per);
+            if (r0 < r1) pool.emplace_back(decode_range, r0, r1);
+        }
+        for (std::thread& th : pool) th.join();
     }
 }
 
