@@ -7,7 +7,10 @@
  * (Section 4.2), one frame from a 6DoF pose, pinhole intrinsics and an ABR
  * resolution rung with a tile-based rasterizer.  This library is that
  * rasterizer: a resident-scene loader and a render call, plus the batched
- * (many views, one launch sequence) and serving (request loop) forms.
+ * (many views, one launch sequence) and serving (request loop) forms; around
+ * it, the backend's JPEG payload encoder (on the GPU), the adaptive client's
+ * latency ABR controller and the scene registry that parses PLY models and
+ * loads, shares and unloads them (host code).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
