@@ -5,11 +5,15 @@
         --write-command CMD [--copy-bytes N]
     python -m paper_2605_08699_amd.profiling launches KERNEL_TRACE_CSV OUT_MD --match SUBSTR --command CMD
         [--title T]
+    python -m paper_2605_08699_amd.profiling counters OUT_MD --run CSV CMD [--run CSV CMD ...] --match SUBSTR
+        [--title T]
 
 `stats` turns a `--kernel-trace --stats` kernel_stats.csv into a table.
 `launches` groups the dispatches of the kernels whose name contains SUBSTR
 in a kernel_trace.csv by (kernel, workgroups): one launch shape per frame
 size, so sizes that share a kernel get a row each.
+`counters` averages, per kernel whose name contains SUBSTR, every counter of
+one or more `--pmc` counter_collection CSVs over that kernel's dispatches.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` counter_collection
 CSVs into HBM bytes per launch of every kernel.  The counters are scaled by
 what they read for the plain device-to-device copies of known size that
@@ -74,6 +78,33 @@ def per_dispatch(path):
         name, v = d.get(k, (r["Kernel_Name"], 0.0))
         d[k] = (name, v + float(r["Counter_Value"]))
     return d
+
+
+def counters(runs, dst, match, title):
+    """Per (kernel, counter): the mean over dispatches of the counter's value
+    (summed over its dimensions within a dispatch)."""
+    acc = collections.defaultdict(lambda: [0, 0.0])
+    order = []
+    for path, _cmd in runs:
+        per = collections.defaultdict(float)  # (dispatch, kernel, counter) -> value
+        for r in csv.DictReader(open(path)):
+            if match not in r["Kernel_Name"]:
+                continue
+            per[(int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"])] += float(r["Counter_Value"])
+        for (_d, name, ctr), v in per.items():
+            key = (short(name).replace("|", "/"), ctr)
+            if key not in acc:
+                order.append(key)
+            acc[key][0] += 1
+            acc[key][1] += v
+    with open(dst, "w") as f:
+        f.write(f"# {title}\n\nCommands (run from the repository root on one MI355X, one counter set per run):\n\n```\n")
+        for _path, cmd in runs:
+            f.write(cmd + "\n")
+        f.write("```\n\n| kernel | counter | dispatches | mean per dispatch |\n|---|---|---:|---:|\n")
+        for key in sorted(order):
+            n, v = acc[key]
+            f.write(f"| `{key[0]}` | {key[1]} | {n} | {v / n:.6g} |\n")
 
 
 def calibration(d, copy_bytes):
@@ -160,8 +191,15 @@ def main():
     c.add_argument("--match", required=True)
     c.add_argument("--command", required=True)
     c.add_argument("--title", default="rocprofv3 launches")
+    e = sub.add_parser("counters")
+    e.add_argument("dst")
+    e.add_argument("--run", nargs=2, action="append", required=True, metavar=("CSV", "CMD"))
+    e.add_argument("--match", required=True)
+    e.add_argument("--title", default="rocprofv3 counters")
     args = ap.parse_args()
-    if args.cmd == "stats":
+    if args.cmd == "counters":
+        counters(args.run, args.dst, args.match, args.title)
+    elif args.cmd == "stats":
         stats(args.src, args.dst, args.command, args.title)
     elif args.cmd == "launches":
         launches(args.src, args.dst, args.match, args.command, args.title)
