@@ -27,6 +27,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -399,11 +400,19 @@ void read_body(FILE* f, const PlyHeader& h, const VertexMap& m, const std::strin
             continue;
         }
         std::vector<std::thread> pool;
+        pool.reserve((size_t)nt);
         const int64_t per = (cnt + nt - 1) / nt;
-        for (int64_t t = 0; t < nt; ++t) {
-            const int64_t r0 = t * per, r1 = std::min(cnt, r0 + per);
-            if (r0 < r1) pool.emplace_back(decode_range, r0, r1);
+        int64_t started = 0;  // records handed to threads
+        try {
+            for (int64_t t = 0; t < nt; ++t) {
+                const int64_t r0 = t * per, r1 = std::min(cnt, r0 + per);
+                if (r0 < r1) pool.emplace_back(decode_range, r0, r1);
+                started = r1;
+            }
+        } catch (const std::system_error&) {
+            // no more threads: this one decodes the rest
         }
+        if (started < cnt) decode_range(started, cnt);
         for (std::thread& th : pool) th.join();
     }
 }
