@@ -25,6 +25,7 @@
 #include <cxxabi.h>
 #include <stdexcept>
 #include <string>
+#include <system_error>
 #include <vector>
 
 #include "../../include/tigas.h"
@@ -459,6 +460,32 @@ bool finite3(const float* p, int n) {
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
     return true;
+}
+
+// fn(i0, i1) over [0, n) split among up to 16 host threads (one thread for
+// small n or when no thread can be started).
+template <typename F>
+void parallel_for(int64_t n, F&& fn) {
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    const int64_t nt = std::min<int64_t>({16, hw, (n + 65535) / 65536});
+    if (nt <= 1) {
+        if (n > 0) fn((int64_t)0, n);
+        return;
+    }
+    const int64_t per = (n + nt - 1) / nt;
+    std::vector<std::thread> pool;
+    pool.reserve((size_t)nt);
+    int64_t started = 0;
+    try {
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t i0 = t * per, i1 = std::min(n, i0 + per);
+            if (i0 < i1) pool.emplace_back([&fn, i0, i1] { fn(i0, i1); });
+            started = i1;
+        }
+    } catch (const std::system_error&) {
+    }
+    if (started < n) fn(started, n);
+    for (std::thread& th : pool) th.join();
 }
 
 // Tile configuration requested by q: {0, 0} asks for the autotuner.
@@ -1822,23 +1849,29 @@ tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tig
         const size_t nn = (size_t)std::max<int64_t>(n, 1);
         // centres: FP32 planes
         std::vector<float> mp(3 * nn);
-        for (int64_t i = 0; i < n; ++i)
-            for (int c = 0; c < 3; ++c) mp[c * n + i] = m[3 * i + c];
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i)
+                for (int c = 0; c < 3; ++c) mp[c * n + i] = m[3 * i + c];
+        });
         s->mean.ensure(mp.size() * 4);
         HIPCHK(hipMemcpy(s->mean.p, mp.data(), (size_t)n * 12, hipMemcpyHostToDevice));
         if (d->storage == TIGAS_ATTR_F32) {
             std::vector<float> a(8 * nn);
-            for (int64_t i = 0; i < n; ++i) {
-                for (int c = 0; c < 4; ++c) a[4 * i + c] = q[4 * i + c];
-                for (int c = 0; c < 3; ++c) a[4 * n + 4 * i + c] = ls[3 * i + c];
-                a[4 * n + 4 * i + 3] = op[i];
-            }
+            parallel_for(n, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i) {
+                    for (int c = 0; c < 4; ++c) a[4 * i + c] = q[4 * i + c];
+                    for (int c = 0; c < 3; ++c) a[4 * n + 4 * i + c] = ls[3 * i + c];
+                    a[4 * n + 4 * i + 3] = op[i];
+                }
+            });
             // SH: the np 16-byte words of a Gaussian are contiguous, so a
             // culled Gaussian's coefficients are never fetched
             const int np = (ncoef + 3) / 4;
             std::vector<float> shp((size_t)np * 4 * nn, 0.f);
-            for (int64_t i = 0; i < n; ++i)
-                for (int k = 0; k < ncoef; ++k) shp[(size_t)i * np * 4 + k] = sh[48 * i + k];
+            parallel_for(n, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i)
+                    for (int k = 0; k < ncoef; ++k) shp[(size_t)i * np * 4 + k] = sh[48 * i + k];
+            });
             s->view.sh_stride = np;
             s->attr.ensure(a.size() * 4);
             s->sh.ensure(shp.size() * 4);
@@ -1848,15 +1881,19 @@ tigas_status tigas_scene_load(tigas_context* ctx, const tigas_scene_desc* d, tig
         } else {
             auto cvt = [&](float f) { return d->storage == TIGAS_ATTR_BF16 ? f32_to_bf16(f) : f32_to_f16(f); };
             std::vector<uint16_t> a(8 * nn);
-            for (int64_t i = 0; i < n; ++i) {
-                for (int c = 0; c < 4; ++c) a[8 * i + c] = cvt(q[4 * i + c]);
-                for (int c = 0; c < 3; ++c) a[8 * i + 4 + c] = cvt(ls[3 * i + c]);
-                a[8 * i + 7] = cvt(op[i]);
-            }
+            parallel_for(n, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i) {
+                    for (int c = 0; c < 4; ++c) a[8 * i + c] = cvt(q[4 * i + c]);
+                    for (int c = 0; c < 3; ++c) a[8 * i + 4 + c] = cvt(ls[3 * i + c]);
+                    a[8 * i + 7] = cvt(op[i]);
+                }
+            });
             const int np = (ncoef + 7) / 8;
             std::vector<uint16_t> shp((size_t)np * 8 * nn, 0);
-            for (int64_t i = 0; i < n; ++i)
-                for (int k = 0; k < ncoef; ++k) shp[(size_t)i * np * 8 + k] = cvt(sh[48 * i + k]);
+            parallel_for(n, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i)
+                    for (int k = 0; k < ncoef; ++k) shp[(size_t)i * np * 8 + k] = cvt(sh[48 * i + k]);
+            });
             s->view.sh_stride = np;
             s->attr.ensure(a.size() * 2);
             s->sh.ensure(shp.size() * 2);
