@@ -53,6 +53,19 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return readlane(wave_incl_scan(v), 63); }
 
+// Inclusive prefix maximum over the 64 lanes of a wave (same lane pattern as
+// wave_incl_scan; lanes without a source see 0, the identity for unsigned
+// maxima).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
 // Exclusive scan over a workgroup of NT threads; *total receives the sum.
 template <int NT>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
@@ -765,6 +778,9 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     __shared__ uint32_t srec[K1_THREADS];
     __shared__ uint32_t sx0[K1_THREADS], stx[K1_THREADS], snx[K1_THREADS], stb[K1_THREADS];
     __shared__ float sinx[K1_THREADS];
+    __shared__ uint32_t own[K1_THREADS];           // round-tagged owner marks of the output slots
+    __shared__ uint32_t wmax[K1_THREADS / 64];
+    static_assert(K1_THREADS == 256, "owner marks keep the Gaussian index in 8 bits");
     const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
     const uint32_t V = cnt->visible;
     uint32_t rec = 0, t = 0;
@@ -781,6 +797,7 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     if (cnt->overflow || tot == 0) return;  // uniform across the workgroup
     pre[threadIdx.x + 1] = ex + t;
     if (threadIdx.x == 0) pre[0] = 0;
+    own[threadIdx.x] = 0u;
     srec[threadIdx.x] = rec;
     if (t) {
         const ViewParams& v = views[blk_view[rec / K1_THREADS]];
@@ -794,14 +811,31 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
     }
     __syncthreads();
     const uint32_t base = blk_off[blockIdx.x];
-    for (uint32_t j = threadIdx.x; j < tot; j += K1_THREADS) {
-        // owner: the last e with pre[e] <= j
-        uint32_t lo = 0, hi = K1_THREADS;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (pre[mid] <= j) lo = mid; else hi = mid;
+    // Output slots in rounds of 256.  The owner of slot j is the last
+    // Gaussian e whose first slot is at or before j: every Gaussian marks its
+    // first slot in the round it falls in with (round << 8) | e, and a
+    // prefix maximum over the round's slots, started from the previous
+    // round's last owner, gives each slot's owner.  Marks of earlier rounds
+    // are smaller than any tag of the current one, so `own` is never cleared.
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t carry = 0;  // owner of the slot before the round
+    for (uint32_t j0 = 0, m = 0; j0 < tot; j0 += K1_THREADS, ++m) {
+        if (t && (ex >> 8) == m) own[ex & (K1_THREADS - 1)] = (m << 8) | threadIdx.x;
+        __syncthreads();
+        const uint32_t incl = wave_incl_max(own[threadIdx.x]);
+        if (lane == 63) wmax[w] = incl;
+        __syncthreads();
+        uint32_t o = max(incl, (m << 8) | carry), all = (m << 8) | carry;
+#pragma unroll
+        for (uint32_t v = 0; v < K1_THREADS / 64; ++v) {
+            const uint32_t x = wmax[v];
+            if (v < w) o = max(o, x);
+            all = max(all, x);
         }
-        const uint32_t e = lo;
+        carry = all & 0xffu;
+        const uint32_t j = j0 + threadIdx.x;
+        if (j >= tot) continue;
+        const uint32_t e = o & 0xffu;
         const uint32_t k = j - pre[e];
         const uint32_t nx = snx[e];
         // k / nx through the FP32 reciprocal, corrected to the exact quotient
