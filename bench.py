@@ -519,7 +519,7 @@ def main():
                     help="W,H,batch_depth,pixels_per_lane for the single-view variants (default: autotuned)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py renders on one GPU only: the rasterizer has no multi-GPU path in this build "
+        print("bench.py renders on one GPU only: the rasterizer has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
