@@ -249,3 +249,15 @@ def test_registry_arguments(tmp_path):
         assert len(reg) == 0
         with pytest.raises(tigas.TigasError):
             reg.acquire("nothing")
+
+
+def test_sweeping_thread_stops_on_close(tmp_path):
+    import time
+    _model_tree(tmp_path)
+    t0 = time.time()
+    for _ in range(3):
+        reg = tigas.Registry(None, str(tmp_path), idle_timeout_s=0.0, sweep_period_s=0.01)
+        time.sleep(0.05)  # several sweeps over models that are not loaded
+        assert len(reg) == 4 and reg.evict_idle() == 0
+        reg.close()
+    assert time.time() - t0 < 5.0
