@@ -370,10 +370,10 @@ def kernel_work(name, w, n, storage, tile_passes):
         # sorted record id and packed tile rectangle per visible Gaussian;
         # tile word + record id per duplicate
         return "hbm", V * 8 + D * 8
-    if "k_sort_downsweep<true, false>" in name or "k_sort_onesweep<true, false>" in name:
+    if "k_sort_downsweep<true, false>" in name:
         # the 4 depth passes: key, record and packed rectangle read and written
         return "hbm", 4 * 24 * V
-    if "k_sort_downsweep<false, false>" in name or "k_sort_onesweep<false, false>" in name:
+    if "k_sort_downsweep<false, false>" in name:
         # the tile passes: key + value read and written per duplicate
         return "hbm", tile_passes * 16 * D
     return None

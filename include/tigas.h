@@ -95,10 +95,11 @@ typedef struct {
 } tigas_intrinsics;
 
 /* Per-request quality knobs.  Zero-initialised means: full resolution,
- * the scene's SH degree, RGB8, black background, autotuned tile/batch. */
+ * SH degree 0 (the colour of the DC term only, the paper's default in
+ * Section 5.1), RGB8, black background, autotuned tile/batch. */
 typedef struct {
     float res_scale;  /* ABR rung, (0, 1]; 0 means 1 */
-    int sh_degree;    /* < 0 or > scene degree: the scene's degree */
+    int sh_degree;    /* 0 .. the scene's degree; < 0: the scene's degree; above it: E_INVALID */
     tigas_format fmt;
     float bg[3];
     int tile_w, tile_h; /* 8x8, 16x16, 16x32 or 32x16; 0x0 = autotuned for the workload's shape */
@@ -132,11 +133,10 @@ typedef struct {
  * tuning cache (the autotuner's choices per workload shape; persisted in the
  * file named by the environment variable TIGAS_TUNE_CACHE when set).  *out
  * is owned by the caller; free with tigas_context_destroy.
- * Environment read here: TIGAS_GRAPHS=0 (no graph capture), TIGAS_SORT=1
- * (single-pass sort), TIGAS_BLEND_CULL=0 (the blend keeps every list entry
- * whose pixel box meets a wave's block, instead of also dropping those whose
- * exponent stays below the skip threshold on the whole block; frames are
- * identical either way). */
+ * Environment read here: TIGAS_GRAPHS=0 (no graph capture),
+ * TIGAS_BLEND_CULL=0 (the blend keeps every list entry whose pixel box meets
+ * a wave's block, instead of also dropping those whose exponent stays below
+ * the skip threshold on the whole block; frames are identical either way). */
 tigas_status tigas_context_create(int device, tigas_context** out);
 void tigas_context_destroy(tigas_context* ctx);
 
@@ -153,7 +153,9 @@ size_t tigas_scene_bytes(const tigas_scene* scene);
  * with (tile | depth) keys, radix sort, tile ranges, front-to-back blend.
  * hip_stream: a hipStream_t of the context's device or NULL for the context
  * stream.  The call returns once the frame is complete in `out`.  E_BUFFER
- * when out->capacity < out_w*out_h*3*(1 or 4) bytes. */
+ * when out->capacity < out_w*out_h*3*(1 or 4) bytes (out_w and out_h are
+ * still written); E_INVALID for null or non-finite arguments and for a
+ * q->sh_degree above the scene's degree. */
 tigas_status tigas_render(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
                           int width, int height, const tigas_quality* q, tigas_frame* out, void* hip_stream);
 
@@ -205,20 +207,6 @@ tigas_status tigas_profile_stages(tigas_context* ctx, int enable);
  * replayed (default on; environment TIGAS_GRAPHS=0 turns it off at context
  * creation).  This switches it for the context. */
 tigas_status tigas_set_graphs(tigas_context* ctx, int enable);
-/* Radix sort of the key lists (the sort stage of Sec. 3's pipeline, the
- * same stable LSD passes either way, so the lists are identical):
- * single_pass = 0 runs each digit pass as count, scan and scatter kernels
- * (the default); 1 runs one histogram kernel per sort and then one kernel
- * per pass whose workgroups chain their digit offsets through a global
- * look-back table (environment TIGAS_SORT=1 selects it at context creation).
- * Its waits on other workgroups are bounded: should one give up, the frame
- * is rendered again with the default passes, which then stay selected for
- * the context, and tigas_sort_fallbacks counts the event.
- * Returns TIGAS_E_INVALID for a null context. */
-tigas_status tigas_set_sort(tigas_context* ctx, int single_pass);
-/* Frames re-rendered because a single-pass sort wait gave up (-1 for a null
- * context). */
-int64_t tigas_sort_fallbacks(const tigas_context* ctx);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 
 /* Kernel timing with HIP events recorded on the rendering stream around every

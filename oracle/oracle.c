@@ -25,6 +25,8 @@
  *     alpha = min(0.99, o * exp(-0.5 d^T conic d)), d = pixel centre - (u,v);
  *     alpha < 1/255: skipped;  T' = T (1 - alpha) < 1e-4: stop, this Gaussian
  *     excluded;  otherwise C += alpha T rgb, T = T';  pixel = C + T bg.
+ *   8-bit frame (Section 5.1, final rasterized frames): each channel
+ *     round-half-up(255 * clamp(c, 0, 1)), in FP32.
  *
  * Readings taken where the paper is silent (each one is listed with its reason
  * in the design notes of the repository):
@@ -403,6 +405,23 @@ void orc_render_pixels(int64_t nv, const double* pre, const double* box, int64_t
         double C0[3] = {0.0, 0.0, 0.0};
         blend_from(&cx, 0, 1.0, C0, 0);
         nbranch[i] = cx.unresolved ? -cx.nb : cx.nb;
+    }
+}
+
+/* ------------------------------------------------------------ 8-bit frame -- */
+
+/* The frame leaves the renderer as 8 bits per channel (Section 5.1, final
+ * rasterized frames).  Reading: each FP32 channel value c maps to
+ * floor(min(max(c, 0), 1) * 255 + 0.5), evaluated in FP32 (one rounded
+ * product, one rounded sum), i.e. round half up on [0, 255]. */
+void orc_pack_rgb8(int64_t n, const float* in, uint8_t* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        float c = in[i];
+        if (!(c > 0.0f)) c = 0.0f; /* also maps NaN to 0 */
+        if (c > 1.0f) c = 1.0f;
+        volatile float scaled = c * 255.0f;
+        volatile float shifted = scaled + 0.5f;
+        out[i] = (uint8_t)floorf(shifted);
     }
 }
 

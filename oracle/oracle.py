@@ -64,6 +64,8 @@ def lib():
         L.orc_prefilter_boxes.restype = None
         L.orc_render_pixels.argtypes = [I64, P, P, I64, P, P, P, D, D, ctypes.c_int, P, P]
         L.orc_render_pixels.restype = None
+        L.orc_pack_rgb8.argtypes = [I64, P, P]
+        L.orc_pack_rgb8.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -196,6 +198,14 @@ def render_nominal(proj: Projected, bg=(0.0, 0.0, 0.0), prefilter: bool = True) 
     """Single-valued FP64 frame [H, W, 3] (no decision forks)."""
     out, nb = render_frame(proj, bg, prefilter=prefilter, band_a=0.0, band_t=0.0, max_branches=1)
     return out[:, :, 0, :3]
+
+
+def pack_rgb8(frame) -> np.ndarray:
+    """8-bit frame of an FP32 frame [..., 3]: round half up of 255 * clamp(c, 0, 1) in FP32."""
+    f = np.ascontiguousarray(np.asarray(frame, np.float32))
+    out = np.zeros(f.shape, np.uint8)
+    lib().orc_pack_rgb8(f.size, _p(f), _p(out))
+    return out
 
 
 def match(gpu_rgb, branches, nbranch, tol: float):

@@ -280,8 +280,7 @@ struct Workspace {
     DevBuf counters;
     // per duplicate (also holds the visible Gaussians during the depth passes)
     DevBuf key[2], val[2], ext[2];
-    DevBuf hist, totals, queue;
-    DevBuf lookback;  // single-pass sort: 256 look-back entries per 2048-key chunk
+    DevBuf hist, queue;
     // emission-order copies for the inspection entry point
     DevBuf dbg_key, dbg_val, dbg_ext;
     // per tile / per view
@@ -350,13 +349,7 @@ struct Workspace {
             grow(ext[i], (size_t)cap * 4);
         }
         grow(hist, (size_t)2 * 256 * SORT_MAX_BLOCKS * 4);  // counts, then segment digit prefixes
-        grow(totals, (size_t)256 * MAX_SORT_PASSES * 4);
-        grow(queue, (8 + MAX_SORT_PASSES) * 4);  // blend band queues, then sort tickets
-        if (lookback.ensure(((size_t)cap / SORT_CHUNK + 2) * 256 * 8)) {
-            // entries carry a frame epoch; zero them once so no garbage can match
-            HIPCHK(hipMemset(lookback.p, 0, lookback.bytes));
-            ++gen;
-        }
+        grow(queue, 8 * 4);                                  // blend band queues
         dup_cap = cap;
     }
     void ensure_tiles(uint32_t n) {
@@ -406,9 +399,7 @@ struct tigas_context {
     std::atomic<bool> profile_kernels{false};
     std::map<std::string, std::pair<int64_t, double>> kernel_ms;  // name -> (launches, total ms)
     std::atomic<bool> use_graphs{true};
-    std::atomic<bool> sort_onepass{false};  // single-pass (look-back) radix sort
     std::atomic<bool> blend_cull{true};     // blend: per-block threshold culling
-    std::atomic<int64_t> sort_fallbacks{0};  // frames redone after a look-back wait gave up
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
     std::mutex tune_mu;
@@ -540,7 +531,8 @@ ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_
     v.width = ow;
     v.height = oh;
     int deg = q ? q->sh_degree : -1;
-    if (deg < 0 || deg > sc->view.sh_degree) deg = sc->view.sh_degree;
+    if (deg > sc->view.sh_degree) fail(TIGAS_E_INVALID, "sh_degree above the scene's degree");
+    if (deg < 0) deg = sc->view.sh_degree;
     v.sh_degree = deg;
     v.fmt = q ? (int)q->fmt : 0;
     if (v.fmt != 0 && v.fmt != 1) fail(TIGAS_E_INVALID, "unknown frame format");
@@ -651,13 +643,11 @@ void prepare(Workspace& ws, const Plan& plan, bool debug) {
 //   -> duplicate in depth order -> tile passes (duplicates) -> ranges -> blend
 // Per-context switches that change the launch sequence (not its results).
 struct LaunchOptions {
-    bool onepass = false;  // single-pass look-back radix sort
-    bool cull = true;      // blend: per-block threshold culling of list entries
+    bool cull = true;  // blend: per-block threshold culling of list entries
 };
 
 int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks,
             const LaunchOptions& opt) {
-    const bool onepass = opt.onepass;
     hipStream_t st = ws.stream;
     auto mark = [&](int i) {
         if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
@@ -676,14 +666,10 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     const int nblk = (int)(plan.nrec / K1_THREADS);
     Counters* cnt = ws.counters.as<Counters>();
     ZeroList zl{};
-    zl.p[0] = ws.totals.as<uint32_t>();
-    zl.n[0] = 256 * MAX_SORT_PASSES;
-    zl.p[1] = ws.queue.as<uint32_t>();
-    zl.n[1] = 8 + MAX_SORT_PASSES;
-    zl.p[2] = ws.ranges.as<uint32_t>();
-    zl.n[2] = 2 * plan.n_tiles;
-    zl.p[3] = nullptr;
-    zl.n[3] = 0;
+    zl.p[0] = ws.queue.as<uint32_t>();
+    zl.n[0] = 8;
+    zl.p[1] = ws.ranges.as<uint32_t>();
+    zl.n[1] = 2 * plan.n_tiles;
     launch_scan_visible(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, zl, st);
     mark(2);
     SortBuffers sb;
@@ -693,21 +679,14 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
         sb.ext[i] = ws.ext[i].as<uint32_t>();
     }
     sb.hist = ws.hist.as<uint32_t>();
-    sb.totals = ws.totals.as<uint32_t>();
     // depth digits, on the visible Gaussians (record order in, depth order
     // out); the tile rectangles travel packed with them when every view has
     // at most 256 x 256 tiles, else the last pass gathers them
     bool packed = true;
     for (const ViewParams& v : plan.views) packed = packed && v.tiles_x <= 256 && v.tiles_y <= 256;
     launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, st);
-    unsigned long long* lb = ws.lookback.as<unsigned long long>();
-    uint32_t* tickets = ws.queue.as<uint32_t>() + 8;
-    const int cv = onepass ? launch_sort_onesweep(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap,
-                                                  std::min(plan.nrec, ws.dup_cap), 0, packed, cnt, 0,
-                                                  packed ? nullptr : o.rect, packed ? nullptr : o.srect, lb,
-                                                  tickets, st)
-                           : launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0,
-                                         packed, cnt, 0, packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
+    const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0, packed, cnt,
+                               packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
     // duplicates in depth order
     const int cd = cv ^ 1;
     launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
@@ -721,10 +700,8 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     }
     // tile digits, on the duplicates
     const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
-    const int cur = onepass ? launch_sort_onesweep(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
-                                                   ws.dup_cap, cd, debug, cnt, 4, nullptr, nullptr, lb, tickets, st)
-                            : launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap,
-                                          sort_blocks(ws.dup_cap), cd, debug, cnt, 4, nullptr, nullptr, st);
+    const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap, sort_blocks(ws.dup_cap), cd,
+                                debug, cnt, nullptr, nullptr, st);
     mark(4);
     launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.fs().host_counters.as<Counters>(), o, vdev,
                   st);
@@ -747,7 +724,6 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         plan.persistent ? ctx->cus * blend_persistent_occupancy(plan.tc.tw, plan.tc.th, plan.tc.bd, plan.tc.ppl) : 0;
     // stage timing needs events between the launches: that runs uncaptured
     LaunchOptions opt;
-    opt.onepass = ctx->sort_onepass.load();
     opt.cull = ctx->blend_cull.load();
     const bool kprof = ctx->profile_kernels.load();
     const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof && !kprof;
@@ -757,7 +733,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         return enqueue(ws, plan, debug, prof, work, pblocks, opt);
     }
     if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks, opt);
-    const std::string key = shape_key(plan, true) + (opt.onepass ? "s1" : "s3") + (opt.cull ? "c1" : "c0") +
+    const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") +
                             (ws.active ? "f1" : "f0");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
@@ -803,26 +779,14 @@ void wait_stream(hipStream_t st) {
 }
 
 // After a launch of `plan` from the active slot has completed: a frame whose
-// single-pass sort gave up, or whose duplicates overflowed the buffers (it
-// then emitted nothing), is rendered again (synchronously); returns the
-// counters of the final attempt.
+// duplicates overflowed the buffers (it then emitted nothing) is rendered
+// again (synchronously) with larger buffers; returns the counters of the
+// final attempt.
 Counters settle_frame(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, bool prof,
                       unsigned long long* work, int& cur, int& rerenders) {
     Counters c;
     std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
     rerenders = 0;
-    if (c.error) {
-        // a bounded wait of the single-pass sort gave up: the lists may be
-        // wrong.  Redo the frame with the three-kernel passes, which have no
-        // inter-workgroup waits, and keep them for this context.
-        ctx->sort_onepass.store(false);
-        if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
-        cur = launch_plan(ctx, ws, plan, debug, prof, work);
-        wait_stream(ws.stream);
-        std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
-        rerenders = 1;
-        ctx->sort_fallbacks.fetch_add(1);
-    }
     if (c.overflow) {
         const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
         if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
@@ -1801,7 +1765,6 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         if (const char* f = std::getenv("TIGAS_TUNE_CACHE")) c->tune_file = f;
         if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
-        if (const char* g = std::getenv("TIGAS_SORT")) c->sort_onepass.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_BLEND_CULL")) c->blend_cull.store(std::atoi(g) != 0);
         load_tune_file(c.get());
         *out = c.release();
@@ -2034,15 +1997,6 @@ tigas_status tigas_render_wait(tigas_context* ctx, int64_t ticket, tigas_stats* 
         render_wait(ctx, ticket, stats, gpu_ms);
     });
 }
-
-tigas_status tigas_set_sort(tigas_context* ctx, int single_pass) {
-    return guard([&] {
-        if (!ctx) fail(TIGAS_E_INVALID, "null context");
-        ctx->sort_onepass.store(single_pass != 0);
-    });
-}
-
-int64_t tigas_sort_fallbacks(const tigas_context* ctx) { return ctx ? ctx->sort_fallbacks.load() : -1; }
 
 tigas_status tigas_set_graphs(tigas_context* ctx, int enable) {
     return guard([&] {

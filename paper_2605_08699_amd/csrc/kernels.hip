@@ -657,8 +657,6 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
             cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
             cnt->fb_listed = cnt->fb_list;  // every preprocess launch has appended
             cnt->fb_list = 0u;                // the next frame appends from zero
-            cnt->epoch += MAX_SORT_PASSES;  // look-back entries of earlier frames never match
-            cnt->error = 0u;
         }
     }
 #pragma unroll
@@ -1067,176 +1065,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
         }
         __syncthreads();
         base[t] += c;
-    }
-}
-
-// ------------------------------------------------- single-pass radix sort
-// One kernel per pass ("chained scan with decoupled look-back"): workgroups
-// take chunks of 2048 keys in the order of an atomic ticket, rank them like
-// the downsweep, publish each digit's chunk count, and add the counts of the
-// chunks before theirs, read back from a global look-back table; a chunk
-// whose predecessor has published its inclusive prefix stops looking back.
-// The digit totals of all passes come from one histogram kernel per sort.
-// Look-back entries are 64-bit: epoch (30 bits) | flag (2 bits) | count (32
-// bits); the epoch changes every pass, so stale entries never match.  Every
-// wait is bounded: on time-out the kernel raises cnt->error and the frame is
-// redone by the host with the three-kernel passes.
-
-constexpr uint64_t LB_AGG = 1ull << 32, LB_INC = 2ull << 32;
-
-__device__ __forceinline__ void lb_store(unsigned long long* p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long lb_load(unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Digit histograms of up to MAX_SORT_PASSES passes in one read of the keys.
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist_all(const uint32_t* __restrict__ keys,
-                                                                const Counters* __restrict__ cnt, int which,
-                                                                uint32_t cap, PassList pl,
-                                                                uint32_t* __restrict__ ghist) {
-    __shared__ uint32_t h[MAX_SORT_PASSES][256];
-    for (int i = threadIdx.x; i < MAX_SORT_PASSES * 256; i += SORT_THREADS) (&h[0][0])[i] = 0u;
-    __syncthreads();
-    const uint32_t D = sort_count(cnt, which, cap);
-    for (uint32_t i = blockIdx.x * SORT_THREADS + threadIdx.x; i < D; i += gridDim.x * SORT_THREADS) {
-        const uint32_t k = keys[i];
-        for (int p = 0; p < pl.n; ++p) atomicAdd(&h[p][(k >> pl.shift[p]) & ((1u << pl.bits[p]) - 1u)], 1u);
-    }
-    __syncthreads();
-    for (int p = 0; p < pl.n; ++p)
-        for (int t = threadIdx.x; t < (1 << pl.bits[p]); t += SORT_THREADS)
-            if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
-}
-
-template <bool EXTRA, bool SUMS>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_onesweep(
-    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
-    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext, Counters* cnt, int which,
-    uint32_t cap, int shift, int bits, const uint32_t* __restrict__ ghist, unsigned long long* lookback,
-    uint32_t* ticket, uint32_t epoch_add, const uint2* __restrict__ rsrc, uint2* __restrict__ rdst) {
-    static_assert(SORT_THREADS == 256, "one thread per digit");
-    constexpr int NW = SORT_THREADS / 64;
-    constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t lstart[256];
-    __shared__ uint32_t wcnt[NW][256];
-    __shared__ uint32_t red[NW];
-    __shared__ uint32_t lkey[SORT_CHUNK];
-    __shared__ uint32_t lval[SORT_CHUNK];
-    __shared__ uint32_t lext[EXTRA ? SORT_CHUNK : 1];
-    __shared__ uint2 lrect[SUMS ? SORT_CHUNK : 1];
-    __shared__ uint32_t chunk_id;
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const uint32_t mask = (1u << bits) - 1u;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t D = sort_count(cnt, which, cap);
-    const uint32_t nchunks = (D + SORT_CHUNK - 1) / SORT_CHUNK;
-    if (t == 0) chunk_id = atomicAdd(ticket, 1u);
-#pragma unroll
-    for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
-    __syncthreads();
-    const uint32_t c = chunk_id;
-    if (c >= nchunks) return;  // uniform
-    const uint64_t epoch = (uint64_t)((cnt->epoch + epoch_add) & 0x3fffffffu) << 34;
-    const uint32_t chunk = c * SORT_CHUNK;
-    const uint32_t end = min(D, chunk + SORT_CHUNK);
-    // global start of digit t: exclusive scan of the digit totals
-    uint32_t tot_all;
-    const uint32_t gstart = block_excl_scan<SORT_THREADS>(t <= (int)mask ? ghist[t] : 0u, red, &tot_all);
-    uint32_t dig[ROUNDS], rank[ROUNDS], ek[ROUNDS], ev[ROUNDS], ee[ROUNDS];
-    uint2 er[ROUNDS];
-    bool ok[ROUNDS];
-#pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-        const uint32_t idx = chunk + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
-        ok[r] = idx < end;
-        const uint32_t ic = ok[r] ? idx : chunk;
-        const uint32_t key = skey[ic];
-        ev[r] = sval[ic];
-        ee[r] = EXTRA ? sext[ic] : 0u;
-        if constexpr (SUMS) er[r] = rsrc[ev[r]];
-        ek[r] = key;
-        const uint32_t d = (key >> shift) & mask;
-        dig[r] = d;
-        uint64_t m = ballot(ok[r]);
-        for (int b = 0; b < bits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bl = ballot(bit);
-            m &= bit ? bl : ~bl;
-        }
-        const uint32_t prior = (uint32_t)__builtin_popcountll(m & lt);
-        uint32_t cur = 0;
-        if (ok[r]) cur = wcnt[w][d];
-        rank[r] = cur + prior;
-        if (ok[r] && prior == 0) wcnt[w][d] = cur + (uint32_t)__builtin_popcountll(m);
-    }
-    __syncthreads();
-    uint32_t cc = 0;
-#pragma unroll
-    for (int j = 0; j < NW; ++j) cc += wcnt[j][t];
-    // publish this chunk's count of digit t, then add those of earlier chunks
-    unsigned long long* mine = lookback + (size_t)c * 256 + t;
-    uint64_t prefix = 0;
-    if (t <= (int)mask) {
-        if (c == 0) {
-            lb_store(mine, epoch | LB_INC | cc);
-        } else {
-            lb_store(mine, epoch | LB_AGG | cc);
-            int64_t j = (int64_t)c - 1;
-            uint32_t spins = 0;
-            while (j >= 0) {
-                const uint64_t v = lb_load(lookback + (size_t)j * 256 + t);
-                if ((v & ~0x3ffffffffull) == epoch && (v & (3ull << 32))) {
-                    prefix += (uint32_t)v;
-                    if (v & LB_INC) break;
-                    --j;
-                    spins = 0;
-                } else if (++spins > (1u << 18)) {
-                    atomicOr(&cnt->error, 1u);
-                    break;
-                } else {
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            lb_store(mine, epoch | LB_INC | (uint32_t)(prefix + cc));
-        }
-    }
-    // chunk-local digit starts and per-wave offsets, as in the downsweep
-    uint32_t tot;
-    const uint32_t ls = block_excl_scan<SORT_THREADS>(cc, red, &tot);
-    lstart[t] = ls;
-    base[t] = gstart + (uint32_t)prefix;
-    uint32_t acc = ls;
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-        const uint32_t x = wcnt[j][t];
-        wcnt[j][t] = acc;
-        acc += x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-        if (ok[r]) {
-            const uint32_t l = wcnt[w][dig[r]] + rank[r];
-            lkey[l] = ek[r];
-            lval[l] = ev[r];
-            if (EXTRA) lext[l] = ee[r];
-            if constexpr (SUMS) lrect[l] = er[r];
-        }
-    }
-    __syncthreads();
-    for (uint32_t l = (uint32_t)t; l < tot; l += SORT_THREADS) {
-        const uint32_t k = lkey[l];
-        const uint32_t d = (k >> shift) & mask;
-        const uint32_t pos = base[d] + (l - lstart[d]);
-        if (pos < D) {
-            dkey[pos] = k;
-            dval[pos] = lval[l];
-            if (EXTRA) dext[pos] = lext[l];
-            if constexpr (SUMS) rdst[pos] = lrect[l];
-        }
     }
 }
 
@@ -1705,7 +1533,7 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
 }
 
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, int totals_base, const uint2* rect_src,
+                int start, bool extra, const Counters* cnt, const uint2* rect_src,
                 uint2* rect_dst, hipStream_t st) {
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
@@ -1729,39 +1557,6 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
         else if (sums) TIGAS_DOWN(false, true);
         else TIGAS_DOWN(false, false);
 #undef TIGAS_DOWN
-        cur ^= 1;
-    }
-    return cur;
-}
-
-int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
-                         uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
-                         const uint2* rect_src, uint2* rect_dst, unsigned long long* lookback, uint32_t* tickets,
-                         hipStream_t st) {
-    PassList pl{};
-    pl.n = npasses;
-    for (int p = 0; p < npasses; ++p) {
-        pl.shift[p] = passes[p].shift;
-        pl.bits[p] = passes[p].bits;
-    }
-    uint32_t* ghist = b.totals + totals_base * 256;
-    TIGAS_LAUNCH(k_sort_hist_all, dim3(512), dim3(SORT_THREADS), st, (const uint32_t*)b.key[start], cnt, which, cap,
-                 pl, ghist);
-    const uint32_t grid = std::max<uint32_t>(1u, (max_items + SORT_CHUNK - 1) / SORT_CHUNK);
-    int cur = start;
-    for (int p = 0; p < npasses; ++p) {
-        const SortPass& ps = passes[p];
-        const bool sums = rect_src && p + 1 == npasses;
-#define TIGAS_ONE(E, S)                                                                                            \
-    TIGAS_LAUNCH((k_sort_onesweep<E, S>), dim3(grid), dim3(SORT_THREADS), st, b.key[cur], b.val[cur], b.ext[cur], \
-                 b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits,               \
-                 (const uint32_t*)(ghist + p * 256), lookback, tickets + totals_base + p,                        \
-                 (uint32_t)(totals_base + p), rect_src, rect_dst)
-        if (extra && sums) TIGAS_ONE(true, true);
-        else if (extra) TIGAS_ONE(true, false);
-        else if (sums) TIGAS_ONE(false, true);
-        else TIGAS_ONE(false, false);
-#undef TIGAS_ONE
         cur ^= 1;
     }
     return cur;

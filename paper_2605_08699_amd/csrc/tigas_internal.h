@@ -56,8 +56,6 @@ struct Counters {
     uint32_t fallbacks;
     uint32_t overflow;  // D exceeded the duplicate capacity: nothing was emitted
     uint32_t fb_list;   // append cursor of the FP64-fallback list (cleared once counted)
-    uint32_t epoch;     // advanced every frame: tags the single-pass sort's look-back entries
-    uint32_t error;     // a bounded wait of the single-pass sort timed out (frame must be redone)
     uint32_t fb_listed; // entries in the FP64-fallback list this frame
 };
 
@@ -99,7 +97,6 @@ struct SortBuffers {
     uint32_t* val[2];
     uint32_t* ext[2];
     uint32_t* hist;    // [256][SORT_MAX_BLOCKS] digit counts per segment, then as many segment digit prefixes
-    uint32_t* totals;  // [MAX_SORT_PASSES][256] digit totals (single-pass sort only)
 };
 
 // Arrays cleared (as u32 words) by the first kernel after preprocess.
@@ -107,12 +104,6 @@ struct ZeroList {
     static constexpr int N = 4;
     uint32_t* p[N];
     uint32_t n[N];
-};
-
-struct PassList {
-    int n;
-    int shift[MAX_SORT_PASSES];
-    int bits[MAX_SORT_PASSES];
 };
 
 struct SortPass {
@@ -141,16 +132,8 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
 // With `rect_src`, the last pass also writes rect_src[value] to rect_dst in
 // sorted order.
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, int totals_base, const uint2* rect_src,
+                int start, bool extra, const Counters* cnt, const uint2* rect_src,
                 uint2* rect_dst, hipStream_t st);
-// The same passes with one kernel each (look-back chained scan) after one
-// histogram kernel; tickets[totals_base + p] must be zero, lookback holds
-// 256 entries per 2048-key chunk of max_items (the most keys the count can
-// reach).
-int launch_sort_onesweep(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap,
-                         uint32_t max_items, int start, bool extra, Counters* cnt, int totals_base,
-                         const uint2* rect_src, uint2* rect_dst, unsigned long long* lookback, uint32_t* tickets,
-                         hipStream_t st);
 // Tile ranges of the sorted list; the same launch recomputes, in FP64, the
 // conic of every Gaussian preprocess listed as near-singular.  host_cnt:
 // pinned host memory that receives a copy of the counters.

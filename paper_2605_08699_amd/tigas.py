@@ -87,7 +87,7 @@ class AbrConfigC(ctypes.Structure):
 EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", "tigas_scene_free",
            "tigas_scene_bytes", "tigas_render", "tigas_render_batch", "tigas_last_stats", "tigas_last_error",
            "tigas_render_debug", "tigas_selftest_wave_scan", "tigas_profile_stages", "tigas_stage_times",
-           "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort", "tigas_sort_fallbacks",
+           "tigas_count_blend_work", "tigas_set_graphs",
            "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait",
            "tigas_jpeg_encode", "tigas_jpeg_max_bytes", "tigas_abr_default_config", "tigas_abr_create",
            "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate")
@@ -128,9 +128,6 @@ def lib():
         L.tigas_selftest_wave_scan.argtypes = [P, P, I]
         L.tigas_profile_stages.argtypes = [P, I]
         L.tigas_set_graphs.argtypes = [P, I]
-        L.tigas_set_sort.argtypes = [P, I]
-        L.tigas_sort_fallbacks.argtypes = [P]
-        L.tigas_sort_fallbacks.restype = I64
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
         L.tigas_profile_kernels.argtypes = [P, I]
         L.tigas_render_submit.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
@@ -152,7 +149,7 @@ def lib():
                                              ctypes.POINTER(I64), ctypes.POINTER(I64)]
         for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
-                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs", "tigas_set_sort",
+                     "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs",
                      "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit",
                      "tigas_render_wait", "tigas_jpeg_encode", "tigas_abr_create", "tigas_abr_observe",
                      "tigas_abr_rate"):
@@ -289,13 +286,6 @@ class Context:
     def set_graphs(self, enable: bool):
         """Capture/replay launch sequences as HIP graphs (default on)."""
         _check(lib().tigas_set_graphs(self.handle, 1 if enable else 0))
-
-    def set_sort(self, single_pass: bool):
-        """Single-pass look-back radix sort (True) or count/scan/scatter passes."""
-        _check(lib().tigas_set_sort(self.handle, 1 if single_pass else 0))
-
-    def sort_fallbacks(self) -> int:
-        return int(lib().tigas_sort_fallbacks(self.handle))
 
     def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=None,
                          batch_depth=None, ppl=None):

@@ -1,13 +1,17 @@
 """Parity at full workload sizes (needs an MI355X).
 
-1M Gaussians at 1280x720 along the 300-pose trajectory (sampled poses,
-sampled pixels against the FP64 oracle one by one, per-Gaussian values and
-bit-exact tile lists on whole frames), and the 3M-Gaussian 1080p scene with
-FP32 / FP16 / BF16 attribute storage (PSNR against the FP64 oracle and
-against the GPU FP32 frames).
+1M Gaussians at 1280x720 and 3M Gaussians at 1920x1080 along their 300-pose
+trajectories: sampled pixels of every 40th pose against the FP64 oracle one by
+one (within 1e-4, no unresolved pixel), per-Gaussian values (FP64-fallback
+conics to 1e-6) and bit-exact tile lists on whole frames, and FP16 / BF16
+attribute storage (PSNR against the FP64 oracle on the same poses and against
+the GPU FP32 frames on all 300).
 """
+import math
+
 import numpy as np
 import pytest
+import torch
 
 from oracle import oracle as orc
 from paper_2605_08699_amd import synth, tigas
@@ -42,7 +46,19 @@ def _sample(rng, W, H, n):
     return idx % W, idx // W
 
 
-@pytest.mark.parametrize("pose_i", [0, 150, 299])
+# the poses whose oracle frames anchor the FP32 parity and the PSNR of the
+# reduced-precision variants: every 40th of the 300-pose trajectory
+ANCHORS = list(range(0, 300, 40))
+
+
+def _psnr_dev(a, b):
+    """PSNR of two frames held in GPU tensors (values clamped to [0, 1])."""
+    d = a.clamp(0, 1).double() - b.clamp(0, 1).double()
+    mse = float((d * d).mean())
+    return math.inf if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+@pytest.mark.parametrize("pose_i", ANCHORS)
 def test_c2_sampled_pixels_match_oracle(ctx, c2, pose_i):
     scene, traj, k = c2
     s = ctx.load_scene(scene)
@@ -68,19 +84,35 @@ def test_c2_preprocess_and_tiles_full_frame(ctx, c2):
     s.free()
 
 
-def test_c3_fp32_sampled_pixels(ctx, c3):
+def test_c3_preprocess_and_tiles_full_frame(ctx, c3):
+    # the headline scene holds near-singular surface splats: their conics come
+    # from the FP64 fallback and must match the oracle to 1e-6 relative
     scene, traj, k = c3
     s = ctx.load_scene(scene)
-    img = ctx.render(s, traj[0], k, 1920, 1080, fmt="f32")
+    _say("c3 k1 pose 0")
+    dbg = ctx.render_debug(s, traj[0], k, 1920, 1080, tile=(16, 32))
+    st = ctx.stats()
     proj = orc.preprocess(scene, traj[0], k, 1920, 1080)
-    px, py = _sample(np.random.default_rng(7), 1920, 1080, 2000)
+    err = gc.check_preprocess(dbg, proj, 1920, 1080)
+    _say("c3 k1", err, "D", dbg["n_dup"], "fallbacks", st["fallbacks"])
+    assert st["fallbacks"] > 0 and err["n_fp64"] > 0
+    gc.check_tiles(dbg, 16, 32)
+    s.free()
+
+
+@pytest.mark.parametrize("pose_i", ANCHORS)
+def test_c3_fp32_sampled_pixels_match_oracle(ctx, c3, pose_i):
+    scene, traj, k = c3
+    s = ctx.load_scene(scene)
+    _say("c3 fp32 pose", pose_i)
+    img = ctx.render(s, traj[pose_i], k, 1920, 1080, fmt="f32")
+    st = ctx.stats()
+    proj = orc.preprocess(scene, traj[pose_i], k, 1920, 1080)
+    px, py = _sample(np.random.default_rng(7 + pose_i), 1920, 1080, 2000)
     br, nb = orc.render_pixels(proj, px, py)
     res = gc.check_frame_pixels(img[py, px], br, nb)
-    _say("c3 fp32", res, ctx.stats())
-    # near-singular surface splats: the FP32 conic carries ~eps*cond(Sigma2D)
-    # relative error; parity at 1e-4 is required for the volumetric workloads,
-    # here the frame must match to PSNR >= 50 dB against the same oracle pixels
-    assert gc.psnr(img[py, px], br[:, 0, :3]) >= 50.0
+    _say("c3 fp32", pose_i, res, st)
+    assert res["n_bad"] == 0 and res["n_unresolved"] == 0, res
     s.free()
 
 
@@ -89,19 +121,28 @@ def test_c3_reduced_precision_psnr(ctx, c3, storage):
     scene, traj, k = c3
     s32 = ctx.load_scene(scene, "f32")
     sh = ctx.load_scene(scene, storage)
-    worst_gpu = np.inf
-    for i in range(0, 300, 10):
-        a = ctx.render(s32, traj[i], k, 1920, 1080, fmt="f32")
-        b = ctx.render(sh, traj[i], k, 1920, 1080, fmt="f32")
-        worst_gpu = min(worst_gpu, gc.psnr(a, b))
-    proj = orc.preprocess(scene, traj[0], k, 1920, 1080)
-    px, py = _sample(np.random.default_rng(11), 1920, 1080, 2000)
-    br, nb = orc.render_pixels(proj, px, py)
-    b0 = ctx.render(sh, traj[0], k, 1920, 1080, fmt="f32")
-    p_oracle = gc.psnr(b0[py, px], br[:, 0, :3])
-    _say(storage, "min PSNR vs GPU FP32 over 30 poses", worst_gpu, "PSNR vs FP64 oracle (pose 0 sample)", p_oracle)
+    # against the GPU FP32 frames: every pose of the trajectory
+    a = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    worst_gpu, mean_gpu = math.inf, 0.0
+    for i in range(300):
+        ctx.render(s32, traj[i], k, 1920, 1080, fmt="f32", out=a)
+        ctx.render(sh, traj[i], k, 1920, 1080, fmt="f32", out=b)
+        p = _psnr_dev(a, b)
+        worst_gpu = min(worst_gpu, p)
+        mean_gpu += p / 300
+    # against the FP64 oracle: sampled pixels of the anchor poses
+    worst_oracle = math.inf
+    for i in ANCHORS:
+        proj = orc.preprocess(scene, traj[i], k, 1920, 1080)
+        px, py = _sample(np.random.default_rng(11 + i), 1920, 1080, 2000)
+        br, nb = orc.render_pixels(proj, px, py)
+        img = ctx.render(sh, traj[i], k, 1920, 1080, fmt="f32")
+        worst_oracle = min(worst_oracle, gc.psnr(img[py, px], br[:, 0, :3]))
+    _say(storage, "PSNR vs GPU FP32 over 300 poses: min", worst_gpu, "mean", mean_gpu,
+         "min PSNR vs FP64 oracle over the anchor poses", worst_oracle)
     assert worst_gpu >= 50.0
-    assert p_oracle >= 50.0
+    assert worst_oracle >= 50.0
     s32.free()
     sh.free()
 
@@ -116,4 +157,4 @@ def test_reduced_precision_decode_matches_oracle_of_rounded_scene(ctx, storage):
     br, nb = orc.render_frame(proj)
     res = gc.check_frame_pixels(img.reshape(-1, 3), br.reshape(-1, br.shape[2], 4), nb.reshape(-1))
     _say(storage, res)
-    assert res["n_bad"] == 0, res
+    assert res["n_bad"] == 0 and res["n_unresolved"] == 0, res

@@ -1,12 +1,15 @@
 """Serving form (needs an MI355X): continuous batching of client requests
 under a memory budget.  Every rendered frame must be identical to rendering
-the request alone."""
+the request alone, and served frames match the FP64 oracle on sampled
+pixels."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import jpeg as oj
+from oracle import oracle as orc
 from paper_2605_08699_amd import synth, tigas
+from tests import gpu_checks as gc
 from tests.handmade import random_tiny_scene
 
 pytestmark = pytest.mark.gpu
@@ -25,13 +28,21 @@ def ctx():
     c.close()
 
 
+SOURCES = {}  # loaded scene handle -> the attributes as the library stores them (for the oracle)
+
+
 @pytest.fixture(scope="module")
 def scenes(ctx):
-    a = ctx.load_scene(synth.c2_scene(150_000), "f32")
-    b = ctx.load_scene(random_tiny_scene(np.random.default_rng(9), n=8000, extent=3.0, depth=(2.0, 9.0)), "f16")
-    c = ctx.load_scene(synth.scene_clusters(seed=61, n=60_000, n_clusters=8, surface_frac=0.4), "bf16")
-    yield [a, b, c]
-    for s in (a, b, c):
+    srcs = [(synth.c2_scene(150_000), "f32"),
+            (random_tiny_scene(np.random.default_rng(9), n=8000, extent=3.0, depth=(2.0, 9.0)), "f16"),
+            (synth.scene_clusters(seed=61, n=60_000, n_clusters=8, surface_frac=0.4), "bf16")]
+    loaded = []
+    for sc, storage in srcs:
+        h = ctx.load_scene(sc, storage)
+        SOURCES[id(h)] = sc if storage == "f32" else gc.round_attrs(sc, storage)
+        loaded.append(h)
+    yield loaded
+    for s in loaded:
         s.free()
 
 
@@ -67,8 +78,17 @@ def test_results_identical_alone_and_in_the_mix(ctx, scenes):
     _say("mix", st)
     assert len(done) == 40 and all(d["status"] == 0 for d in done)
     assert st["batches"] < 40 and st["max_batch_seen"] > 1      # requests were batched together
+    rng = np.random.default_rng(3)
     for i in range(40):
         np.testing.assert_array_equal(outs[i], _alone(ctx, meta[i]), err_msg=f"request {i}")
+        # and each served frame against the FP64 oracle on sampled pixels
+        sc, pose, k, rung = meta[i]
+        proj = orc.preprocess(SOURCES[id(sc)], pose, k, W, H, scale=rung)
+        idx = rng.choice(proj.out_w * proj.out_h, 200, replace=False)
+        px, py = idx % proj.out_w, idx // proj.out_w
+        br, nb = orc.render_pixels(proj, px, py)
+        res = gc.check_frame_pixels(outs[i][py, px], br, nb)
+        assert res["n_bad"] == 0 and res["n_unresolved"] == 0, (i, res)
 
 
 def test_jpeg_payloads_in_the_mix(ctx, scenes):

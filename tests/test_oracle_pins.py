@@ -10,6 +10,7 @@ import math
 import numpy as np
 import pytest
 import scipy.special as sps
+from scipy.spatial.transform import Rotation
 
 from oracle import oracle as orc
 from paper_2605_08699_amd import synth
@@ -184,7 +185,9 @@ def test_offaxis_axis_aligned_covariance(x0):
 def test_ewa_matches_finite_difference_jacobian():
     # the 2D covariance is the first-order push-forward of the 3D covariance
     # through the pinhole map: J_num Sigma J_num^T + 0.3 I with J_num from
-    # central differences of the projection (inside the 1.3x FoV clamp)
+    # central differences of the projection (inside the 1.3x FoV clamp) and
+    # Sigma = R_q S S^T R_q^T with R_q from scipy's quaternion conversion, so a
+    # transposed or conjugated rotation in the oracle fails here
     rng = np.random.default_rng(11)
     cam_t = np.array([0.4, -0.3, -5.0])
     R = synth.look_at(cam_t, [0.2, 0.1, 0.0]).astype(np.float32)
@@ -204,8 +207,8 @@ def test_ewa_matches_finite_difference_jacobian():
         h = 1e-5
         Jn = np.column_stack([(proj(mu + h * e) - proj(mu - h * e)) / (2 * h) for e in np.eye(3)])
         q = s.quats[g].astype(np.float64)
-        q /= np.linalg.norm(q)
-        Rq = synth._quat_to_mat(q[None])[0]
+        # rotation of the unit quaternion (w, x, y, z) from scipy (scalar-last order)
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
         S = np.diag(np.exp(s.log_scales[g].astype(np.float64)))
         Sig = Rq @ S @ S @ Rq.T
         C2 = Jn @ Sig @ Jn.T + 0.3 * np.eye(2)
@@ -414,3 +417,22 @@ def test_rungs_reproduce_the_paper_ladder():
         ow, oh, (fx, fy, cx, cy) = orc.rung(k, 1280, 720, float(sc))
         assert (ow, oh) == (int(w), int(h))
         assert (cx, cy) == (ow / 2, oh / 2)
+
+
+def test_rgb8_pack_levels_midpoints_and_clamp():
+    # every level k/255 maps to k; values a few ulps below the midpoint
+    # (k + 1/2)/255 map to k, a few ulps above to k + 1 (round half up);
+    # outside [0, 1] (and NaN) the value is clamped first
+    k = np.arange(256)
+    lv = (k / 255.0).astype(np.float32)
+    np.testing.assert_array_equal(orc.pack_rgb8(lv), k)
+    mid = ((k[:-1] + 0.5) / 255.0).astype(np.float32)
+    below = np.nextafter(np.nextafter(mid, np.float32(0)), np.float32(0))
+    above = np.nextafter(np.nextafter(mid, np.float32(1)), np.float32(1))
+    np.testing.assert_array_equal(orc.pack_rgb8(below), k[:-1])
+    np.testing.assert_array_equal(orc.pack_rgb8(above), k[:-1] + 1)
+    edge = np.array([-1.0, -0.0, 1.0, 1.5, 1e30, np.inf, -np.inf, np.nan], np.float32)
+    np.testing.assert_array_equal(orc.pack_rgb8(edge), [0, 0, 255, 255, 255, 255, 0, 0])
+    # monotone over a dense sweep of [0, 1]
+    x = np.linspace(0, 1, 100001, dtype=np.float32)
+    assert np.all(np.diff(orc.pack_rgb8(x).astype(int)) >= 0)
