@@ -30,11 +30,32 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed FMA), TFLOP/s
 # (1); a contribution adds transmittance (2), weight (1), 3 FMA colour (6)
 FLOPS_EVAL = 12
 FLOPS_CONTRIB = 9
+# the cost model of the scope table: 15 VALU operations + 1 exp per evaluation
+OPS_EVAL_MODEL = 16
 
 
 def _stats(ts):
     a = np.asarray(ts) * 1e3
     return float(np.median(a)), float(np.percentile(a, 99))
+
+
+def pose_index(i, steps, n_poses):
+    """Timed frame i of `steps` renders pose pose_index(...) of the trajectory:
+    fewer steps than poses are spread evenly over the whole trajectory (every
+    n_poses/steps-th pose), more wrap around it."""
+    return (i * n_poses) // steps if steps <= n_poses else i % n_poses
+
+
+def timed_poses(steps, n_poses):
+    """Description of the poses a run of `steps` frames times."""
+    idx = sorted({pose_index(i, steps, n_poses) for i in range(steps)})
+    if len(idx) == n_poses:
+        return dict(poses=n_poses, pose_indices=f"all {n_poses} poses" + (", wrapping" if steps > n_poses else ""))
+    stride = idx[1] - idx[0] if len(idx) > 1 else 0
+    even = all(idx[j + 1] - idx[j] == stride for j in range(len(idx) - 1))
+    desc = (f"{idx[0]}, {idx[1]}, ..., {idx[-1]} (every {stride}th of {n_poses})" if even and len(idx) > 2 else
+            ", ".join(str(x) for x in idx[:8]) + (" ..." if len(idx) > 8 else "") + f" of {n_poses}")
+    return dict(poses=len(idx), pose_indices=desc)
 
 
 def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch, count_work, tile_kw):
@@ -51,7 +72,7 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
         t0 = time.perf_counter()
         for i in range(steps):
             t = time.perf_counter()
-            ctx.render(s, traj[i % len(traj)], k, W, H, out=out, **tile_kw)
+            ctx.render(s, traj[pose_index(i, steps, len(traj))], k, W, H, out=out, **tile_kw)
             lat.append(time.perf_counter() - t)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
@@ -68,7 +89,7 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        t = ctx.render_async(s, traj[i % len(traj)], k, W, H, outs[i % 2], **tile_kw)
+        t = ctx.render_async(s, traj[pose_index(i, steps, len(traj))], k, W, H, outs[i % 2], **tile_kw)
         if prev is not None:
             res.append(ctx.wait(prev))
         prev = t
@@ -96,7 +117,8 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
     work = dict(frames=0, visible=0, duplicates=0, evaluations=0, contributions=0, fallbacks=0)
     if count_work:
         for i in range(steps):
-            e, c = ctx.count_blend_work(s, traj[i % len(traj)], k, W, H, tile=(cfg["tile_w"], cfg["tile_h"]),
+            e, c = ctx.count_blend_work(s, traj[pose_index(i, steps, len(traj))], k, W, H,
+                                        tile=(cfg["tile_w"], cfg["tile_h"]),
                                         batch_depth=cfg["batch_depth"], ppl=cfg["pixels_per_lane"])
             st = ctx.stats()
             work["frames"] += 1
@@ -112,6 +134,42 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
                work=work, scene_bytes=s.bytes, kernels=kernels)
     s.free()
     return res
+
+
+def run_plain(ctx, scene, traj, k, W, H, steps, warmup, torch):
+    """The plain FP32 single-view renderer on another workload: frames/s and
+    p50/p99 host latency per frame (graph replay, autotuned tile) over the
+    same evenly spread poses, and the GPU time per frame (HIP events) of the
+    same frames submitted asynchronously."""
+    s = ctx.load_scene(scene, "f32")
+    out = torch.empty((H, W, 3), dtype=torch.uint8, device="cuda")
+    n = len(traj)
+    for i in range(warmup):
+        ctx.render(s, traj[i % n], k, W, H, out=out)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        t = time.perf_counter()
+        ctx.render(s, traj[pose_index(i, steps, n)], k, W, H, out=out)
+        lat.append(time.perf_counter() - t)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    st = ctx.stats()
+    outs = [out, torch.empty_like(out)]
+    gms, prev = [], None
+    for i in range(steps):
+        t = ctx.render_async(s, traj[pose_index(i, steps, n)], k, W, H, outs[i % 2])
+        if prev is not None:
+            gms.append(ctx.wait(prev)["gpu_ms"])
+        prev = t
+    gms.append(ctx.wait(prev)["gpu_ms"])
+    p50, p99 = _stats(lat)
+    s.free()
+    return dict(n_gaussians=scene.n, width=W, height=H, **timed_poses(steps, n), frames_per_s=steps / total,
+                ms_per_frame=1e3 * total / steps, p50_ms=p50, p99_ms=p99, gpu_ms_mean=float(np.mean(gms)),
+                tile=f"{st['tile_w']}x{st['tile_h']}", batch_depth=st["batch_depth"],
+                pixels_per_lane=st["pixels_per_lane"], visible_last=st["visible"], duplicates_last=st["duplicates"])
 
 
 def run_batched(ctx, scene, torch, steps=30, warmup=3):
@@ -279,16 +337,20 @@ def run_abr_clients(ctx, torch, tigas, serving_scenes, seconds=4.0, n_clients=16
                 bandwidth_mbps=[round(float(b) / 1e6, 1) for b in mean_bw])
 
 
-def run_serving(ctx, torch, tigas, serving_scenes, seconds=3.0, warm=0.5, rates=(10.0, 20.0, 30.0, 40.0, 50.0),
-                budget_gb=48, batch_mpx=6.0):
+def run_serving(ctx, torch, tigas, serving_scenes, seconds=10.0, warm=1.0, sweep_seconds=4.0,
+                rates=(30.0, 40.0, 45.0, 50.0), budget_gb=48, batch_mpx=6.0, slots=2):
     """The serving form: 64 clients (Poisson arrivals, random rungs of
     1920x1080, their own 6DoF walks) on 4 resident FP16 scenes of 0.5/1/3/6M
     Gaussians, replayed open-loop into the library's continuous-batching
-    server (2 slots, memory budget).  Full offered load (60 req/s per client)
-    with latest-pose-wins, then a rate sweep without supersession to find the
-    largest per-client rate whose p99 latency for 1080p frames of the 3M scene
-    stays within 10 ms; then full load and 40 req/s per client again with each
-    frame also encoded as its JPEG payload."""
+    server (memory budget).  Full offered load (60 req/s per client) for
+    `seconds` after `warm` seconds of warm-up, with latest-pose-wins; then a
+    shorter rate sweep without supersession for the largest per-client rate
+    whose p99 latency for 1080p frames of the 3M scene stays within 10 ms;
+    then full load and 40 req/s per client again with each frame also encoded
+    as its JPEG payload.  A superseded request is not rendered: its client
+    sees the frame of the request that replaced it, so besides the latency of
+    rendered requests the report gives a p99 that counts each superseded
+    request from its own arrival to that frame's completion."""
     from paper_2605_08699_amd import synth
     scenes = [ctx.load_scene(sc, "f16") for sc in serving_scenes]
     k = synth.fov_intrinsics(1920, 1080)
@@ -296,9 +358,9 @@ def run_serving(ctx, torch, tigas, serving_scenes, seconds=3.0, warm=0.5, rates=
     jpeg_outs = [torch.empty(8 << 20, dtype=torch.uint8, device="cuda") for _ in range(64)]
     ladder_q = {0.25: 10, 0.5: 35, 0.75: 65, 1.0: 90}
 
-    def trace(rate, jpeg=False):
-        clients = synth.serving_clients(64, rate_hz=rate, duration_s=seconds)
-        reqs, meta = [], []
+    def trace(rate, duration, jpeg=False):
+        clients = synth.serving_clients(64, rate_hz=rate, duration_s=duration)
+        reqs = []
         for c, cl in enumerate(clients):
             for j in range(len(cl.arrivals_s)):
                 reqs.append((cl.arrivals_s[j], c, cl.scene_id, cl.poses[j], float(cl.rungs[j])))
@@ -308,41 +370,61 @@ def run_serving(ctx, torch, tigas, serving_scenes, seconds=3.0, warm=0.5, rates=
               for t, c, sid, pose, rung in reqs]
         return cs, reqs
 
-    def run(rate, supersede, jpeg=False):
-        cs, reqs = trace(rate, jpeg)
-        with tigas.Server(ctx, slots=2, max_batch=64, hbm_budget=int(budget_gb * 2 ** 30), supersede=supersede,
+    def run(rate, supersede, measured, jpeg=False):
+        cs, reqs = trace(rate, warm + measured, jpeg)
+        with tigas.Server(ctx, slots=slots, max_batch=64, hbm_budget=int(budget_gb * 2 ** 30), supersede=supersede,
                           max_batch_pixels=int(batch_mpx * 1e6)) as sv:
             done = sv.replay(cs)
             st = sv.stats()
-        lat, lat_hd = [], []
-        for d, r in zip(done, reqs):
-            if d["status"] != 0 or r[0] < warm:
+        lat, lat_hd, lat_all, lat_all_hd = [], [], [], []
+        # completion of the next rendered request of each client, for the superseded ones
+        next_done = {}
+        served_by = [None] * len(done)
+        for i in range(len(done) - 1, -1, -1):
+            c = reqs[i][1]
+            if done[i]["status"] == 0:
+                next_done[c] = done[i]["done_s"]
+            served_by[i] = next_done.get(c)
+        for d, r, sb in zip(done, reqs, served_by):
+            if r[0] < warm:
                 continue
-            ms = 1e3 * (d["done_s"] - d["arrival_s"])
-            lat.append(ms)
-            if r[2] == 2 and r[4] == 1.0:
-                lat_hd.append(ms)
+            hd = r[2] == 2 and r[4] == 1.0
+            if d["status"] == 0:
+                ms = 1e3 * (d["done_s"] - d["arrival_s"])
+                lat.append(ms)
+                lat_all.append(ms)
+                if hd:
+                    lat_hd.append(ms)
+                    lat_all_hd.append(ms)
+            elif d["status"] == 1 and sb is not None:
+                ms = 1e3 * (sb - d["arrival_s"])
+                lat_all.append(ms)
+                if hd:
+                    lat_all_hd.append(ms)
         rendered = sum(1 for d, r in zip(done, reqs) if d["status"] == 0 and r[0] >= warm)
         jb = [d["jpeg_bytes"] for d, r in zip(done, reqs) if d["status"] == 0 and r[0] >= warm and jpeg]
         pct = lambda a, q: float(np.percentile(a, q)) if a else None
-        return dict(rate_per_client=rate, offered_req_per_s=len(reqs) / seconds, rendered_frames_per_s=rendered /
-                    (seconds - warm), p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p50_ms_1080p_3M=pct(lat_hd, 50),
-                    p99_ms_1080p_3M=pct(lat_hd, 99), superseded=st["superseded"], deferred=st["deferred"],
-                    admitted=st["admitted"], batches=st["batches"],
-                    mean_batch=st["admitted"] / max(st["batches"], 1), failed=st["failed"],
+        return dict(rate_per_client=rate, measured_s=measured, warmup_s=warm, supersede=supersede,
+                    offered_req_per_s=sum(1 for r in reqs if r[0] >= warm) / measured,
+                    rendered_frames_per_s=rendered / measured, p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
+                    p50_ms_1080p_3M=pct(lat_hd, 50), p99_ms_1080p_3M=pct(lat_hd, 99),
+                    p99_ms_counting_superseded=pct(lat_all, 99),
+                    p99_ms_1080p_3M_counting_superseded=pct(lat_all_hd, 99),
+                    superseded=st["superseded"], deferred=st["deferred"], admitted=st["admitted"],
+                    batches=st["batches"], mean_batch=st["admitted"] / max(st["batches"], 1), failed=st["failed"],
                     jpeg_mean_bytes=float(np.mean(jb)) if jb else None,
                     jpeg_over_capacity=sum(1 for b in jb if b > (8 << 20)))
 
-    full = run(60.0, True)
-    sweep = [run(r, False) for r in rates]
+    full = run(60.0, True, seconds)
+    sweep = [run(r, False, sweep_seconds) for r in rates]
     # the same with the per-request payload: every frame also encoded as the
     # JPEG of its rung's quality (Table 1), done when the payload is
-    full_jpeg = run(60.0, True, jpeg=True)
-    at40_jpeg = run(40.0, False, jpeg=True)
+    full_jpeg = run(60.0, True, seconds, jpeg=True)
+    at40_jpeg = run(40.0, False, sweep_seconds, jpeg=True)
     ok = [x["rate_per_client"] for x in sweep if x["p99_ms_1080p_3M"] is not None and x["p99_ms_1080p_3M"] <= 10.0]
     for s_ in scenes:
         s_.free()
-    return dict(seconds=seconds, warmup_s=warm, clients=64, hbm_budget_gb=budget_gb, slots=2,
+    return dict(seconds=seconds, warmup_s=warm, clients=64, hbm_budget_gb=budget_gb, slots=slots,
                 max_batch_megapixels=batch_mpx,
                 full_load_latest_pose_wins=full, sweep_no_supersede=sweep,
                 with_jpeg={"full_load_latest_pose_wins": full_jpeg, "rate_40_no_supersede": at40_jpeg,
@@ -408,9 +490,13 @@ def roofline(v, n, storage):
         traffic = measured_traffic(name)
         if bound == "alu":
             ach = amount / sec / 1e12
+            # the survey's cost model: 15 VALU operations + 1 exp per evaluation
+            evals = w["evaluations"] / max(w["frames"], 1) / max(k["launches_per_frame"], 1e-9)
+            ach16 = OPS_EVAL_MODEL * evals / sec / 1e12
             return dict(kernel=name, bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                         frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=traffic, avg_us=k["avg_us"],
-                        per_launch=amount, dominant=ranked[0][0])
+                        per_launch=amount, dominant=ranked[0][0], evaluations_per_launch=evals,
+                        achieved_16_ops_per_evaluation=ach16, frac_16_ops_per_evaluation=ach16 / FP32_VECTOR_PEAK_TFLOPS)
         ach = amount / sec / 1e9
         return dict(kernel=name, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                     traffic=traffic, avg_us=k["avg_us"], per_launch=amount, dominant=ranked[0][0])
@@ -439,22 +525,62 @@ def hbm_copy(torch, mib=1024, reps=20):
     return dict(bytes_read=n * 4, bytes_written=n * 4, us=sec * 1e6, gbps=moved / sec / 1e9)
 
 
-def cpu_baseline(scene, pose, k, W, H, n_pix=100_000):
-    """The FP64 oracle, untuned, on a bounded sample of one frame."""
-    from oracle import oracle as orc
-    rng = np.random.default_rng(0)
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_frame_s(orc, scene, pose, k, W, H, n_pix, seed=0):
+    """Seconds of one full frame of the FP64 oracle, extrapolated from the
+    projection + depth order of every Gaussian and n_pix random pixels."""
+    rng = np.random.default_rng(seed)
     t0 = time.perf_counter()
     proj = orc.preprocess(scene, pose, k, W, H)
     _ = proj.order
     proj.boxes()
     t1 = time.perf_counter()
-    idx = rng.choice(W * H, n_pix, replace=False)
-    orc.render_pixels(proj, idx % W, idx // W)
+    if n_pix >= W * H:
+        yy, xx = np.mgrid[0:H, 0:W]
+        orc.render_pixels(proj, xx.reshape(-1), yy.reshape(-1))
+        n_pix = W * H
+    else:
+        idx = rng.choice(W * H, n_pix, replace=False)
+        orc.render_pixels(proj, idx % W, idx // W)
     t2 = time.perf_counter()
-    frame_s = (t1 - t0) + (t2 - t1) * (W * H / n_pix)
-    return dict(value=1.0 / frame_s, unit="frames/s", cores=orc.num_threads(), kind="oracle",
-                sample=f"pose 0: FP64 projection + depth order of all {scene.n} Gaussians ({t1 - t0:.2f} s) and "
-                       f"{n_pix} random pixels of the {W}x{H} frame ({t2 - t1:.2f} s), extrapolated to the full frame")
+    return (t1 - t0) + (t2 - t1) * (W * H / n_pix), t1 - t0, t2 - t1
+
+
+def cpu_baseline(scene, pose, k, W, H, c1=None, n_pix=100_000, n_pix_1t=8_000):
+    """The FP64 oracle, untuned, on bounded samples: the headline frame (pose
+    0 of the 3M-Gaussian 1080p trajectory) on all host threads and on one
+    thread, and the full 20k-Gaussian 256x256 frame on all threads."""
+    from oracle import oracle as orc
+    threads = orc.num_threads()
+    frame_s, proj_s, pix_s = _oracle_frame_s(orc, scene, pose, k, W, H, n_pix)
+    orc.set_threads(1)
+    try:
+        frame_1t, proj_1t, pix_1t = _oracle_frame_s(orc, scene, pose, k, W, H, n_pix_1t, seed=1)
+    finally:
+        orc.set_threads(threads)
+    res = dict(value=1.0 / frame_s, unit="frames/s", cores=threads, kind="oracle", cpu_model=cpu_model(),
+               sample=f"pose 0 of the {scene.n}-Gaussian {W}x{H} trajectory: FP64 projection + depth order of every "
+                      f"Gaussian ({proj_s:.2f} s) and {n_pix} random pixels ({pix_s:.2f} s) on {threads} threads, "
+                      f"extrapolated to the full frame",
+               seconds_per_frame=frame_s,
+               one_thread={"value": 1.0 / frame_1t, "unit": "frames/s", "seconds_per_frame": frame_1t,
+                           "sample": f"the same frame on 1 thread: projection {proj_1t:.2f} s, {n_pix_1t} random "
+                                     f"pixels {pix_1t:.2f} s, extrapolated"})
+    if c1 is not None:
+        sc1, p1, k1, W1, H1 = c1
+        f1, _, _ = _oracle_frame_s(orc, sc1, p1, k1, W1, H1, W1 * H1)
+        res["c1_full_frame"] = {"seconds_per_frame": f1, "frames_per_s": 1.0 / f1, "threads": threads,
+                                "sample": f"every pixel of the {sc1.n}-Gaussian {W1}x{H1} frame"}
+    return res
 
 
 def run_registry(ctx, tigas, synth):
@@ -510,11 +636,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the 20k/256x256 and 1M/1280x720 renderer runs")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-jpeg", action="store_true")
     ap.add_argument("--no-abr", action="store_true")
     ap.add_argument("--no-registry", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured seconds of each full-load serving run (after 1 s of warm-up)")
     ap.add_argument("--tile", default=None,
                     help="W,H,batch_depth,pixels_per_lane for the single-view variants (default: autotuned)")
     args = ap.parse_args()
@@ -561,7 +689,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3M Gaussians (64 clusters + 40% surface splats, SH deg 3), 1920x1080, "
                                "300-pose 6DoF trajectory, FP32 attributes, RGB8 frame in HBM",
-                   "n_gaussians": scene.n, "width": W, "height": H, "poses": len(traj),
+                   "n_gaussians": scene.n, "width": W, "height": H, "trajectory_poses": len(traj),
+                   **timed_poses(args.steps, len(traj)),
                    "tile": main_v["tile"], "batch_depth": main_v["batch_depth"],
                    "pixels_per_lane": main_v["pixels_per_lane"]},
         "p50_ms": main_v["p50_ms"],
@@ -576,10 +705,22 @@ def main():
                                               "scene_bytes", "tile", "batch_depth", "pixels_per_lane", "pipelined")}
                      for kk, vv in variants.items()},
         "roofline": {x: rl[x] for x in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "roofline_kernel": {x: rl[x] for x in ("kernel", "avg_us", "per_launch", "dominant")},
+        "roofline_kernel": {x: rl[x] for x in ("kernel", "avg_us", "per_launch", "dominant", "evaluations_per_launch",
+                                               "achieved_16_ops_per_evaluation", "frac_16_ops_per_evaluation")
+                            if x in rl},
         "hbm_copy": copy,
         "kernels": main_v["kernels"],
     }
+    if not args.no_plain:
+        # the plain FP32 renderer on the two smaller workloads, same steps
+        c1s, c1p, c1k, c1w, c1h = synth.c1_single_view()
+        line["plain_20k_256"] = run_plain(ctx, c1s, c1p, c1k, c1w, c1h, args.steps, args.warmup, torch)
+        line["plain_1M_720p"] = run_plain(ctx, synth.c2_scene(), synth.c2_trajectory(300),
+                                          synth.fov_intrinsics(1280, 720), 1280, 720, args.steps, args.warmup, torch)
+        for key in ("plain_20k_256", "plain_1M_720p"):
+            p = line[key]
+            print(f"# {key}: {p['frames_per_s']:.0f} frames/s, p50 {p['p50_ms']:.3f} ms, p99 {p['p99_ms']:.3f} ms",
+                  file=sys.stderr, flush=True)
     if not args.no_batched:
         line["batched"] = run_batched(ctx, scene, torch)
         print(f"# batched: {line['batched']['views_per_s']:.0f} views/s "
@@ -613,7 +754,8 @@ def main():
               f"{g['parse_ms']:.0f} ms), resident acquire {g['resident_acquire_us']:.1f} us", file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(scene, traj[0], k, W, H)
+        c1s, c1p, c1k, c1w, c1h = synth.c1_single_view()
+        line["cpu_baseline"] = cpu_baseline(scene, traj[0], k, W, H, c1=(c1s, c1p[0], c1k, c1w, c1h))
     print(json.dumps(line), flush=True)
 
 

@@ -425,6 +425,15 @@ void orc_pack_rgb8(int64_t n, const float* in, uint8_t* out) {
     }
 }
 
+/* Number of OpenMP threads the pixel loops use from now on (n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -66,6 +66,8 @@ def lib():
         L.orc_render_pixels.restype = None
         L.orc_pack_rgb8.argtypes = [I64, P, P]
         L.orc_pack_rgb8.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -78,6 +80,11 @@ def _p(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def rung(intr, width: int, height: int, scale: float = 1.0):

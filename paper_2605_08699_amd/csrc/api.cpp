@@ -269,6 +269,32 @@ struct TimerScope {
     ~TimerScope() { g_kernel_timer = prev; }
 };
 
+// Device memory of one launch sequence as plain pointers (a workspace's
+// buffers, or any other memory laid out the same way).
+struct FrameMem {
+    hipStream_t stream = nullptr;
+    ViewParams* views = nullptr;      // device view parameters of the plan
+    const void* views_src = nullptr;  // pinned host copy read by a copy (graphs re-read it on replay);
+                                      // null: a single view uploaded as a kernel argument
+    PreOut pre{};
+    Counters* cnt = nullptr;
+    Counters* cnt_out = nullptr;  // receives the final counters (pinned host memory or device memory)
+    uint32_t* key[2] = {nullptr, nullptr};
+    uint32_t* val[2] = {nullptr, nullptr};
+    uint32_t* ext[2] = {nullptr, nullptr};
+    uint32_t* hist = nullptr;
+    uint32_t* queue = nullptr;
+    uint2* ranges = nullptr;
+    uint32_t* blk_off = nullptr;
+    uint32_t* blk_sum2 = nullptr;
+    uint32_t* blk_off2 = nullptr;
+    uint32_t dup_cap = 0;
+    hipEvent_t* ev = nullptr;  // 7 stage-boundary events (stage timing only)
+    uint32_t* dbg_key = nullptr;
+    uint32_t* dbg_val = nullptr;
+    uint32_t* dbg_ext = nullptr;
+};
+
 struct Workspace {
     hipStream_t stream = nullptr;
     std::mutex mu;  // one launch sequence at a time per workspace
@@ -303,6 +329,32 @@ struct Workspace {
     uint64_t gen = 1;  // bumped whenever a buffer is reallocated (captured graphs hold its pointers)
     std::map<std::string, GraphEntry> graphs;
 
+    FrameMem mem() {
+        FrameMem m;
+        m.stream = stream;
+        m.views = fs().views.as<ViewParams>();
+        m.views_src = fs().host_views.p;
+        m.pre = pre();
+        m.cnt = counters.as<Counters>();
+        m.cnt_out = fs().host_counters.as<Counters>();
+        for (int i = 0; i < 2; ++i) {
+            m.key[i] = key[i].as<uint32_t>();
+            m.val[i] = val[i].as<uint32_t>();
+            m.ext[i] = ext[i].as<uint32_t>();
+        }
+        m.hist = hist.as<uint32_t>();
+        m.queue = queue.as<uint32_t>();
+        m.ranges = ranges.as<uint2>();
+        m.blk_off = blk_off.as<uint32_t>();
+        m.blk_sum2 = blk_sum2.as<uint32_t>();
+        m.blk_off2 = blk_off2.as<uint32_t>();
+        m.dup_cap = dup_cap;
+        m.ev = ev[0] ? ev : nullptr;
+        m.dbg_key = dbg_key.as<uint32_t>();
+        m.dbg_val = dbg_val.as<uint32_t>();
+        m.dbg_ext = dbg_ext.as<uint32_t>();
+        return m;
+    }
     PreOut pre() const {
         PreOut o;
         o.rec = recs.as<Rec>();
@@ -646,16 +698,21 @@ struct LaunchOptions {
     bool cull = true;  // blend: per-block threshold culling of list entries
 };
 
-int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks,
+int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks,
             const LaunchOptions& opt) {
-    hipStream_t st = ws.stream;
+    hipStream_t st = m.stream;
     auto mark = [&](int i) {
-        if (prof) HIPCHK(hipEventRecord(ws.ev[i], st));
+        if (prof) HIPCHK(hipEventRecord(m.ev[i], st));
     };
     const int nv = (int)plan.views.size();
-    HIPCHK(hipMemcpyAsync(ws.fs().views.p, ws.fs().host_views.p, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
-    const PreOut o = ws.pre();
-    const ViewParams* vdev = ws.fs().views.as<ViewParams>();
+    if (m.views_src) {
+        HIPCHK(hipMemcpyAsync(m.views, m.views_src, sizeof(ViewParams) * nv, hipMemcpyHostToDevice, st));
+    } else {
+        if (nv != 1) fail(TIGAS_E_INVALID, "kernel-argument view upload takes one view");
+        launch_store_view(plan.views[0], m.views, st);
+    }
+    const PreOut& o = m.pre;
+    const ViewParams* vdev = m.views;
     mark(0);
     for (const Group& g : plan.groups) {
         if (g.n_pad == 0) continue;
@@ -664,50 +721,49 @@ int enqueue(Workspace& ws, const Plan& plan, bool debug, bool prof, unsigned lon
     }
     mark(1);
     const int nblk = (int)(plan.nrec / K1_THREADS);
-    Counters* cnt = ws.counters.as<Counters>();
+    Counters* cnt = m.cnt;
     ZeroList zl{};
-    zl.p[0] = ws.queue.as<uint32_t>();
+    zl.p[0] = m.queue;
     zl.n[0] = 8;
-    zl.p[1] = ws.ranges.as<uint32_t>();
+    zl.p[1] = reinterpret_cast<uint32_t*>(m.ranges);
     zl.n[1] = 2 * plan.n_tiles;
-    launch_scan_visible(o, nblk, ws.blk_off.as<uint32_t>(), cnt, ws.dup_cap, zl, st);
+    launch_scan_visible(o, nblk, m.blk_off, cnt, m.dup_cap, zl, st);
     mark(2);
     SortBuffers sb;
     for (int i = 0; i < 2; ++i) {
-        sb.key[i] = ws.key[i].as<uint32_t>();
-        sb.val[i] = ws.val[i].as<uint32_t>();
-        sb.ext[i] = ws.ext[i].as<uint32_t>();
+        sb.key[i] = m.key[i];
+        sb.val[i] = m.val[i];
+        sb.ext[i] = m.ext[i];
     }
-    sb.hist = ws.hist.as<uint32_t>();
+    sb.hist = m.hist;
     // depth digits, on the visible Gaussians (record order in, depth order
     // out); the tile rectangles travel packed with them when every view has
     // at most 256 x 256 tiles, else the last pass gathers them
     bool packed = true;
     for (const ViewParams& v : plan.views) packed = packed && v.tiles_x <= 256 && v.tiles_y <= 256;
-    launch_compact(o, nblk, ws.blk_off.as<uint32_t>(), sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, st);
-    const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, ws.dup_cap, sort_blocks(plan.nrec), 0, packed, cnt,
+    launch_compact(o, nblk, m.blk_off, sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, st);
+    const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, m.dup_cap, sort_blocks(plan.nrec), 0, packed, cnt,
                                packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
     // duplicates in depth order
     const int cd = cv ^ 1;
-    launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, ws.blk_sum2.as<uint32_t>(), ws.blk_off2.as<uint32_t>(), cnt,
-                     ws.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
+    launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, m.blk_sum2, m.blk_off2, cnt,
+                     m.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
     mark(3);
     if (debug) {
-        const size_t bytes = (size_t)ws.dup_cap * 4;
-        HIPCHK(hipMemcpyAsync(ws.dbg_key.p, sb.key[cd], bytes, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(ws.dbg_val.p, sb.val[cd], bytes, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(ws.dbg_ext.p, sb.ext[cd], bytes, hipMemcpyDeviceToDevice, st));
+        const size_t bytes = (size_t)m.dup_cap * 4;
+        HIPCHK(hipMemcpyAsync(m.dbg_key, sb.key[cd], bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(m.dbg_val, sb.val[cd], bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(m.dbg_ext, sb.ext[cd], bytes, hipMemcpyDeviceToDevice, st));
     }
     // tile digits, on the duplicates
     const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
-    const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, ws.dup_cap, sort_blocks(ws.dup_cap), cd,
+    const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, m.dup_cap, sort_blocks(m.dup_cap), cd,
                                 debug, cnt, nullptr, nullptr, st);
     mark(4);
-    launch_ranges(sb.key[cur], cnt, ws.dup_cap, ws.ranges.as<uint2>(), ws.fs().host_counters.as<Counters>(), o, vdev,
-                  st);
+    launch_ranges(sb.key[cur], cnt, m.dup_cap, m.ranges, m.cnt_out, o, vdev, st);
     mark(5);
-    launch_blend(vdev, nv, plan.n_tiles, ws.ranges.as<uint2>(), sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th,
-                 plan.tc.bd, plan.tc.ppl, work, plan.persistent ? ws.queue.as<uint32_t>() : nullptr, pblocks, opt.cull, st);
+    launch_blend(vdev, nv, plan.n_tiles, m.ranges, sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th, plan.tc.bd,
+                 plan.tc.ppl, work, plan.persistent ? m.queue : nullptr, pblocks, opt.cull, st);
     mark(6);
     HIPCHK(hipGetLastError());
     return cur;
@@ -730,9 +786,9 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     if (kprof) {
         ws.ktimer.reset();
         TimerScope ts(&ws.ktimer);
-        return enqueue(ws, plan, debug, prof, work, pblocks, opt);
+        return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
     }
-    if (!graph) return enqueue(ws, plan, debug, prof, work, pblocks, opt);
+    if (!graph) return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
     const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") +
                             (ws.active ? "f1" : "f0");
     GraphEntry& g = ws.graphs[key];
@@ -747,7 +803,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         HIPCHK(hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal));
         int cur = 0;
         try {
-            cur = enqueue(ws, plan, debug, prof, work, pblocks, opt);
+            cur = enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
         } catch (...) {
             (void)hipStreamEndCapture(ws.stream, &graph_t);
             if (graph_t) (void)hipGraphDestroy(graph_t);

@@ -1453,6 +1453,21 @@ __global__ __launch_bounds__(TW* TH / PPL) void k_blend_persistent(BlendArgs A, 
     }
 }
 
+// One view's parameters, passed by value as a kernel argument, stored to
+// device memory (the allocation-free entry point has no pinned host copy).
+__global__ void k_store_view(ViewParams v, ViewParams* __restrict__ dst) {
+    constexpr int W = (int)(sizeof(ViewParams) / 4);
+    static_assert(sizeof(ViewParams) % 4 == 0, "view parameters are whole words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) reinterpret_cast<uint32_t*>(dst)[i] = src[i];
+}
+
+// Fill of n words (clears the counter block the allocation-free entry point
+// keeps in its fixed scratch array).
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t value) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = value;
+}
+
 __global__ void k_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     const uint32_t x = i < n ? in[i] : 0u;
@@ -1492,6 +1507,15 @@ void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const Vi
     else preprocess_deg<2>(deg, grid, s, views_dev, nviews, rec_base, n_pad, view_base, o, st);
 }
 
+
+void launch_store_view(const ViewParams& v, ViewParams* dst, hipStream_t st) {
+    TIGAS_LAUNCH(k_store_view, dim3(1), dim3(64), st, v, dst);
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t value, hipStream_t st) {
+    if (n == 0) return;
+    TIGAS_LAUNCH(k_fill_u32, dim3(std::min<uint32_t>(1024u, (n + 255) / 256)), dim3(256), st, p, n, value);
+}
 
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st) {

@@ -114,6 +114,10 @@ struct SortPass {
 // ---- launchers (kernels.hip) ----
 void launch_preprocess(const SceneView& s, const ViewParams* views_dev, const ViewParams* views_host, int nviews,
                        uint32_t rec_base, uint32_t n_pad, uint32_t view_base, const PreOut& o, hipStream_t st);
+// One view's parameters stored to device memory by a kernel (argument by value).
+void launch_store_view(const ViewParams& v, ViewParams* dst, hipStream_t st);
+// p[0 .. n) = value, by a kernel (no memset node in captured sequences).
+void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t value, hipStream_t st);
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st);
 // Visible records as (depth key, record) pairs; with ext, also each one's

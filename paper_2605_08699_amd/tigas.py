@@ -147,7 +147,8 @@ def lib():
         L.tigas_count_blend_work.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                              ctypes.POINTER(QualityC), ctypes.POINTER(FrameC),
                                              ctypes.POINTER(I64), ctypes.POINTER(I64)]
-        for name in ("tigas_context_create", "tigas_scene_load", "tigas_render", "tigas_render_debug",
+        for name in ("tigas_context_create", "tigas_scene_load", "tigas_render",
+                     "tigas_render_debug",
                      "tigas_render_batch", "tigas_last_stats", "tigas_selftest_wave_scan", "tigas_profile_stages",
                      "tigas_stage_times", "tigas_count_blend_work", "tigas_set_graphs",
                      "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit",
