@@ -207,6 +207,13 @@ tigas_status tigas_profile_stages(tigas_context* ctx, int enable);
  * replayed (default on; environment TIGAS_GRAPHS=0 turns it off at context
  * creation).  This switches it for the context. */
 tigas_status tigas_set_graphs(tigas_context* ctx, int enable);
+/* Single-view renders place the tile digit of the (tile | depth) keys by
+ * counting (per-block tile histograms of the depth-ordered Gaussians, then
+ * each entry written straight to its sorted position) when the view's tile
+ * grid has at most 8192 tiles; otherwise, and when this is switched off
+ * (environment TIGAS_TILE_BIN=0 at context creation), by radix passes over the
+ * emitted duplicates.  The sorted lists are identical either way. */
+tigas_status tigas_set_tile_binning(tigas_context* ctx, int enable);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 
 /* Kernel timing with HIP events recorded on the rendering stream around every

@@ -282,9 +282,12 @@ struct FrameMem {
     uint32_t* key[2] = {nullptr, nullptr};
     uint32_t* val[2] = {nullptr, nullptr};
     uint32_t* ext[2] = {nullptr, nullptr};
-    uint32_t* hist = nullptr;
+    uint32_t* hist = nullptr;      // digit counts per sort segment
+    uint32_t* hist_pre = nullptr;  // segment digit prefixes
     uint32_t* queue = nullptr;
     uint2* ranges = nullptr;
+    uint32_t* bin_hist = nullptr;  // binned tile digit: block histograms, group starts
+    uint32_t* bin_gsum = nullptr;
     uint32_t* blk_off = nullptr;
     uint32_t* blk_sum2 = nullptr;
     uint32_t* blk_off2 = nullptr;
@@ -311,6 +314,7 @@ struct Workspace {
     DevBuf dbg_key, dbg_val, dbg_ext;
     // per tile / per view
     DevBuf ranges;
+    DevBuf bin_hist, bin_gsum;
     DevBuf frame_staging;
     static constexpr int NSLOT = 2;
     FrameSlot slot[NSLOT];
@@ -343,8 +347,11 @@ struct Workspace {
             m.ext[i] = ext[i].as<uint32_t>();
         }
         m.hist = hist.as<uint32_t>();
+        m.hist_pre = m.hist + (size_t)256 * SORT_MAX_BLOCKS;
         m.queue = queue.as<uint32_t>();
         m.ranges = ranges.as<uint2>();
+        m.bin_hist = bin_hist.as<uint32_t>();
+        m.bin_gsum = bin_gsum.as<uint32_t>();
         m.blk_off = blk_off.as<uint32_t>();
         m.blk_sum2 = blk_sum2.as<uint32_t>();
         m.blk_off2 = blk_off2.as<uint32_t>();
@@ -452,6 +459,7 @@ struct tigas_context {
     std::map<std::string, std::pair<int64_t, double>> kernel_ms;  // name -> (launches, total ms)
     std::atomic<bool> use_graphs{true};
     std::atomic<bool> blend_cull{true};     // blend: per-block threshold culling
+    std::atomic<bool> tile_bin{true};       // single view: tile digit placed by counting
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
     std::mutex tune_mu;
@@ -666,6 +674,15 @@ std::string shape_key(const Plan& plan, bool with_tiles) {
     return k;
 }
 
+// Buffers of the binned tile digit for a single-view plan (they depend on the
+// duplicate capacity too: call again after it grows).
+void ensure_bin(Workspace& ws, const Plan& plan) {
+    if (plan.views.size() != 1 || !bin_fits(plan.views[0].tiles_x, plan.views[0].tiles_y)) return;
+    const size_t nbc = std::max<size_t>(1, (plan.nrec + BIN_BLOCK - 1) / BIN_BLOCK);
+    ws.grow(ws.bin_hist, nbc * plan.n_tiles * 4);
+    ws.grow(ws.bin_gsum, ((size_t)(BIN_GROUPS + 2) * plan.n_tiles + bin_emit_groups(ws.dup_cap, plan.nrec)) * 4);
+}
+
 void prepare(Workspace& ws, const Plan& plan, bool debug) {
     if (ws.counters.ensure(sizeof(Counters))) {
         // the FP64-list count is cleared by each frame after use; start at zero
@@ -680,6 +697,7 @@ void prepare(Workspace& ws, const Plan& plan, bool debug) {
     uint64_t est = std::max<uint64_t>((uint64_t)ws.last_D + ws.last_D / 4, (uint64_t)plan.nrec * 4);
     est = std::max<uint64_t>(est, 1u << 20);
     ws.ensure_dups((uint32_t)std::min<uint64_t>(est, 0xfff00000ull));
+    ensure_bin(ws, plan);
     if (debug) {
         const size_t bytes = (size_t)ws.dup_cap * 4;
         ws.dbg_key.ensure(bytes);
@@ -696,7 +714,14 @@ void prepare(Workspace& ws, const Plan& plan, bool debug) {
 // Per-context switches that change the launch sequence (not its results).
 struct LaunchOptions {
     bool cull = true;  // blend: per-block threshold culling of list entries
+    bool bin = true;   // single view: tile digit placed by counting (else radix passes over the duplicates)
 };
+
+// Whether the plan's tile digit is placed by counting.
+bool use_bin(const Plan& plan, const LaunchOptions& opt) {
+    return opt.bin && plan.views.size() == 1 && plan.views[0].tiles_x <= 256 && plan.views[0].tiles_y <= 256 &&
+           bin_fits(plan.views[0].tiles_x, plan.views[0].tiles_y);
+}
 
 int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned long long* work, int pblocks,
             const LaunchOptions& opt) {
@@ -736,6 +761,7 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
         sb.ext[i] = m.ext[i];
     }
     sb.hist = m.hist;
+    sb.pre = m.hist_pre;
     // depth digits, on the visible Gaussians (record order in, depth order
     // out); the tile rectangles travel packed with them when every view has
     // at most 256 x 256 tiles, else the last pass gathers them
@@ -744,10 +770,13 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
     launch_compact(o, nblk, m.blk_off, sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, st);
     const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, m.dup_cap, sort_blocks(plan.nrec), 0, packed, cnt,
                                packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
-    // duplicates in depth order
     const int cd = cv ^ 1;
-    launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, m.blk_sum2, m.blk_off2, cnt,
-                     m.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
+    const bool bin = use_bin(plan, opt);
+    if (!bin || debug) {
+        // duplicates in depth order (kept for inspection only when binning)
+        launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, m.blk_sum2, m.blk_off2, cnt,
+                         m.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
+    }
     mark(3);
     if (debug) {
         const size_t bytes = (size_t)m.dup_cap * 4;
@@ -755,18 +784,35 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
         HIPCHK(hipMemcpyAsync(m.dbg_val, sb.val[cd], bytes, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(m.dbg_ext, sb.ext[cd], bytes, hipMemcpyDeviceToDevice, st));
     }
-    // tile digits, on the duplicates
-    const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
-    const int cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, m.dup_cap, sort_blocks(m.dup_cap), cd,
-                                debug, cnt, nullptr, nullptr, st);
-    mark(4);
-    launch_ranges(sb.key[cur], cnt, m.dup_cap, m.ranges, m.cnt_out, o, vdev, st);
-    mark(5);
+    int cur = cd;
+    if (bin) {
+        // tile digit by counting, straight from the depth-ordered Gaussians
+        const ViewParams& v = plan.views[0];
+        launch_bin(sb.val[cv], sb.ext[cv], cnt, plan.nrec, m.dup_cap, v.tiles_x, v.tiles_y, m.bin_hist, m.bin_gsum,
+                   m.blk_sum2, m.blk_off2, m.ranges, m.cnt_out, o, vdev, sb.val[cd], debug ? sb.key[cd] : nullptr,
+                   debug ? sb.ext[cd] : nullptr, st);
+        mark(4);
+        mark(5);
+    } else {
+        // tile digits, on the duplicates
+        const std::vector<SortPass> tp = tile_passes(plan.n_tiles);
+        cur = launch_sort(sb, tp.data(), (int)tp.size(), /*which=*/0, m.dup_cap, sort_blocks(m.dup_cap), cd, debug,
+                          cnt, nullptr, nullptr, st);
+        mark(4);
+        launch_ranges(sb.key[cur], cnt, m.dup_cap, m.ranges, m.cnt_out, o, vdev, st);
+        mark(5);
+    }
     launch_blend(vdev, nv, plan.n_tiles, m.ranges, sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th, plan.tc.bd,
                  plan.tc.ppl, work, plan.persistent ? m.queue : nullptr, pblocks, opt.cull, st);
     mark(6);
     HIPCHK(hipGetLastError());
     return cur;
+}
+
+bool plan_binned(tigas_context* ctx, const Plan& plan) {
+    LaunchOptions opt;
+    opt.bin = ctx->tile_bin.load();
+    return use_bin(plan, opt);
 }
 
 // Launch the plan once: from a captured graph when allowed (captured on the
@@ -781,6 +827,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     // stage timing needs events between the launches: that runs uncaptured
     LaunchOptions opt;
     opt.cull = ctx->blend_cull.load();
+    opt.bin = ctx->tile_bin.load();
     const bool kprof = ctx->profile_kernels.load();
     const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof && !kprof;
     if (kprof) {
@@ -789,7 +836,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
     }
     if (!graph) return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
-    const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") +
+    const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") + (opt.bin ? "b1" : "b0") +
                             (ws.active ? "f1" : "f0");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
@@ -847,6 +894,7 @@ Counters settle_frame(tigas_context* ctx, Workspace& ws, const Plan& plan, bool 
         const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
         if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
         ws.ensure_dups((uint32_t)want);
+        ensure_bin(ws, plan);
         if (debug) prepare(ws, plan, debug);
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
         cur = launch_plan(ctx, ws, plan, debug, prof, work);
@@ -859,13 +907,13 @@ Counters settle_frame(tigas_context* ctx, Workspace& ws, const Plan& plan, bool 
     return c;
 }
 
-tigas_stats frame_stats(const Plan& plan, const Counters& c, int rerenders) {
+tigas_stats frame_stats(const Plan& plan, const Counters& c, int rerenders, bool binned) {
     tigas_stats st{};
     st.visible = c.visible;
     st.duplicates = c.D;
     st.fallbacks = c.fallbacks;
     st.tiles = plan.n_tiles;
-    st.sort_passes = 4 + (int64_t)tile_passes(plan.n_tiles).size();
+    st.sort_passes = 4 + (binned ? 1 : (int64_t)tile_passes(plan.n_tiles).size());
     st.rerenders = rerenders;
     st.tile_w = plan.tc.tw;
     st.tile_h = plan.tc.th;
@@ -930,7 +978,7 @@ void finish_async(tigas_context* ctx, Workspace& ws, int si) {
         ws.active = si;
         int cur = f.cur, rerenders = 0;
         const Counters c = settle_frame(ctx, ws, f.plan, false, false, nullptr, cur, rerenders);
-        d.stats = frame_stats(f.plan, c, rerenders);
+        d.stats = frame_stats(f.plan, c, rerenders, plan_binned(ctx, f.plan));
         record_stats(ctx, ws, d.stats, false);
     } catch (const Error& e) {
         d.status = e.st;
@@ -963,7 +1011,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
     wait_stream(ws.stream);
     int rerenders = 0;
     const Counters c = settle_frame(ctx, ws, plan, debug, prof, work, cur, rerenders);
-    record_stats(ctx, ws, frame_stats(plan, c, rerenders), prof);
+    record_stats(ctx, ws, frame_stats(plan, c, rerenders, plan_binned(ctx, plan)), prof);
     return cur;
 }
 
@@ -1822,6 +1870,7 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         if (const char* f = std::getenv("TIGAS_TUNE_CACHE")) c->tune_file = f;
         if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_BLEND_CULL")) c->blend_cull.store(std::atoi(g) != 0);
+        if (const char* g = std::getenv("TIGAS_TILE_BIN")) c->tile_bin.store(std::atoi(g) != 0);
         load_tune_file(c.get());
         *out = c.release();
     });
@@ -2060,6 +2109,14 @@ tigas_status tigas_set_graphs(tigas_context* ctx, int enable) {
         ctx->use_graphs.store(enable != 0);
     });
 }
+
+tigas_status tigas_set_tile_binning(tigas_context* ctx, int enable) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        ctx->tile_bin.store(enable != 0);
+    });
+}
+
 
 tigas_status tigas_count_blend_work(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
                                     int width, int height, const tigas_quality* q, tigas_frame* out,

@@ -17,6 +17,10 @@
 //   k_duplicate    one (tile | depth) key per (Gaussian, overlapped tile)
 //   k_ranges       [start, end) of every tile in the sorted list, and the
 //                  FP64 conics of the near-singular Gaussians
+//   k_bin_*        single views: the tile digit placed by counting instead
+//                  (per-block tile histograms from 2D difference grids, their
+//                  prefixes, then every (Gaussian, tile) entry written straight
+//                  to its sorted position; the ranges are the tile starts)
 //   k_blend        front-to-back compositing, one wave64 per 8x8 pixel block,
 //                  Gaussians staged per wave in LDS, per-wave early exit
 //
@@ -862,9 +866,27 @@ __device__ __forceinline__ uint32_t sort_count(const Counters* cnt, int which, u
     if (which == 1) return min(cnt->visible, cap);
     return cnt->overflow ? 0u : min(cnt->D, cap);
 }
+// Segment of workgroup `wg` of a pass: consecutive workgroup ids go
+// round-robin to the 8 XCDs, so XCD x is given a contiguous run of segments
+// (the runs of one digit written by neighbouring segments then meet in one
+// L2 and leave it as whole cache lines).
+__device__ __forceinline__ int xcd_segment(int wg, int nb) {
+    const int per = nb >> 3, rem = nb & 7, x = wg & 7;
+    return x * per + min(x, rem) + (wg >> 3);
+}
+__device__ __forceinline__ uint64_t segment_len(uint32_t D, int nb) {
+    const uint64_t per = ((uint64_t)D + nb - 1) / nb;
+    return (per + SORT_CHUNK - 1) / SORT_CHUNK * SORT_CHUNK;
+}
+// The segment of workgroup wg: the segments that hold keys are spread over
+// the XCDs in contiguous runs, the empty ones keep their own index.
+__device__ __forceinline__ int pass_segment(uint32_t D, int nb, int wg) {
+    const uint64_t per = segment_len(D, nb);
+    const int nact = per ? (int)min((uint64_t)nb, ((uint64_t)D + per - 1) / per) : 0;
+    return wg < nact ? xcd_segment(wg, nact) : wg;
+}
 __device__ __forceinline__ void segment(uint32_t D, int nb, int b, uint32_t* beg, uint32_t* end) {
-    uint64_t per = ((uint64_t)D + nb - 1) / nb;
-    per = (per + SORT_CHUNK - 1) / SORT_CHUNK * SORT_CHUNK;
+    const uint64_t per = segment_len(D, nb);
     const uint64_t s = min((uint64_t)D, per * (uint64_t)b);
     *beg = (uint32_t)s;
     *end = (uint32_t)min((uint64_t)D, s + per);
@@ -891,7 +913,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     for (int i = threadIdx.x; i < NH * ROW; i += SORT_THREADS) h[i] = 0u;
     __syncthreads();
     uint32_t beg, end;
-    segment(sort_count(cnt, which, cap), nb, blockIdx.x, &beg, &end);
+    const uint32_t D = sort_count(cnt, which, cap);
+    const int seg = pass_segment(D, nb, (int)blockIdx.x);
+    segment(D, nb, seg, &beg, &end);
     const uint32_t mask = (1u << bits) - 1u;
     uint32_t* hrow = h + (w * 4 + (lane & 3)) * ROW;
     // each wave walks blocks of 8 rows of 64 keys (8 loads in flight per lane)
@@ -916,8 +940,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     uint32_t tot;
     const uint32_t e = block_excl_scan<SORT_THREADS>(s, red, &tot);
     if (t <= (int)mask) {
-        hist[(size_t)t * nb + blockIdx.x] = s;
-        pre[(size_t)t * nb + blockIdx.x] = e;
+        hist[(size_t)t * nb + seg] = s;
+        pre[(size_t)t * nb + seg] = e;
     }
 }
 
@@ -991,8 +1015,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t beg, end;
     const uint32_t D = sort_count(cnt, which, cap);
-    segment(D, nb, blockIdx.x, &beg, &end);
-    base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + blockIdx.x] : 0u;
+    const int seg = pass_segment(D, nb, (int)blockIdx.x);
+    segment(D, nb, seg, &beg, &end);
+    base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + seg] : 0u;
     for (uint32_t chunk = beg; chunk < end; chunk += SORT_CHUNK) {
 #pragma unroll
         for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
@@ -1114,6 +1139,541 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ til
     const uint32_t nfb = min(cnt->fb_listed, fb_cap);
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nfb; i += gridDim.x * 256)
         conic_fp64(fb_list[i], views, blk_view, recs);
+}
+
+// ---------------------------------------------------- binned tile digit
+// The most significant digit of the (tile | depth) key, the tile id, placed
+// by counting instead of by radix passes over the duplicates: the Gaussians
+// arrive in depth order, and entry (g, t) belongs at
+//   start(t) + #{Gaussians before g, in depth order, whose rectangle holds t}.
+// The count over whole blocks of BIN_BLOCK Gaussians comes from per-block
+// tile histograms (a 2D difference array over the tile grid: +1/-1 at the
+// four corners of each rectangle, then 2D prefix sums) and their prefixes
+// over blocks.  Entries are emitted in their depth-first order, BIN_PAIRS per
+// workgroup (so a few large near Gaussians do not load one workgroup): a
+// workgroup recounts the Gaussians of its block before its first round,
+// and inside a round of 256 Gaussians the waves' column and row ballots give,
+// per tile, the lanes whose rectangles hold it.  Each entry is written
+// straight to its sorted position; the tile ranges fall out of the tile
+// starts.  Single view, tile grid of at most BIN_GRID_MAX cells.
+
+// Inclusive 2D prefix sums of an h1 x w1 grid (row-major, w1 <= 256) held in
+// LDS, by a workgroup of 256 threads: rows (one wave per row, DPP scans), then
+// columns (one thread per column, eight rows in flight).
+__device__ void grid_prefix2d(uint32_t* g, int w1, int h1) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int y = w; y < h1; y += 4) {
+        uint32_t carry = 0;
+        for (int c0 = 0; c0 < w1; c0 += 64) {
+            const int x = c0 + lane;
+            const uint32_t v = x < w1 ? g[y * w1 + x] : 0u;
+            const uint32_t sc = wave_incl_scan(v) + carry;
+            if (x < w1) g[y * w1 + x] = sc;
+            carry = readlane(sc, 63);
+        }
+    }
+    __syncthreads();
+    const int x = threadIdx.x;
+    if (x < w1) {
+        uint32_t run = 0;
+        int y = 0;
+        for (; y + 8 <= h1; y += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = g[(y + k) * w1 + x];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                run += v[k];
+                g[(y + k) * w1 + x] = run;
+            }
+        }
+        for (; y < h1; ++y) {
+            run += g[y * w1 + x];
+            g[y * w1 + x] = run;
+        }
+    }
+    __syncthreads();
+}
+
+// Adds one packed tile rectangle to the 2D difference grid g (stride w1).
+// Corners in the extra column x = tiles_x or row y = tiles_y are left out:
+// they only affect cells outside the tile grid, which nothing reads (and
+// rectangles clamped to the frame's right or bottom edge would all meet
+// there).
+__device__ __forceinline__ void grid_add_rect(uint32_t* g, int w1, int tiles_x, int tiles_y, uint32_t p) {
+    const int x0 = (int)(p & 0xffu), y0 = (int)((p >> 8) & 0xffu), x1 = (int)((p >> 16) & 0xffu) + 1,
+              y1 = (int)(p >> 24) + 1;
+    atomicAdd(&g[y0 * w1 + x0], 1u);
+    if (x1 < tiles_x) atomicAdd(&g[y0 * w1 + x1], 0xffffffffu);
+    if (y1 < tiles_y) {
+        atomicAdd(&g[y1 * w1 + x0], 0xffffffffu);
+        if (x1 < tiles_x) atomicAdd(&g[y1 * w1 + x1], 1u);
+    }
+}
+
+// The rectangles of depth-ordered Gaussians [i0, i1) into the grid.
+__device__ __forceinline__ void grid_add_rects(uint32_t* g, int w1, int tiles_x, int tiles_y,
+                                               const uint32_t* __restrict__ packed, uint32_t i0, uint32_t i1) {
+    constexpr int U = 8;  // loads in flight per thread
+    for (uint32_t b = i0; b < i1; b += 256 * U) {
+        uint32_t pk[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint32_t i = b + (uint32_t)(k * 256) + threadIdx.x;
+            pk[k] = i < i1 ? packed[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (b + (uint32_t)(k * 256) + threadIdx.x < i1) grid_add_rect(g, w1, tiles_x, tiles_y, pk[k]);
+    }
+}
+
+__device__ __forceinline__ uint32_t bin_valid(const Counters* cnt) { return cnt->overflow ? 0u : cnt->visible; }
+
+__device__ __forceinline__ uint32_t rect_count(uint32_t p) {
+    return (((p >> 16) & 0xffu) - (p & 0xffu) + 1u) * ((p >> 24) - ((p >> 8) & 0xffu) + 1u);
+}
+
+// tile id -> (tx, ty) with the FP32 reciprocal of tiles_x, corrected to the
+// exact quotient
+__device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, float inv_tx, uint32_t* tx, uint32_t* ty) {
+    uint32_t q = (uint32_t)((float)t * inv_tx);
+    if (q * tiles_x > t) --q;
+    if ((q + 1) * tiles_x <= t) ++q;
+    *ty = q;
+    *tx = t - q * tiles_x;
+}
+
+// Per block of BIN_BLOCK depth-ordered Gaussians: how many of their
+// rectangles hold each tile, and the entry count of each of its rounds of
+// 256 Gaussians.  The same launch recomputes, in FP64, the conic of every
+// Gaussian preprocess listed as near-singular (nothing reads those
+// coefficients before the blend).
+__global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ packed, const Counters* __restrict__ cnt,
+                                                  int tiles_x, int tiles_y, uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ round_cnt,
+                                                  const uint2* __restrict__ fb_list, uint32_t fb_cap,
+                                                  const ViewParams* __restrict__ views,
+                                                  const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
+    static_assert(BIN_BLOCK == 8 * 256, "a block is eight rounds of 256");
+    __shared__ uint32_t g[BIN_GRID_MAX];
+    __shared__ uint32_t wsum[8][4];
+    const uint32_t nfb = min(cnt->fb_listed, fb_cap);
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nfb; i += gridDim.x * 256)
+        conic_fp64(fb_list[i], views, blk_view, recs);
+    const uint32_t V = bin_valid(cnt);
+    const uint32_t b0 = blockIdx.x * BIN_BLOCK;
+    if (b0 >= V) return;  // uniform
+    const int w1 = tiles_x + 1, h1 = tiles_y + 1;
+    for (int c = threadIdx.x; c < w1 * h1; c += 256) g[c] = 0u;
+    uint32_t pk[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t i = b0 + (uint32_t)(k * 256) + threadIdx.x;
+        pk[k] = i < V ? packed[i] : 0u;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool in = b0 + (uint32_t)(k * 256) + threadIdx.x < V;
+        if (in) grid_add_rect(g, w1, tiles_x, tiles_y, pk[k]);
+        const uint32_t ws = wave_sum(in ? rect_count(pk[k]) : 0u);
+        if (lane == 0) wsum[k][w] = ws;
+    }
+    __syncthreads();
+    const uint32_t nrounds = (V + 255) / 256;
+    if (threadIdx.x < 8 && blockIdx.x * 8 + threadIdx.x < nrounds) {
+        const int k = threadIdx.x;
+        round_cnt[blockIdx.x * 8 + k] = wsum[k][0] + wsum[k][1] + wsum[k][2] + wsum[k][3];
+    }
+    grid_prefix2d(g, w1, h1);
+    const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
+    const float inv_tx = 1.0f / (float)tiles_x;
+    uint32_t* row = hist + (size_t)blockIdx.x * n_tiles;
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += 256) {
+        uint32_t tx, ty;
+        tile_xy(t, (uint32_t)tiles_x, inv_tx, &tx, &ty);
+        row[t] = g[ty * w1 + tx];
+    }
+}
+
+__device__ __forceinline__ void bin_groups(uint32_t V, uint32_t* nb, uint32_t* bpg) {
+    *nb = (V + BIN_BLOCK - 1) / BIN_BLOCK;
+    *bpg = (*nb + BIN_GROUPS - 1) / BIN_GROUPS;
+}
+
+// Per tile and group of consecutive blocks: the exclusive prefix of the
+// block histograms inside the group (in place) and the group's total.
+__global__ __launch_bounds__(256) void k_bin_prefix(uint32_t* __restrict__ hist, const Counters* __restrict__ cnt,
+                                                    uint32_t n_tiles, uint32_t* __restrict__ gsum) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    uint32_t nb, bpg;
+    bin_groups(bin_valid(cnt), &nb, &bpg);
+    const uint32_t b0 = blockIdx.y * bpg, b1 = min(nb, b0 + bpg);
+    uint32_t run = 0;
+    for (uint32_t b = b0; b < b1; b += 8) {
+        uint32_t h[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h[k] = b + k < b1 ? hist[(size_t)(b + k) * n_tiles + t] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (b + k < b1) hist[(size_t)(b + k) * n_tiles + t] = run;
+            run += h[k];
+        }
+    }
+    gsum[blockIdx.y * n_tiles + t] = run;
+}
+
+// Per tile: the exclusive prefix of the group totals over groups (in place)
+// and the tile's total, stored after the BIN_GROUPS group rows.
+__global__ __launch_bounds__(256) void k_bin_groups(uint32_t* __restrict__ gsum, const Counters* __restrict__ cnt,
+                                                    uint32_t n_tiles) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    uint32_t nb, bpg;
+    bin_groups(bin_valid(cnt), &nb, &bpg);
+    const uint32_t ng = bpg ? (nb + bpg - 1) / bpg : 0u;
+    uint32_t x[BIN_GROUPS];
+#pragma unroll
+    for (int g = 0; g < BIN_GROUPS; ++g) x[g] = (uint32_t)g < ng ? gsum[g * n_tiles + t] : 0u;
+    uint32_t run = 0;
+#pragma unroll
+    for (int g = 0; g < BIN_GROUPS; ++g) {
+        if ((uint32_t)g < ng) gsum[g * n_tiles + t] = run;
+        run += x[g];
+    }
+    gsum[BIN_GROUPS * n_tiles + t] = run;
+}
+
+// Two workgroups.  The first: exclusive scan of the tile totals (the start
+// of each tile's list, stored in the row after the totals), the tile ranges,
+// and the frame's counters stored to the host-visible block.  The second:
+// exclusive scan of the rounds' entry counts (round_off[r], the total after
+// the last round) and, per emission workgroup k < nwg, the round holding its
+// first unit of work (the cost split of k_bin_emit): start_round[k].
+__global__ __launch_bounds__(1024) void k_bin_tiles(uint32_t* __restrict__ gsum, const Counters* __restrict__ cnt,
+                                                    uint32_t n_tiles, uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ round_cnt,
+                                                    uint32_t* __restrict__ round_off, uint32_t* __restrict__ start_round,
+                                                    uint32_t nwg, Counters* host_cnt) {
+    __shared__ uint32_t red[16];
+    const uint32_t V = bin_valid(cnt);
+    constexpr int K = BIN_TILES_MAX / 1024;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *host_cnt = *cnt;
+        if (V == 0) return;  // uniform; the ranges were cleared
+        const uint32_t* tot_row = gsum + (size_t)BIN_GROUPS * n_tiles;
+        uint32_t* start_row = gsum + (size_t)(BIN_GROUPS + 1) * n_tiles;
+        uint32_t tot[K], sum = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t t = threadIdx.x * K + k;
+            tot[k] = t < n_tiles ? tot_row[t] : 0u;
+            sum += tot[k];
+        }
+        uint32_t total;
+        uint32_t start = block_excl_scan<1024>(sum, red, &total);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t t = threadIdx.x * K + k;
+            if (t < n_tiles) {
+                ranges[t] = tot[k] ? make_uint2(start, start + tot[k]) : make_uint2(0u, 0u);
+                start_row[t] = start;
+            }
+            start += tot[k];
+        }
+        return;
+    }
+    if (V == 0) return;  // uniform
+    // rounds, in chunks of 1024 x K
+    const uint32_t nrounds = (V + 255) / 256;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nrounds; c0 += 1024 * K) {
+        uint32_t x[K], s = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t r = c0 + threadIdx.x * K + k;
+            x[k] = r < nrounds ? round_cnt[r] : 0u;
+            s += x[k];
+        }
+        uint32_t ctot;
+        uint32_t o = carry + block_excl_scan<1024>(s, red, &ctot);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t r = c0 + threadIdx.x * K + k;
+            if (r < nrounds) {
+                round_off[r] = o;
+                // workgroups whose first unit falls in round r's cost range
+                const uint64_t c_lo = (uint64_t)o + (uint64_t)BIN_ROUND_COST * r;
+                const uint64_t c_hi = (uint64_t)(o + x[k]) + (uint64_t)BIN_ROUND_COST * (r + 1);
+                for (uint64_t wk = (c_lo + BIN_PAIRS - 1) / BIN_PAIRS; wk < nwg && wk * BIN_PAIRS < c_hi; ++wk)
+                    start_round[wk] = r;
+            }
+            o += x[k];
+        }
+        carry += ctot;
+    }
+    if (threadIdx.x == 0) round_off[nrounds] = carry;
+}
+
+// Inclusive XOR prefix over the 64 lanes of a wave (same lane pattern as
+// wave_incl_scan; lanes without a source see 0, the identity).
+__device__ __forceinline__ uint32_t wave_incl_xor(uint32_t v) {
+    v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// Lane masks of one wave over the columns (or rows) 0..n-1: bit l of m[x] is
+// set when lane l's interval [lo, hi] holds x.  Each lane toggles its bit at
+// lo and at hi + 1 (m has n + 1 entries, cleared by the caller), and the XOR
+// prefix over x leaves each bit set exactly inside its interval.
+__device__ __forceinline__ void wave_interval_masks(unsigned long long* m, int n, bool valid, int lo, int hi) {
+    const int lane = (int)(threadIdx.x & 63);
+    if (valid) {
+        atomicXor(&m[lo], 1ull << lane);
+        atomicXor(&m[hi + 1], 1ull << lane);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t clo = 0, chi = 0;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int x = c0 + lane;
+        const unsigned long long v = x < n ? m[x] : 0ull;
+        const uint32_t slo = wave_incl_xor((uint32_t)v) ^ clo, shi = wave_incl_xor((uint32_t)(v >> 32)) ^ chi;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (x < n) m[x] = ((unsigned long long)shi << 32) | slo;
+        clo = readlane(slo, 63);
+        chi = readlane(shi, 63);
+    }
+}
+
+// Writes the entries of the depth-first emission order (Gaussians in depth
+// order, tiles row-major over each rectangle) to their sorted positions:
+// record ids, and with DEBUG also each entry's tile id and depth word; each
+// workgroup takes BIN_PAIRS units of work.  cntr holds, per tile, the
+// position of its next entry; inside a round each entry adds the count of
+// earlier Gaussians of the round that hold its tile (the waves' column and
+// row lane masks), and the round's last Gaussian holding a tile moves that
+// tile's position.
+template <bool DEBUG>
+__global__ __launch_bounds__(256) void k_bin_emit(const uint32_t* __restrict__ sorted_rec,
+                                                  const uint32_t* __restrict__ packed, const Counters* __restrict__ cnt,
+                                                  const uint32_t* __restrict__ hist, const uint32_t* __restrict__ gsum,
+                                                  const uint32_t* __restrict__ round_off,
+                                                  const uint32_t* __restrict__ start_round, int tiles_x, int tiles_y,
+                                                  uint32_t* __restrict__ val_out, uint32_t* __restrict__ tile_out,
+                                                  uint32_t* __restrict__ depth_out,
+                                                  const uint32_t* __restrict__ zkey) {
+    // dynamic LDS sized for the view's grid: column and row lane masks per
+    // wave (one spare entry each for the interval ends), next position per cell
+    extern __shared__ __align__(16) unsigned char bin_smem[];
+    unsigned long long* colm = reinterpret_cast<unsigned long long*>(bin_smem);  // [4][tiles_x + 1]
+    unsigned long long* rowm = colm + 4 * (tiles_x + 1);                         // [4][tiles_y + 1]
+    uint32_t* cntr = reinterpret_cast<uint32_t*>(rowm + 4 * (tiles_y + 1));
+    __shared__ uint32_t red[4], wmax[4], pick;
+    __shared__ uint32_t pre[257], own[256], srec[256], spk[256];
+    __shared__ float sinv[256];
+    const uint32_t V = bin_valid(cnt);
+    const uint32_t D = cnt->D;
+    if (V == 0) return;  // uniform
+    // Work is split by cost: a round of 256 Gaussians costs its entries plus
+    // BIN_ROUND_COST (its fixed steps), so round r starts at cost
+    // C(r) = round_off[r] + BIN_ROUND_COST r; its first BIN_ROUND_COST units
+    // stand for the fixed steps, the rest for its entries in order.
+    const uint32_t nrounds = (V + 255) / 256;
+    const uint64_t total_cost = (uint64_t)round_off[nrounds] + (uint64_t)BIN_ROUND_COST * nrounds;
+    const uint32_t nact = (uint32_t)((total_cost + BIN_PAIRS - 1) / BIN_PAIRS);
+    if (blockIdx.x >= nact) return;  // uniform
+    // XCD x takes a contiguous run of the cost ranges in use: the entries
+    // neighbouring workgroups write to one tile's list are adjacent and meet
+    // in one L2
+    const uint64_t A = (uint64_t)xcd_segment((int)blockIdx.x, (int)nact) * BIN_PAIRS;
+    const uint64_t B = min(total_cost, A + BIN_PAIRS);
+    auto cost = [&](uint32_t r) -> uint64_t { return (uint64_t)round_off[r] + (uint64_t)BIN_ROUND_COST * r; };
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the round holding cost A (the last r with C(r) <= A)
+    const uint32_t R = start_round[A / BIN_PAIRS];
+    // entered part way (past its fixed steps and first entries), round R is
+    // counted into the start positions and its entries step back by their
+    // tile's count in the round
+    const bool part = A > cost(R) + BIN_ROUND_COST;
+    const uint32_t cb = R * 256 / BIN_BLOCK;
+    uint32_t nb, bpg;
+    bin_groups(V, &nb, &bpg);
+    const uint32_t grp = cb / bpg;
+    const int w1 = tiles_x + 1, h1 = tiles_y + 1, ncell = w1 * h1;
+    const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
+    const float inv_tx = 1.0f / (float)tiles_x;
+    // next positions at the start of round R (of R + 1 when entered part
+    // way): tile starts, block prefixes, and the block's Gaussians before
+    for (int c = threadIdx.x; c < ncell; c += 256) cntr[c] = 0u;
+    __syncthreads();
+    grid_add_rects(cntr, w1, tiles_x, tiles_y, packed, cb * BIN_BLOCK, part ? min(V, R * 256 + 256) : R * 256);
+    __syncthreads();
+    grid_prefix2d(cntr, w1, h1);
+    {
+        const uint32_t* hrow = hist + (size_t)cb * n_tiles;
+        const uint32_t* grow = gsum + (size_t)grp * n_tiles;
+        const uint32_t* srow = gsum + (size_t)(BIN_GROUPS + 1) * n_tiles;
+        constexpr int U = 8;
+        for (uint32_t t0 = 0; t0 < n_tiles; t0 += 256 * U) {
+            uint32_t h[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t t = t0 + (uint32_t)(k * 256) + threadIdx.x;
+                h[k] = t < n_tiles ? hrow[t] + grow[t] + srow[t] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t t = t0 + (uint32_t)(k * 256) + threadIdx.x;
+                if (t < n_tiles) {
+                    uint32_t tx, ty;
+                    tile_xy(t, (uint32_t)tiles_x, inv_tx, &tx, &ty);
+                    cntr[ty * w1 + tx] += h[k];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long* cw = colm + w * (tiles_x + 1);
+    unsigned long long* rw = rowm + w * (tiles_y + 1);
+    // each round loads the next one's Gaussians ahead
+    uint32_t nx_rec = 0, nx_p = 0;
+    if (R * 256 + threadIdx.x < V) {
+        nx_rec = sorted_rec[R * 256 + threadIdx.x];
+        nx_p = packed[R * 256 + threadIdx.x];
+    }
+    for (uint32_t r = R; r < nrounds; ++r) {
+        const uint64_t cr = cost(r);
+        if (cr >= B) break;  // uniform
+        const uint32_t i = r * 256 + threadIdx.x;
+        const bool valid = i < V;
+        const uint32_t rec = nx_rec, p = nx_p;
+        if (i + 256 < V) {
+            nx_rec = sorted_rec[i + 256];
+            nx_p = packed[i + 256];
+        }
+        uint32_t n = 0;
+        int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+        if (valid) {
+            x0 = (int)(p & 0xffu);
+            y0 = (int)((p >> 8) & 0xffu);
+            x1 = (int)((p >> 16) & 0xffu);
+            y1 = (int)(p >> 24);
+            n = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        }
+        // this wave's column and row lane masks
+        for (int x = lane; x <= tiles_x; x += 64) cw[x] = 0ull;
+        for (int y = lane; y <= tiles_y; y += 64) rw[y] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_interval_masks(cw, tiles_x, valid, x0, x1);
+        wave_interval_masks(rw, tiles_y, valid, y0, y1);
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<256>(n, red, &tot);
+        // this workgroup's slots of the round: [js, je)
+        const uint64_t c0 = cr + BIN_ROUND_COST;
+        const uint32_t js = (uint32_t)min((uint64_t)tot, A > c0 ? A - c0 : 0ull);
+        const uint32_t je = (uint32_t)min((uint64_t)tot, B > c0 ? B - c0 : 0ull);
+        const bool first_part = part && r == R;
+        const uint32_t wstart = js & ~255u;
+        pre[threadIdx.x + 1] = ex + n;
+        if (threadIdx.x == 0) {
+            pre[0] = 0;
+            pick = 0u;
+        }
+        own[threadIdx.x] = 0u;
+        srec[threadIdx.x] = rec;
+        spk[threadIdx.x] = p;
+        sinv[threadIdx.x] = valid ? 1.0f / (float)(x1 - x0 + 1) : 0.0f;
+        __syncthreads();
+        // owner of the slot before the first window: the last Gaussian whose
+        // first slot precedes it
+        if (wstart > 0 && n && ex < wstart) atomicMax(&pick, threadIdx.x);
+        __syncthreads();
+        uint32_t carry = pick;
+        // a move of a next position found in a window is applied once every
+        // read of that window is done (after the next barrier)
+        int pend_cell = -1;
+        uint32_t pend_val = 0;
+        // windows of 256 slots: a slot's owner is the last Gaussian whose
+        // first slot is at or before it (round-tagged marks and a prefix
+        // maximum, as in k_duplicate)
+        for (uint32_t j0 = wstart, m = wstart >> 8; j0 < je; j0 += 256, ++m) {
+            if (n && (ex >> 8) == m) own[ex & 255u] = (m << 8) | threadIdx.x;
+            __syncthreads();
+            if (pend_cell >= 0) {
+                cntr[pend_cell] += pend_val;
+                pend_cell = -1;
+            }
+            const uint32_t incl = wave_incl_max(own[threadIdx.x]);
+            if (lane == 63) wmax[w] = incl;
+            __syncthreads();
+            uint32_t o = max(incl, (m << 8) | carry), all = (m << 8) | carry;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t xw = wmax[v];
+                if (v < w) o = max(o, xw);
+                all = max(all, xw);
+            }
+            carry = all & 0xffu;
+            const uint32_t j = j0 + threadIdx.x;
+            if (j >= js && j < je) {
+                const uint32_t eo = o & 0xffu;
+                const uint32_t k = j - pre[eo];
+                const uint32_t pk = spk[eo];
+                const uint32_t ex0 = pk & 0xffu, ey0 = (pk >> 8) & 0xffu;
+                const uint32_t nx = ((pk >> 16) & 0xffu) - ex0 + 1u;
+                // k / nx through the FP32 reciprocal, corrected to the exact quotient
+                uint32_t qq = (uint32_t)((float)k * sinv[eo]);
+                if (qq * nx > k) --qq;
+                if ((qq + 1) * nx <= k) ++qq;
+                const int ty = (int)(ey0 + qq), tx = (int)(ex0 + (k - qq * nx));
+                const int we = (int)(eo >> 6), le = (int)(eo & 63u);
+                const unsigned long long below = le == 0 ? 0ull : (~0ull >> (64 - le));
+                uint32_t before = 0, total = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const unsigned long long mm = colm[v * (tiles_x + 1) + tx] & rowm[v * (tiles_y + 1) + ty];
+                    const uint32_t c = (uint32_t)__builtin_popcountll(mm);
+                    total += c;
+                    if (v < we) before += c;
+                    else if (v == we) before += (uint32_t)__builtin_popcountll(mm & below);
+                }
+                const int cell = ty * w1 + tx;
+                const uint32_t pos = cntr[cell] + before - (first_part ? total : 0u);
+                if (pos < D) {
+                    const uint32_t rr = srec[eo];
+                    val_out[pos] = rr;
+                    if (DEBUG) {
+                        tile_out[pos] = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)tx;
+                        depth_out[pos] = zkey[rr];
+                    }
+                }
+                // the round's last Gaussian holding the tile: no later slot
+                // of the round reads its position
+                if (!first_part && before + 1u == total) {
+                    pend_cell = cell;
+                    pend_val = total;
+                }
+            }
+        }
+        __syncthreads();
+        if (pend_cell >= 0) cntr[pend_cell] += pend_val;
+        if (je < tot) break;  // uniform: the range ends inside this round
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------- blend
@@ -1477,13 +2037,14 @@ __global__ void k_wave_scan_selftest(const uint32_t* in, uint32_t* out, int n) {
 
 // ------------------------------------------------------------- launchers
 
-#define TIGAS_LAUNCH(kernel, grid, block, st, ...)                                        \
+#define TIGAS_LAUNCH_SHM(kernel, grid, block, shm, st, ...)                               \
     do {                                                                                  \
         KernelTimer* kt_ = g_kernel_timer;                                                \
         if (kt_) kt_->before(reinterpret_cast<const void*>(kernel), st);                 \
-        hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                      \
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                    \
         if (kt_) kt_->after(st);                                                          \
     } while (0)
+#define TIGAS_LAUNCH(kernel, grid, block, st, ...) TIGAS_LAUNCH_SHM(kernel, grid, block, 0, st, __VA_ARGS__)
 
 template <int ST>
 static void preprocess_deg(int deg, dim3 grid, const SceneView& s, const ViewParams* v, int nv, uint32_t rb,
@@ -1562,7 +2123,7 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
-        uint32_t* pre = b.hist + (size_t)256 * SORT_MAX_BLOCKS;
+        uint32_t* pre = b.pre;
         TIGAS_LAUNCH(k_sort_upsweep, dim3(nblocks), dim3(SORT_THREADS), st, (const uint32_t*)b.key[cur], cnt, which,
                      cap, ps.shift, ps.bits, b.hist, pre, nblocks);
         const int ndig = 1 << ps.bits;
@@ -1594,6 +2155,45 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
     TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(16384u, std::max<uint32_t>(1u, (cap + 1023) / 1024))), dim3(256), st,
                  tile_sorted, cnt, cap, ranges, host_cnt, (const uint2*)o.fb_list, o.fb_cap, views_dev,
                  (const uint32_t*)o.blk_view, o.rec);
+}
+
+uint32_t bin_emit_groups(uint32_t cap, uint32_t nrec) {
+    const uint64_t max_cost = (uint64_t)cap + (uint64_t)BIN_ROUND_COST * ((nrec + 255) / 256);
+    return std::max<uint32_t>(1u, (uint32_t)((max_cost + BIN_PAIRS - 1) / BIN_PAIRS));
+}
+
+bool bin_fits(int tiles_x, int tiles_y) {
+    return tiles_x >= 1 && tiles_y >= 1 && tiles_x <= 255 && tiles_y <= 255 &&
+           (tiles_x + 1) * (tiles_y + 1) <= BIN_GRID_MAX && tiles_x * tiles_y <= BIN_TILES_MAX;
+}
+
+void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const Counters* cnt, uint32_t nrec,
+                uint32_t cap, int tiles_x, int tiles_y, uint32_t* hist, uint32_t* gsum, uint32_t* round_cnt,
+                uint32_t* round_off, uint2* ranges, Counters* host_cnt, const PreOut& o, const ViewParams* views_dev,
+                uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, hipStream_t st) {
+    const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
+    const uint32_t nbc = std::max<uint32_t>(1u, (nrec + BIN_BLOCK - 1) / BIN_BLOCK);
+    TIGAS_LAUNCH(k_bin_hist, dim3(nbc), dim3(256), st, sorted_packed, cnt, tiles_x, tiles_y, hist, round_cnt,
+                 (const uint2*)o.fb_list, o.fb_cap, views_dev, (const uint32_t*)o.blk_view, o.rec);
+    TIGAS_LAUNCH(k_bin_prefix, dim3((n_tiles + 255) / 256, BIN_GROUPS), dim3(256), st, hist, cnt, n_tiles, gsum);
+    TIGAS_LAUNCH(k_bin_groups, dim3((n_tiles + 255) / 256), dim3(256), st, gsum, cnt, n_tiles);
+    // enough emission workgroups for the largest cost the capacities allow
+    const uint32_t nwg = bin_emit_groups(cap, nrec);
+    uint32_t* start_round = gsum + (size_t)(BIN_GROUPS + 2) * n_tiles;
+    TIGAS_LAUNCH(k_bin_tiles, dim3(2), dim3(1024), st, gsum, cnt, n_tiles, ranges, (const uint32_t*)round_cnt,
+                 round_off, start_round, nwg, host_cnt);
+    const size_t ncell = (size_t)(tiles_x + 1) * (tiles_y + 1);
+    const size_t lds = 8 * 4 * (size_t)(tiles_x + 1 + tiles_y + 1) + 4 * ncell;
+    if (tile_out)
+        TIGAS_LAUNCH_SHM(k_bin_emit<true>, dim3(nwg), dim3(256), lds, st, sorted_rec, sorted_packed, cnt,
+                         (const uint32_t*)hist, (const uint32_t*)gsum, (const uint32_t*)round_off,
+                         (const uint32_t*)start_round, tiles_x, tiles_y, val_out, tile_out, depth_out,
+                         (const uint32_t*)o.zkey);
+    else
+        TIGAS_LAUNCH_SHM(k_bin_emit<false>, dim3(nwg), dim3(256), lds, st, sorted_rec, sorted_packed, cnt,
+                         (const uint32_t*)hist, (const uint32_t*)gsum, (const uint32_t*)round_off,
+                         (const uint32_t*)start_round, tiles_x, tiles_y, val_out, tile_out, depth_out,
+                         (const uint32_t*)o.zkey);
 }
 
 template <int TW, int TH, int BD, int PPL>

@@ -15,6 +15,16 @@ constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;  // counts per workgroup of the chunked scans
 constexpr int MAX_SORT_PASSES = 8;
+// Binned tile digit (single view): Gaussians per histogram block (eight
+// rounds of 256), work per emission workgroup (entries, with each round of
+// 256 Gaussians also counting BIN_ROUND_COST), groups of blocks for the
+// prefix, cells of the (tiles_x + 1) x (tiles_y + 1) difference grid, tiles.
+constexpr int BIN_BLOCK = 2048;
+constexpr int BIN_PAIRS = 8192;
+constexpr int BIN_ROUND_COST = 1024;  // fixed steps of a round, in entries
+constexpr int BIN_GROUPS = 32;
+constexpr int BIN_GRID_MAX = 8448;
+constexpr int BIN_TILES_MAX = 8192;
 
 // Resident scene (device pointers).  Layout by storage precision:
 //   mean:  f32 planes [3][n] (x, y, z)
@@ -96,7 +106,8 @@ struct SortBuffers {
     uint32_t* key[2];
     uint32_t* val[2];
     uint32_t* ext[2];
-    uint32_t* hist;    // [256][SORT_MAX_BLOCKS] digit counts per segment, then as many segment digit prefixes
+    uint32_t* hist;    // [256][segments] digit counts per segment
+    uint32_t* pre;     // [256][segments] segment digit prefixes
 };
 
 // Arrays cleared (as u32 words) by the first kernel after preprocess.
@@ -143,6 +154,21 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
 // pinned host memory that receives a copy of the counters.
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    const PreOut& o, const ViewParams* views_dev, hipStream_t st);
+// Tile placement by counting (single view, packed rectangles, a tile grid
+// that fits BIN_GRID_MAX / BIN_TILES_MAX): from the depth-ordered records and
+// packed rectangles, writes each (Gaussian, tile) entry's record id to its
+// sorted position in val_out (with tile_out/depth_out, also its tile id and
+// depth word), the tile ranges, the counters to host_cnt, and runs the FP64
+// conic fallback.  hist: ceil(nrec / BIN_BLOCK) x tiles words; gsum:
+// (BIN_GROUPS + 2) x tiles words (group rows, tile totals, tile starts) and
+// bin_emit_groups(cap, nrec) more (each emission workgroup's first round);
+// round_cnt / round_off: nrec / 256 + 1 words; cap: the entry capacity.
+bool bin_fits(int tiles_x, int tiles_y);
+uint32_t bin_emit_groups(uint32_t cap, uint32_t nrec);
+void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const Counters* cnt, uint32_t nrec,
+                uint32_t cap, int tiles_x, int tiles_y, uint32_t* hist, uint32_t* gsum, uint32_t* round_cnt,
+                uint32_t* round_off, uint2* ranges, Counters* host_cnt, const PreOut& o, const ViewParams* views_dev,
+                uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, hipStream_t st);
 // Baseline JPEG of an RGB8 frame: one workgroup per restart interval of
 // JPEG_SEG_MCUS MCUs; the header is written by the host.
 constexpr int JPEG_THREADS = 128;

@@ -90,7 +90,8 @@ EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", 
            "tigas_count_blend_work", "tigas_set_graphs",
            "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait",
            "tigas_jpeg_encode", "tigas_jpeg_max_bytes", "tigas_abr_default_config", "tigas_abr_create",
-           "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate")
+           "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate",
+           "tigas_set_tile_binning")
 
 _lib = None
 
@@ -128,6 +129,7 @@ def lib():
         L.tigas_selftest_wave_scan.argtypes = [P, P, I]
         L.tigas_profile_stages.argtypes = [P, I]
         L.tigas_set_graphs.argtypes = [P, I]
+        L.tigas_set_tile_binning.argtypes = [P, I]
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
         L.tigas_profile_kernels.argtypes = [P, I]
         L.tigas_render_submit.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
@@ -287,6 +289,11 @@ class Context:
     def set_graphs(self, enable: bool):
         """Capture/replay launch sequences as HIP graphs (default on)."""
         _check(lib().tigas_set_graphs(self.handle, 1 if enable else 0))
+
+    def set_tile_binning(self, enable: bool):
+        """Single views: tile digit by counting (True, the default) or by radix
+        passes over the duplicates (False); identical lists either way."""
+        _check(lib().tigas_set_tile_binning(self.handle, int(bool(enable))))
 
     def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=None,
                          batch_depth=None, ppl=None):

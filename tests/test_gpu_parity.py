@@ -53,14 +53,24 @@ def test_c1_preprocess_matches_oracle(ctx, c1):
     assert err["uv"] < 1e-4
 
 
+@pytest.mark.parametrize("binning", [True, False])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 32), (32, 16)])
-def test_c1_tile_lists_sort_and_ranges_bit_exact(ctx, c1, tile):
+def test_c1_tile_lists_sort_and_ranges_bit_exact(ctx, c1, tile, binning):
+    """Both placements of the tile digit (counting, radix passes) give the
+    sorted list of the plain 64-bit key sort."""
     scene, poses, k, W, H = c1
     s = ctx.load_scene(scene)
-    _say("c1 tiles", tile)
-    dbg = ctx.render_debug(s, poses[0], k, W, H, tile=tile)
+    _say("c1 tiles", tile, "binning", binning)
+    ctx.set_tile_binning(binning)
+    try:
+        dbg = ctx.render_debug(s, poses[0], k, W, H, tile=tile)
+        passes = ctx.stats()["sort_passes"]
+    finally:
+        ctx.set_tile_binning(True)
     gc.check_tiles(dbg, *tile)
     assert dbg["n_dup"] > scene.n
+    # 4 depth passes, then one counting placement or the radix tile passes
+    assert passes == (5 if binning else 4 + math.ceil(math.log2((W // tile[0]) * (H // tile[1])) / 8))
 
 
 def test_c1_frame_matches_oracle(ctx, c1):
