@@ -178,6 +178,49 @@ tigas_status tigas_render_submit(tigas_scene* scene, const tigas_pose* pose, con
  * the frame's own error otherwise. */
 tigas_status tigas_render_wait(tigas_context* ctx, int64_t ticket, tigas_stats* stats, float* gpu_ms);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free render, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It renders the same frame as tigas_render with the same tile
+ * configuration, but every buffer of its launch sequence lies in one static
+ * device array of TIGAS_NOALLOC_SCRATCH_BYTES per device (set up when a
+ * context is created on the device, held until the process ends); the call
+ * allocates nothing, neither device nor pinned host memory.
+ *
+ * The launch sequence is enqueued on hip_stream (NULL: the context stream)
+ * and the call returns without waiting; the frame is complete when the
+ * stream has passed it, and `scene` must stay loaded until then.  Only
+ * kernels are enqueued (no memset or copy), so the call may be captured.
+ * out must be device memory (out->is_device); out_w/out_h are written.
+ * Tiles: q's tile_w/tile_h/batch_depth/pixels_per_lane, or 16x16, depth 64,
+ * one pixel per lane when zero (no autotuner).
+ * counters: device-accessible memory (device, or pinned host) that receives
+ * the frame's counters when it completes; may be NULL.  When the frame has
+ * more (Gaussian, tile) pairs than the array holds, nothing is composited
+ * (the frame is the background) and counters->overflow is 1: the caller
+ * renders it with tigas_render instead.
+ * Limits: the scene's records (n rounded up to 256) take 92 bytes each and
+ * every (Gaussian, tile) pair 24 bytes, out of the 64 MiB; a scene whose
+ * records leave fewer pair slots than records is refused with E_INVALID.
+ * Every call on one device shares that device's array and leaves its
+ * contents there: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.
+ * Errors as tigas_render, plus E_INVALID for a host frame.
+ * ------------------------------------------------------------------------- */
+#define TIGAS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+typedef struct {
+    uint32_t duplicates; /* D: (Gaussian, tile) pairs (saturates at 2^32-1) */
+    uint32_t visible;    /* Gaussians that touched a tile */
+    uint32_t fallbacks;  /* 2D covariances inverted on the FP64 path */
+    uint32_t overflow;   /* 1: more pairs than the scratch array holds; the frame is the background */
+    uint32_t reserved[2];
+} tigas_frame_counters;
+
+tigas_status tigas_render_noalloc(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                                  int width, int height, const tigas_quality* q, tigas_frame* out,
+                                  tigas_frame_counters* counters, void* hip_stream);
+
 /* Renders n_views views, each with its own scene, pose, intrinsics, size and
  * quality q[i] (rung, SH degree, format, background; q may be NULL for
  * defaults; the tile size and batch depth of q[0] apply to all views), with one

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <atomic>
 #include <chrono>
 #include <cstdlib>
@@ -165,6 +166,17 @@ uint16_t f32_to_f16(float f) {
 }
 
 }  // namespace
+
+static_assert(sizeof(tigas_frame_counters) == sizeof(Counters), "public counters mirror the device counters");
+static_assert(offsetof(tigas_frame_counters, duplicates) == offsetof(Counters, D) &&
+                  offsetof(tigas_frame_counters, visible) == offsetof(Counters, visible) &&
+                  offsetof(tigas_frame_counters, fallbacks) == offsetof(Counters, fallbacks) &&
+                  offsetof(tigas_frame_counters, overflow) == offsetof(Counters, overflow),
+              "public counters mirror the device counters");
+
+// Scratch array of the allocation-free render (see render_noalloc): one copy
+// per device, held until the process ends.
+static __device__ __align__(256) unsigned char scratch[TIGAS_NOALLOC_SCRATCH_BYTES];
 
 // ------------------------------------------------------------- objects
 
@@ -1239,6 +1251,126 @@ void render_wait(tigas_context* ctx, int64_t ticket, tigas_stats* stats, float* 
     if (gpu_ms) *gpu_ms = d.gpu_ms;
 }
 
+// ------------------------------------------------ allocation-free render
+// Every buffer of the launch sequence is carved out of `scratch`, one static
+// device array per device.  Host code never uses the array's name as an
+// address (it names a host-side stand-in): its device address comes from
+// hipGetSymbolAddress, taken once per device when a context is created there.
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+std::string g_scratch_err[kScratchDevices];
+
+void* scratch_address(int device) {
+    if (device < 0 || device >= kScratchDevices) fail(TIGAS_E_INVALID, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device])
+        fail(TIGAS_E_DEVICE, "scratch array of this device is not set up: " +
+                                 (g_scratch_err[device].empty() ? std::string("no context was created on it")
+                                                                : g_scratch_err[device]));
+    return g_scratch_ptr[device];
+}
+
+// Bump allocator over the scratch array (256-byte aligned pieces).
+struct Carver {
+    char* base;
+    size_t cap, off = 0;
+    template <typename T>
+    T* take(size_t bytes) {
+        off = (off + 255) / 256 * 256;
+        T* p = reinterpret_cast<T*>(base + off);
+        off += std::max<size_t>(bytes, 4);
+        return p;
+    }
+};
+
+// Lays out a single-view launch sequence of nrec records and n_tiles tiles
+// in the scratch array; the duplicate buffers take what is left.
+FrameMem carve_scratch(void* scratch_dev, uint32_t nrec, uint32_t n_tiles, Counters* cnt_out, hipStream_t st) {
+    Carver c{static_cast<char*>(scratch_dev), (size_t)TIGAS_NOALLOC_SCRATCH_BYTES};
+    FrameMem m;
+    m.stream = st;
+    m.views = c.take<ViewParams>(sizeof(ViewParams));
+    m.views_src = nullptr;  // the view is stored by a kernel
+    m.cnt = c.take<Counters>(sizeof(Counters));
+    m.cnt_out = cnt_out ? cnt_out : c.take<Counters>(sizeof(Counters));
+    m.queue = c.take<uint32_t>(8 * 4);
+    PreOut& o = m.pre;
+    o.rec = c.take<Rec>((size_t)nrec * sizeof(Rec));
+    o.rect = c.take<uint2>((size_t)nrec * 8);
+    o.srect = c.take<uint2>((size_t)nrec * 8);
+    o.zkey = c.take<uint32_t>((size_t)nrec * 4);
+    o.fb_list = c.take<uint2>((size_t)nrec * 8);
+    o.fb_cap = nrec;
+    const size_t nb = (size_t)nrec / K1_THREADS + 1;
+    o.blk_sum = c.take<uint32_t>(nb * 4);
+    o.blk_vis = c.take<uint32_t>(nb * 4);
+    o.blk_fb = c.take<uint32_t>(nb * 4);
+    o.blk_view = c.take<uint32_t>(nb * 4);
+    m.blk_off = c.take<uint32_t>(nb * 4);
+    m.blk_sum2 = c.take<uint32_t>(nb * 4);
+    m.blk_off2 = c.take<uint32_t>(nb * 4);
+    const size_t nch = nb / SCAN_CHUNK + 2;
+    o.chunk_vis = c.take<uint32_t>(nch * 4);
+    o.chunk_fb = c.take<uint32_t>(nch * 4);
+    o.chunk_dups = c.take<uint32_t>(nch * 4);
+    o.chunk_dup = c.take<unsigned long long>(nch * 8);
+    o.cnt = m.cnt;
+    m.ranges = c.take<uint2>((size_t)std::max<uint32_t>(n_tiles, 1) * 8);
+    m.bin_hist = c.take<uint32_t>(((size_t)nrec + BIN_BLOCK - 1) / BIN_BLOCK * n_tiles * 4);
+    // the first-round table sized for the largest duplicate capacity below
+    m.bin_gsum = c.take<uint32_t>(((size_t)(BIN_GROUPS + 2) * n_tiles + bin_emit_groups(16u << 20, nrec)) * 4);
+    // sort passes over at most 16M keys use at most 1024 segments
+    m.hist = c.take<uint32_t>((size_t)256 * 1024 * 4);
+    m.hist_pre = c.take<uint32_t>((size_t)256 * 1024 * 4);
+    // six duplicate arrays of dup_cap words (keys, values, extra; two each)
+    const size_t left = c.cap > c.off + 6 * 256 ? c.cap - c.off - 6 * 256 : 0;
+    const uint64_t dup_cap = std::min<uint64_t>(left / 24 / 256 * 256, 16u << 20);
+    if (dup_cap < std::max<uint64_t>(nrec, 1))
+        fail(TIGAS_E_INVALID, "scene too large for the allocation-free render: its records and the duplicate "
+                              "buffers need more than the " + std::to_string(TIGAS_NOALLOC_SCRATCH_BYTES >> 20) +
+                                  " MiB scratch array");
+    for (int i = 0; i < 2; ++i) {
+        m.key[i] = c.take<uint32_t>(dup_cap * 4);
+        m.val[i] = c.take<uint32_t>(dup_cap * 4);
+        m.ext[i] = c.take<uint32_t>(dup_cap * 4);
+    }
+    if (c.off > c.cap) fail(TIGAS_E_DEVICE, "scratch layout exceeds the array");
+    m.dup_cap = (uint32_t)dup_cap;
+    return m;
+}
+
+void render_noalloc(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width, int height,
+                    const tigas_quality* q, tigas_frame* out, tigas_frame_counters* counters, void* hip_stream) {
+    if (!scene || !out) fail(TIGAS_E_INVALID, "scene and frame are required");
+    if (!out->is_device) fail(TIGAS_E_INVALID, "the allocation-free render writes a device frame only");
+    tigas_context* ctx = scene->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    void* scratch_dev = scratch_address(ctx->device);
+    SceneRef ref(scene);
+    Plan plan;
+    plan.views.push_back(make_view(scene, pose, intr, width, height, q));
+    const uint32_t n_pad = round_up((uint64_t)scene->view.n, K1_THREADS);
+    plan.groups.push_back({scene, 0, 1, 0, n_pad});
+    plan.nrec = n_pad;
+    ViewParams& v = plan.views[0];
+    out->out_w = v.width;
+    out->out_h = v.height;
+    if (!out->data || out->capacity < frame_bytes(v)) fail(TIGAS_E_BUFFER, "output frame buffer too small");
+    v.out_ptr = (uint64_t)(uintptr_t)out->data;
+    set_tiles(plan, tile_cfg(q));  // as requested, else 16x16 tiles: no autotuner here
+    const hipStream_t st = pick_stream(ctx, hip_stream);
+    const FrameMem m =
+        carve_scratch(scratch_dev, plan.nrec, plan.n_tiles, reinterpret_cast<Counters*>(counters), st);
+    // the previous call's counters stay in the array: start this frame from zero
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m.cnt), sizeof(Counters) / 4, 0u, st);
+    LaunchOptions opt;
+    opt.cull = ctx->blend_cull.load();
+    opt.bin = ctx->tile_bin.load();
+    (void)enqueue(m, plan, false, false, nullptr, 0, opt);
+}
+
 void debug_copy(Workspace& ws, const Plan& plan, int cur, int64_t n, uint32_t n_pad, tigas_debug_out* dbg) {
     Counters c;
     std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
@@ -1866,6 +1998,19 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         hipDeviceProp_t prop;
         HIPCHK(hipGetDeviceProperties(&prop, device));
         c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        if (device < kScratchDevices) {  // device address of this device's scratch array, once per device
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            if (!g_scratch_ptr[device]) {
+                void* ptr = nullptr;
+                const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+                if (e == hipSuccess && ptr) {
+                    g_scratch_ptr[device] = ptr;
+                } else {  // only the allocation-free render needs it: it reports this error
+                    (void)hipGetLastError();
+                    g_scratch_err[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+                }
+            }
+        }
         HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         if (const char* f = std::getenv("TIGAS_TUNE_CACHE")) c->tune_file = f;
         if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
@@ -1991,6 +2136,12 @@ size_t tigas_scene_bytes(const tigas_scene* s) { return s ? s->bytes : 0; }
 tigas_status tigas_render(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width,
                           int height, const tigas_quality* q, tigas_frame* out, void* hip_stream) {
     return guard([&] { render_one(scene, pose, intr, width, height, q, out, hip_stream, nullptr); });
+}
+
+tigas_status tigas_render_noalloc(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr,
+                                  int width, int height, const tigas_quality* q, tigas_frame* out,
+                                  tigas_frame_counters* counters, void* hip_stream) {
+    return guard([&] { render_noalloc(scene, pose, intr, width, height, q, out, counters, hip_stream); });
 }
 
 tigas_status tigas_render_debug(tigas_scene* scene, const tigas_pose* pose, const tigas_intrinsics* intr, int width,

@@ -90,7 +90,7 @@ EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", 
            "tigas_count_blend_work", "tigas_set_graphs",
            "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait",
            "tigas_jpeg_encode", "tigas_jpeg_max_bytes", "tigas_abr_default_config", "tigas_abr_create",
-           "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate",
+           "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate", "tigas_render_noalloc",
            "tigas_set_tile_binning")
 
 _lib = None
@@ -134,6 +134,8 @@ def lib():
         L.tigas_profile_kernels.argtypes = [P, I]
         L.tigas_render_submit.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
                                           ctypes.POINTER(QualityC), ctypes.POINTER(FrameC), P, ctypes.POINTER(I64)]
+        L.tigas_render_noalloc.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
+                                           ctypes.POINTER(QualityC), ctypes.POINTER(FrameC), P, P]
         L.tigas_render_wait.argtypes = [P, I64, ctypes.POINTER(StatsC), ctypes.POINTER(ctypes.c_float)]
         L.tigas_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimeC), I, ctypes.POINTER(I)]
         L.tigas_jpeg_encode.argtypes = [P, P, I, I, I, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
@@ -358,6 +360,24 @@ class Context:
                                          int(width), int(height), ctypes.byref(q), ctypes.byref(fr), st,
                                          ctypes.byref(t)))
         return int(t.value)
+
+    def render_noalloc(self, scene: Scene, pose, intr, width, height, out, counters=None, res_scale=1.0,
+                       fmt="rgb8", bg=(0, 0, 0), tile=None, batch_depth=None, sh_degree=-1, stream=None,
+                       ppl=None) -> None:
+        """Enqueue one frame into the GPU tensor ``out`` through the
+        allocation-free entry point (buffers in the library's static device
+        array) and return without waiting.  ``counters``: a GPU int32 tensor
+        of 6 elements receiving (duplicates, visible, fallbacks, overflow, -, -)
+        when the frame completes, or None."""
+        q = quality_c(res_scale, sh_degree, fmt, bg, tile, batch_depth, ppl)
+        fr = FrameC(ctypes.c_void_p(int(out.data_ptr())), out.numel() * out.element_size(), int(out.is_cuda), 0, 0)
+        cp = None
+        if counters is not None:
+            assert counters.is_cuda and counters.numel() * counters.element_size() >= 24
+            cp = ctypes.c_void_p(int(counters.data_ptr()))
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(lib().tigas_render_noalloc(scene.handle, ctypes.byref(pose_c(pose)), ctypes.byref(intr_c(intr)),
+                                          int(width), int(height), ctypes.byref(q), ctypes.byref(fr), cp, st))
 
     def wait(self, ticket: int) -> dict:
         """Wait for a submitted frame; its stats plus ``gpu_ms``."""
