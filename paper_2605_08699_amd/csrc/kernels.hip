@@ -1018,6 +1018,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const int seg = pass_segment(D, nb, (int)blockIdx.x);
     segment(D, nb, seg, &beg, &end);
     base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + seg] : 0u;
+    // the keys of the next chunk are loaded while the current one is ranked
+    uint32_t nk[ROUNDS], nv[ROUNDS], ne[ROUNDS];
+    auto load_chunk = [&](uint32_t c) {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const uint32_t idx = c + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
+            const uint32_t ic = idx < end ? idx : c;  // clamped: loads never depend on a branch
+            nk[r] = skey[ic];
+            nv[r] = sval[ic];
+            ne[r] = EXTRA ? sext[ic] : 0u;
+        }
+    };
+    if (beg < end) load_chunk(beg);
     for (uint32_t chunk = beg; chunk < end; chunk += SORT_CHUNK) {
 #pragma unroll
         for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
@@ -1027,14 +1040,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
         bool ok[ROUNDS];
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
+            ek[r] = nk[r];
+            ev[r] = nv[r];
+            ee[r] = ne[r];
+        }
+        if (chunk + SORT_CHUNK < end) load_chunk(chunk + SORT_CHUNK);
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
             const uint32_t idx = chunk + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
             ok[r] = idx < end;
-            const uint32_t ic = ok[r] ? idx : chunk;  // clamped: loads never depend on a branch
-            const uint32_t key = skey[ic];
-            ev[r] = sval[ic];
-            ee[r] = EXTRA ? sext[ic] : 0u;
+            const uint32_t key = ek[r];
             if constexpr (SUMS) er[r] = rsrc[ev[r]];
-            ek[r] = key;
             const uint32_t d = (key >> shift) & mask;
             dig[r] = d;
             uint64_t m = ballot(ok[r]);
