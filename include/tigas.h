@@ -303,7 +303,7 @@ typedef struct {
                           creation; 0 = unlimited (workspaces grow on demand) */
     int supersede;     /* 1: a client's newer request replaces its request still waiting (latest pose wins) */
     int tile_w, tile_h, batch_depth; /* 0 = 16x32 tiles, depth 64 */
-    int pixels_per_lane;             /* 0 = 2 for tiles 16 or more tall */
+    int pixels_per_lane;             /* 1 or 2 (tiles 16 or more tall); 0 = 1 */
     int64_t max_batch_pixels; /* output pixels per batch (bounds a batch's duration); 0 = no cap */
 } tigas_server_config;
 

@@ -2396,7 +2396,8 @@ tigas_status tigas_server_create(tigas_context* ctx, const tigas_server_config* 
         q.batch_depth = sv->cfg.batch_depth;
         const TileCfg tc = tile_cfg(&q);
         sv->cfg.batch_depth = tc.bd;
-        if (sv->cfg.pixels_per_lane == 0) sv->cfg.pixels_per_lane = tc.th >= 16 ? 2 : 1;
+        // one pixel per lane: the faster blend for the mixed batches of the serving load
+        if (sv->cfg.pixels_per_lane == 0) sv->cfg.pixels_per_lane = 1;
         sv->t0 = std::chrono::steady_clock::now();
         for (int i = 0; i < sv->cfg.slots; ++i) {
             std::unique_ptr<tigas_server::Slot> sl(new tigas_server::Slot());

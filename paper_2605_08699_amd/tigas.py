@@ -538,10 +538,10 @@ class Server:
     """Continuous-batching request loop of the library (tigas_server_*)."""
 
     def __init__(self, ctx: Context, slots=2, max_batch=64, hbm_budget=0, supersede=False, tile=(16, 32),
-                 batch_depth=64, max_batch_pixels=0):
+                 batch_depth=64, max_batch_pixels=0, ppl=0):
         L = _server_lib()
         cfg = ServerConfigC(int(slots), int(max_batch), int(hbm_budget), 1 if supersede else 0, int(tile[0]),
-                            int(tile[1]), int(batch_depth), 0, int(max_batch_pixels))
+                            int(tile[1]), int(batch_depth), int(ppl), int(max_batch_pixels))
         h = ctypes.c_void_p()
         _check(L.tigas_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
