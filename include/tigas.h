@@ -257,6 +257,16 @@ tigas_status tigas_set_graphs(tigas_context* ctx, int enable);
  * (environment TIGAS_TILE_BIN=0 at context creation), by radix passes over the
  * emitted duplicates.  The sorted lists are identical either way. */
 tigas_status tigas_set_tile_binning(tigas_context* ctx, int enable);
+/* Tighter tile culling: a (Gaussian, tile) entry of the tile lists is
+ * emitted only when the Gaussian's exponent can reach the skip threshold at
+ * one of the tile's pixel centres (the exact maximum of the concave quadratic
+ * over the tile's pixel rectangle, with the blend's rounding margin), not for
+ * every tile of its bounding rectangle.  Fewer entries to sort and stage;
+ * frames are identical (a dropped entry is one every pixel of its tile would
+ * skip).  Off by default (environment TIGAS_TILE_CULL=1 at context creation
+ * turns it on); while on, single views use the radix tile passes, since the
+ * counting placement needs whole rectangles. */
+tigas_status tigas_set_tile_culling(tigas_context* ctx, int enable);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 
 /* Kernel timing with HIP events recorded on the rendering stream around every

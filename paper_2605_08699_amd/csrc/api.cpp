@@ -472,6 +472,7 @@ struct tigas_context {
     std::atomic<bool> use_graphs{true};
     std::atomic<bool> blend_cull{true};     // blend: per-block threshold culling
     std::atomic<bool> tile_bin{true};       // single view: tile digit placed by counting
+    std::atomic<bool> tile_cull{false};     // duplicates only for tiles each Gaussian can reach
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
     std::mutex tune_mu;
@@ -725,13 +726,22 @@ void prepare(Workspace& ws, const Plan& plan, bool debug) {
 //   -> duplicate in depth order -> tile passes (duplicates) -> ranges -> blend
 // Per-context switches that change the launch sequence (not its results).
 struct LaunchOptions {
-    bool cull = true;  // blend: per-block threshold culling of list entries
-    bool bin = true;   // single view: tile digit placed by counting (else radix passes over the duplicates)
+    bool cull = true;         // blend: per-block threshold culling of list entries
+    bool bin = true;          // single view: tile digit placed by counting (else radix passes over the duplicates)
+    bool cull_tiles = false;  // duplicates only for tiles the Gaussian can reach (radix passes then)
 };
+
+// Whether every view's tile rectangles fit the packed one-word form.
+bool packed_rects(const Plan& plan) {
+    bool packed = true;
+    for (const ViewParams& v : plan.views) packed = packed && v.tiles_x <= 256 && v.tiles_y <= 256;
+    return packed;
+}
 
 // Whether the plan's tile digit is placed by counting.
 bool use_bin(const Plan& plan, const LaunchOptions& opt) {
-    return opt.bin && plan.views.size() == 1 && plan.views[0].tiles_x <= 256 && plan.views[0].tiles_y <= 256 &&
+    return opt.bin && !(opt.cull_tiles && packed_rects(plan)) && plan.views.size() == 1 &&
+           plan.views[0].tiles_x <= 256 && plan.views[0].tiles_y <= 256 &&
            bin_fits(plan.views[0].tiles_x, plan.views[0].tiles_y);
 }
 
@@ -777,14 +787,17 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
     // depth digits, on the visible Gaussians (record order in, depth order
     // out); the tile rectangles travel packed with them when every view has
     // at most 256 x 256 tiles, else the last pass gathers them
-    bool packed = true;
-    for (const ViewParams& v : plan.views) packed = packed && v.tiles_x <= 256 && v.tiles_y <= 256;
-    launch_compact(o, nblk, m.blk_off, sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, st);
+    const bool packed = packed_rects(plan);
+    launch_compact(o, nblk, m.blk_off, sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, vdev, st);
     const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, m.dup_cap, sort_blocks(plan.nrec), 0, packed, cnt,
                                packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
     const int cd = cv ^ 1;
     const bool bin = use_bin(plan, opt);
-    if (!bin || debug) {
+    if (!bin && opt.cull_tiles && packed) {
+        // duplicates in depth order, only for the tiles each Gaussian can reach
+        launch_duplicate_culled(o, nblk, sb.val[cv], sb.ext[cv], m.blk_sum2, m.blk_off2, cnt, vdev, plan.tc.tw,
+                                plan.tc.th, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
+    } else if (!bin || debug) {
         // duplicates in depth order (kept for inspection only when binning)
         launch_duplicate(o, nblk, sb.val[cv], o.srect, packed ? sb.ext[cv] : nullptr, m.blk_sum2, m.blk_off2, cnt,
                          m.dup_cap, vdev, sb.key[cd], sb.val[cd], debug ? sb.ext[cd] : nullptr, st);
@@ -824,6 +837,7 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
 bool plan_binned(tigas_context* ctx, const Plan& plan) {
     LaunchOptions opt;
     opt.bin = ctx->tile_bin.load();
+    opt.cull_tiles = ctx->tile_cull.load();
     return use_bin(plan, opt);
 }
 
@@ -840,6 +854,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     LaunchOptions opt;
     opt.cull = ctx->blend_cull.load();
     opt.bin = ctx->tile_bin.load();
+    opt.cull_tiles = ctx->tile_cull.load();
     const bool kprof = ctx->profile_kernels.load();
     const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof && !kprof;
     if (kprof) {
@@ -848,7 +863,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
         return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
     }
     if (!graph) return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
-    const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") + (opt.bin ? "b1" : "b0") +
+    const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") + (opt.bin ? "b1" : "b0") + (opt.cull_tiles ? "t1" : "t0") +
                             (ws.active ? "f1" : "f0");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
@@ -1368,6 +1383,7 @@ void render_noalloc(tigas_scene* scene, const tigas_pose* pose, const tigas_intr
     LaunchOptions opt;
     opt.cull = ctx->blend_cull.load();
     opt.bin = ctx->tile_bin.load();
+    opt.cull_tiles = ctx->tile_cull.load();
     (void)enqueue(m, plan, false, false, nullptr, 0, opt);
 }
 
@@ -2016,6 +2032,7 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         if (const char* g = std::getenv("TIGAS_GRAPHS")) c->use_graphs.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_BLEND_CULL")) c->blend_cull.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_TILE_BIN")) c->tile_bin.store(std::atoi(g) != 0);
+        if (const char* g = std::getenv("TIGAS_TILE_CULL")) c->tile_cull.store(std::atoi(g) != 0);
         load_tune_file(c.get());
         *out = c.release();
     });
@@ -2265,6 +2282,13 @@ tigas_status tigas_set_tile_binning(tigas_context* ctx, int enable) {
     return guard([&] {
         if (!ctx) fail(TIGAS_E_INVALID, "null context");
         ctx->tile_bin.store(enable != 0);
+    });
+}
+
+tigas_status tigas_set_tile_culling(tigas_context* ctx, int enable) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        ctx->tile_cull.store(enable != 0);
     });
 }
 

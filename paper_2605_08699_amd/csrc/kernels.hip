@@ -7,7 +7,8 @@
 //                  exclusive scans of per-block counts (chunk totals, then
 //                  each chunk; wave64 DPP scans)
 //   k_compact      visible Gaussians as (depth key, record, packed tile
-//                  rectangle) triples
+//                  rectangle) triples; the FP64 conics of the near-singular
+//                  Gaussians
 //   k_sort_*       LSD radix sort passes, 8-bit digits, reduce-then-scan,
 //                  LDS-atomic digit counts, ballot/mbcnt ranking inside a
 //                  wave, DPP scans; the depth digits of the (tile | depth)
@@ -15,8 +16,10 @@
 //                  duplication, the tile digits on the duplicates after it
 //   k_sorted_sums  tile counts per 256 depth-ordered Gaussians
 //   k_duplicate    one (tile | depth) key per (Gaussian, overlapped tile)
-//   k_ranges       [start, end) of every tile in the sorted list, and the
-//                  FP64 conics of the near-singular Gaussians
+//   k_duplicate_culled
+//                  the same, keeping only the tiles where the Gaussian can
+//                  reach the skip threshold at some pixel (count, then emit)
+//   k_ranges       [start, end) of every tile in the sorted list
 //   k_bin_*        single views: the tile digit placed by counting instead
 //                  (per-block tile histograms from 2D difference grids, their
 //                  prefixes, then every (Gaussian, tile) entry written straight
@@ -203,6 +206,8 @@ __device__ __forceinline__ void sh_colour(const float* k, float x, float y, floa
 constexpr float NEAR_Z = 0.2f;
 constexpr float DILATION = 0.3f;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
+// log2(1/255): below it, 2^e < 1/255 and a Gaussian is skipped at the pixel.
+constexpr float LOG2_ALPHA_MIN = -7.99435343685886f;
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN255 = 5.5412635451584258f;
 constexpr float KAPPA_INV = 1.0f / 64.0f;  // FP64 fallback when a*c > 64 det
@@ -672,13 +677,23 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
 // Emission offsets: exclusive scan of the duplicate counts of the
 // depth-sorted visible Gaussians, per 256-element block (second kernel of the
 // chunked scan).
+// With `cnt`, workgroup 0 also stores the sum of the counts as the frame's
+// duplicate count D (the count once tiles are culled), unless the frame
+// overflowed: D then keeps the whole rectangles' count the buffers are grown to.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_dups(const uint32_t* __restrict__ blk_sum, int nblk,
                                                             const uint32_t* __restrict__ tot,
-                                                            uint32_t* __restrict__ blk_off) {
+                                                            uint32_t* __restrict__ blk_off, int nchunks,
+                                                            Counters* cnt) {
     __shared__ uint32_t red[SCAN_THREADS / 64];
     __shared__ unsigned long long red64[SCAN_THREADS / 64];
     __shared__ uint32_t stage[SCAN_STAGE];
     scan_chunk(blk_sum, nblk, tot, blk_off, red, red64, stage);
+    if (cnt && blockIdx.x == 0) {
+        uint64_t D = 0;
+        for (int c = (int)threadIdx.x; c < nchunks; c += SCAN_THREADS) D += tot[c];
+        D = block_sum_u64(D, red64);
+        if (threadIdx.x == 0 && !cnt->overflow) cnt->D = (uint32_t)min(D, 0xffffffffull);
+    }
 }
 
 // Tile rectangle (tx0 | ty0 << 16, nx | ny << 16) packed into one word as
@@ -701,8 +716,16 @@ __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restri
                                                         const uint2* __restrict__ rect,
                                                         const uint32_t* __restrict__ blk_off, int nblk,
                                                         uint32_t* __restrict__ key, uint32_t* __restrict__ val,
-                                                        uint32_t* __restrict__ ext) {
+                                                        uint32_t* __restrict__ ext, const Counters* __restrict__ cnt,
+                                                        const uint2* __restrict__ fb_list, uint32_t fb_cap,
+                                                        const ViewParams* __restrict__ views,
+                                                        const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
     __shared__ uint32_t red[K1_THREADS / 64];
+    // the FP64 conics of the near-singular Gaussians (a few hundred per
+    // frame), before anything reads the exponent coefficients
+    const uint32_t nfb = min(cnt->fb_listed, fb_cap);
+    for (uint32_t k = blockIdx.x * K1_THREADS + threadIdx.x; k < nfb; k += gridDim.x * K1_THREADS)
+        conic_fp64(fb_list[k], views, blk_view, recs);
     const uint32_t nrec = (uint32_t)nblk * K1_THREADS;  // a multiple of 4
     const uint32_t r0 = (blockIdx.x * K1_THREADS + threadIdx.x) * 4u;
     uint4 z = make_uint4(0u, 0u, 0u, 0u), ra = z, rb = z;
@@ -731,8 +754,11 @@ __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restri
     }
 }
 
-// Tiles in a tile rectangle (tx0 | ty0 << 16, nx | ny << 16).
+// Tiles in a tile rectangle (tx0 | ty0 << 16, nx | ny << 16), and in a packed one.
 __device__ __forceinline__ uint32_t rect_tiles(uint2 r) { return (r.y & 0xffffu) * (r.y >> 16); }
+__device__ __forceinline__ uint32_t rect_count(uint32_t p) {
+    return (((p >> 16) & 0xffu) - (p & 0xffu) + 1u) * ((p >> 24) - ((p >> 8) & 0xffu) + 1u);
+}
 
 // Per 256 depth-sorted visible Gaussians: the sum of their tile counts (zero
 // past the visible count); workgroups stride over the nblk blocks.  The
@@ -851,6 +877,136 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate(const uint32_t* __rest
         val_out[base + j] = r;
         if (DEPTH) depth_out[base + j] = zkey[r];
     }
+}
+
+
+// ------------------------------------------------- tighter tile culling
+// Whether a Gaussian can reach the skip threshold (alpha >= 1/255) at some
+// pixel centre of a tile: the exact maximum of its exponent
+// e(d) = A dx^2 + B dx dy + C dy^2 + L over the rectangle of the tile's pixel
+// centres inside the frame (as in the blend's block test: the centre when it
+// lies inside, else the better of the two faces facing it, each maximised at a
+// clamped stationary point), compared with the threshold less the blend's
+// margin, so a dropped tile is one every pixel of it would skip.  Plain FP32
+// operations only (IEEE division, no fused or approximate ones), in this
+// order, so a CPU reference reproduces every decision bit for bit.
+// (ox, oy): the tile's pixel origin; (cw, ch): its pixels inside the frame.
+__device__ __forceinline__ bool tile_reaches(float uhi, float vhi, float ulo, float vlo, float A, float B, float C,
+                                             float L, float ox, float oy, float cw, float ch) {
+    const float u = (uhi - ox) + ulo, v = (vhi - oy) + vlo;
+    const float dx0 = 0.5f - u, dx1 = (cw - 0.5f) - u;
+    const float dy0 = 0.5f - v, dy1 = (ch - 0.5f) - v;
+    if (!(A < 0.0f && C < 0.0f && B * B < (4.0f * A) * C)) return true;  // not concave: keep it
+    float q = 0.0f;
+    if (!(dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f)) {
+        const float cx = dx1 < 0.0f ? dx1 : dx0;
+        const float sy = fminf(fmaxf((-B * cx) / (2.0f * C), dy0), dy1);
+        const float ex = (A * cx + B * sy) * cx + (C * sy) * sy;
+        const float cy = dy1 < 0.0f ? dy1 : dy0;
+        const float sx = fminf(fmaxf((-B * cy) / (2.0f * A), dx0), dx1);
+        const float ey = (C * cy + B * sx) * cy + (A * sx) * sx;
+        q = fmaxf(ex, ey);
+    }
+    const float r2 = fmaxf(dx0 * dx0, dx1 * dx1) + fmaxf(dy0 * dy0, dy1 * dy1);
+    const float margin = 0.02f + (1e-5f * ((fabsf(A) + fabsf(B)) + fabsf(C))) * r2;
+    return !(q + L < LOG2_ALPHA_MIN - margin);  // keeps NaN
+}
+
+// The tile-culled duplicates: the same enumeration of (Gaussian, tile in its
+// rectangle) slots as k_duplicate, each kept only when tile_reaches says so.
+// COUNT: per block of 256 depth-ordered Gaussians, the number of kept entries
+// (block_cnt).  Otherwise the kept entries are written in slot order,
+// compacted, from the block's offset (blk_off, the exclusive scan of the
+// counts).  The records already hold the FP64 conics of the near-singular
+// Gaussians (patched by k_compact), so both launches test the final
+// coefficients.
+template <bool COUNT, bool DEPTH>
+__global__ __launch_bounds__(K1_THREADS) void k_duplicate_culled(
+    const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ sorted_packed,
+    const uint32_t* __restrict__ zkey, const uint32_t* __restrict__ blk_off, uint32_t* __restrict__ block_cnt,
+    const uint32_t* __restrict__ blk_view, const Counters* __restrict__ cnt, const ViewParams* __restrict__ views,
+    const Rec* __restrict__ recs, int tile_w, int tile_h, uint32_t* __restrict__ tile_out,
+    uint32_t* __restrict__ val_out, uint32_t* __restrict__ depth_out) {
+    __shared__ uint32_t red[K1_THREADS / 64];
+    __shared__ uint32_t pre[K1_THREADS + 1];
+    __shared__ uint32_t srec[K1_THREADS], spk[K1_THREADS], stb[K1_THREADS], swh[K1_THREADS];
+    __shared__ float4 sr0[K1_THREADS], sr1[K1_THREADS];
+    __shared__ uint32_t own[K1_THREADS];
+    __shared__ uint32_t wmax[K1_THREADS / 64];
+    const uint32_t i = blockIdx.x * K1_THREADS + threadIdx.x;
+    const uint32_t V = cnt->visible;
+    uint32_t rec = 0, p = 0, t = 0;
+    if (i < V) {
+        rec = sorted_rec[i];
+        p = sorted_packed[i];
+        t = rect_count(p);
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<K1_THREADS>(t, red, &tot);
+    if (!COUNT && (cnt->overflow || tot == 0)) return;  // uniform across the workgroup
+    pre[threadIdx.x + 1] = ex + t;
+    if (threadIdx.x == 0) pre[0] = 0;
+    own[threadIdx.x] = 0u;
+    srec[threadIdx.x] = rec;
+    spk[threadIdx.x] = p;
+    if (t) {
+        const ViewParams& v = views[blk_view[rec / K1_THREADS]];
+        stb[threadIdx.x] = v.tile_base;
+        swh[threadIdx.x] = (uint32_t)v.width | ((uint32_t)v.height << 16);
+        sr0[threadIdx.x] = recs[rec].r0;
+        sr1[threadIdx.x] = recs[rec].r1;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t base = COUNT ? 0u : blk_off[blockIdx.x];
+    uint32_t kept_before = 0;  // kept entries of this block in earlier rounds
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0, m = 0; j0 < tot; j0 += K1_THREADS, ++m) {
+        if (t && (ex >> 8) == m) own[ex & (K1_THREADS - 1)] = (m << 8) | threadIdx.x;
+        __syncthreads();
+        const uint32_t incl = wave_incl_max(own[threadIdx.x]);
+        if (lane == 63) wmax[w] = incl;
+        __syncthreads();
+        uint32_t o = max(incl, (m << 8) | carry), all = (m << 8) | carry;
+#pragma unroll
+        for (uint32_t vv = 0; vv < K1_THREADS / 64; ++vv) {
+            const uint32_t x = wmax[vv];
+            if (vv < w) o = max(o, x);
+            all = max(all, x);
+        }
+        carry = all & 0xffu;
+        const uint32_t j = j0 + threadIdx.x;
+        bool keep = false;
+        uint32_t tile = 0, r = 0;
+        if (j < tot) {
+            const uint32_t e = o & 0xffu;
+            const uint32_t k = j - pre[e];
+            const uint32_t pk = spk[e];
+            const uint32_t x0 = pk & 0xffu, y0 = (pk >> 8) & 0xffu;
+            const uint32_t nx = ((pk >> 16) & 0xffu) - x0 + 1u;
+            const uint32_t q = k / nx;
+            const uint32_t ty = y0 + q, tx = x0 + (k - q * nx);
+            const uint32_t wh = swh[e];
+            const int W = (int)(wh & 0xffffu), H = (int)(wh >> 16);
+            const int px = (int)tx * tile_w, py = (int)ty * tile_h;
+            const float4 a = sr0[e], c = sr1[e];
+            keep = tile_reaches(a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w, (float)px, (float)py,
+                                (float)min(tile_w, W - px), (float)min(tile_h, H - py));
+            const int tiles_x = (W + tile_w - 1) / tile_w;
+            tile = stb[e] + ty * (uint32_t)tiles_x + tx;
+            r = srec[e];
+        }
+        uint32_t kept_round;
+        const uint32_t kex = block_excl_scan<K1_THREADS>(keep ? 1u : 0u, red, &kept_round);
+        if (!COUNT && keep) {
+            const uint32_t pos = base + kept_before + kex;
+            tile_out[pos] = tile;
+            val_out[pos] = r;
+            if (DEPTH) depth_out[pos] = zkey[r];
+        }
+        kept_before += kept_round;
+    }
+    if (COUNT && threadIdx.x == 0) block_cnt[blockIdx.x] = kept_before;
 }
 
 // ------------------------------------------------------------- radix sort
@@ -1116,10 +1272,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
 // are final here: one thread also stores them to the host-visible block the
 // host reads after the frame (no separate copy).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tile, const Counters* __restrict__ cnt,
-                                                uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt,
-                                                const uint2* __restrict__ fb_list, uint32_t fb_cap,
-                                                const ViewParams* __restrict__ views,
-                                                const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
+                                                uint32_t cap, uint2* __restrict__ ranges, Counters* host_cnt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t D = sort_count(cnt, 0, cap);
     // each wave takes 256 consecutive words per step, four per lane (one
@@ -1151,10 +1304,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ til
             }
         }
     }
-    // the FP64 conics of the near-singular Gaussians (a few hundred per frame)
-    const uint32_t nfb = min(cnt->fb_listed, fb_cap);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nfb; i += gridDim.x * 256)
-        conic_fp64(fb_list[i], views, blk_view, recs);
 }
 
 // ---------------------------------------------------- binned tile digit
@@ -1246,10 +1395,6 @@ __device__ __forceinline__ void grid_add_rects(uint32_t* g, int w1, int tiles_x,
 
 __device__ __forceinline__ uint32_t bin_valid(const Counters* cnt) { return cnt->overflow ? 0u : cnt->visible; }
 
-__device__ __forceinline__ uint32_t rect_count(uint32_t p) {
-    return (((p >> 16) & 0xffu) - (p & 0xffu) + 1u) * ((p >> 24) - ((p >> 8) & 0xffu) + 1u);
-}
-
 // tile id -> (tx, ty) with the FP32 reciprocal of tiles_x, corrected to the
 // exact quotient
 __device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, float inv_tx, uint32_t* tx, uint32_t* ty) {
@@ -1262,21 +1407,13 @@ __device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, float inv_
 
 // Per block of BIN_BLOCK depth-ordered Gaussians: how many of their
 // rectangles hold each tile, and the entry count of each of its rounds of
-// 256 Gaussians.  The same launch recomputes, in FP64, the conic of every
-// Gaussian preprocess listed as near-singular (nothing reads those
-// coefficients before the blend).
+// 256 Gaussians.
 __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ packed, const Counters* __restrict__ cnt,
                                                   int tiles_x, int tiles_y, uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ round_cnt,
-                                                  const uint2* __restrict__ fb_list, uint32_t fb_cap,
-                                                  const ViewParams* __restrict__ views,
-                                                  const uint32_t* __restrict__ blk_view, Rec* __restrict__ recs) {
+                                                  uint32_t* __restrict__ round_cnt) {
     static_assert(BIN_BLOCK == 8 * 256, "a block is eight rounds of 256");
     __shared__ uint32_t g[BIN_GRID_MAX];
     __shared__ uint32_t wsum[8][4];
-    const uint32_t nfb = min(cnt->fb_listed, fb_cap);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nfb; i += gridDim.x * 256)
-        conic_fp64(fb_list[i], views, blk_view, recs);
     const uint32_t V = bin_valid(cnt);
     const uint32_t b0 = blockIdx.x * BIN_BLOCK;
     if (b0 >= V) return;  // uniform
@@ -1723,8 +1860,6 @@ struct Stage {
     float2 c[64 * BD];  // b, v_rel1
 };
 
-// log2(1/255): below it, 2^e < 1/255 and a Gaussian is skipped at the pixel.
-constexpr float LOG2_ALPHA_MIN = -7.99435343685886f;
 
 // Does the Gaussian with exponent e(d) = A dx^2 + B dx dy + C dy^2 + L
 // (negative-definite quadratic part) stay below the skip threshold on the
@@ -2105,10 +2240,11 @@ void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters*
 }
 
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, uint32_t* ext,
-                    hipStream_t st) {
+                    const ViewParams* views_dev, hipStream_t st) {
     if (nblk == 0) return;
     TIGAS_LAUNCH(k_compact, dim3((nblk + 3) / 4), dim3(K1_THREADS), st, o.zkey, (const uint2*)o.rect,
-                 blk_off, nblk, key, val, ext);
+                 blk_off, nblk, key, val, ext, (const Counters*)o.cnt, (const uint2*)o.fb_list, o.fb_cap, views_dev,
+                 (const uint32_t*)o.blk_view, o.rec);
 }
 
 void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
@@ -2124,13 +2260,39 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
                  (const uint32_t*)nullptr, (const uint32_t*)nullptr, o.chunk_dups, (unsigned long long*)nullptr,
                  (uint32_t*)nullptr);
     TIGAS_LAUNCH(k_scan_dups, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_sum2, nblk,
-                 (const uint32_t*)o.chunk_dups, blk_off2);
+                 (const uint32_t*)o.chunk_dups, blk_off2, nchunks, (Counters*)nullptr);
     if (depth_out)
         TIGAS_LAUNCH(k_duplicate<true>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect, sorted_packed,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
     else
         TIGAS_LAUNCH(k_duplicate<false>, dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_rect, sorted_packed,
                      o.zkey, (const uint32_t*)blk_off2, o.blk_view, cnt, cap, views_dev, tile_out, val_out, depth_out);
+}
+
+void launch_duplicate_culled(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint32_t* sorted_packed,
+                             uint32_t* blk_cnt, uint32_t* blk_off, Counters* cnt, const ViewParams* views_dev,
+                             int tile_w, int tile_h, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
+                             hipStream_t st) {
+    if (nblk == 0) return;
+    TIGAS_LAUNCH((k_duplicate_culled<true, false>), dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_packed,
+                 o.zkey, (const uint32_t*)nullptr, blk_cnt, (const uint32_t*)o.blk_view, (const Counters*)cnt,
+                 views_dev, (const Rec*)o.rec, tile_w, tile_h, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                 (uint32_t*)nullptr);
+    const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_cnt, nblk,
+                 (const uint32_t*)nullptr, (const uint32_t*)nullptr, o.chunk_dups, (unsigned long long*)nullptr,
+                 (uint32_t*)nullptr);
+    // the kept count becomes the frame's duplicate count D
+    TIGAS_LAUNCH(k_scan_dups, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)blk_cnt, nblk,
+                 (const uint32_t*)o.chunk_dups, blk_off, nchunks, cnt);
+    if (depth_out)
+        TIGAS_LAUNCH((k_duplicate_culled<false, true>), dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_packed,
+                     o.zkey, (const uint32_t*)blk_off, blk_cnt, (const uint32_t*)o.blk_view, (const Counters*)cnt,
+                     views_dev, (const Rec*)o.rec, tile_w, tile_h, tile_out, val_out, depth_out);
+    else
+        TIGAS_LAUNCH((k_duplicate_culled<false, false>), dim3(nblk), dim3(K1_THREADS), st, sorted_rec, sorted_packed,
+                     o.zkey, (const uint32_t*)blk_off, blk_cnt, (const uint32_t*)o.blk_view, (const Counters*)cnt,
+                     views_dev, (const Rec*)o.rec, tile_w, tile_h, tile_out, val_out, depth_out);
 }
 
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
@@ -2169,8 +2331,7 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
     // than a large frame needs (the capacity may have been sized by a much
     // larger frame)
     TIGAS_LAUNCH(k_ranges, dim3(std::min<uint32_t>(16384u, std::max<uint32_t>(1u, (cap + 1023) / 1024))), dim3(256), st,
-                 tile_sorted, cnt, cap, ranges, host_cnt, (const uint2*)o.fb_list, o.fb_cap, views_dev,
-                 (const uint32_t*)o.blk_view, o.rec);
+                 tile_sorted, cnt, cap, ranges, host_cnt);
 }
 
 uint32_t bin_emit_groups(uint32_t cap, uint32_t nrec) {
@@ -2189,8 +2350,7 @@ void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const
                 uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, hipStream_t st) {
     const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
     const uint32_t nbc = std::max<uint32_t>(1u, (nrec + BIN_BLOCK - 1) / BIN_BLOCK);
-    TIGAS_LAUNCH(k_bin_hist, dim3(nbc), dim3(256), st, sorted_packed, cnt, tiles_x, tiles_y, hist, round_cnt,
-                 (const uint2*)o.fb_list, o.fb_cap, views_dev, (const uint32_t*)o.blk_view, o.rec);
+    TIGAS_LAUNCH(k_bin_hist, dim3(nbc), dim3(256), st, sorted_packed, cnt, tiles_x, tiles_y, hist, round_cnt);
     TIGAS_LAUNCH(k_bin_prefix, dim3((n_tiles + 255) / 256, BIN_GROUPS), dim3(256), st, hist, cnt, n_tiles, gsum);
     TIGAS_LAUNCH(k_bin_groups, dim3((n_tiles + 255) / 256), dim3(256), st, gsum, cnt, n_tiles);
     // enough emission workgroups for the largest cost the capacities allow

@@ -133,8 +133,10 @@ void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters*
                          const ZeroList& zl, hipStream_t st);
 // Visible records as (depth key, record) pairs; with ext, also each one's
 // tile rectangle packed into one word (views of at most 256 x 256 tiles).
+// The same launch recomputes, in FP64, the conic of every Gaussian
+// preprocess listed as near-singular (before anything reads it).
 void launch_compact(const PreOut& o, int nblk, const uint32_t* blk_off, uint32_t* key, uint32_t* val, uint32_t* ext,
-                    hipStream_t st);
+                    const ViewParams* views_dev, hipStream_t st);
 // The depth-ordered tile rectangles come packed (sorted_packed, carried by the
 // depth passes) or, when that is null, as two words (sorted_rect).
 void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint2* sorted_rect,
@@ -142,6 +144,15 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
                       uint32_t* blk_sum2, uint32_t* blk_off2, const Counters* cnt, uint32_t cap,
                       const ViewParams* views_dev, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
                       hipStream_t st);
+// Duplicates with tighter tile culling (packed rectangles only): per
+// (Gaussian, tile of its rectangle), kept when the Gaussian can reach the
+// skip threshold at one of the tile's pixels; the kept entries in emission
+// order (blk_cnt, blk_off: per-256-Gaussian kept counts and their scan), and
+// the kept count stored as the frame's D.
+void launch_duplicate_culled(const PreOut& o, int nblk, const uint32_t* sorted_rec, const uint32_t* sorted_packed,
+                             uint32_t* blk_cnt, uint32_t* blk_off, Counters* cnt, const ViewParams* views_dev,
+                             int tile_w, int tile_h, uint32_t* tile_out, uint32_t* val_out, uint32_t* depth_out,
+                             hipStream_t st);
 // Runs LSD passes over the count selected by `which` (0 duplicates, 1 visible)
 // starting in buffer `start`; returns the buffer index holding the result.
 // With `rect_src`, the last pass also writes rect_src[value] to rect_dst in
@@ -149,17 +160,15 @@ void launch_duplicate(const PreOut& o, int nblk, const uint32_t* sorted_rec, con
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
                 int start, bool extra, const Counters* cnt, const uint2* rect_src,
                 uint2* rect_dst, hipStream_t st);
-// Tile ranges of the sorted list; the same launch recomputes, in FP64, the
-// conic of every Gaussian preprocess listed as near-singular.  host_cnt:
-// pinned host memory that receives a copy of the counters.
+// Tile ranges of the sorted list.  host_cnt: pinned host memory (or device
+// memory) that receives a copy of the counters.
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    const PreOut& o, const ViewParams* views_dev, hipStream_t st);
 // Tile placement by counting (single view, packed rectangles, a tile grid
 // that fits BIN_GRID_MAX / BIN_TILES_MAX): from the depth-ordered records and
 // packed rectangles, writes each (Gaussian, tile) entry's record id to its
 // sorted position in val_out (with tile_out/depth_out, also its tile id and
-// depth word), the tile ranges, the counters to host_cnt, and runs the FP64
-// conic fallback.  hist: ceil(nrec / BIN_BLOCK) x tiles words; gsum:
+// depth word), the tile ranges and the counters to host_cnt.  hist: ceil(nrec / BIN_BLOCK) x tiles words; gsum:
 // (BIN_GROUPS + 2) x tiles words (group rows, tile totals, tile starts) and
 // bin_emit_groups(cap, nrec) more (each emission workgroup's first round);
 // round_cnt / round_off: nrec / 256 + 1 words; cap: the entry capacity.

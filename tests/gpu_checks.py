@@ -83,13 +83,19 @@ def check_preprocess(dbg, proj, W, H):
     return err
 
 
-def check_tiles(dbg, tile_w, tile_h):
+def check_tiles(dbg, tile_w, tile_h, cull=False):
     """Keys, values and ranges byte-identical to the CPU reference built from
-    the GPU's own per-Gaussian footprints and depth keys."""
+    the GPU's own per-Gaussian footprints and depth keys (with cull, less the
+    entries the tile test drops, decided from the GPU's own exponent
+    coefficients)."""
     bbox = dbg["bbox"].astype(np.int64)
     rects, counts = tref.tile_rects(bbox, tile_w, tile_h)
     np.testing.assert_array_equal(counts, dbg["touched"].astype(np.int64))
-    keys, vals = tref.duplicates(rects, counts, dbg["zkey"], dbg["tiles_x"])
+    keep = None
+    if cull:
+        H, W = dbg["image"].shape[:2]
+        keep = tref.tile_keep(dbg["rec"], rects, counts, W, H, tile_w, tile_h)
+    keys, vals = tref.duplicates(rects, counts, dbg["zkey"], dbg["tiles_x"], keep=keep)
     assert keys.shape[0] == dbg["n_dup"]
     # the GPU emits Gaussians in depth order (its depth digits are sorted first)
     ek, ev = tref.depth_first_emission(keys, vals)

@@ -51,6 +51,31 @@ def test_batch_equals_single_renders(ctx, c2small, tile, ppl):
     s.free()
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (16, 32)])
+def test_culled_batch_equals_whole_rectangle_batch(ctx, c2small, tile):
+    """A batch of uneven views (global tile ids over several grids) with the
+    tighter tile culling: the same frames, fewer entries."""
+    scene, traj, k = c2small
+    s = ctx.load_scene(scene)
+    poses = [traj[i] for i in range(0, 64, 8)]
+    scales = [RUNGS[i % 4] for i in range(len(poses))]
+    ks = [k] * len(poses)
+    args = ([s] * len(poses), poses, ks, [1280] * len(poses), [720] * len(poses), scales)
+    full = ctx.render_batch(*args, fmt="f32", tile=tile, batch_depth=64)
+    d_full = ctx.stats()["duplicates"]
+    ctx.set_tile_culling(True)
+    try:
+        got = ctx.render_batch(*args, fmt="f32", tile=tile, batch_depth=64)
+        d_culled = ctx.stats()["duplicates"]
+    finally:
+        ctx.set_tile_culling(False)
+    _say("culled batch", tile, d_culled, "of", d_full)
+    for i in range(len(poses)):
+        np.testing.assert_array_equal(got[i], full[i], err_msg=f"view {i}")
+    assert d_culled < d_full
+    s.free()
+
+
 def test_batch_of_several_scenes_and_rgb8(ctx, c2small):
     scene, traj, k = c2small
     other = random_tiny_scene(np.random.default_rng(5), n=5000, extent=2.0, depth=(3.0, 8.0))

@@ -73,6 +73,28 @@ def test_c1_tile_lists_sort_and_ranges_bit_exact(ctx, c1, tile, binning):
     assert passes == (5 if binning else 4 + math.ceil(math.log2((W // tile[0]) * (H // tile[1])) / 8))
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 32), (32, 16)])
+def test_culled_tile_lists_bit_exact_and_frames_unchanged(ctx, c1, tile):
+    """Tighter tile culling: the lists equal the reference less exactly the
+    entries its tile test drops, fewer entries are sorted, and the frame is
+    bit-identical to the one rendered from whole rectangles."""
+    scene, poses, k, W, H = c1
+    s = ctx.load_scene(scene)
+    ctx.set_tile_culling(True)
+    try:
+        dbg = ctx.render_debug(s, poses[0], k, W, H, tile=tile)
+        culled = ctx.render(s, poses[0], k, W, H, fmt="f32", tile=tile)
+        d_culled = ctx.stats()["duplicates"]
+    finally:
+        ctx.set_tile_culling(False)
+    gc.check_tiles(dbg, *tile, cull=True)
+    full = ctx.render(s, poses[0], k, W, H, fmt="f32", tile=tile)
+    d_full = ctx.stats()["duplicates"]
+    _say("culled", tile, d_culled, "of", d_full)
+    np.testing.assert_array_equal(culled, full)
+    assert d_culled == dbg["n_dup"] and d_culled < d_full
+
+
 def test_c1_frame_matches_oracle(ctx, c1):
     scene, poses, k, W, H = c1
     s = ctx.load_scene(scene)

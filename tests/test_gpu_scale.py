@@ -100,6 +100,29 @@ def test_c3_preprocess_and_tiles_full_frame(ctx, c3):
     s.free()
 
 
+def test_c3_culled_tile_lists_full_frame_and_frames_unchanged(ctx, c3):
+    # tighter tile culling on the headline scene (near-singular splats tested
+    # with their FP64 conics): lists bit-exact against the reference's tile
+    # test, fewer entries, and the frames of three poses bit-identical
+    scene, traj, k = c3
+    s = ctx.load_scene(scene)
+    ctx.set_tile_culling(True)
+    try:
+        dbg = ctx.render_debug(s, traj[0], k, 1920, 1080, tile=(16, 32))
+        culled = [ctx.render(s, traj[i], k, 1920, 1080, fmt="f32", tile=(16, 32)) for i in (0, 150, 280)]
+        d_culled = ctx.stats()["duplicates"]
+    finally:
+        ctx.set_tile_culling(False)
+    gc.check_tiles(dbg, 16, 32, cull=True)
+    full = [ctx.render(s, traj[i], k, 1920, 1080, fmt="f32", tile=(16, 32)) for i in (0, 150, 280)]
+    d_full = ctx.stats()["duplicates"]
+    _say("c3 culled D", d_culled, "of", d_full, f"({1 - d_culled / d_full:.1%} fewer)")
+    for a, b in zip(culled, full):
+        np.testing.assert_array_equal(a, b)
+    assert d_culled < d_full
+    s.free()
+
+
 @pytest.mark.parametrize("pose_i", ANCHORS)
 def test_c3_fp32_sampled_pixels_match_oracle(ctx, c3, pose_i):
     scene, traj, k = c3
