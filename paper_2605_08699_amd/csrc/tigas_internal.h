@@ -21,7 +21,7 @@ constexpr int MAX_SORT_PASSES = 8;
 // prefix, cells of the (tiles_x + 1) x (tiles_y + 1) difference grid, tiles.
 constexpr int BIN_BLOCK = 2048;
 constexpr int BIN_PAIRS = 8192;
-constexpr int BIN_ROUND_COST = 1024;  // fixed steps of a round, in entries
+constexpr int BIN_ROUND_COST = 2048;  // fixed steps of a round, in entries
 constexpr int BIN_GROUPS = 32;
 constexpr int BIN_GRID_MAX = 8448;
 constexpr int BIN_TILES_MAX = 8192;
