@@ -62,3 +62,50 @@ def test_traffic_round_trip(tmp_path):
     assert sha == profiling.source_sha1()
     # mean fetch 200 KiB x 2 + mean write 50 KiB x 1 per launch
     assert abs(t["tigas::k_z(int)"] - (200 * 2 + 50) * 1024) < 1e-6
+
+
+def test_traffic_over_two_runs_calibrates_each_run_on_its_own_copies(tmp_path):
+    copy = "__amd_rocclr_copyBuffer"
+    n = 1 << 20
+    f1, w1, f2, w2 = (tmp_path / x for x in ("f1.csv", "w1.csv", "f2.csv", "w2.csv"))
+    # run 1 scales fetch by 2, run 2 by 4; k_z runs in both, k_a only in run 2
+    _counter_csv(f1, [(1, copy, "FETCH_SIZE", n / 1024 / 2), (2, "tigas::k_z(int)", "FETCH_SIZE", 100.0)])
+    _counter_csv(w1, [(1, copy, "WRITE_SIZE", n / 1024), (2, "tigas::k_z(int)", "WRITE_SIZE", 10.0)])
+    _counter_csv(f2, [(1, copy, "FETCH_SIZE", n / 1024 / 4), (2, "tigas::k_z(int)", "FETCH_SIZE", 100.0),
+                      (3, "tigas::k_a(int)", "FETCH_SIZE", 7.0)])
+    _counter_csv(w2, [(1, copy, "WRITE_SIZE", n / 1024), (2, "tigas::k_z(int)", "WRITE_SIZE", 30.0),
+                      (3, "tigas::k_a(int)", "WRITE_SIZE", 1.0)])
+    out = tmp_path / "t.md"
+    profiling.traffic([str(f1), str(f2)], [str(w1), str(w2)], str(out), ["fc1", "fc2"], ["wc1", "wc2"], n)
+    _sha, t = profiling.read_traffic(str(out))
+    assert abs(t["tigas::k_z(int)"] - ((100 * 2 + 100 * 4) / 2 + (10 + 30) / 2) * 1024) < 1e-6
+    assert abs(t["tigas::k_a(int)"] - (7 * 4 + 1) * 1024) < 1e-6
+    text = out.read_text()
+    assert all(c in text for c in ("fc1", "fc2", "wc1", "wc2")) and text.count("Calibration:") == 2
+
+
+def test_bandwidth_divides_bytes_by_launch_time(tmp_path):
+    copy = "__amd_rocclr_copyBuffer"
+    n = 1 << 20
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    _counter_csv(fetch, [(1, copy, "FETCH_SIZE", n / 1024), (2, "tigas::k_z(int)", "FETCH_SIZE", 1000.0)])
+    _counter_csv(write, [(1, copy, "WRITE_SIZE", n / 1024), (2, "tigas::k_z(int)", "WRITE_SIZE", 0.0)])
+    tmd = tmp_path / "t.md"
+    profiling.traffic(str(fetch), str(write), str(tmd), "fc", "wc", n)
+    stats = tmp_path / "s.csv"
+    with open(stats, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Name", "Calls", "AverageNs"])
+        w.writerow(["tigas::k_z(int)", 3, 1024.0])  # 1000 KiB in 1.024 us: 1e12 B/s
+    lds = tmp_path / "l.csv"
+    # two dispatches: (100 - 20) and (60 - 0) active cycles over the CUs
+    _counter_csv(lds, [(1, "tigas::k_z(int)", "SQ_LDS_IDX_ACTIVE", 100.0),
+                       (1, "tigas::k_z(int)", "SQ_LDS_BANK_CONFLICT", 20.0),
+                       (2, "tigas::k_z(int)", "SQ_LDS_IDX_ACTIVE", 60.0),
+                       (2, "tigas::k_z(int)", "SQ_INSTS_LDS", 5.0)])
+    out = tmp_path / "b.md"
+    profiling.bandwidth(str(tmd), [str(stats)], str(lds), str(out), "t", ["cmd"])
+    row = [l for l in out.read_text().splitlines() if l.startswith("| `tigas::k_z`")][0].split(" | ")
+    assert row[1] == "1.0" and row[3] == "1000" and row[4] == "0.125"  # 1000 GB/s of 8000
+    lds_bytes = (80 + 60) / 2 * profiling.LDS_BYTES_PER_CLOCK
+    assert abs(float(row[6]) - round(lds_bytes / 1.024e-6 / 1e9)) <= 1
