@@ -98,6 +98,26 @@ def run_variant(ctx, tigas, scene, storage, traj, k, W, H, steps, warmup, torch,
     g = np.array([r["gpu_ms"] for r in res])
     pipelined = dict(frames_per_s=steps / total, gpu_ms_p50=float(np.median(g)), gpu_ms_p99=float(np.percentile(g, 99)),
                      gpu_ms_mean=float(g.mean()))
+    # and on two streams (each with its own workspace): consecutive frames of
+    # the trajectory run concurrently, one frame's latency-bound sort launches
+    # beside the other's blend
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs2 = [out, outs[1]]
+    for j, st in enumerate(streams):  # warm each stream's workspace and graph
+        ctx.render(s, traj[0], k, W, H, out=outs2[j], stream=st.cuda_stream, **tile_kw)
+    torch.cuda.synchronize()
+    pend = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        j = i % 2
+        pend.append(ctx.render_async(s, traj[pose_index(i, steps, len(traj))], k, W, H, outs2[j],
+                                     stream=streams[j].cuda_stream, **tile_kw))
+        if len(pend) > 2:
+            ctx.wait(pend.pop(0))
+    for t in pend:
+        ctx.wait(t)
+    torch.cuda.synchronize()
+    pipelined["two_streams_frames_per_s"] = steps / (time.perf_counter() - t0)
     # the same frames again with HIP events between the stages (uncaptured launches)
     ctx.profile_stages(True)
     prof = timed("stages")
@@ -458,6 +478,10 @@ def kernel_work(name, w, n, storage, tile_passes):
     if "k_sort_downsweep<false, false>" in name:
         # the tile passes: key + value read and written per duplicate
         return "hbm", tile_passes * 16 * D
+    if "k_bin_emit" in name:
+        # depth-ordered record and packed rectangle read per visible Gaussian,
+        # one record id written per entry
+        return "hbm", V * 8 + D * 4
     return None
 
 

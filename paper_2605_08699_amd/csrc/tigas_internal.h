@@ -14,6 +14,8 @@ constexpr int SORT_MAX_BLOCKS = 4096; // workgroups per sort pass (at most)
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;  // counts per workgroup of the chunked scans
+constexpr int SCAN_ONE_CHUNKS = 4;        // visible-record scan in one workgroup up to this many chunks
+constexpr uint32_t SCAN_ONE_ZERO = 1u << 17;  // ... and this many per-frame words to clear
 constexpr int MAX_SORT_PASSES = 8;
 // Binned tile digit (single view): Gaussians per histogram block (eight
 // rounds of 256), work per emission workgroup (entries, with each round of
