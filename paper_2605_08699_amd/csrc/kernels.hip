@@ -674,69 +674,6 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible(const uint32_t* _
             zl.p[k][i] = 0u;
 }
 
-// One-workgroup form of the two launches above for up to SCAN_ONE_CHUNKS
-// chunks of per-block counts (a single view of up to 8M Gaussians): the
-// workgroup walks the chunks in order, scanning each from the running total
-// of those before it, and sums the duplicate and fallback counts on the way.
-// One launch instead of two short ones on the frame's critical path.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_visible_one(const uint32_t* __restrict__ blk_vis, int nblk,
-                                                                   const uint32_t* __restrict__ blk_dup,
-                                                                   const uint32_t* __restrict__ blk_fb,
-                                                                   uint32_t* __restrict__ blk_off, Counters* cnt,
-                                                                   uint32_t cap, ZeroList zl) {
-    __shared__ uint32_t red[SCAN_THREADS / 64];
-    __shared__ unsigned long long red64[SCAN_THREADS / 64];
-    __shared__ uint32_t stage[SCAN_STAGE];
-    uint64_t D = 0, F = 0;
-    uint32_t running = 0;
-    for (int base = 0; base < nblk; base += SCAN_CHUNK) {
-#pragma unroll
-        for (int r = 0; r < SCAN_ITEMS; ++r) {
-            const int i = r * SCAN_THREADS + (int)threadIdx.x;
-            uint32_t v = 0;
-            if (base + i < nblk) {
-                v = blk_vis[base + i];
-                D += blk_dup[base + i];
-                F += blk_fb[base + i];
-            }
-            stage[spad(i)] = v;
-        }
-        __syncthreads();
-        uint32_t loc[SCAN_ITEMS];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) {
-            loc[j] = sum;
-            sum += stage[spad((int)threadIdx.x * SCAN_ITEMS + j)];
-        }
-        uint32_t total;
-        const uint32_t ex = block_excl_scan<SCAN_THREADS>(sum, red, &total);
-#pragma unroll
-        for (int j = 0; j < SCAN_ITEMS; ++j) stage[spad((int)threadIdx.x * SCAN_ITEMS + j)] = running + ex + loc[j];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < SCAN_ITEMS; ++r) {
-            const int i = r * SCAN_THREADS + (int)threadIdx.x;
-            if (base + i < nblk) blk_off[base + i] = stage[spad(i)];
-        }
-        running += total;
-        __syncthreads();  // the next chunk reuses the stage
-    }
-    D = block_sum_u64(D, red64);
-    F = block_sum_u64(F, red64);
-    if (threadIdx.x == 0) {
-        cnt->D = D > 0xffffffffull ? 0xffffffffu : (uint32_t)D;
-        cnt->visible = running;
-        cnt->fallbacks = (uint32_t)F;
-        cnt->overflow = D > (uint64_t)cap ? 1u : 0u;
-        cnt->fb_listed = cnt->fb_list;
-        cnt->fb_list = 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < ZeroList::N; ++k)
-        for (uint32_t i = threadIdx.x; i < zl.n[k]; i += SCAN_THREADS) zl.p[k][i] = 0u;
-}
-
 // Emission offsets: exclusive scan of the duplicate counts of the
 // depth-sorted visible Gaussians, per 256-element block (second kernel of the
 // chunked scan).
@@ -2295,13 +2232,6 @@ void launch_fill_u32(uint32_t* p, uint32_t n, uint32_t value, hipStream_t st) {
 void launch_scan_visible(const PreOut& o, int nblk, uint32_t* blk_off, Counters* cnt, uint32_t cap,
                          const ZeroList& zl, hipStream_t st) {
     const int nchunks = std::max(1, (nblk + SCAN_CHUNK - 1) / SCAN_CHUNK);
-    uint64_t zero_words = 0;
-    for (int k = 0; k < ZeroList::N; ++k) zero_words += zl.n[k];
-    if (nchunks <= SCAN_ONE_CHUNKS && zero_words <= SCAN_ONE_ZERO) {
-        TIGAS_LAUNCH(k_scan_visible_one, dim3(1), dim3(SCAN_THREADS), st, (const uint32_t*)o.blk_vis, nblk,
-                     (const uint32_t*)o.blk_sum, (const uint32_t*)o.blk_fb, blk_off, cnt, cap, zl);
-        return;
-    }
     TIGAS_LAUNCH(k_chunk_totals, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)o.blk_vis, nblk,
                  (const uint32_t*)o.blk_sum, (const uint32_t*)o.blk_fb, o.chunk_vis, o.chunk_dup, o.chunk_fb);
     TIGAS_LAUNCH(k_scan_visible, dim3(nchunks), dim3(SCAN_THREADS), st, (const uint32_t*)o.blk_vis, nblk,

@@ -11,11 +11,12 @@ constexpr int K1_THREADS = 256;       // one Gaussian per thread in preprocess /
 constexpr int SORT_THREADS = 256;     // 4 wave64 per sort workgroup
 constexpr int SORT_CHUNK = 2048;      // keys ranked per workgroup step (4 waves x 8 rounds x 64)
 constexpr int SORT_MAX_BLOCKS = 4096; // workgroups per sort pass (at most)
-constexpr int SCAN_THREADS = 1024;
-constexpr int SCAN_ITEMS = 8;
+// Chunked scans of per-block counts: one count per thread, so that many short
+// workgroups (on many compute units) read in parallel the counts that the
+// previous kernel's workgroups on every XCD just wrote.
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 1;
 constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;  // counts per workgroup of the chunked scans
-constexpr int SCAN_ONE_CHUNKS = 4;        // visible-record scan in one workgroup up to this many chunks
-constexpr uint32_t SCAN_ONE_ZERO = 1u << 17;  // ... and this many per-frame words to clear
 constexpr int MAX_SORT_PASSES = 8;
 // Binned tile digit (single view): Gaussians per histogram block (eight
 // rounds of 256), work per emission workgroup (entries, with each round of
