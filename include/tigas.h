@@ -267,6 +267,17 @@ tigas_status tigas_set_tile_binning(tigas_context* ctx, int enable);
  * turns it on); while on, single views use the radix tile passes, since the
  * counting placement needs whole rectangles. */
 tigas_status tigas_set_tile_culling(tigas_context* ctx, int enable);
+/* Depth order of the visible Gaussians (the depth digits of the radix sort,
+ * Sections 4.1 and 5.1): passes = 3 (the default) sorts the FP32 depth bits
+ * less the frame's smallest visible depth key in three passes of 9-bit
+ * digits when those keys span less than 2^27 (depths within about 16
+ * octaves) and every view has at most 256 x 256 tiles; a frame whose keys
+ * span more is detected on the GPU, rendered again with four passes, and the
+ * context keeps four passes from then on (counted in tigas_stats.rerenders).
+ * passes = 4 always takes four 8-bit passes of the whole key (environment
+ * TIGAS_DEPTH_PASSES=4 at context creation).  The order, and so every frame,
+ * is identical either way.  E_INVALID for another value. */
+tigas_status tigas_set_depth_passes(tigas_context* ctx, int passes);
 tigas_status tigas_stage_times(tigas_context* ctx, tigas_stage_ms* out);
 
 /* Kernel timing with HIP events recorded on the rendering stream around every

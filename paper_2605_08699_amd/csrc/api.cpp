@@ -296,6 +296,8 @@ struct FrameMem {
     uint32_t* ext[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;      // digit counts per sort segment
     uint32_t* hist_pre = nullptr;  // segment digit prefixes
+    uint32_t* zr = nullptr;        // three-pass depth sort: key range and per-segment ranges
+    uint32_t* segmm = nullptr;     //   (null: the four-pass depth sort only)
     uint32_t* queue = nullptr;
     uint2* ranges = nullptr;
     uint32_t* bin_hist = nullptr;  // binned tile digit: block histograms, group starts
@@ -321,7 +323,7 @@ struct Workspace {
     DevBuf counters;
     // per duplicate (also holds the visible Gaussians during the depth passes)
     DevBuf key[2], val[2], ext[2];
-    DevBuf hist, queue;
+    DevBuf hist, queue, sortrange;
     // emission-order copies for the inspection entry point
     DevBuf dbg_key, dbg_val, dbg_ext;
     // per tile / per view
@@ -359,7 +361,9 @@ struct Workspace {
             m.ext[i] = ext[i].as<uint32_t>();
         }
         m.hist = hist.as<uint32_t>();
-        m.hist_pre = m.hist + (size_t)256 * SORT_MAX_BLOCKS;
+        m.hist_pre = m.hist + (size_t)512 * SORT_MAX_BLOCKS;
+        m.zr = sortrange.as<uint32_t>();
+        m.segmm = m.zr + 2;
         m.queue = queue.as<uint32_t>();
         m.ranges = ranges.as<uint2>();
         m.bin_hist = bin_hist.as<uint32_t>();
@@ -419,7 +423,8 @@ struct Workspace {
             grow(val[i], (size_t)cap * 4);
             grow(ext[i], (size_t)cap * 4);
         }
-        grow(hist, (size_t)2 * 256 * SORT_MAX_BLOCKS * 4);  // counts, then segment digit prefixes
+        grow(hist, (size_t)2 * 512 * SORT_MAX_BLOCKS * 4);  // counts, then segment digit prefixes
+        grow(sortrange, (size_t)(2 + 2 * SORT_MAX_BLOCKS) * 4);
         grow(queue, 8 * 4);                                  // blend band queues
         dup_cap = cap;
     }
@@ -473,6 +478,7 @@ struct tigas_context {
     std::atomic<bool> blend_cull{true};     // blend: per-block threshold culling
     std::atomic<bool> tile_bin{true};       // single view: tile digit placed by counting
     std::atomic<bool> tile_cull{false};     // duplicates only for tiles each Gaussian can reach
+    std::atomic<bool> depth4{false};        // four-pass depth sort (requested, or after a frame too deep for three)
     double stage_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t stage_frames = 0;
     std::mutex tune_mu;
@@ -618,7 +624,12 @@ ViewParams make_view(const tigas_scene* sc, const tigas_pose* pose, const tigas_
 size_t frame_bytes(const ViewParams& v) { return (size_t)v.width * v.height * 3 * (v.fmt == 1 ? 4 : 1); }
 
 // Depth digits of the (tile | depth) key: positive FP32 bit patterns, bit 31 clear.
-const SortPass kDepthPasses[4] = {{0, 8}, {8, 8}, {16, 8}, {24, 7}};
+const SortPass kDepthPasses[4] = {{0, 8, -1}, {8, 8, -1}, {16, 8, -1}, {24, 7, -1}};
+// Three passes of 9-bit digits of the key less the frame's smallest key, for
+// frames whose visible keys span less than 2^27 (depths within about 16
+// octaves); a wider frame is flagged by the first pass's scan, skipped by the
+// later passes and rendered again with kDepthPasses.
+const SortPass kDepthPasses3[3] = {{0, 9, 0}, {9, 9, 1}, {18, 9, 2}};
 
 // The fewest passes of at most 8 bits, with the bits spread evenly over them
 // (e.g. 12 bits as 6 + 6): fewer digits per pass give longer runs of equal
@@ -630,7 +641,7 @@ std::vector<SortPass> tile_passes(uint32_t n_tiles) {
     int sh = 0;
     for (int i = 0; i < np; ++i) {
         const int b = (tb - sh + (np - i) - 1) / (np - i);
-        p.push_back({sh, b});
+        p.push_back({sh, b, -1});
         sh += b;
     }
     return p;
@@ -729,6 +740,7 @@ struct LaunchOptions {
     bool cull = true;         // blend: per-block threshold culling of list entries
     bool bin = true;          // single view: tile digit placed by counting (else radix passes over the duplicates)
     bool cull_tiles = false;  // duplicates only for tiles the Gaussian can reach (radix passes then)
+    bool depth3 = true;       // three-pass depth sort (when the rectangles pack and the buffers are there)
 };
 
 // Whether every view's tile rectangles fit the packed one-word form.
@@ -784,13 +796,19 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
     }
     sb.hist = m.hist;
     sb.pre = m.hist_pre;
+    sb.zr = m.zr;
+    sb.segmm = m.segmm;
     // depth digits, on the visible Gaussians (record order in, depth order
     // out); the tile rectangles travel packed with them when every view has
-    // at most 256 x 256 tiles, else the last pass gathers them
+    // at most 256 x 256 tiles, else the last pass gathers them.  Three 9-bit
+    // passes when the rectangles pack (a frame whose keys turn out to span
+    // too much is flagged and redone with four), else four 8-bit passes.
     const bool packed = packed_rects(plan);
+    const bool depth3 = opt.depth3 && packed && m.zr;
     launch_compact(o, nblk, m.blk_off, sb.key[0], sb.val[0], packed ? sb.ext[0] : nullptr, vdev, st);
-    const int cv = launch_sort(sb, kDepthPasses, 4, /*which=*/1, m.dup_cap, sort_blocks(plan.nrec), 0, packed, cnt,
-                               packed ? nullptr : o.rect, packed ? nullptr : o.srect, st);
+    const int cv = launch_sort(sb, depth3 ? kDepthPasses3 : kDepthPasses, depth3 ? 3 : 4, /*which=*/1, m.dup_cap,
+                               sort_blocks(plan.nrec), 0, packed, cnt, packed ? nullptr : o.rect,
+                               packed ? nullptr : o.srect, st);
     const int cd = cv ^ 1;
     const bool bin = use_bin(plan, opt);
     if (!bin && opt.cull_tiles && packed) {
@@ -841,6 +859,11 @@ bool plan_binned(tigas_context* ctx, const Plan& plan) {
     return use_bin(plan, opt);
 }
 
+// Depth passes of the context's frames of this plan (after a frame settled).
+int depth_passes(tigas_context* ctx, const Plan& plan) {
+    return !ctx->depth4.load() && packed_rects(plan) ? 3 : 4;
+}
+
 // Launch the plan once: from a captured graph when allowed (captured on the
 // first use of its shape, re-captured after any workspace reallocation), else
 // eagerly.  Returns the sort buffer index.
@@ -855,6 +878,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     opt.cull = ctx->blend_cull.load();
     opt.bin = ctx->tile_bin.load();
     opt.cull_tiles = ctx->tile_cull.load();
+    opt.depth3 = !ctx->depth4.load();
     const bool kprof = ctx->profile_kernels.load();
     const bool graph = ctx->use_graphs.load() && plan.allow_graph && !debug && !work && !prof && !kprof;
     if (kprof) {
@@ -864,7 +888,7 @@ int launch_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug,
     }
     if (!graph) return enqueue(ws.mem(), plan, debug, prof, work, pblocks, opt);
     const std::string key = shape_key(plan, true) + (opt.cull ? "c1" : "c0") + (opt.bin ? "b1" : "b0") + (opt.cull_tiles ? "t1" : "t0") +
-                            (ws.active ? "f1" : "f0");
+                            (opt.depth3 ? "d3" : "d4") + (ws.active ? "f1" : "f0");
     GraphEntry& g = ws.graphs[key];
     if (!g.exec || g.gen != ws.gen) {
         if (g.exec) HIPCHK(hipGraphExecDestroy(g.exec));
@@ -918,29 +942,35 @@ Counters settle_frame(tigas_context* ctx, Workspace& ws, const Plan& plan, bool 
     std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
     rerenders = 0;
     if (c.overflow) {
-        const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
-        if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
-        ws.ensure_dups((uint32_t)want);
-        ensure_bin(ws, plan);
+        // bit 1: the visible depth keys span too much for the three-pass
+        // sort: four passes from now on; bit 0: more duplicates than the
+        // buffers hold: grow them
+        if (c.overflow & 2u) ctx->depth4.store(true);
+        if (c.overflow & 1u) {
+            const uint64_t want = (uint64_t)c.D + c.D / 4 + 1024;
+            if (want > 0xfff00000ull) fail(TIGAS_E_OOM, "duplicate count exceeds the 32-bit index range");
+            ws.ensure_dups((uint32_t)want);
+            ensure_bin(ws, plan);
+        }
         if (debug) prepare(ws, plan, debug);
         if (work) HIPCHK(hipMemsetAsync(work, 0, 16, ws.stream));
         cur = launch_plan(ctx, ws, plan, debug, prof, work);
         wait_stream(ws.stream);
         std::memcpy(&c, ws.fs().host_counters.p, sizeof(c));
-        if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth");
+        if (c.overflow) fail(TIGAS_E_DEVICE, "duplicate buffer overflow after regrowth or four-pass depth sort");
         rerenders += 1;
     }
     ws.last_D = c.D;
     return c;
 }
 
-tigas_stats frame_stats(const Plan& plan, const Counters& c, int rerenders, bool binned) {
+tigas_stats frame_stats(const Plan& plan, const Counters& c, int rerenders, bool binned, int depth_passes) {
     tigas_stats st{};
     st.visible = c.visible;
     st.duplicates = c.D;
     st.fallbacks = c.fallbacks;
     st.tiles = plan.n_tiles;
-    st.sort_passes = 4 + (binned ? 1 : (int64_t)tile_passes(plan.n_tiles).size());
+    st.sort_passes = depth_passes + (binned ? 1 : (int64_t)tile_passes(plan.n_tiles).size());
     st.rerenders = rerenders;
     st.tile_w = plan.tc.tw;
     st.tile_h = plan.tc.th;
@@ -1005,7 +1035,7 @@ void finish_async(tigas_context* ctx, Workspace& ws, int si) {
         ws.active = si;
         int cur = f.cur, rerenders = 0;
         const Counters c = settle_frame(ctx, ws, f.plan, false, false, nullptr, cur, rerenders);
-        d.stats = frame_stats(f.plan, c, rerenders, plan_binned(ctx, f.plan));
+        d.stats = frame_stats(f.plan, c, rerenders, plan_binned(ctx, f.plan), depth_passes(ctx, f.plan));
         record_stats(ctx, ws, d.stats, false);
     } catch (const Error& e) {
         d.status = e.st;
@@ -1038,7 +1068,7 @@ int run_plan(tigas_context* ctx, Workspace& ws, const Plan& plan, bool debug, un
     wait_stream(ws.stream);
     int rerenders = 0;
     const Counters c = settle_frame(ctx, ws, plan, debug, prof, work, cur, rerenders);
-    record_stats(ctx, ws, frame_stats(plan, c, rerenders, plan_binned(ctx, plan)), prof);
+    record_stats(ctx, ws, frame_stats(plan, c, rerenders, plan_binned(ctx, plan), depth_passes(ctx, plan)), prof);
     return cur;
 }
 
@@ -2033,6 +2063,7 @@ tigas_status tigas_context_create(int device, tigas_context** out) {
         if (const char* g = std::getenv("TIGAS_BLEND_CULL")) c->blend_cull.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_TILE_BIN")) c->tile_bin.store(std::atoi(g) != 0);
         if (const char* g = std::getenv("TIGAS_TILE_CULL")) c->tile_cull.store(std::atoi(g) != 0);
+        if (const char* g = std::getenv("TIGAS_DEPTH_PASSES")) c->depth4.store(std::atoi(g) == 4);
         load_tune_file(c.get());
         *out = c.release();
     });
@@ -2289,6 +2320,14 @@ tigas_status tigas_set_tile_culling(tigas_context* ctx, int enable) {
     return guard([&] {
         if (!ctx) fail(TIGAS_E_INVALID, "null context");
         ctx->tile_cull.store(enable != 0);
+    });
+}
+
+tigas_status tigas_set_depth_passes(tigas_context* ctx, int passes) {
+    return guard([&] {
+        if (!ctx) fail(TIGAS_E_INVALID, "null context");
+        if (passes != 3 && passes != 4) fail(TIGAS_E_INVALID, "depth passes must be 3 or 4");
+        ctx->depth4.store(passes == 4);
     });
 }
 

@@ -1018,6 +1018,37 @@ __global__ __launch_bounds__(K1_THREADS) void k_duplicate_culled(
 // (digit, segment); downsweep: rank (wave ballots + per-wave LDS counters)
 // and scatter.
 
+// Three-pass depth sort: 9-bit digits of (key - base), base = the smallest
+// visible key with its low 9 bits cleared (so the first pass, run before the
+// smallest key is known, takes the key's own low 9 bits), when the keys span
+// less than 2^27; wider frames are flagged and redone with the four 8-bit
+// passes of the whole key.
+constexpr int DEPTH3_BITS = 27;
+__device__ __forceinline__ bool depth_wide(uint32_t lo, uint32_t hi) {
+    return lo <= hi && ((hi - (lo & ~511u)) >> DEPTH3_BITS) != 0u;
+}
+// Digit base of a pass: fixed passes (adapt < 0) and the first adaptive pass
+// take the key as it is; later adaptive passes subtract the base from the
+// smallest and largest keys in zr, and are skipped (false) in a wide frame.
+__device__ __forceinline__ bool pass_digit(int adapt, const uint32_t* zr, uint32_t* kbase) {
+    *kbase = 0u;
+    if (adapt <= 0) return true;
+    const uint32_t lo = zr[0], hi = zr[1];
+    if (depth_wide(lo, hi)) return false;
+    if (lo <= hi) *kbase = lo & ~511u;
+    return true;
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
 __device__ __forceinline__ uint32_t sort_count(const Counters* cnt, int which, uint32_t cap) {
     if (which == 1) return min(cnt->visible, cap);
     return cnt->overflow ? 0u : min(cnt->D, cap);
@@ -1052,19 +1083,28 @@ __device__ __forceinline__ void segment(uint32_t D, int nb, int b, uint32_t* beg
 // b, pre[d * nb + b] = keys of digits below d in segment b (the segment's
 // exclusive digit prefix).  Summed over segments, pre gives each digit's global
 // start, so no kernel needs device-wide atomics on the 256 digit totals.
+template <int NDIG, bool MINMAX>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* __restrict__ keys,
                                                                const Counters* __restrict__ cnt, int which,
-                                                               uint32_t cap, int shift, int bits,
+                                                               uint32_t cap, int shift, int bits, int adapt,
+                                                               const uint32_t* __restrict__ zr,
                                                                uint32_t* __restrict__ hist,
-                                                               uint32_t* __restrict__ pre, int nb) {
-    static_assert(SORT_THREADS == 256, "one thread per digit");
-    // NH sub-histograms (one per wave and lane residue mod 4), rows of 257
-    // words so that the copies of one digit sit in different LDS banks: keys
-    // of one digit in one row of 64 (the leading depth digit is nearly
-    // constant) meet at most 16 to an address
-    constexpr int NW = SORT_THREADS / 64, NH = NW * 4, ROW = 257;
+                                                               uint32_t* __restrict__ pre, int nb,
+                                                               uint32_t* __restrict__ segmm) {
+    static_assert(NDIG % SORT_THREADS == 0, "whole digits per thread");
+    constexpr int DPT = NDIG / SORT_THREADS;  // digits per thread
+    // NH sub-histograms, rows of NDIG+1 words so that the copies of one digit
+    // sit in different LDS banks.  8-bit digits: one per wave and lane
+    // residue mod 4, so that keys of one digit in one row of 64 (the leading
+    // digit of the whole depth key is nearly constant) meet at most 16 to an
+    // address; 9-bit digits (of the key less the smallest key, spread over
+    // many values in every pass): one per wave
+    constexpr int NW = SORT_THREADS / 64, LPW = NDIG > 256 ? 1 : 4, NH = NW * LPW, ROW = NDIG + 1;
     __shared__ uint32_t red[NW];
     __shared__ uint32_t h[NH * ROW];
+    __shared__ uint32_t wlo[NW], whi[NW];
+    uint32_t kbase;
+    if (!pass_digit(adapt, zr, &kbase)) return;  // uniform: a wide frame, redone with four passes
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < NH * ROW; i += SORT_THREADS) h[i] = 0u;
     __syncthreads();
@@ -1073,7 +1113,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     const int seg = pass_segment(D, nb, (int)blockIdx.x);
     segment(D, nb, seg, &beg, &end);
     const uint32_t mask = (1u << bits) - 1u;
-    uint32_t* hrow = h + (w * 4 + (lane & 3)) * ROW;
+    uint32_t* hrow = h + (w * LPW + (lane & (LPW - 1))) * ROW;
+    uint32_t lo = 0xffffffffu, hi = 0u;  // MINMAX: the segment's smallest and largest key
     // each wave walks blocks of 8 rows of 64 keys (8 loads in flight per lane)
     constexpr int U = 8;
     for (uint32_t blk = beg + (uint32_t)w * 64 * U; blk < end; blk += SORT_THREADS * U) {
@@ -1085,19 +1126,54 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (blk + u * 64 + lane < end) atomicAdd(&hrow[(kk[u] >> shift) & mask], 1u);
+            if (blk + u * 64 + lane < end) {
+                atomicAdd(&hrow[((kk[u] - kbase) >> shift) & mask], 1u);
+                if (MINMAX) {
+                    lo = min(lo, kk[u]);
+                    hi = max(hi, kk[u]);
+                }
+            }
+    }
+    if (MINMAX) {
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane == 0) {
+            wlo[w] = lo;
+            whi[w] = hi;
+        }
     }
     __syncthreads();
-    const int t = threadIdx.x;
-    uint32_t s = 0;
+    if (MINMAX && threadIdx.x == 0) {
 #pragma unroll
-    for (int j = 0; j < NH; ++j) s += h[j * ROW + t];
-    if (t > (int)mask) s = 0;
+        for (int v = 1; v < NW; ++v) {
+            lo = min(lo, wlo[v]);
+            hi = max(hi, whi[v]);
+        }
+        segmm[2 * seg] = lo;
+        segmm[2 * seg + 1] = hi;
+    }
+    // thread t: digits t DPT .. t DPT + DPT - 1
+    const int t = threadIdx.x;
+    uint32_t sd[DPT], s = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = t * DPT + j;
+        uint32_t x = 0;
+#pragma unroll
+        for (int k = 0; k < NH; ++k) x += h[k * ROW + d];
+        sd[j] = d > (int)mask ? 0u : x;
+        s += sd[j];
+    }
     uint32_t tot;
-    const uint32_t e = block_excl_scan<SORT_THREADS>(s, red, &tot);
-    if (t <= (int)mask) {
-        hist[(size_t)t * nb + seg] = s;
-        pre[(size_t)t * nb + seg] = e;
+    uint32_t e = block_excl_scan<SORT_THREADS>(s, red, &tot);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = t * DPT + j;
+        if (d <= (int)mask) {
+            hist[(size_t)d * nb + seg] = sd[j];
+            pre[(size_t)d * nb + seg] = e;
+        }
+        e += sd[j];
     }
 }
 
@@ -1108,11 +1184,41 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
 // through LDS.
 template <int NJ>
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ pre,
-                                                   int nb, int ndig) {
+                                                   int nb, int ndig, int adapt, uint32_t* __restrict__ zr,
+                                                   const uint32_t* __restrict__ segmm, Counters* cnt) {
     __shared__ uint32_t qsum[4], qpre[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int d = blockIdx.x;
+    if (adapt == 0 && d == ndig) {
+        // the extra workgroup of the first pass of the three-pass depth sort:
+        // the smallest and largest key over the segments; a frame whose keys
+        // span 2^27 or more is flagged for the four-pass sort
+        uint32_t lo = 0xffffffffu, hi = 0u;
+        for (int i = threadIdx.x; i < nb; i += 256) {
+            lo = min(lo, segmm[2 * i]);
+            hi = max(hi, segmm[2 * i + 1]);
+        }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane == 0) {
+            qsum[w] = lo;
+            qpre[w] = hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int v = 1; v < 4; ++v) {
+                lo = min(lo, qsum[v]);
+                hi = max(hi, qpre[v]);
+            }
+            zr[0] = lo;
+            zr[1] = hi;
+            if (depth_wide(lo, hi)) atomicOr(&cnt->overflow, 2u);
+        }
+        return;
+    }
     if (d >= ndig) return;  // whole workgroup exits together
+    uint32_t kbase;
+    if (!pass_digit(adapt, zr, &kbase)) return;  // uniform
     uint32_t* row = hist + (size_t)d * nb;
     const uint32_t* prow = pre + (size_t)d * nb;
     const int j0 = w * NJ * 64;
@@ -1149,23 +1255,27 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
 // SUMS (last depth pass): each Gaussian's tile rectangle is gathered once
 // here and written in depth order, so that k_sorted_sums and k_duplicate read
 // it contiguously instead of gathering by record.
-template <bool EXTRA, bool SUMS>
+template <bool EXTRA, bool SUMS, int NDIG>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext,
-    const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits,
-    const uint32_t* __restrict__ hist, int nb, const uint2* __restrict__ rsrc, uint2* __restrict__ rdst) {
-    static_assert(SORT_THREADS == 256, "one thread per digit");
+    const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits, int adapt,
+    const uint32_t* __restrict__ zr, const uint32_t* __restrict__ hist, int nb, const uint2* __restrict__ rsrc,
+    uint2* __restrict__ rdst) {
+    static_assert(NDIG % SORT_THREADS == 0, "whole digits per thread");
+    constexpr int DPT = NDIG / SORT_THREADS;  // digits per thread
     constexpr int NW = SORT_THREADS / 64;
     constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
-    __shared__ uint32_t base[256];    // global position of the next key of each digit
-    __shared__ uint32_t lstart[256];  // chunk-local start of each digit
-    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t base[NDIG];    // global position of the next key of each digit
+    __shared__ uint32_t lstart[NDIG];  // chunk-local start of each digit
+    __shared__ uint32_t wcnt[NW][NDIG];
     __shared__ uint32_t red[NW];
     __shared__ uint32_t lkey[SORT_CHUNK];
     __shared__ uint32_t lval[SORT_CHUNK];
     __shared__ uint32_t lext[EXTRA ? SORT_CHUNK : 1];
     __shared__ uint2 lrect[SUMS ? SORT_CHUNK : 1];
+    uint32_t kbase;
+    if (!pass_digit(adapt, zr, &kbase)) return;  // uniform: a wide frame, redone with four passes
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -1173,7 +1283,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t D = sort_count(cnt, which, cap);
     const int seg = pass_segment(D, nb, (int)blockIdx.x);
     segment(D, nb, seg, &beg, &end);
-    base[t] = (t <= (int)mask) ? hist[(size_t)t * nb + seg] : 0u;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = t * DPT + j;
+        base[d] = (d <= (int)mask) ? hist[(size_t)d * nb + seg] : 0u;
+    }
     // the keys of the next chunk are loaded while the current one is ranked
     uint32_t nk[ROUNDS], nv[ROUNDS], ne[ROUNDS];
     auto load_chunk = [&](uint32_t c) {
@@ -1189,7 +1303,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     if (beg < end) load_chunk(beg);
     for (uint32_t chunk = beg; chunk < end; chunk += SORT_CHUNK) {
 #pragma unroll
-        for (int j = 0; j < NW; ++j) wcnt[j][t] = 0u;
+        for (int j = 0; j < NW; ++j)
+#pragma unroll
+            for (int q = 0; q < DPT; ++q) wcnt[j][t * DPT + q] = 0u;
         __syncthreads();
         uint32_t dig[ROUNDS], rank[ROUNDS], ek[ROUNDS], ev[ROUNDS], ee[ROUNDS];
         uint2 er[ROUNDS];
@@ -1207,7 +1323,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             ok[r] = idx < end;
             const uint32_t key = ek[r];
             if constexpr (SUMS) er[r] = rsrc[ev[r]];
-            const uint32_t d = (key >> shift) & mask;
+            const uint32_t d = ((key - kbase) >> shift) & mask;
             dig[r] = d;
             uint64_t m = ballot(ok[r]);
             for (int b = 0; b < bits; ++b) {
@@ -1222,19 +1338,29 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             if (ok[r] && prior == 0) wcnt[w][d] = cur + (uint32_t)__builtin_popcountll(m);
         }
         __syncthreads();
-        // digit t: chunk-local start, then per-wave local offsets
-        uint32_t c = 0;
+        // digits t DPT ..: chunk-local start, then per-wave local offsets
+        uint32_t c[DPT], csum = 0;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) c += wcnt[j][t];
+        for (int q = 0; q < DPT; ++q) {
+            c[q] = 0;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) c[q] += wcnt[j][t * DPT + q];
+            csum += c[q];
+        }
         uint32_t tot;
-        const uint32_t ls = block_excl_scan<SORT_THREADS>(c, red, &tot);
-        lstart[t] = ls;
-        uint32_t acc = ls;
+        uint32_t ls = block_excl_scan<SORT_THREADS>(csum, red, &tot);
 #pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            const uint32_t x = wcnt[j][t];
-            wcnt[j][t] = acc;
-            acc += x;
+        for (int q = 0; q < DPT; ++q) {
+            const int d = t * DPT + q;
+            lstart[d] = ls;
+            uint32_t acc = ls;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const uint32_t x = wcnt[j][d];
+                wcnt[j][d] = acc;
+                acc += x;
+            }
+            ls += c[q];
         }
         __syncthreads();
 #pragma unroll
@@ -1250,7 +1376,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
         __syncthreads();
         for (uint32_t l = (uint32_t)t; l < tot; l += SORT_THREADS) {
             const uint32_t k = lkey[l];
-            const uint32_t d = (k >> shift) & mask;
+            const uint32_t d = ((k - kbase) >> shift) & mask;
             const uint32_t pos = base[d] + (l - lstart[d]);
             if (pos < D) {
                 const uint32_t vv = lval[l];
@@ -1261,7 +1387,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             }
         }
         __syncthreads();
-        base[t] += c;
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) base[t * DPT + q] += c[q];
     }
 }
 
@@ -2296,29 +2423,45 @@ void launch_duplicate_culled(const PreOut& o, int nblk, const uint32_t* sorted_r
 }
 
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, const uint2* rect_src,
+                int start, bool extra, Counters* cnt, const uint2* rect_src,
                 uint2* rect_dst, hipStream_t st) {
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
         uint32_t* pre = b.pre;
-        TIGAS_LAUNCH(k_sort_upsweep, dim3(nblocks), dim3(SORT_THREADS), st, (const uint32_t*)b.key[cur], cnt, which,
-                     cap, ps.shift, ps.bits, b.hist, pre, nblocks);
-        const int ndig = 1 << ps.bits;
-        if (nblocks <= 1024)
-            TIGAS_LAUNCH(k_sort_scan<4>, dim3(ndig), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig);
+        const bool wide = ps.bits > 8;  // 9-bit digits: 512 per pass
+        if (ps.adapt == 0)
+            TIGAS_LAUNCH((k_sort_upsweep<512, true>), dim3(nblocks), dim3(SORT_THREADS), st,
+                         (const uint32_t*)b.key[cur], cnt, which, cap, ps.shift, ps.bits, ps.adapt,
+                         (const uint32_t*)b.zr, b.hist, pre, nblocks, b.segmm);
+        else if (wide)
+            TIGAS_LAUNCH((k_sort_upsweep<512, false>), dim3(nblocks), dim3(SORT_THREADS), st,
+                         (const uint32_t*)b.key[cur], cnt, which, cap, ps.shift, ps.bits, ps.adapt,
+                         (const uint32_t*)b.zr, b.hist, pre, nblocks, b.segmm);
         else
-            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 256>), dim3(ndig), dim3(256), st, b.hist,
-                         (const uint32_t*)pre, nblocks, ndig);
+            TIGAS_LAUNCH((k_sort_upsweep<256, false>), dim3(nblocks), dim3(SORT_THREADS), st,
+                         (const uint32_t*)b.key[cur], cnt, which, cap, ps.shift, ps.bits, ps.adapt,
+                         (const uint32_t*)b.zr, b.hist, pre, nblocks, b.segmm);
+        const int ndig = 1 << ps.bits;
+        // the first adaptive pass has one more workgroup: the key range
+        const int nscan = ndig + (ps.adapt == 0 ? 1 : 0);
+        if (nblocks <= 1024)
+            TIGAS_LAUNCH(k_sort_scan<4>, dim3(nscan), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig,
+                         ps.adapt, b.zr, (const uint32_t*)b.segmm, cnt);
+        else
+            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 256>), dim3(nscan), dim3(256), st, b.hist,
+                         (const uint32_t*)pre, nblocks, ndig, ps.adapt, b.zr, (const uint32_t*)b.segmm, cnt);
         const bool sums = rect_src && p + 1 == npasses;
-#define TIGAS_DOWN(E, S)                                                                                        \
-    TIGAS_LAUNCH((k_sort_downsweep<E, S>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],      \
+#define TIGAS_DOWN(E, S, N)                                                                                     \
+    TIGAS_LAUNCH((k_sort_downsweep<E, S, N>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],   \
                  b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits, \
-                 (const uint32_t*)b.hist, nblocks, rect_src, rect_dst)
-        if (extra && sums) TIGAS_DOWN(true, true);
-        else if (extra) TIGAS_DOWN(true, false);
-        else if (sums) TIGAS_DOWN(false, true);
-        else TIGAS_DOWN(false, false);
+                 ps.adapt, (const uint32_t*)b.zr, (const uint32_t*)b.hist, nblocks, rect_src, rect_dst)
+        if (wide && extra && !sums) TIGAS_DOWN(true, false, 512);
+        else if (wide) throw std::runtime_error("9-bit sort digits are for the packed-rectangle depth passes");
+        else if (extra && sums) TIGAS_DOWN(true, true, 256);
+        else if (extra) TIGAS_DOWN(true, false, 256);
+        else if (sums) TIGAS_DOWN(false, true, 256);
+        else TIGAS_DOWN(false, false, 256);
 #undef TIGAS_DOWN
         cur ^= 1;
     }

@@ -109,8 +109,10 @@ struct SortBuffers {
     uint32_t* key[2];
     uint32_t* val[2];
     uint32_t* ext[2];
-    uint32_t* hist;    // [256][segments] digit counts per segment
-    uint32_t* pre;     // [256][segments] segment digit prefixes
+    uint32_t* hist;    // [512][segments] digit counts per segment
+    uint32_t* pre;     // [512][segments] segment digit prefixes
+    uint32_t* zr;      // 2 words: smallest and largest visible depth key (three-pass depth sort)
+    uint32_t* segmm;   // [segments][2]: each segment's smallest and largest key
 };
 
 // Arrays cleared (as u32 words) by the first kernel after preprocess.
@@ -122,7 +124,8 @@ struct ZeroList {
 
 struct SortPass {
     int shift;
-    int bits;  // <= 8
+    int bits;   // <= 8, or 9 for the passes of the three-pass depth sort
+    int adapt;  // -1: a fixed digit of the key; 0..2: pass of the three-pass depth sort
 };
 
 // ---- launchers (kernels.hip) ----
@@ -161,7 +164,7 @@ void launch_duplicate_culled(const PreOut& o, int nblk, const uint32_t* sorted_r
 // With `rect_src`, the last pass also writes rect_src[value] to rect_dst in
 // sorted order.
 int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int which, uint32_t cap, int nblocks,
-                int start, bool extra, const Counters* cnt, const uint2* rect_src,
+                int start, bool extra, Counters* cnt, const uint2* rect_src,
                 uint2* rect_dst, hipStream_t st);
 // Tile ranges of the sorted list.  host_cnt: pinned host memory (or device
 // memory) that receives a copy of the counters.

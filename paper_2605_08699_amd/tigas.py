@@ -91,7 +91,7 @@ EXPORTS = ("tigas_context_create", "tigas_context_destroy", "tigas_scene_load", 
            "tigas_profile_kernels", "tigas_kernel_times", "tigas_render_submit", "tigas_render_wait",
            "tigas_jpeg_encode", "tigas_jpeg_max_bytes", "tigas_abr_default_config", "tigas_abr_create",
            "tigas_abr_destroy", "tigas_abr_observe", "tigas_abr_rate", "tigas_render_noalloc",
-           "tigas_set_tile_binning", "tigas_set_tile_culling")
+           "tigas_set_tile_binning", "tigas_set_tile_culling", "tigas_set_depth_passes")
 
 _lib = None
 
@@ -131,6 +131,7 @@ def lib():
         L.tigas_set_graphs.argtypes = [P, I]
         L.tigas_set_tile_binning.argtypes = [P, I]
         L.tigas_set_tile_culling.argtypes = [P, I]
+        L.tigas_set_depth_passes.argtypes = [P, I]
         L.tigas_stage_times.argtypes = [P, ctypes.POINTER(StageC)]
         L.tigas_profile_kernels.argtypes = [P, I]
         L.tigas_render_submit.argtypes = [P, ctypes.POINTER(PoseC), ctypes.POINTER(IntrC), I, I,
@@ -302,6 +303,12 @@ class Context:
         """Emit list entries only for tiles each Gaussian can reach (identical
         frames, fewer entries); off by default."""
         _check(lib().tigas_set_tile_culling(self.handle, int(bool(enable))))
+
+    def set_depth_passes(self, passes: int):
+        """Depth sort in three 9-bit passes with a four-pass fallback for
+        frames too deep (3, the default) or always four 8-bit passes (4);
+        identical frames either way."""
+        _check(lib().tigas_set_depth_passes(self.handle, int(passes)))
 
     def count_blend_work(self, scene: Scene, pose, intr, width, height, res_scale=1.0, tile=None,
                          batch_depth=None, ppl=None):

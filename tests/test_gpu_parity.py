@@ -69,8 +69,85 @@ def test_c1_tile_lists_sort_and_ranges_bit_exact(ctx, c1, tile, binning):
         ctx.set_tile_binning(True)
     gc.check_tiles(dbg, *tile)
     assert dbg["n_dup"] > scene.n
-    # 4 depth passes, then one counting placement or the radix tile passes
-    assert passes == (5 if binning else 4 + math.ceil(math.log2((W // tile[0]) * (H // tile[1])) / 8))
+    # 3 depth passes, then one counting placement or the radix tile passes
+    assert passes == (4 if binning else 3 + math.ceil(math.log2((W // tile[0]) * (H // tile[1])) / 8))
+
+
+@pytest.mark.parametrize("binning", [True, False])
+def test_c1_three_and_four_pass_depth_sorts_give_identical_lists_and_frames(ctx, c1, binning):
+    scene, poses, k, W, H = c1
+    s = ctx.load_scene(scene)
+    got = {}
+    ctx.set_tile_binning(binning)
+    try:
+        for passes in (3, 4):
+            ctx.set_depth_passes(passes)
+            dbg = ctx.render_debug(s, poses[0], k, W, H, tile=(16, 16))
+            got[passes] = (dbg, ctx.stats())
+    finally:
+        ctx.set_depth_passes(3)
+        ctx.set_tile_binning(True)
+    _say("depth passes", {p: g[1]["sort_passes"] for p, g in got.items()})
+    tile_passes = 1 if binning else math.ceil(math.log2((W // 16) * (H // 16)) / 8)
+    for passes, (dbg, st) in got.items():
+        gc.check_tiles(dbg, 16, 16)
+        assert st["rerenders"] == 0
+        assert st["sort_passes"] == passes + tile_passes
+    for key in ("svals", "skeys", "ranges", "image"):
+        np.testing.assert_array_equal(got[3][0][key], got[4][0][key])
+
+
+def test_frame_too_deep_for_three_passes_is_rendered_again_with_four():
+    # depths from 0.5 to 2e7 (their FP32 keys span more than 2^27), sizes
+    # growing with depth so that every Gaussian covers a few pixels
+    rng = np.random.default_rng(5)
+    n = 600
+    z = np.exp(rng.uniform(math.log(0.5), math.log(2e7), n))
+    means = np.column_stack([rng.uniform(-0.35, 0.35, n) * z, rng.uniform(-0.25, 0.25, n) * z, z])
+    ls = np.repeat(np.log(0.02 * z)[:, None], 3, axis=1) + rng.normal(0.0, 0.3, (n, 3))
+    scene = make_scene(means, ls, rng.normal(size=(n, 4)), rng.normal(1.0, 1.0, n), rng.uniform(0.0, 1.0, (n, 3)))
+    W, H = 200, 136
+    k = intr(150.0, W / 2, H / 2)
+    c = tigas.Context(0)  # the switch to four passes is kept per context
+    try:
+        s = c.load_scene(scene)
+        img = c.render(s, eye_pose(), k, W, H, fmt="f32", tile=(16, 16))
+        st = c.stats()
+        _say("deep frame", st)
+        assert st["rerenders"] == 1 and st["sort_passes"] == 5
+        proj = orc.preprocess(scene, eye_pose(), k, W, H)
+        br, nb = orc.render_frame(proj)
+        res = gc.check_frame_pixels(img.reshape(-1, 3), br.reshape(-1, br.shape[2], 4), nb.reshape(-1))
+        assert res["n_bad"] == 0 and res["n_unresolved"] == 0, res
+        # later frames take four passes from the start
+        dbg = c.render_debug(s, eye_pose(), k, W, H, tile=(16, 16))
+        st2 = c.stats()
+        assert st2["rerenders"] == 0 and st2["sort_passes"] == 5
+        zk = dbg["zkey"][dbg["touched"] > 0].astype(np.int64)
+        assert zk.max() - (zk.min() & ~511) >= 1 << 27  # the frame is too deep for three passes
+        gc.check_tiles(dbg, 16, 16)
+        np.testing.assert_array_equal(img, dbg["image"])
+    finally:
+        c.close()
+
+
+def test_frame_just_shallow_enough_keeps_three_passes(ctx):
+    # the same construction with depths from 0.5 to 1000: keys span less than 2^27
+    rng = np.random.default_rng(6)
+    n = 600
+    z = np.exp(rng.uniform(math.log(0.5), math.log(1000.0), n))
+    means = np.column_stack([rng.uniform(-0.35, 0.35, n) * z, rng.uniform(-0.25, 0.25, n) * z, z])
+    ls = np.repeat(np.log(0.02 * z)[:, None], 3, axis=1)
+    scene = make_scene(means, ls, None, np.full(n, 1.0), rng.uniform(0.0, 1.0, (n, 3)))
+    W, H = 200, 136
+    k = intr(150.0, W / 2, H / 2)
+    s = ctx.load_scene(scene)
+    dbg = ctx.render_debug(s, eye_pose(), k, W, H, tile=(16, 16))
+    st = ctx.stats()
+    zk = dbg["zkey"][dbg["touched"] > 0].astype(np.int64)
+    assert 1 << 25 < zk.max() - (zk.min() & ~511) < 1 << 27
+    assert st["rerenders"] == 0 and st["sort_passes"] == 4
+    gc.check_tiles(dbg, 16, 16)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 32), (32, 16)])
