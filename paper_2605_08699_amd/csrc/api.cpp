@@ -295,7 +295,7 @@ struct FrameMem {
     uint32_t* val[2] = {nullptr, nullptr};
     uint32_t* ext[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;      // digit counts per sort segment
-    uint32_t* hist_pre = nullptr;  // segment digit prefixes
+    uint32_t* hist_tot = nullptr;  // per-digit totals
     uint32_t* zr = nullptr;        // three-pass depth sort: key range and per-segment ranges
     uint32_t* segmm = nullptr;     //   (null: the four-pass depth sort only)
     uint32_t* queue = nullptr;
@@ -361,7 +361,7 @@ struct Workspace {
             m.ext[i] = ext[i].as<uint32_t>();
         }
         m.hist = hist.as<uint32_t>();
-        m.hist_pre = m.hist + (size_t)512 * SORT_MAX_BLOCKS;
+        m.hist_tot = m.hist + (size_t)512 * SORT_MAX_BLOCKS;
         m.zr = sortrange.as<uint32_t>();
         m.segmm = m.zr + 2;
         m.queue = queue.as<uint32_t>();
@@ -423,7 +423,7 @@ struct Workspace {
             grow(val[i], (size_t)cap * 4);
             grow(ext[i], (size_t)cap * 4);
         }
-        grow(hist, (size_t)2 * 512 * SORT_MAX_BLOCKS * 4);  // counts, then segment digit prefixes
+        grow(hist, ((size_t)512 * SORT_MAX_BLOCKS + 512) * 4);  // counts per (digit, segment), then digit totals
         grow(sortrange, (size_t)(2 + 2 * SORT_MAX_BLOCKS) * 4);
         grow(queue, 8 * 4);                                  // blend band queues
         dup_cap = cap;
@@ -795,7 +795,7 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
         sb.ext[i] = m.ext[i];
     }
     sb.hist = m.hist;
-    sb.pre = m.hist_pre;
+    sb.dtot = m.hist_tot;
     sb.zr = m.zr;
     sb.segmm = m.segmm;
     // depth digits, on the visible Gaussians (record order in, depth order
@@ -1368,7 +1368,7 @@ FrameMem carve_scratch(void* scratch_dev, uint32_t nrec, uint32_t n_tiles, Count
     m.bin_gsum = c.take<uint32_t>(((size_t)(BIN_GROUPS + 2) * n_tiles + bin_emit_groups(16u << 20, nrec)) * 4);
     // sort passes over at most 16M keys use at most 1024 segments
     m.hist = c.take<uint32_t>((size_t)256 * 1024 * 4);
-    m.hist_pre = c.take<uint32_t>((size_t)256 * 1024 * 4);
+    m.hist_tot = c.take<uint32_t>((size_t)512 * 4);
     // six duplicate arrays of dup_cap words (keys, values, extra; two each)
     const size_t left = c.cap > c.off + 6 * 256 ? c.cap - c.off - 6 * 256 : 0;
     const uint64_t dup_cap = std::min<uint64_t>(left / 24 / 256 * 256, 16u << 20);

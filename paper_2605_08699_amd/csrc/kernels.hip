@@ -1088,8 +1088,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
                                                                const Counters* __restrict__ cnt, int which,
                                                                uint32_t cap, int shift, int bits, int adapt,
                                                                const uint32_t* __restrict__ zr,
-                                                               uint32_t* __restrict__ hist,
-                                                               uint32_t* __restrict__ pre, int nb,
+                                                               uint32_t* __restrict__ hist, int nb,
                                                                uint32_t* __restrict__ segmm) {
     static_assert(NDIG % SORT_THREADS == 0, "whole digits per thread");
     constexpr int DPT = NDIG / SORT_THREADS;  // digits per thread
@@ -1100,7 +1099,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     // address; 9-bit digits (of the key less the smallest key, spread over
     // many values in every pass): one per wave
     constexpr int NW = SORT_THREADS / 64, LPW = NDIG > 256 ? 1 : 4, NH = NW * LPW, ROW = NDIG + 1;
-    __shared__ uint32_t red[NW];
     __shared__ uint32_t h[NH * ROW];
     __shared__ uint32_t wlo[NW], whi[NW];
     uint32_t kbase;
@@ -1154,36 +1152,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_upsweep(const uint32_t* _
     }
     // thread t: digits t DPT .. t DPT + DPT - 1
     const int t = threadIdx.x;
-    uint32_t sd[DPT], s = 0;
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
         const int d = t * DPT + j;
         uint32_t x = 0;
 #pragma unroll
         for (int k = 0; k < NH; ++k) x += h[k * ROW + d];
-        sd[j] = d > (int)mask ? 0u : x;
-        s += sd[j];
-    }
-    uint32_t tot;
-    uint32_t e = block_excl_scan<SORT_THREADS>(s, red, &tot);
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-        const int d = t * DPT + j;
-        if (d <= (int)mask) {
-            hist[(size_t)d * nb + seg] = sd[j];
-            pre[(size_t)d * nb + seg] = e;
-        }
-        e += sd[j];
+        if (d <= (int)mask) hist[(size_t)d * nb + seg] = x;
     }
 }
 
-// One workgroup per digit: the digit's global start (the sum of the
-// segments' exclusive digit prefixes), then its exclusive offsets over the
-// segments.  The four waves take consecutive quarters of the digit's row
+// One workgroup per digit: the digit's exclusive offsets over the segments
+// (within the digit) and its total.  The four waves take consecutive quarters of the digit's row
 // (NJ * 64 segments each) and learn the totals of the quarters before theirs
 // through LDS.
 template <int NJ>
-__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ pre,
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ dtot,
                                                    int nb, int ndig, int adapt, uint32_t* __restrict__ zr,
                                                    const uint32_t* __restrict__ segmm, Counters* cnt) {
     __shared__ uint32_t qsum[4], qpre[4];
@@ -1220,24 +1204,20 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
     uint32_t kbase;
     if (!pass_digit(adapt, zr, &kbase)) return;  // uniform
     uint32_t* row = hist + (size_t)d * nb;
-    const uint32_t* prow = pre + (size_t)d * nb;
     const int j0 = w * NJ * 64;
     uint32_t x[NJ];  // 4 * NJ * 64 >= nb
-    uint32_t part = 0, mine = 0;
+    uint32_t mine = 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
         const int j = j0 + q * 64 + lane;
         x[q] = j < nb ? row[j] : 0u;
         mine += x[q];
-        part += j < nb ? prow[j] : 0u;
     }
-    const uint32_t ws = wave_sum(mine), wp = wave_sum(part);
-    if (lane == 0) {
-        qsum[w] = ws;
-        qpre[w] = wp;
-    }
+    const uint32_t ws = wave_sum(mine);
+    if (lane == 0) qsum[w] = ws;
     __syncthreads();
-    uint32_t running = qpre[0] + qpre[1] + qpre[2] + qpre[3];
+    if (threadIdx.x == 0) dtot[d] = qsum[0] + qsum[1] + qsum[2] + qsum[3];
+    uint32_t running = 0;
     for (int v = 0; v < w; ++v) running += qsum[v];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
@@ -1260,8 +1240,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext,
     const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits, int adapt,
-    const uint32_t* __restrict__ zr, const uint32_t* __restrict__ hist, int nb, const uint2* __restrict__ rsrc,
-    uint2* __restrict__ rdst) {
+    const uint32_t* __restrict__ zr, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot, int nb,
+    const uint2* __restrict__ rsrc, uint2* __restrict__ rdst) {
     static_assert(NDIG % SORT_THREADS == 0, "whole digits per thread");
     constexpr int DPT = NDIG / SORT_THREADS;  // digits per thread
     constexpr int NW = SORT_THREADS / 64;
@@ -1283,10 +1263,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t D = sort_count(cnt, which, cap);
     const int seg = pass_segment(D, nb, (int)blockIdx.x);
     segment(D, nb, seg, &beg, &end);
+    // a digit's first position: the totals of the digits below it (scanned
+    // here from the per-digit totals) plus its offset in this segment
+    {
+        uint32_t tt[DPT], ts = 0;
 #pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-        const int d = t * DPT + j;
-        base[d] = (d <= (int)mask) ? hist[(size_t)d * nb + seg] : 0u;
+        for (int j = 0; j < DPT; ++j) {
+            const int d = t * DPT + j;
+            tt[j] = d <= (int)mask ? dtot[d] : 0u;
+            ts += tt[j];
+        }
+        uint32_t all;
+        uint32_t st = block_excl_scan<SORT_THREADS>(ts, red, &all);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = t * DPT + j;
+            base[d] = d <= (int)mask ? st + hist[(size_t)d * nb + seg] : 0u;
+            st += tt[j];
+        }
     }
     // the keys of the next chunk are loaded while the current one is ranked
     uint32_t nk[ROUNDS], nv[ROUNDS], ne[ROUNDS];
@@ -2428,34 +2422,34 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
     int cur = start;
     for (int p = 0; p < npasses; ++p) {
         const SortPass& ps = passes[p];
-        uint32_t* pre = b.pre;
         const bool wide = ps.bits > 8;  // 9-bit digits: 512 per pass
         if (ps.adapt == 0)
             TIGAS_LAUNCH((k_sort_upsweep<512, true>), dim3(nblocks), dim3(SORT_THREADS), st,
                          (const uint32_t*)b.key[cur], cnt, which, cap, ps.shift, ps.bits, ps.adapt,
-                         (const uint32_t*)b.zr, b.hist, pre, nblocks, b.segmm);
+                         (const uint32_t*)b.zr, b.hist, nblocks, b.segmm);
         else if (wide)
             TIGAS_LAUNCH((k_sort_upsweep<512, false>), dim3(nblocks), dim3(SORT_THREADS), st,
                          (const uint32_t*)b.key[cur], cnt, which, cap, ps.shift, ps.bits, ps.adapt,
-                         (const uint32_t*)b.zr, b.hist, pre, nblocks, b.segmm);
+                         (const uint32_t*)b.zr, b.hist, nblocks, b.segmm);
         else
             TIGAS_LAUNCH((k_sort_upsweep<256, false>), dim3(nblocks), dim3(SORT_THREADS), st,
                          (const uint32_t*)b.key[cur], cnt, which, cap, ps.shift, ps.bits, ps.adapt,
-                         (const uint32_t*)b.zr, b.hist, pre, nblocks, b.segmm);
+                         (const uint32_t*)b.zr, b.hist, nblocks, b.segmm);
         const int ndig = 1 << ps.bits;
         // the first adaptive pass has one more workgroup: the key range
         const int nscan = ndig + (ps.adapt == 0 ? 1 : 0);
         if (nblocks <= 1024)
-            TIGAS_LAUNCH(k_sort_scan<4>, dim3(nscan), dim3(256), st, b.hist, (const uint32_t*)pre, nblocks, ndig,
-                         ps.adapt, b.zr, (const uint32_t*)b.segmm, cnt);
+            TIGAS_LAUNCH(k_sort_scan<4>, dim3(nscan), dim3(256), st, b.hist, b.dtot, nblocks, ndig, ps.adapt, b.zr,
+                         (const uint32_t*)b.segmm, cnt);
         else
-            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 256>), dim3(nscan), dim3(256), st, b.hist,
-                         (const uint32_t*)pre, nblocks, ndig, ps.adapt, b.zr, (const uint32_t*)b.segmm, cnt);
+            TIGAS_LAUNCH((k_sort_scan<SORT_MAX_BLOCKS / 256>), dim3(nscan), dim3(256), st, b.hist, b.dtot, nblocks,
+                         ndig, ps.adapt, b.zr, (const uint32_t*)b.segmm, cnt);
         const bool sums = rect_src && p + 1 == npasses;
 #define TIGAS_DOWN(E, S, N)                                                                                     \
     TIGAS_LAUNCH((k_sort_downsweep<E, S, N>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],   \
                  b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits, \
-                 ps.adapt, (const uint32_t*)b.zr, (const uint32_t*)b.hist, nblocks, rect_src, rect_dst)
+                 ps.adapt, (const uint32_t*)b.zr, (const uint32_t*)b.hist, (const uint32_t*)b.dtot, nblocks, rect_src, \
+                 rect_dst)
         if (wide && extra && !sums) TIGAS_DOWN(true, false, 512);
         else if (wide) throw std::runtime_error("9-bit sort digits are for the packed-rectangle depth passes");
         else if (extra && sums) TIGAS_DOWN(true, true, 256);

@@ -109,8 +109,8 @@ struct SortBuffers {
     uint32_t* key[2];
     uint32_t* val[2];
     uint32_t* ext[2];
-    uint32_t* hist;    // [512][segments] digit counts per segment
-    uint32_t* pre;     // [512][segments] segment digit prefixes
+    uint32_t* hist;    // [512][segments] digit counts per segment (then each digit's offsets)
+    uint32_t* dtot;    // [512] per-digit totals
     uint32_t* zr;      // 2 words: smallest and largest visible depth key (three-pass depth sort)
     uint32_t* segmm;   // [segments][2]: each segment's smallest and largest key
 };
