@@ -704,7 +704,8 @@ void ensure_bin(Workspace& ws, const Plan& plan) {
     if (plan.views.size() != 1 || !bin_fits(plan.views[0].tiles_x, plan.views[0].tiles_y)) return;
     const size_t nbc = std::max<size_t>(1, (plan.nrec + BIN_BLOCK - 1) / BIN_BLOCK);
     ws.grow(ws.bin_hist, nbc * plan.n_tiles * 4);
-    ws.grow(ws.bin_gsum, ((size_t)(BIN_GROUPS + 2) * plan.n_tiles + bin_emit_groups(ws.dup_cap, plan.nrec)) * 4);
+    ws.grow(ws.bin_gsum, ((size_t)(BIN_GROUPS + 2) * plan.n_tiles + BIN_TILES_MAX / 256 + nbc +
+                          bin_emit_groups(ws.dup_cap, plan.nrec)) * 4);
 }
 
 void prepare(Workspace& ws, const Plan& plan, bool debug) {
@@ -1365,7 +1366,8 @@ FrameMem carve_scratch(void* scratch_dev, uint32_t nrec, uint32_t n_tiles, Count
     m.ranges = c.take<uint2>((size_t)std::max<uint32_t>(n_tiles, 1) * 8);
     m.bin_hist = c.take<uint32_t>(((size_t)nrec + BIN_BLOCK - 1) / BIN_BLOCK * n_tiles * 4);
     // the first-round table sized for the largest duplicate capacity below
-    m.bin_gsum = c.take<uint32_t>(((size_t)(BIN_GROUPS + 2) * n_tiles + bin_emit_groups(16u << 20, nrec)) * 4);
+    m.bin_gsum = c.take<uint32_t>(((size_t)(BIN_GROUPS + 2) * n_tiles + BIN_TILES_MAX / 256 +
+                                   ((size_t)nrec + BIN_BLOCK - 1) / BIN_BLOCK + 1 + bin_emit_groups(16u << 20, nrec)) * 4);
     // sort passes over at most 16M keys use at most 1024 segments
     m.hist = c.take<uint32_t>((size_t)256 * 1024 * 4);
     m.hist_tot = c.take<uint32_t>((size_t)512 * 4);

@@ -1531,7 +1531,7 @@ __device__ __forceinline__ void tile_xy(uint32_t t, uint32_t tiles_x, float inv_
 // 256 Gaussians.
 __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ packed, const Counters* __restrict__ cnt,
                                                   int tiles_x, int tiles_y, uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ round_cnt) {
+                                                  uint32_t* __restrict__ round_cnt, uint32_t* __restrict__ blk_tot) {
     static_assert(BIN_BLOCK == 8 * 256, "a block is eight rounds of 256");
     __shared__ uint32_t g[BIN_GRID_MAX];
     __shared__ uint32_t wsum[8][4];
@@ -1560,6 +1560,12 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ p
     if (threadIdx.x < 8 && blockIdx.x * 8 + threadIdx.x < nrounds) {
         const int k = threadIdx.x;
         round_cnt[blockIdx.x * 8 + k] = wsum[k][0] + wsum[k][1] + wsum[k][2] + wsum[k][3];
+    }
+    if (threadIdx.x == 0) {  // the block's entries (its eight rounds)
+        uint32_t b = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) b += wsum[k][0] + wsum[k][1] + wsum[k][2] + wsum[k][3];
+        blk_tot[blockIdx.x] = b;
     }
     grid_prefix2d(g, w1, h1);
     const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
@@ -1603,12 +1609,13 @@ __global__ __launch_bounds__(256) void k_bin_prefix(uint32_t* __restrict__ hist,
 // Per tile: the exclusive prefix of the group totals over groups (in place)
 // and the tile's total, stored after the BIN_GROUPS group rows.
 __global__ __launch_bounds__(256) void k_bin_groups(uint32_t* __restrict__ gsum, const Counters* __restrict__ cnt,
-                                                    uint32_t n_tiles) {
+                                                    uint32_t n_tiles, uint32_t* __restrict__ tchunk) {
+    __shared__ uint32_t red[4];
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
+    const bool in = t < n_tiles;
     uint32_t nb, bpg;
     bin_groups(bin_valid(cnt), &nb, &bpg);
-    const uint32_t ng = bpg ? (nb + bpg - 1) / bpg : 0u;
+    const uint32_t ng = in && bpg ? (nb + bpg - 1) / bpg : 0u;
     uint32_t x[BIN_GROUPS];
 #pragma unroll
     for (int g = 0; g < BIN_GROUPS; ++g) x[g] = (uint32_t)g < ng ? gsum[g * n_tiles + t] : 0u;
@@ -1618,78 +1625,66 @@ __global__ __launch_bounds__(256) void k_bin_groups(uint32_t* __restrict__ gsum,
         if ((uint32_t)g < ng) gsum[g * n_tiles + t] = run;
         run += x[g];
     }
-    gsum[BIN_GROUPS * n_tiles + t] = run;
+    if (in) gsum[BIN_GROUPS * n_tiles + t] = run;
+    // the 256 tiles' total, for the tile starts
+    const uint32_t c = block_sum<256>(run, red);
+    if (threadIdx.x == 0) tchunk[blockIdx.x] = c;
 }
 
-// Two workgroups.  The first: exclusive scan of the tile totals (the start
-// of each tile's list, stored in the row after the totals), the tile ranges,
-// and the frame's counters stored to the host-visible block.  The second:
-// exclusive scan of the rounds' entry counts (round_off[r], the total after
-// the last round) and, per emission workgroup k < nwg, the round holding its
-// first unit of work (the cost split of k_bin_emit): start_round[k].
-__global__ __launch_bounds__(1024) void k_bin_tiles(uint32_t* __restrict__ gsum, const Counters* __restrict__ cnt,
-                                                    uint32_t n_tiles, uint2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ round_cnt,
-                                                    uint32_t* __restrict__ round_off, uint32_t* __restrict__ start_round,
-                                                    uint32_t nwg, Counters* host_cnt) {
-    __shared__ uint32_t red[16];
+// Tile starts and round offsets, each in chunks of 256 (one workgroup per
+// chunk, so that many compute units read the totals the previous kernels
+// wrote): workgroups [0, ntc) take 256 tiles each, starting from the totals
+// of the tile chunks before theirs, and store each tile's start (in the row
+// after the totals) and range; the others take 256 rounds each, starting
+// from the entry totals of the histogram blocks (eight rounds each) before
+// theirs, and store each round's offset and, in start_round, the first round
+// of every emission workgroup.  Workgroup 0 also copies the counters for the
+// host (the frame's counters are final here).
+__global__ __launch_bounds__(256) void k_bin_tiles(uint32_t* __restrict__ gsum, const Counters* __restrict__ cnt,
+                                                   uint32_t n_tiles, uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ round_cnt,
+                                                   uint32_t* __restrict__ round_off, uint32_t* __restrict__ start_round,
+                                                   uint32_t nwg, Counters* host_cnt,
+                                                   const uint32_t* __restrict__ tchunk,
+                                                   const uint32_t* __restrict__ blk_tot) {
+    __shared__ uint32_t red[4];
+    __shared__ unsigned long long red64[4];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *host_cnt = *cnt;
     const uint32_t V = bin_valid(cnt);
-    constexpr int K = BIN_TILES_MAX / 1024;
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) *host_cnt = *cnt;
-        if (V == 0) return;  // uniform; the ranges were cleared
-        const uint32_t* tot_row = gsum + (size_t)BIN_GROUPS * n_tiles;
-        uint32_t* start_row = gsum + (size_t)(BIN_GROUPS + 1) * n_tiles;
-        uint32_t tot[K], sum = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t t = threadIdx.x * K + k;
-            tot[k] = t < n_tiles ? tot_row[t] : 0u;
-            sum += tot[k];
-        }
-        uint32_t total;
-        uint32_t start = block_excl_scan<1024>(sum, red, &total);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t t = threadIdx.x * K + k;
-            if (t < n_tiles) {
-                ranges[t] = tot[k] ? make_uint2(start, start + tot[k]) : make_uint2(0u, 0u);
-                start_row[t] = start;
-            }
-            start += tot[k];
+    if (V == 0) return;  // uniform; the ranges were cleared
+    const uint32_t ntc = (n_tiles + 255) / 256;
+    if (blockIdx.x < ntc) {
+        const uint32_t c = blockIdx.x;
+        const uint32_t before = block_sum<256>(threadIdx.x < c ? tchunk[threadIdx.x] : 0u, red);
+        const uint32_t t = c * 256 + threadIdx.x;
+        const uint32_t tot = t < n_tiles ? gsum[(size_t)BIN_GROUPS * n_tiles + t] : 0u;
+        uint32_t all;
+        const uint32_t start = before + block_excl_scan<256>(tot, red, &all);
+        if (t < n_tiles) {
+            ranges[t] = tot ? make_uint2(start, start + tot) : make_uint2(0u, 0u);
+            gsum[(size_t)(BIN_GROUPS + 1) * n_tiles + t] = start;
         }
         return;
     }
-    if (V == 0) return;  // uniform
-    // rounds, in chunks of 1024 x K
+    const uint32_t k = blockIdx.x - ntc;
     const uint32_t nrounds = (V + 255) / 256;
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < nrounds; c0 += 1024 * K) {
-        uint32_t x[K], s = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t r = c0 + threadIdx.x * K + k;
-            x[k] = r < nrounds ? round_cnt[r] : 0u;
-            s += x[k];
-        }
-        uint32_t ctot;
-        uint32_t o = carry + block_excl_scan<1024>(s, red, &ctot);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t r = c0 + threadIdx.x * K + k;
-            if (r < nrounds) {
-                round_off[r] = o;
-                // workgroups whose first unit falls in round r's cost range
-                const uint64_t c_lo = (uint64_t)o + (uint64_t)BIN_ROUND_COST * r;
-                const uint64_t c_hi = (uint64_t)(o + x[k]) + (uint64_t)BIN_ROUND_COST * (r + 1);
-                for (uint64_t wk = (c_lo + BIN_PAIRS - 1) / BIN_PAIRS; wk < nwg && wk * BIN_PAIRS < c_hi; ++wk)
-                    start_round[wk] = r;
-            }
-            o += x[k];
-        }
-        carry += ctot;
+    if (k * 256 >= nrounds) return;  // uniform
+    uint64_t p = 0;
+    for (uint32_t b = threadIdx.x; b < 32 * k; b += 256) p += blk_tot[b];
+    const uint32_t before = (uint32_t)block_sum_u64(p, red64);
+    const uint32_t r = k * 256 + threadIdx.x;
+    const uint32_t x = r < nrounds ? round_cnt[r] : 0u;
+    uint32_t all;
+    const uint32_t o = before + block_excl_scan<256>(x, red, &all);
+    if (r < nrounds) {
+        round_off[r] = o;
+        // workgroups whose first unit falls in round r's cost range
+        const uint64_t c_lo = (uint64_t)o + (uint64_t)BIN_ROUND_COST * r;
+        const uint64_t c_hi = (uint64_t)(o + x) + (uint64_t)BIN_ROUND_COST * (r + 1);
+        for (uint64_t wk = (c_lo + BIN_PAIRS - 1) / BIN_PAIRS; wk < nwg && wk * BIN_PAIRS < c_hi; ++wk)
+            start_round[wk] = r;
+        if (r + 1 == nrounds) round_off[nrounds] = o + x;
     }
-    if (threadIdx.x == 0) round_off[nrounds] = carry;
 }
 
 // Inclusive XOR prefix over the 64 lanes of a wave (same lane pattern as
@@ -2487,14 +2482,19 @@ void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const
                 uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, hipStream_t st) {
     const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
     const uint32_t nbc = std::max<uint32_t>(1u, (nrec + BIN_BLOCK - 1) / BIN_BLOCK);
-    TIGAS_LAUNCH(k_bin_hist, dim3(nbc), dim3(256), st, sorted_packed, cnt, tiles_x, tiles_y, hist, round_cnt);
+    // after the BIN_GROUPS + 2 rows of gsum: the 256-tile chunk totals, the
+    // histogram blocks' entry totals, then the first-round table
+    uint32_t* tchunk = gsum + (size_t)(BIN_GROUPS + 2) * n_tiles;
+    uint32_t* blk_tot = tchunk + BIN_TILES_MAX / 256;
+    uint32_t* start_round = blk_tot + nbc;
+    TIGAS_LAUNCH(k_bin_hist, dim3(nbc), dim3(256), st, sorted_packed, cnt, tiles_x, tiles_y, hist, round_cnt, blk_tot);
     TIGAS_LAUNCH(k_bin_prefix, dim3((n_tiles + 255) / 256, BIN_GROUPS), dim3(256), st, hist, cnt, n_tiles, gsum);
-    TIGAS_LAUNCH(k_bin_groups, dim3((n_tiles + 255) / 256), dim3(256), st, gsum, cnt, n_tiles);
+    TIGAS_LAUNCH(k_bin_groups, dim3((n_tiles + 255) / 256), dim3(256), st, gsum, cnt, n_tiles, tchunk);
     // enough emission workgroups for the largest cost the capacities allow
     const uint32_t nwg = bin_emit_groups(cap, nrec);
-    uint32_t* start_round = gsum + (size_t)(BIN_GROUPS + 2) * n_tiles;
-    TIGAS_LAUNCH(k_bin_tiles, dim3(2), dim3(1024), st, gsum, cnt, n_tiles, ranges, (const uint32_t*)round_cnt,
-                 round_off, start_round, nwg, host_cnt);
+    const uint32_t ntc = (n_tiles + 255) / 256, nrc = std::max<uint32_t>(1u, (nrec + 255) / 256 / 256 + 1);
+    TIGAS_LAUNCH(k_bin_tiles, dim3(ntc + nrc), dim3(256), st, gsum, cnt, n_tiles, ranges, (const uint32_t*)round_cnt,
+                 round_off, start_round, nwg, host_cnt, (const uint32_t*)tchunk, (const uint32_t*)blk_tot);
     const size_t ncell = (size_t)(tiles_x + 1) * (tiles_y + 1);
     const size_t lds = 8 * 4 * (size_t)(tiles_x + 1 + tiles_y + 1) + 4 * ncell;
     if (tile_out)
