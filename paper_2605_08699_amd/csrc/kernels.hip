@@ -734,12 +734,14 @@ __global__ __launch_bounds__(K1_THREADS) void k_compact(const uint32_t* __restri
         ra = *reinterpret_cast<const uint4*>(rect + r0);
         rb = *reinterpret_cast<const uint4*>(rect + r0 + 2);
     }
+    // loaded with the inputs, not after the scan: one memory round trip less
+    const uint32_t boff = (uint32_t)blockIdx.x * 4u < (uint32_t)nblk ? blk_off[blockIdx.x * 4] : 0u;
     const bool v0 = ra.y != 0u, v1 = ra.w != 0u, v2 = rb.y != 0u, v3 = rb.w != 0u;
     const uint32_t c = (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2 + (uint32_t)v3;
     uint32_t tot;
     const uint32_t ex = block_excl_scan<K1_THREADS>(c, red, &tot);
     if (c) {
-        uint32_t pos = blk_off[blockIdx.x * 4] + ex;
+        uint32_t pos = boff + ex;
         if (ext) {
             if (v0) { key[pos] = z.x; val[pos] = r0; ext[pos] = pack_rect(make_uint2(ra.x, ra.y)); ++pos; }
             if (v1) { key[pos] = z.y; val[pos] = r0 + 1; ext[pos] = pack_rect(make_uint2(ra.z, ra.w)); ++pos; }
@@ -1263,6 +1265,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
     const uint32_t D = sort_count(cnt, which, cap);
     const int seg = pass_segment(D, nb, (int)blockIdx.x);
     segment(D, nb, seg, &beg, &end);
+    // the keys of the next chunk are loaded while the current one is ranked
+    // (the first chunk's while the digit starts are formed)
+    uint32_t nk[ROUNDS], nv[ROUNDS], ne[ROUNDS];
+    auto load_chunk = [&](uint32_t c) {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const uint32_t idx = c + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
+            const uint32_t ic = idx < end ? idx : c;  // clamped: loads never depend on a branch
+            nk[r] = skey[ic];
+            nv[r] = sval[ic];
+            ne[r] = EXTRA ? sext[ic] : 0u;
+        }
+    };
+    if (beg < end) load_chunk(beg);
     // a digit's first position: the totals of the digits below it (scanned
     // here from the per-digit totals) plus its offset in this segment
     {
@@ -1282,19 +1298,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             st += tt[j];
         }
     }
-    // the keys of the next chunk are loaded while the current one is ranked
-    uint32_t nk[ROUNDS], nv[ROUNDS], ne[ROUNDS];
-    auto load_chunk = [&](uint32_t c) {
-#pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-            const uint32_t idx = c + (uint32_t)(w * (SORT_CHUNK / NW) + r * 64 + lane);
-            const uint32_t ic = idx < end ? idx : c;  // clamped: loads never depend on a branch
-            nk[r] = skey[ic];
-            nv[r] = sval[ic];
-            ne[r] = EXTRA ? sext[ic] : 0u;
-        }
-    };
-    if (beg < end) load_chunk(beg);
     for (uint32_t chunk = beg; chunk < end; chunk += SORT_CHUNK) {
 #pragma unroll
         for (int j = 0; j < NW; ++j)
