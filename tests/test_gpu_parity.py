@@ -97,6 +97,13 @@ def test_c1_three_and_four_pass_depth_sorts_give_identical_lists_and_frames(ctx,
         np.testing.assert_array_equal(got[3][0][key], got[4][0][key])
 
 
+def test_depth_passes_other_than_three_or_four_are_refused(ctx):
+    for bad in (0, 2, 5, -1):
+        with pytest.raises(tigas.TigasError, match="E_INVALID"):
+            ctx.set_depth_passes(bad)
+    ctx.set_depth_passes(3)
+
+
 def test_frame_too_deep_for_three_passes_is_rendered_again_with_four():
     # depths from 0.5 to 2e7 (their FP32 keys span more than 2^27), sizes
     # growing with depth so that every Gaussian covers a few pixels
