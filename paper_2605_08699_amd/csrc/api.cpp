@@ -300,6 +300,7 @@ struct FrameMem {
     uint32_t* segmm = nullptr;     //   (null: the four-pass depth sort only)
     uint32_t* queue = nullptr;
     uint2* ranges = nullptr;
+    uint32_t* order = nullptr;     // the blend's dispatch order of the tiles
     uint32_t* bin_hist = nullptr;  // binned tile digit: block histograms, group starts
     uint32_t* bin_gsum = nullptr;
     uint32_t* blk_off = nullptr;
@@ -366,6 +367,7 @@ struct Workspace {
         m.segmm = m.zr + 2;
         m.queue = queue.as<uint32_t>();
         m.ranges = ranges.as<uint2>();
+        m.order = reinterpret_cast<uint32_t*>(m.ranges + tile_cap);  // after the ranges, in the same buffer
         m.bin_hist = bin_hist.as<uint32_t>();
         m.bin_gsum = bin_gsum.as<uint32_t>();
         m.blk_off = blk_off.as<uint32_t>();
@@ -430,7 +432,7 @@ struct Workspace {
     }
     void ensure_tiles(uint32_t n) {
         if (n <= tile_cap && ranges.p) return;
-        grow(ranges, (size_t)std::max<uint32_t>(n, 1) * 8);
+        grow(ranges, (size_t)std::max<uint32_t>(n, 1) * 12);  // ranges, then the dispatch order
         tile_cap = std::max<uint32_t>(n, 1);
     }
     void ensure_views(int n) {
@@ -834,7 +836,7 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
         const ViewParams& v = plan.views[0];
         launch_bin(sb.val[cv], sb.ext[cv], cnt, plan.nrec, m.dup_cap, v.tiles_x, v.tiles_y, m.bin_hist, m.bin_gsum,
                    m.blk_sum2, m.blk_off2, m.ranges, m.cnt_out, o, vdev, sb.val[cd], debug ? sb.key[cd] : nullptr,
-                   debug ? sb.ext[cd] : nullptr, st);
+                   debug ? sb.ext[cd] : nullptr, m.order, st);
         mark(4);
         mark(5);
     } else {
@@ -844,10 +846,12 @@ int enqueue(const FrameMem& m, const Plan& plan, bool debug, bool prof, unsigned
                           cnt, nullptr, nullptr, st);
         mark(4);
         launch_ranges(sb.key[cur], cnt, m.dup_cap, m.ranges, m.cnt_out, o, vdev, st);
+        if (!plan.persistent) launch_tile_order(m.ranges, plan.n_tiles, m.order, st);
         mark(5);
     }
     launch_blend(vdev, nv, plan.n_tiles, m.ranges, sb.val[cur], o, plan.nrec, plan.tc.tw, plan.tc.th, plan.tc.bd,
-                 plan.tc.ppl, work, plan.persistent ? m.queue : nullptr, pblocks, opt.cull, st);
+                 plan.tc.ppl, work, plan.persistent ? m.queue : nullptr, pblocks, opt.cull,
+                 plan.persistent ? nullptr : m.order, st);
     mark(6);
     HIPCHK(hipGetLastError());
     return cur;
@@ -1364,6 +1368,7 @@ FrameMem carve_scratch(void* scratch_dev, uint32_t nrec, uint32_t n_tiles, Count
     o.chunk_dup = c.take<unsigned long long>(nch * 8);
     o.cnt = m.cnt;
     m.ranges = c.take<uint2>((size_t)std::max<uint32_t>(n_tiles, 1) * 8);
+    m.order = c.take<uint32_t>((size_t)std::max<uint32_t>(n_tiles, 1) * 4);
     m.bin_hist = c.take<uint32_t>(((size_t)nrec + BIN_BLOCK - 1) / BIN_BLOCK * n_tiles * 4);
     // the first-round table sized for the largest duplicate capacity below
     m.bin_gsum = c.take<uint32_t>(((size_t)(BIN_GROUPS + 2) * n_tiles + BIN_TILES_MAX / 256 +

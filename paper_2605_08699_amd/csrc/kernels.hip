@@ -1729,6 +1729,51 @@ __device__ __forceinline__ void wave_interval_masks(unsigned long long* m, int n
     }
 }
 
+// Dense-first dispatch order of a frame's tiles for the blend: tiles by
+// decreasing list length in 64 buckets of a quarter octave each (lengths up
+// to 2^16 apart), so the longest lists start first and short ones fill the
+// end of the launch instead of long ones running on after the rest are done.
+// Within a bucket the order is whatever the atomics give: every tile's
+// pixels are computed on their own, so the order changes only the timing.
+// One workgroup of NT threads; hist: 64 words of LDS.
+__device__ __forceinline__ uint32_t length_bucket(uint32_t n) {
+    const uint32_t x = n + 1u;
+    const int msb = 31 - __builtin_clz(x);
+    const uint32_t frac = msb >= 2 ? (x >> (msb - 2)) & 3u : (x << (2 - msb)) & 3u;
+    return 63u - min(63u, 4u * (uint32_t)msb + frac);
+}
+template <int NT>
+__device__ void tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ order,
+                           uint32_t* hist) {
+    for (int i = (int)threadIdx.x; i < 64; i += NT) hist[i] = 0u;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += NT) {
+        const uint2 r = ranges[t];
+        atomicAdd(&hist[length_bucket(r.y - r.x)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < 64; ++b) {
+            const uint32_t c = hist[b];
+            hist[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += NT) {
+        const uint2 r = ranges[t];
+        order[atomicAdd(&hist[length_bucket(r.y - r.x)], 1u)] = t;
+    }
+}
+
+// The same as a launch of its own, for frames whose ranges come from k_ranges.
+__global__ __launch_bounds__(256) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                    uint32_t* __restrict__ order) {
+    __shared__ uint32_t hist[64];
+    tile_order<256>(ranges, n_tiles, order, hist);
+}
+
 // Writes the entries of the depth-first emission order (Gaussians in depth
 // order, tiles row-major over each rectangle) to their sorted positions:
 // record ids, and with DEBUG also each entry's tile id and depth word; each
@@ -1736,9 +1781,12 @@ __device__ __forceinline__ void wave_interval_masks(unsigned long long* m, int n
 // position of its next entry; inside a round each entry adds the count of
 // earlier Gaussians of the round that hold its tile (the waves' column and
 // row lane masks), and the round's last Gaussian holding a tile moves that
-// tile's position.
+// tile's position.  Workgroup 0 writes the blend's dispatch order from the
+// (final) ranges instead, when `order` is given; the others take the
+// emission work.
 template <bool DEBUG>
-__global__ __launch_bounds__(256) void k_bin_emit(const uint32_t* __restrict__ sorted_rec,
+__global__ __launch_bounds__(256) void k_bin_emit(const uint2* __restrict__ ranges, uint32_t* __restrict__ order,
+                                                  const uint32_t* __restrict__ sorted_rec,
                                                   const uint32_t* __restrict__ packed, const Counters* __restrict__ cnt,
                                                   const uint32_t* __restrict__ hist, const uint32_t* __restrict__ gsum,
                                                   const uint32_t* __restrict__ round_off,
@@ -1755,6 +1803,11 @@ __global__ __launch_bounds__(256) void k_bin_emit(const uint32_t* __restrict__ s
     __shared__ uint32_t red[4], wmax[4], pick;
     __shared__ uint32_t pre[257], own[256], srec[256], spk[256];
     __shared__ float sinv[256];
+    if (blockIdx.x == 0) {  // uniform
+        if (order) tile_order<256>(ranges, (uint32_t)(tiles_x * tiles_y), order, pre);
+        return;
+    }
+    const int bid = (int)blockIdx.x - 1;  // the emission workgroup
     const uint32_t V = bin_valid(cnt);
     const uint32_t D = cnt->D;
     if (V == 0) return;  // uniform
@@ -1765,11 +1818,11 @@ __global__ __launch_bounds__(256) void k_bin_emit(const uint32_t* __restrict__ s
     const uint32_t nrounds = (V + 255) / 256;
     const uint64_t total_cost = (uint64_t)round_off[nrounds] + (uint64_t)BIN_ROUND_COST * nrounds;
     const uint32_t nact = (uint32_t)((total_cost + BIN_PAIRS - 1) / BIN_PAIRS);
-    if (blockIdx.x >= nact) return;  // uniform
+    if ((uint32_t)bid >= nact) return;  // uniform
     // XCD x takes a contiguous run of the cost ranges in use: the entries
     // neighbouring workgroups write to one tile's list are adjacent and meet
     // in one L2
-    const uint64_t A = (uint64_t)xcd_segment((int)blockIdx.x, (int)nact) * BIN_PAIRS;
+    const uint64_t A = (uint64_t)xcd_segment(bid, (int)nact) * BIN_PAIRS;
     const uint64_t B = min(total_cost, A + BIN_PAIRS);
     auto cost = [&](uint32_t r) -> uint64_t { return (uint64_t)round_off[r] + (uint64_t)BIN_ROUND_COST * r; };
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1967,6 +2020,7 @@ struct BlendArgs {
     uint32_t nrec;
     unsigned long long* work;
     int cull;  // drop entries below the skip threshold on the whole block (never changes a pixel)
+    const uint32_t* order;  // dense-first dispatch order of the tiles (null: XCD chunks)
 };
 
 // Per-wave LDS slice of staged Gaussians: block-relative centre (u, v of the
@@ -2238,19 +2292,27 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& A, uint32_t tile, in
     }
 }
 
-// One workgroup per tile.  XCD-aware mapping: consecutive workgroup ids go
-// round-robin to the 8 XCDs; XCD x takes the chunks of BLEND_CHUNK
-// consecutive tiles numbered x, x + 8, x + 16, ..., so neighbouring tiles
-// (which share Gaussians) meet in the same L2 while every XCD gets a share of
-// every part of the image (dense and sparse regions alike).
+// One workgroup per tile, in the dense-first order when one is given (the
+// longest lists first: the launch ends with short tiles instead of a tail of
+// long ones).  Otherwise XCD-aware: consecutive workgroup ids go round-robin
+// to the 8 XCDs; XCD x takes the chunks of BLEND_CHUNK consecutive tiles
+// numbered x, x + 8, x + 16, ..., so neighbouring tiles (which share
+// Gaussians) meet in the same L2 while every XCD gets a share of every part
+// of the image (dense and sparse regions alike).
 constexpr uint32_t BLEND_CHUNK = 16;
 template <int TW, int TH, int BD, int PPL, bool COUNT>
 __global__ __launch_bounds__(TW* TH / PPL) void k_blend(BlendArgs A) {
     constexpr int NW = TW * TH / (64 * PPL);
     __shared__ Stage<BD> stage[NW];
-    const uint32_t j = blockIdx.x >> 3, x = blockIdx.x & 7;
-    const uint32_t tile = ((j / BLEND_CHUNK) * 8u + x) * BLEND_CHUNK + (j % BLEND_CHUNK);
-    if (tile >= A.n_tiles) return;
+    uint32_t tile;
+    if (A.order) {
+        if (blockIdx.x >= A.n_tiles) return;
+        tile = A.order[blockIdx.x];
+    } else {
+        const uint32_t j = blockIdx.x >> 3, x = blockIdx.x & 7;
+        tile = ((j / BLEND_CHUNK) * 8u + x) * BLEND_CHUNK + (j % BLEND_CHUNK);
+        if (tile >= A.n_tiles) return;
+    }
     blend_tile<TW, TH, BD, PPL, COUNT>(A, tile, threadIdx.x >> 6, stage[threadIdx.x >> 6]);
 }
 
@@ -2460,6 +2522,10 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
     return cur;
 }
 
+void launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t st) {
+    if (n_tiles) TIGAS_LAUNCH(k_tile_order, dim3(1), dim3(256), st, ranges, n_tiles, order);
+}
+
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    const PreOut& o, const ViewParams* views_dev, hipStream_t st) {
     // one 1024-word step per workgroup at capacity, but no more workgroups
@@ -2482,7 +2548,7 @@ bool bin_fits(int tiles_x, int tiles_y) {
 void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const Counters* cnt, uint32_t nrec,
                 uint32_t cap, int tiles_x, int tiles_y, uint32_t* hist, uint32_t* gsum, uint32_t* round_cnt,
                 uint32_t* round_off, uint2* ranges, Counters* host_cnt, const PreOut& o, const ViewParams* views_dev,
-                uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, hipStream_t st) {
+                uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, uint32_t* order, hipStream_t st) {
     const uint32_t n_tiles = (uint32_t)(tiles_x * tiles_y);
     const uint32_t nbc = std::max<uint32_t>(1u, (nrec + BIN_BLOCK - 1) / BIN_BLOCK);
     // after the BIN_GROUPS + 2 rows of gsum: the 256-tile chunk totals, the
@@ -2500,13 +2566,16 @@ void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const
                  round_off, start_round, nwg, host_cnt, (const uint32_t*)tchunk, (const uint32_t*)blk_tot);
     const size_t ncell = (size_t)(tiles_x + 1) * (tiles_y + 1);
     const size_t lds = 8 * 4 * (size_t)(tiles_x + 1 + tiles_y + 1) + 4 * ncell;
+    // one more workgroup: the blend's dispatch order
     if (tile_out)
-        TIGAS_LAUNCH_SHM(k_bin_emit<true>, dim3(nwg), dim3(256), lds, st, sorted_rec, sorted_packed, cnt,
+        TIGAS_LAUNCH_SHM(k_bin_emit<true>, dim3(nwg + 1), dim3(256), lds, st, (const uint2*)ranges, order, sorted_rec,
+                         sorted_packed, cnt,
                          (const uint32_t*)hist, (const uint32_t*)gsum, (const uint32_t*)round_off,
                          (const uint32_t*)start_round, tiles_x, tiles_y, val_out, tile_out, depth_out,
                          (const uint32_t*)o.zkey);
     else
-        TIGAS_LAUNCH_SHM(k_bin_emit<false>, dim3(nwg), dim3(256), lds, st, sorted_rec, sorted_packed, cnt,
+        TIGAS_LAUNCH_SHM(k_bin_emit<false>, dim3(nwg + 1), dim3(256), lds, st, (const uint2*)ranges, order,
+                         sorted_rec, sorted_packed, cnt,
                          (const uint32_t*)hist, (const uint32_t*)gsum, (const uint32_t*)round_off,
                          (const uint32_t*)start_round, tiles_x, tiles_y, val_out, tile_out, depth_out,
                          (const uint32_t*)o.zkey);
@@ -2537,9 +2606,10 @@ static void blend_bd(int bd, const BlendArgs& A, bool count, uint32_t* queue, in
 
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st) {
+                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull,
+                  const uint32_t* order, hipStream_t st) {
     if (n_tiles == 0) return;
-    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec, nrec, work, cull ? 1 : 0};
+    const BlendArgs A{views_dev, nviews, n_tiles, ranges, vals, o.rec, nrec, work, cull ? 1 : 0, order};
     const bool count = work != nullptr;
     if (count) queue = nullptr;
     const bool two = ppl == 2 && tile_h >= 16;

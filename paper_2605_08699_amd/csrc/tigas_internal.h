@@ -170,6 +170,9 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
 // memory) that receives a copy of the counters.
 void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t cap, uint2* ranges, Counters* host_cnt,
                    const PreOut& o, const ViewParams* views_dev, hipStream_t st);
+// The blend's dense-first dispatch order of n_tiles tiles (longest lists
+// first) from their ranges: order receives a permutation of 0 .. n_tiles-1.
+void launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t st);
 // Tile placement by counting (single view, packed rectangles, a tile grid
 // that fits BIN_GRID_MAX / BIN_TILES_MAX): from the depth-ordered records and
 // packed rectangles, writes each (Gaussian, tile) entry's record id to its
@@ -178,12 +181,13 @@ void launch_ranges(const uint32_t* tile_sorted, const Counters* cnt, uint32_t ca
 // (BIN_GROUPS + 2) x tiles words (group rows, tile totals, tile starts) and
 // bin_emit_groups(cap, nrec) more (each emission workgroup's first round);
 // round_cnt / round_off: nrec / 256 + 1 words; cap: the entry capacity.
+// order (may be null): receives the blend's dense-first dispatch order.
 bool bin_fits(int tiles_x, int tiles_y);
 uint32_t bin_emit_groups(uint32_t cap, uint32_t nrec);
 void launch_bin(const uint32_t* sorted_rec, const uint32_t* sorted_packed, const Counters* cnt, uint32_t nrec,
                 uint32_t cap, int tiles_x, int tiles_y, uint32_t* hist, uint32_t* gsum, uint32_t* round_cnt,
                 uint32_t* round_off, uint2* ranges, Counters* host_cnt, const PreOut& o, const ViewParams* views_dev,
-                uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, hipStream_t st);
+                uint32_t* val_out, uint32_t* tile_out, uint32_t* depth_out, uint32_t* order, hipStream_t st);
 // Baseline JPEG of an RGB8 frame: one workgroup per restart interval of
 // JPEG_SEG_MCUS MCUs; the header is written by the host.
 constexpr int JPEG_THREADS = 128;
@@ -209,7 +213,10 @@ struct JpegArgs {
 void launch_jpeg(const JpegArgs& a, hipStream_t st);
 void launch_blend(const ViewParams* views_dev, int nviews, uint32_t n_tiles, const uint2* ranges,
                   const uint32_t* vals, const PreOut& o, uint32_t nrec, int tile_w, int tile_h, int batch_depth,
-                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull, hipStream_t st);
+                  int ppl, unsigned long long* work, uint32_t* queue, int persistent_blocks, bool cull,
+                  const uint32_t* order, hipStream_t st);
+// order (one workgroup per tile, without queue): the tiles' dispatch order,
+// or null for the XCD-chunked order.
 // With `queue` (8 counters cleared per frame) the blend runs as a persistent
 // kernel of persistent_blocks workgroups pulling tiles from work queues.
 // ppl: pixels per lane (1, or 2 for tiles at least 16 tall).  cull: drop,
