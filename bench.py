@@ -475,7 +475,7 @@ def kernel_work(name, w, n, storage, tile_passes):
     if "k_sort_downsweep<true, false, " in name:
         # the depth passes (three of 9-bit digits, else four of 8 bits): key,
         # record and packed rectangle read and written
-        return "hbm", (3 if ", 512>" in name else 4) * 24 * V
+        return "hbm", (3 if "false, 512" in name else 4) * 24 * V
     if "k_sort_downsweep<false, false, " in name:
         # the tile passes: key + value read and written per duplicate
         return "hbm", tile_passes * 16 * D
@@ -503,7 +503,7 @@ def roofline(v, n, storage):
     """Roofline of the dominant kernel of the FP32 run: algorithmic work per
     launch / average launch duration (HIP events around every launch)."""
     w = v["work"]
-    depth_passes = 3 if any("k_sort_downsweep<true, false, 512>" in k for k in v["kernels"]) else 4
+    depth_passes = 3 if any("k_sort_downsweep<true, false, 512" in k for k in v["kernels"]) else 4
     tile_passes = v["sort_passes"] - depth_passes
     ranked = sorted(v["kernels"].items(), key=lambda kv: -kv[1]["ms_per_frame"])
     for name, k in ranked:

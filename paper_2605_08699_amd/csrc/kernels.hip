@@ -1233,21 +1233,24 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
 
 // Chunks of 2048 keys are ranked (per-wave ballot match + per-wave digit
 // counters), staged in LDS in chunk-local digit order, and written out so that
-// consecutive threads store consecutive positions of each digit run.
+// consecutive threads store consecutive positions of each digit run.  NT
+// threads: 512 for the 9-bit depth digits (a digit per thread, four rounds
+// of ranking per wave instead of eight: one chunk per workgroup, so the
+// launch lasts about one workgroup's chain of rounds), else 256.
 // SUMS (last depth pass): each Gaussian's tile rectangle is gathered once
 // here and written in depth order, so that k_sorted_sums and k_duplicate read
 // it contiguously instead of gathering by record.
-template <bool EXTRA, bool SUMS, int NDIG>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
+template <bool EXTRA, bool SUMS, int NDIG, int NT>
+__global__ __launch_bounds__(NT) void k_sort_downsweep(
     const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval, const uint32_t* __restrict__ sext,
     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, uint32_t* __restrict__ dext,
     const Counters* __restrict__ cnt, int which, uint32_t cap, int shift, int bits, int adapt,
     const uint32_t* __restrict__ zr, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot, int nb,
     const uint2* __restrict__ rsrc, uint2* __restrict__ rdst) {
-    static_assert(NDIG % SORT_THREADS == 0, "whole digits per thread");
-    constexpr int DPT = NDIG / SORT_THREADS;  // digits per thread
-    constexpr int NW = SORT_THREADS / 64;
-    constexpr int ROUNDS = SORT_CHUNK / SORT_THREADS;
+    static_assert(NDIG % NT == 0, "whole digits per thread");
+    constexpr int DPT = NDIG / NT;  // digits per thread
+    constexpr int NW = NT / 64;
+    constexpr int ROUNDS = SORT_CHUNK / NT;
     __shared__ uint32_t base[NDIG];    // global position of the next key of each digit
     __shared__ uint32_t lstart[NDIG];  // chunk-local start of each digit
     __shared__ uint32_t wcnt[NW][NDIG];
@@ -1290,7 +1293,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             ts += tt[j];
         }
         uint32_t all;
-        uint32_t st = block_excl_scan<SORT_THREADS>(ts, red, &all);
+        uint32_t st = block_excl_scan<NT>(ts, red, &all);
 #pragma unroll
         for (int j = 0; j < DPT; ++j) {
             const int d = t * DPT + j;
@@ -1345,7 +1348,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             csum += c[q];
         }
         uint32_t tot;
-        uint32_t ls = block_excl_scan<SORT_THREADS>(csum, red, &tot);
+        uint32_t ls = block_excl_scan<NT>(csum, red, &tot);
 #pragma unroll
         for (int q = 0; q < DPT; ++q) {
             const int d = t * DPT + q;
@@ -1371,7 +1374,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_downsweep(
             }
         }
         __syncthreads();
-        for (uint32_t l = (uint32_t)t; l < tot; l += SORT_THREADS) {
+        for (uint32_t l = (uint32_t)t; l < tot; l += NT) {
             const uint32_t k = lkey[l];
             const uint32_t d = ((k - kbase) >> shift) & mask;
             const uint32_t pos = base[d] + (l - lstart[d]);
@@ -2506,7 +2509,8 @@ int launch_sort(const SortBuffers& b, const SortPass* passes, int npasses, int w
                          ndig, ps.adapt, b.zr, (const uint32_t*)b.segmm, cnt);
         const bool sums = rect_src && p + 1 == npasses;
 #define TIGAS_DOWN(E, S, N)                                                                                     \
-    TIGAS_LAUNCH((k_sort_downsweep<E, S, N>), dim3(nblocks), dim3(SORT_THREADS), st, b.key[cur], b.val[cur],   \
+    TIGAS_LAUNCH((k_sort_downsweep<E, S, N, N == 512 ? 512 : SORT_THREADS>), dim3(nblocks),                   \
+                 dim3(N == 512 ? 512 : SORT_THREADS), st, b.key[cur], b.val[cur],                                 \
                  b.ext[cur], b.key[cur ^ 1], b.val[cur ^ 1], b.ext[cur ^ 1], cnt, which, cap, ps.shift, ps.bits, \
                  ps.adapt, (const uint32_t*)b.zr, (const uint32_t*)b.hist, (const uint32_t*)b.dtot, nblocks, rect_src, \
                  rect_dst)
