@@ -109,3 +109,47 @@ def test_bandwidth_divides_bytes_by_launch_time(tmp_path):
     assert row[1] == "1.0" and row[3] == "1000" and row[4] == "0.125"  # 1000 GB/s of 8000
     lds_bytes = (80 + 60) / 2 * profiling.LDS_BYTES_PER_CLOCK
     assert abs(float(row[6]) - round(lds_bytes / 1.024e-6 / 1e9)) <= 1
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)  # no GPU work: main() runs only as a script
+    return mod
+
+
+def test_roofline_picks_the_blend_and_counts_its_work_per_launch():
+    """The roofline line of the FP32 run: the costliest kernel with a work
+    model is the blend (ALU-bound), its flops are 12 per evaluation and 9 per
+    contribution, per launch, divided by the average launch time."""
+    b = _bench_module()
+    work = dict(frames=2, visible=2 * 1.5e6, duplicates=2 * 6e6, evaluations=2 * 2e8, contributions=2 * 1.2e8,
+                fallbacks=0)
+    kernels = {
+        "void tigas::k_blend<16, 32, 1, 1, false>(tigas::BlendArgs)":
+            dict(launches_per_frame=1.0, avg_us=150.0, ms_per_frame=0.150),
+        "void tigas::k_preprocess<0, 3>(tigas::SceneView, ...)": dict(launches_per_frame=1.0, avg_us=133.0,
+                                                                      ms_per_frame=0.133),
+        "void tigas::k_sort_downsweep<true, false, 512, 512>(unsigned int const*, ...)":
+            dict(launches_per_frame=3.0, avg_us=19.0, ms_per_frame=0.057),
+    }
+    r = b.roofline(dict(work=work, kernels=kernels, sort_passes=4), 3_000_000, "f32")
+    assert r["bound"] == "alu" and "k_blend" in r["kernel"]
+    flops = 12 * 2e8 + 9 * 1.2e8
+    assert abs(r["achieved"] - flops / 150e-6 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 157.3) < 1e-12
+
+
+def test_depth_pass_bytes_follow_the_three_pass_kernel_names():
+    """Three 9-bit depth passes (kernel named with 512 digits and 512
+    threads) move 24 bytes per visible Gaussian each; the tile passes of the
+    radix path 16 bytes per duplicate each."""
+    b = _bench_module()
+    w = dict(frames=1, visible=1e6, duplicates=5e6, evaluations=0, contributions=0)
+    bound, amount = b.kernel_work("void tigas::k_sort_downsweep<true, false, 512, 512>(...)", w, 3e6, "f32", 0)
+    assert bound == "hbm" and amount == 3 * 24 * 1e6
+    bound, amount = b.kernel_work("void tigas::k_sort_downsweep<true, false, 256, 256>(...)", w, 3e6, "f32", 0)
+    assert amount == 4 * 24 * 1e6
+    bound, amount = b.kernel_work("void tigas::k_sort_downsweep<false, false, 256, 256>(...)", w, 3e6, "f32", 2)
+    assert amount == 2 * 16 * 5e6
